@@ -1,0 +1,102 @@
+"""Seeded synthetic inputs for the HQMC workloads.
+
+This module only draws random numbers and lays them out; it holds none of the
+method's arithmetic, so the product library, the tests and the CPU oracle can
+all be fed from it without sharing any computation.
+
+Layouts
+  theta  float64 (2, Nt, L, L): angle on the bond from site (x, y) to its +x
+         (d=0) or +y (d=1) neighbour in slice tau, indexed [d, tau, y, x]
+  vector complex128 (Nt, L, L), indexed [tau, y, x]
+
+The paper generates its workloads itself by Monte Carlo; the stand-ins here
+are its hot start (angles i.i.d. uniform on [0, 2 pi)), the pi-flux
+configuration it builds its preconditioner on (Methods, CG method and
+preconditioner), pi-flux plus Gaussian noise as a stand-in for thermalised
+configurations, and complex Gaussian sources.
+"""
+from dataclasses import dataclass, field
+from typing import List
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class Workload:
+    """One named workload: lattice, couplings, trajectory shape, precision."""
+    name: str
+    L: int
+    Nt: int
+    dtau: float = 0.1
+    t: float = 1.0
+    J: float = 1.0
+    K: float = 1.0
+    seed: int = 0
+    n_steps: int = 10
+    traj_len: float = 1.0
+    tol: float = 1e-10
+    precision: str = "fp64"
+    n_traj: int = 1
+    chains: List[int] = field(default_factory=list)
+
+    @property
+    def N(self) -> int:
+        return self.L * self.L * self.Nt
+
+
+# The five workloads of the hot path (lattice sizes, couplings, CG residual,
+# trajectory shape).  Trajectory length is 1 everywhere.
+WORKLOADS = {
+    "cpu_small": Workload("cpu_small", L=6, Nt=10, seed=1001, n_steps=10, tol=1e-10),
+    "fp64_l12": Workload("fp64_l12", L=12, Nt=120, seed=1002, n_steps=20, tol=1e-10,
+                         n_traj=20),
+    "mixed_l24": Workload("mixed_l24", L=24, Nt=240, seed=1003, n_steps=20, tol=1e-8,
+                          precision="mixed"),
+    "batched_chains": Workload("batched_chains", L=0, Nt=0, seed=1004, n_steps=20,
+                               tol=1e-8, precision="mixed"),
+    "learned_l66": Workload("learned_l66", L=66, Nt=660, seed=1005, n_steps=20, tol=1e-8,
+                            precision="mixed"),
+}
+
+
+def hot_start_theta(L: int, Nt: int, seed: int) -> np.ndarray:
+    """Angles i.i.d. uniform on [0, 2 pi) on every spatial bond of every slice."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0.0, 2.0 * np.pi, size=(2, Nt, L, L))
+
+
+def pi_flux_theta(L: int, Nt: int) -> np.ndarray:
+    """theta_x = 0, theta_y(x, y) = pi x: flux pi through every plaquette for even L."""
+    th = np.zeros((2, Nt, L, L))
+    th[1] = np.pi * np.arange(L)[None, None, :]
+    return th
+
+
+def noisy_pi_flux_theta(L: int, Nt: int, sigma: float, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return pi_flux_theta(L, Nt) + rng.normal(0.0, sigma, size=(2, Nt, L, L))
+
+
+def gauss_cvec(L: int, Nt: int, seed: int) -> np.ndarray:
+    """Complex Gaussian vector, Re and Im i.i.d. N(0, 1/2)."""
+    rng = np.random.default_rng(seed)
+    s = np.sqrt(0.5)
+    return (rng.normal(0.0, s, size=(Nt, L, L))
+            + 1j * rng.normal(0.0, s, size=(Nt, L, L)))
+
+
+def gauss_real(shape, seed: int, scale: float = 1.0) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return rng.normal(0.0, scale, size=shape)
+
+
+def gauge_angles(L: int, seed: int) -> np.ndarray:
+    """Random site angles alpha_s (shape (L, L)) for gauge transformations."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-np.pi, np.pi, size=(L, L))
+
+
+def chain_sizes(n_chains: int = 64, seed: int = 1004, sizes=(8, 12, 16, 20)) -> List[int]:
+    """Linear sizes of independent chains, drawn uniformly from ``sizes``."""
+    rng = np.random.default_rng(seed)
+    return [int(x) for x in rng.choice(np.asarray(sizes), size=n_chains)]

@@ -1,0 +1,374 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: every check is a closed form,
+an identity the paper states, a library routine (scipy expm / LU / solve), a
+finite difference, or a published test vector.  Each names the passage it
+pins.  All run on the CPU in seconds.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle as O
+from paper_2508_16298_amd import inputs
+
+
+def _lat(L=4, Nt=4, **kw):
+    return O.lat(L, Nt, **kw)
+
+
+def _cdot(a, b):
+    return np.vdot(a.reshape(-1), b.reshape(-1))
+
+
+# ---------------------------------------------------------------------------
+# Philox4x32-10: known-answer vectors published with the generator
+# (Salmon et al., SC'11, Random123 distribution's kat_vectors).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("ctr,key,expect", [
+    ([0, 0, 0, 0], [0, 0], [0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8]),
+    ([0xffffffff] * 4, [0xffffffff] * 2, [0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd]),
+    ([0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344], [0xa4093822, 0x299f31d0],
+     [0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1]),
+])
+def test_philox_known_answers(ctr, key, expect):
+    out = O.philox4x32_10(ctr, key)
+    assert [int(x) for x in out] == expect
+
+
+def test_heatbath_distribution():
+    """Step (i): p ~ exp(-p^2) (variance 1/2), R ~ exp(-|R|^2) (Re, Im variance 1/2)."""
+    p = _lat(12, 40)
+    mom, R = O.heatbath(p, seed=7, traj=3)
+    n = mom.size
+    for x in (mom.reshape(-1), R.real.reshape(-1), R.imag.reshape(-1)):
+        m = x.size
+        assert abs(x.mean()) < 5 * np.sqrt(0.5 / m)
+        assert abs(x.var() - 0.5) < 5 * 0.5 * np.sqrt(2.0 / m)
+    # distinct trajectories and seeds give distinct streams
+    mom2, _ = O.heatbath(p, seed=7, traj=4)
+    mom3, _ = O.heatbath(p, seed=8, traj=3)
+    assert np.abs(mom - mom2).max() > 0.1 and np.abs(mom - mom3).max() > 0.1
+    assert n == 2 * p.N
+    u = [O.metropolis_uniform(5, k) for k in range(2000)]
+    assert 0.0 <= min(u) and max(u) < 1.0 and abs(np.mean(u) - 0.5) < 5 * np.sqrt(1 / 12 / 2000)
+
+
+# ---------------------------------------------------------------------------
+# Bond families (Fig. 1, Eq. 24)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("L", [2, 4, 6, 12])
+def test_bond_table_invariants(L):
+    tab = O.bond_tables(L)
+    Vs = L * L
+    assert tab.shape == (4, Vs // 2, 3)
+    for f in range(4):
+        sites = np.concatenate([tab[f, :, 0], tab[f, :, 1]])
+        assert sorted(sites.tolist()) == list(range(Vs)), "each site once per family"
+        assert np.all(np.diff(tab[f, :, 0]) > 0), "sorted by origin site"
+        for i, j, b in tab[f]:
+            d, s = divmod(int(b), Vs)
+            assert s == i
+            x, y = i % L, i // L
+            assert d == (0 if f < 2 else 1)
+            par = x % 2 if d == 0 else y % 2
+            assert par == f % 2
+            exp_j = y * L + (x + 1) % L if d == 0 else ((y + 1) % L) * L + x
+            assert j == exp_j
+    assert sorted(tab[:, :, 2].reshape(-1).tolist()) == list(range(2 * Vs)), "all bonds once"
+
+
+# ---------------------------------------------------------------------------
+# B_tau (Eq. 24 and the 2x2 block formula)
+# ---------------------------------------------------------------------------
+def _hopping_matrix(L, theta_slice_x, theta_slice_y, t, dtau):
+    """V of B = e^V written straight from [V]_ij = t dtau e^{i theta_ij} (Methods)."""
+    Vs = L * L
+    V = np.zeros((Vs, Vs), dtype=complex)
+    for y in range(L):
+        for x in range(L):
+            s = y * L + x
+            for d, th in ((0, theta_slice_x), (1, theta_slice_y)):
+                j = y * L + (x + 1) % L if d == 0 else ((y + 1) % L) * L + x
+                V[s, j] += t * dtau * np.exp(1j * th[y, x])
+                V[j, s] += t * dtau * np.exp(-1j * th[y, x])
+    return V
+
+
+def test_B_hermitian_unimodular_and_bipartite():
+    p = _lat(4, 3)
+    th = inputs.hot_start_theta(4, 3, seed=11)
+    for tau in range(3):
+        B = O.dense_B(p, th, tau)
+        assert np.abs(B - B.conj().T).max() < 1e-14
+        assert abs(np.linalg.det(B) - 1.0) < 1e-12
+        # D B D = B^{-1} with D = (-1)^{x+y} (bipartite lattice, each factor odd in T)
+        D = np.diag([(-1.0) ** (x + y) for y in range(4) for x in range(4)])
+        assert np.abs(D @ B @ D - np.linalg.inv(B)).max() < 1e-12
+
+
+def test_B_trotter_error_is_third_order():
+    """The symmetric checkerboard product differs from e^V at O(dtau^3)."""
+    L = 4
+    th = inputs.hot_start_theta(L, 1, seed=3)
+    errs = []
+    for dtau in (0.2, 0.1, 0.05):
+        p = _lat(L, 1, dtau=dtau)
+        B = O.dense_B(p, th, 0)
+        V = _hopping_matrix(L, th[0, 0], th[1, 0], 1.0, dtau)
+        errs.append(np.abs(B - sla.expm(V)).max())
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 6.5 < r1 < 9.5 and 6.5 < r2 < 9.5, errs
+    assert errs[1] < 5e-3
+
+
+def _free_B_eigs(L, t, dtau):
+    q = 2 * np.pi * np.arange(L // 2) / (L // 2)
+    ch = np.cosh(t * dtau) ** 2 + np.sinh(t * dtau) ** 2 * np.cos(q)
+    lam = np.exp(np.arccosh(np.maximum(ch, 1.0)))
+    one = np.concatenate([lam, 1 / lam])
+    return np.sort(np.outer(one, one).reshape(-1))
+
+
+@pytest.mark.parametrize("L", [4, 6])
+def test_B_free_spectrum_closed_form(L):
+    """theta = 0: B = X (x) Y with eigenvalues lambda_x^{+-1} lambda_y^{+-1},
+    cosh eps(q) = cosh^2(t dtau) + sinh^2(t dtau) cos q, q = 2 pi m / (L/2)."""
+    p = _lat(L, 1)
+    B = O.dense_B(p, np.zeros((2, 1, L, L)), 0)
+    ev = np.sort(np.linalg.eigvalsh(B))
+    assert np.abs(ev - _free_B_eigs(L, 1.0, 0.1)).max() < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# M (Eq. M_alpha), M^dag, M^dag M
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("L,Nt", [(4, 4), (4, 7)])
+def test_free_M_spectrum_and_det(L, Nt):
+    """theta = 0: M is normal with eigenvalues 1 - mu e^{-i w_n}, w_n = (2n+1) pi / Nt
+    (antiperiodic), so M^dag M has 1 - 2 mu cos w_n + mu^2 and det M = prod (1 + mu^Nt)."""
+    p = _lat(L, Nt)
+    th = np.zeros((2, Nt, L, L))
+    M = O.dense_M(p, th)
+    mu = _free_B_eigs(L, 1.0, 0.1)
+    w = (2 * np.arange(Nt) + 1) * np.pi / Nt
+    expect = np.sort((1 - 2 * np.outer(mu, np.cos(w)) + mu[:, None] ** 2).reshape(-1))
+    Om = O.dense_MdagM(p, th)
+    assert np.abs(np.sort(np.linalg.eigvalsh(Om)) - expect).max() < 1e-12
+    sign, logdet = np.linalg.slogdet(M)
+    assert abs(logdet - np.sum(np.log1p(mu ** Nt))) < 1e-11
+    assert abs(sign - 1) < 1e-12
+
+
+def test_det_M_equals_det_one_plus_product_and_is_real():
+    """Eq. 4: det M = det(1 + B_{Nt} ... B_1), and det M is real (sign-free)."""
+    L, Nt = 4, 5
+    p = _lat(L, Nt)
+    th = inputs.hot_start_theta(L, Nt, seed=21)
+    M = O.dense_M(p, th)
+    lu, piv = sla.lu_factor(M)
+    dg = np.diag(lu)
+    logabs = np.sum(np.log(np.abs(dg)))
+    phase = np.prod(dg / np.abs(dg)) * (-1) ** np.sum(piv != np.arange(len(piv)))
+    P = np.eye(L * L, dtype=complex)
+    for tau in range(Nt):
+        P = O.dense_B(p, th, tau) @ P
+    ref = np.linalg.det(np.eye(L * L) + P)
+    assert abs(abs(phase.imag)) < 1e-10
+    assert abs(logabs - np.log(abs(ref))) < 1e-10
+    assert abs(np.angle(phase) - np.angle(ref)) < 1e-9 or abs(abs(np.angle(phase) - np.angle(ref)) - 2 * np.pi) < 1e-9
+    assert abs(ref.imag) / abs(ref) < 1e-12
+
+
+def test_M_adjoint_and_MdagM():
+    L, Nt = 4, 6
+    p = _lat(L, Nt)
+    th = inputs.hot_start_theta(L, Nt, seed=5)
+    u = inputs.gauss_cvec(L, Nt, 1)
+    v = inputs.gauss_cvec(L, Nt, 2)
+    lhs = _cdot(u, O.apply_M(p, th, v))
+    rhs = _cdot(O.apply_M(p, th, u, dagger=True), v)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    M = O.dense_M(p, th)
+    Md = O.dense_M(p, th, dagger=True)
+    assert np.abs(Md - M.conj().T).max() < 1e-14
+    Om = O.dense_MdagM(p, th)
+    assert np.abs(Om - M.conj().T @ M).max() < 1e-12
+
+
+def _gauge_transform(theta, alpha):
+    """theta^alpha_{d,tau,s} = theta + alpha_s - alpha_{s+e_d} (tau independent)."""
+    th = theta.copy()
+    th[0] += alpha[None, :, :] - np.roll(alpha, -1, axis=1)[None, :, :]
+    th[1] += alpha[None, :, :] - np.roll(alpha, -1, axis=0)[None, :, :]
+    return th
+
+
+def test_M_gauge_covariance():
+    """M(theta^alpha) = U M(theta) U^dag, U = diag(e^{i alpha_s}) in every slice."""
+    L, Nt = 4, 5
+    p = _lat(L, Nt)
+    th = inputs.hot_start_theta(L, Nt, seed=8)
+    al = inputs.gauge_angles(L, seed=9)
+    U = np.exp(1j * al)[None, :, :]
+    v = inputs.gauss_cvec(L, Nt, 3)
+    lhs = O.apply_M(p, _gauge_transform(th, al), U * v)
+    rhs = U * O.apply_M(p, th, v).reshape(Nt, L, L)
+    assert np.abs(lhs.reshape(Nt, L, L) - rhs).max() < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# CG solve (Eq. pCG)
+# ---------------------------------------------------------------------------
+def test_cg_matches_dense_solve_and_pseudofermion_identity():
+    L, Nt = 4, 6
+    p = _lat(L, Nt)
+    th = inputs.hot_start_theta(L, Nt, seed=12)
+    R = inputs.gauss_cvec(L, Nt, 13)
+    eta = O.apply_M(p, th, R, dagger=True)
+    X, st, it, rel = O.cg_solve(p, th, eta, tol=1e-12)
+    assert st == 0 and rel <= 1e-12 and it > 0
+    Om = O.dense_MdagM(p, th)
+    Xd = np.linalg.solve(Om, eta.reshape(-1))
+    assert np.linalg.norm(X.reshape(-1) - Xd) < 1e-8 * np.linalg.norm(Xd)
+    # eta^dag (M^dag M)^{-1} eta = R^dag R when eta = M^dag R
+    assert abs(_cdot(eta, X).real - _cdot(R, R).real) < 1e-9 * _cdot(R, R).real
+
+
+def test_cg_reports_nonconvergence():
+    L, Nt = 4, 6
+    p = _lat(L, Nt)
+    th = inputs.hot_start_theta(L, Nt, seed=12)
+    eta = inputs.gauss_cvec(L, Nt, 14)
+    X, st, it, rel = O.cg_solve(p, th, eta, tol=1e-12, maxit=3)
+    assert st == 1 and it == 3 and rel > 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Fermion force (SM SI) against central finite differences of S_F
+# ---------------------------------------------------------------------------
+def test_fermion_force_finite_difference():
+    L, Nt = 4, 3
+    p = _lat(L, Nt)
+    th = inputs.hot_start_theta(L, Nt, seed=31)
+    eta = inputs.gauss_cvec(L, Nt, 32).reshape(-1)
+
+    def SF(theta):
+        Om = O.dense_MdagM(p, theta)
+        return np.vdot(eta, np.linalg.solve(Om, eta)).real
+
+    X = np.linalg.solve(O.dense_MdagM(p, th), eta)
+    F = O.fermion_force(p, th, X)
+    h = 1e-5
+    Ffd = np.zeros_like(th)
+    flat = th.reshape(-1)
+    for b in range(flat.size):
+        tp, tm = flat.copy(), flat.copy()
+        tp[b] += h
+        tm[b] -= h
+        Ffd.reshape(-1)[b] = -(SF(tp.reshape(th.shape)) - SF(tm.reshape(th.shape))) / (2 * h)
+    assert np.abs(F - Ffd).max() < 1e-7 * np.abs(Ffd).max(), np.abs(F - Ffd).max()
+
+
+def test_fermion_force_gauge_invariant():
+    """S_F(theta^alpha, U eta) = S_F(theta, eta), so the force is unchanged."""
+    L, Nt = 4, 4
+    p = _lat(L, Nt)
+    th = inputs.hot_start_theta(L, Nt, seed=41)
+    al = inputs.gauge_angles(L, seed=42)
+    U = np.exp(1j * al)[None]
+    eta = inputs.gauss_cvec(L, Nt, 43)
+    thg = _gauge_transform(th, al)
+    X, *_ = O.cg_solve(p, th, eta, tol=1e-13)
+    Xg, *_ = O.cg_solve(p, thg, U * eta, tol=1e-13)
+    F = O.fermion_force(p, th, X)
+    Fg = O.fermion_force(p, thg, Xg)
+    assert np.abs(F - Fg).max() < 1e-8 * np.abs(F).max()
+
+
+# ---------------------------------------------------------------------------
+# Compact gauge action (Results, L_B^c; Methods) and its force
+# ---------------------------------------------------------------------------
+def test_bosonic_action_closed_forms():
+    L, Nt, J, K, dtau = 4, 5, 1.3, 0.7, 0.1
+    p = _lat(L, Nt, J=J, K=K, dtau=dtau)
+    n = L * L * Nt
+    assert abs(O.bosonic_action(p, np.zeros((2, Nt, L, L))) - K * dtau * n) < 1e-12
+    assert abs(O.bosonic_action(p, inputs.pi_flux_theta(L, Nt)) + K * dtau * n) < 1e-10
+    # one bond displaced by a: its time link term twice, two plaquettes with +-a
+    a = 0.37
+    th = np.zeros((2, Nt, L, L))
+    th[1, 2, 1, 3] = a
+    expect = 2 * (1 - np.cos(a)) / (J * dtau) + K * dtau * (n - 2 + 2 * np.cos(a))
+    assert abs(O.bosonic_action(p, th) - expect) < 1e-12
+
+
+def test_bosonic_action_gauge_invariant_and_force_fd():
+    L, Nt = 4, 4
+    p = _lat(L, Nt, J=1.0, K=1.0)
+    th = inputs.hot_start_theta(L, Nt, seed=51)
+    al = inputs.gauge_angles(L, seed=52)
+    assert abs(O.bosonic_action(p, _gauge_transform(th, al)) - O.bosonic_action(p, th)) < 1e-9
+    F = O.bosonic_force(p, th)
+    h = 1e-6
+    flat = th.reshape(-1)
+    Ffd = np.zeros_like(flat)
+    for b in range(flat.size):
+        tp, tm = flat.copy(), flat.copy()
+        tp[b] += h
+        tm[b] -= h
+        Ffd[b] = -(O.bosonic_action(p, tp.reshape(th.shape))
+                   - O.bosonic_action(p, tm.reshape(th.shape))) / (2 * h)
+    assert np.abs(F.reshape(-1) - Ffd).max() < 1e-6 * np.abs(Ffd).max()
+
+
+# ---------------------------------------------------------------------------
+# Leapfrog and trajectory (Eq. leapfrog, Eq. H_hmc, steps (i)-(iv))
+# ---------------------------------------------------------------------------
+def _md_inputs(L, Nt, seed):
+    p = _lat(L, Nt)
+    th = inputs.noisy_pi_flux_theta(L, Nt, 0.3, seed)
+    mom = inputs.gauss_real((2, Nt, L, L), seed + 1, np.sqrt(0.5))
+    R = inputs.gauss_cvec(L, Nt, seed + 2)
+    eta = O.apply_M(p, th, R, dagger=True)
+    return p, th, mom, eta
+
+
+def test_leapfrog_energy_error_is_second_order():
+    p, th, mom, eta = _md_inputs(4, 4, 61)
+    dH = []
+    for n in (4, 8, 16, 32):
+        _, _, hb, ha = O.leapfrog(p, th, mom, eta, n, traj_len=0.5, tol=1e-13)
+        dH.append(abs(ha - hb))
+    slope = np.polyfit(np.log([0.5 / 4, 0.5 / 8, 0.5 / 16, 0.5 / 32]), np.log(dH), 1)[0]
+    assert 1.8 < slope < 2.2, (slope, dH)
+
+
+def test_leapfrog_reversible():
+    p, th, mom, eta = _md_inputs(4, 4, 71)
+    th1, m1, _, _ = O.leapfrog(p, th, mom, eta, 10, traj_len=0.5, tol=1e-14)
+    th2, m2, _, _ = O.leapfrog(p, th1, -m1, eta, 10, traj_len=0.5, tol=1e-14)
+    assert np.abs(th2 - th).max() < 1e-9
+    assert np.abs(m2 + mom).max() < 1e-9
+
+
+def test_trajectory_bookkeeping():
+    """H0/H1 decompose as S_B + sum p^2 + S_F; S_F0 = R^dag R (eta = M^dag R);
+    rejection restores theta; acceptance follows min(1, e^{-dH}) with the drawn u."""
+    L, Nt = 4, 4
+    p = _lat(L, Nt)
+    th = inputs.hot_start_theta(L, Nt, seed=81)
+    th1, res, mom, R, eta = O.hmc_trajectory(p, th, seed=81, traj=0, n_steps=10, tol=1e-12)
+    assert res["n_solves"] == 11 and res["status"] == 0
+    assert abs(res["H0"] - (res["SB0"] + res["K0"] + res["SF0"])) < 1e-9
+    assert abs(res["SF0"] - np.vdot(R, R).real) < 1e-8 * res["SF0"]
+    assert abs(res["K0"] - np.sum(mom ** 2)) < 1e-9
+    mom_ref, R_ref = O.heatbath(p, 81, 0)
+    assert np.array_equal(mom, mom_ref.reshape(mom.shape)) and np.array_equal(R, R_ref.reshape(-1))
+    assert abs(res["SB0"] - O.bosonic_action(p, th)) < 1e-9
+    acc = res["dH"] <= 0 or res["u"] < np.exp(-res["dH"])
+    assert bool(res["accepted"]) == acc
+    if not acc:
+        assert np.array_equal(th1, th)
+    else:
+        assert abs(res["SB1"] - O.bosonic_action(p, th1)) < 1e-9
