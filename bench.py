@@ -1,0 +1,170 @@
+"""Benchmark: seconds per HMC trajectory and the achieved bandwidth of the
+fused M^dag M kernel, on one MI355X.
+
+Workload (default): L=24, Nt=240, dtau=0.1, t=1, J=K=1, theta = pi flux plus
+Gaussian noise (sigma 0.3, seed 1013; the stand-in for a thermalised
+configuration -- a hot start at this size sits next to det M = 0 and its
+molecular dynamics diverges), 20 leapfrog steps of total length 1, CG to true
+relative residual 1e-8, mixed precision (complex-FP32 matvecs and force, FP64
+solution, reliable updates and reductions).  One step = one trajectory of the
+chain: heat bath, 21 solves, 21 forces, leapfrog, Metropolis.
+
+Prints one JSON line.  The roofline block is for the dominant kernel (the
+fused FP32 M^dag M): algorithmic bytes per launch = 24 B per site (v in, out
+written, one FP32 angle per bond) / its average duration, timed with HIP
+events on the handle's stream over the timed region (every 8th launch).
+The CPU baseline is the plain FP64 oracle on a bounded sample (a fixed
+number of CG iterations plus one force at the same lattice), scaled to the
+trajectory's measured CG iteration count.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="mixed_l24")
+    ap.add_argument("--prec", default=None, help="override: fp64 or mixed")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=200, help="oracle CG iterations in the CPU sample")
+    ap.add_argument("--profile-every", type=int, default=8)
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, total_cg_iters, n_solves, n_iter):
+    """Oracle (plain FP64 C, single thread) on a bounded sample of the same
+    workload: n_iter CG iterations and one fermion force at the same lattice
+    and theta, scaled to the trajectory's CG iteration and solve counts."""
+    import numpy as np
+    import oracle as O
+    from paper_2508_16298_amd import inputs
+    p = O.lat(wl.L, wl.Nt, wl.dtau, wl.t, wl.J, wl.K)
+    th = wl.initial_theta()
+    R = inputs.gauss_cvec(wl.L, wl.Nt, wl.seed + 1)
+    eta = O.apply_M(p, th, R, dagger=True)
+    t0 = time.perf_counter()
+    X, st, it, rel = O.cg_solve(p, th, eta, tol=1e-30, maxit=n_iter)
+    t_cg = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.fermion_force(p, th, X)
+    O.bosonic_force(p, th)
+    t_force = time.perf_counter() - t0
+    per_iter = t_cg / max(it, 1)
+    est = per_iter * total_cg_iters + t_force * n_solves
+    return {
+        "value": est, "unit": "s/trajectory", "cores": 1, "kind": "oracle",
+        "sample": (f"oracle FP64 CG, {it} iterations ({t_cg:.1f} s) + one fermion and gauge force "
+                   f"({t_force:.2f} s) at L={wl.L} Nt={wl.Nt}, same theta; scaled to the GPU "
+                   f"trajectory's {total_cg_iters} CG iterations and {n_solves} forces "
+                   f"(extrapolation, single thread)"),
+    }
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {a.gpus} is not supported (this path has no "
+              "multi-GPU sharding; see DESIGN.md for how it would shard along tau)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2508_16298_amd import inputs
+    from paper_2508_16298_amd import qedhmc as Q
+
+    wl = inputs.WORKLOADS[a.workload]
+    prec = a.prec or wl.precision
+    th0 = wl.initial_theta()
+    theta = torch.from_numpy(th0).cuda()
+    lat = Q.Lattice(wl.L, wl.Nt, dtau=wl.dtau, t=wl.t, J=wl.J, K=wl.K, seed=wl.seed)
+
+    # load every kernel once (code objects, LDS attributes) before timing
+    v = torch.zeros((wl.Nt, wl.L, wl.L), dtype=torch.complex128, device="cuda")
+    v[0, 0, 0] = 1.0
+    lat.cg_solve(theta, v, tol=1e-3, maxit=50, prec=prec)
+    lat.fermion_force(theta, v, prec=prec)
+    lat.bosonic_action_force(theta)
+    torch.cuda.synchronize()
+
+    traj = 0
+    for _ in range(a.warmup):
+        lat.hmc_trajectory(theta, traj, wl.n_steps, wl.traj_len, wl.tol, prec=prec)
+        traj += 1
+    torch.cuda.synchronize()
+
+    lat.profile(a.profile_every)
+    results = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        results.append(lat.hmc_trajectory(theta, traj, wl.n_steps, wl.traj_len, wl.tol, prec=prec))
+        traj += 1
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kcls = Q.K_MDAGM_FP32 if prec != "fp64" else Q.K_MDAGM_FP64
+    n_k, ms_k = lat.profile_read(kcls)
+    lat.profile(0)
+
+    N = wl.L * wl.L * wl.Nt
+    bytes_per_site = 24 if prec != "fp64" else 48
+    alg_bytes = bytes_per_site * N
+    avg_ms = ms_k / max(n_k, 1)
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9 if n_k else None
+    s_per_traj = elapsed / a.steps
+    cg_total = sum(r["cg_iters_total"] for r in results) // a.steps
+    n_solves = results[-1]["n_solves"]
+
+    out = {
+        "metric": "s per HMC trajectory + M†M matvec HBM GB/s at L=24 Nτ=240, CG resid 1e-8",
+        "value": s_per_traj,
+        "unit": "s/trajectory",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * s_per_traj,
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "c64+f64" if prec != "fp64" else "c128",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{wl.name}: L={wl.L} Nt={wl.Nt} dtau={wl.dtau} t={wl.t} J={wl.J} K={wl.K}, "
+                         f"theta {wl.theta}{' sigma %g' % wl.sigma if wl.sigma else ''}, {wl.n_steps} leapfrog steps, length {wl.traj_len}, "
+                         f"CG true residual {wl.tol}, {'mixed FP32/FP64' if prec != 'fp64' else 'FP64'}"),
+            "L": wl.L, "Nt": wl.Nt, "sites": N, "n_steps": wl.n_steps, "tol": wl.tol,
+            "precision": prec,
+        },
+        "matvec_gbs": achieved,
+        "cg_iters_per_traj": cg_total,
+        "traj": [{k: r[k] for k in ("dH", "accepted", "cg_iters_total", "cg_iters_max",
+                                    "reliable_updates", "max_true_resid", "status")} for r in results],
+        "roofline": {
+            "bound": "hbm",
+            "kernel": f"k_mdagm<{'float' if prec != 'fp64' else 'double'}> (fused M^dag M)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+            "traffic": None,
+            "alg_bytes_per_launch": alg_bytes,
+            "avg_launch_us": avg_ms * 1e3,
+            "timed_launches": n_k,
+        },
+    }
+    lat.close()
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, cg_total, n_solves, a.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * qedhmc.h -- C ABI of the MI355X-native hybrid quantum Monte Carlo (HQMC)
+ * hot path for lattice QED3: a compact U(1) gauge field theta on the spatial
+ * bonds of an L x L x N_tau lattice coupled to two identical fermion flavours
+ * through one complex pseudofermion.
+ *
+ * Paper passages the calls implement (arXiv 2508.16298):
+ *   qedhmc_apply_M / qedhmc_apply_B   Methods, Eq. (M_alpha) and Eq. (24)
+ *   qedhmc_apply_MdagM                Methods, "Matrix-free representation of
+ *                                     M^dagger M v"
+ *   qedhmc_cg_solve                   Methods, "CG method and preconditioner",
+ *                                     Eq. (pCG)
+ *   qedhmc_fermion_force              Supplemental Material SI,
+ *                                     Eq. (force&CG) and Eq. (fermion_force)
+ *   qedhmc_bosonic_action_force       Results, compact Lagrangian L_B^c
+ *   qedhmc_heatbath                   Methods, HQMC algorithm step (i)
+ *   qedhmc_hmc_trajectory             Methods, HQMC steps (i)-(iv),
+ *                                     Eq. (leapfrog), Eq. (H_hmc)
+ *
+ * Conventions shared by every call
+ *   site        s = y*L + x, periodic in x and y; space-time n = tau*L*L + s
+ *   theta       device double[2][Nt][L][L]: angle of the bond from site s to
+ *               s + e_d (d = 0: +x, d = 1: +y) in slice tau
+ *   vectors     device interleaved complex [Nt][L][L]: double2 for
+ *               QEDHMC_FP64, float2 for QEDHMC_FP32 (the precision argument)
+ *   B_tau       symmetric checkerboard product E3 E2 E1 E0(2h) E1 E2 E3 with
+ *               h = t*dtau/2 over the bond families f0 (x-bonds leaving even
+ *               x), f1 (odd x), f2 (y-bonds leaving even y), f3 (odd y); each
+ *               bond block is cosh(a) 1 + sinh(a) [[0, e^{i theta}],
+ *               [e^{-i theta}, 0]]
+ *   M           (Mv)_0 = v_0 + B_{Nt-1} v_{Nt-1},
+ *               (Mv)_tau = v_tau - B_{tau-1} v_{tau-1}   (antiperiodic in tau)
+ *
+ * Ownership and ordering
+ *   The caller owns every device buffer passed in (16-byte aligned).  The
+ *   handle owns its workspace, allocated by qedhmc_init_lattice and freed by
+ *   qedhmc_destroy.  Every call enqueues work on the handle's HIP stream;
+ *   calls that return host scalars synchronise that stream before returning.
+ *   A handle is not thread-safe: calls on one handle must not overlap.
+ *
+ * Errors
+ *   Every call returns a qedhmc_status and never throws.  QEDHMC_EINVAL
+ *   means nothing was written (null pointer, odd or too small L, Nt < 1,
+ *   bad enum, tol <= 0, maxit < 1).  QEDHMC_ENOCONV still writes the
+ *   partial solution, the iteration count and the true residual.
+ *   QEDHMC_EHIP wraps a HIP runtime error; qedhmc_last_error() returns the
+ *   message of the last failing call on the calling thread.
+ */
+#ifndef QEDHMC_H
+#define QEDHMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qedhmc_ctx *qedhmc_t;
+
+typedef enum {
+    QEDHMC_OK = 0,
+    QEDHMC_EINVAL = 1,
+    QEDHMC_ENOCONV = 2,
+    QEDHMC_EHIP = 3,
+    QEDHMC_ENOMEM = 4,
+    QEDHMC_EUNSUPPORTED = 5
+} qedhmc_status;
+
+/* Arithmetic of a call.  For apply calls it is the vector element type
+ * (FP64: double2, FP32: float2).  For solves, forces and trajectories,
+ * QEDHMC_FP32 selects the mixed path: complex-FP32 matvecs and force,
+ * FP64 solution, FP64 reliable-update residuals every 50 iterations and
+ * FP64 reductions. */
+typedef enum { QEDHMC_FP64 = 0, QEDHMC_FP32 = 1 } qedhmc_precision;
+
+typedef enum { QEDHMC_PC_NONE = 0 } qedhmc_precond;
+
+/* Lattice, couplings and the seed of the trajectory random streams.
+ * L even, 2 <= L <= 90; Nt >= 1. */
+typedef struct {
+    int32_t L, Nt;
+    double dtau, t, J, K;
+    uint64_t seed;
+} qedhmc_params;
+
+/* Result of one trajectory (all energies FP64). */
+typedef struct {
+    double dH, H0, H1;     /* H = S_B + sum p^2 + Re eta^dag X           */
+    double SB0, SB1;       /* compact gauge action at start / end         */
+    double SF0, SF1;       /* fermion action from the solves              */
+    double K0, K1;         /* sum p^2 at start / end                      */
+    double u;              /* Metropolis uniform                          */
+    int32_t accepted;      /* 1: theta holds the proposal; 0: restored    */
+    int32_t n_solves;      /* N_md + 1                                    */
+    int32_t cg_iters_total, cg_iters_max;
+    int32_t status;        /* worst solve status (0 ok, 2 no convergence) */
+    int32_t reliable_updates;
+    double max_true_resid; /* largest final true relative residual        */
+} qedhmc_traj_result;
+
+/* Create a handle: validates params, builds the bond tables on the device
+ * and allocates the workspace.  stream: a hipStream_t (NULL = null stream).
+ * Lattice definition: Methods, "Model and partition function". */
+qedhmc_status qedhmc_init_lattice(const qedhmc_params *params, void *stream,
+                                  qedhmc_t *out);
+qedhmc_status qedhmc_destroy(qedhmc_t h);
+qedhmc_status qedhmc_set_stream(qedhmc_t h, void *stream);
+/* Message of the last failing call on this thread ("" if none). */
+const char *qedhmc_last_error(void);
+
+/* Copy the device bond tables to host memory: int32 [4][L*L/2][3], rows
+ * (origin site i, target site j, bond index d*L*L + i) per family f0..f3,
+ * in increasing i (Fig. 1 families used by Eq. 24). */
+qedhmc_status qedhmc_get_bond_tables(qedhmc_t h, int32_t *host_out);
+
+/* out = B_tau in on one slice (Eq. 24); in/out: device complex [L][L]. */
+qedhmc_status qedhmc_apply_B(qedhmc_t h, const double *theta, int32_t tau,
+                             const void *in, void *out, qedhmc_precision prec);
+
+/* out = M in (dagger = 0) or M^dag in (dagger = 1), Eq. (M_alpha).
+ * in and out must not alias. */
+qedhmc_status qedhmc_apply_M(qedhmc_t h, const double *theta, const void *in,
+                             void *out, int32_t dagger, qedhmc_precision prec);
+
+/* out = M^dag M in, fused (Methods, matrix-free M^dagger M v).  in and out
+ * must not alias. */
+qedhmc_status qedhmc_apply_MdagM(qedhmc_t h, const double *theta,
+                                 const void *in, void *out,
+                                 qedhmc_precision prec);
+
+/* Solve M^dag M x = rhs by conjugate gradient from x = 0 (Eq. pCG), stopping
+ * when the true residual |rhs - M^dag M x| / |rhs| <= tol (recomputed in FP64
+ * at exit).  rhs, x: device complex FP64 [Nt][L][L].  iters and
+ * true_rel_resid (host pointers, nullable) receive the iteration count and
+ * the final true relative residual.  prec = QEDHMC_FP32 runs the mixed path.
+ * Returns QEDHMC_ENOCONV (x still written) when maxit is reached. */
+qedhmc_status qedhmc_cg_solve(qedhmc_t h, const double *theta,
+                              const double *rhs, double *x, double tol,
+                              int32_t maxit, qedhmc_precision prec,
+                              qedhmc_precond pc, int32_t *iters,
+                              double *true_rel_resid);
+
+/* F = -dS_F/dtheta with S_F = eta^dag (M^dag M)^{-1} eta, given the solve
+ * X = (M^dag M)^{-1} eta (SM SI):  F_{b,tau} = 2 Re[Yt_tau^dag dB_tau X_tau],
+ * Y = M X, Yt_tau = -Y_{tau+1} (tau < Nt-1), Yt_{Nt-1} = +Y_0.
+ * X: device complex FP64; F: device double[2][Nt][L][L] (overwritten). */
+qedhmc_status qedhmc_fermion_force(qedhmc_t h, const double *theta,
+                                   const double *X, double *F,
+                                   qedhmc_precision prec);
+
+/* Compact gauge action
+ *   S_B = 1/(J dtau) sum [1 - cos(theta_{tau+1} - theta_tau)]
+ *         + K dtau sum_plaquettes cos(curl theta)
+ * (tau periodic) into *S_B_host (nullable) and, if F_B is not NULL, its force
+ * -dS_B/dtheta into device double[2][Nt][L][L]. */
+qedhmc_status qedhmc_bosonic_action_force(qedhmc_t h, const double *theta,
+                                          double *S_B_host, double *F_B);
+
+/* Heat bath of trajectory traj_index (step (i)): momenta p ~ N(0, 1/2) per
+ * bond and source R with Re, Im ~ N(0, 1/2) per site, from Philox4x32-10
+ * (key = seed, counter = (element, traj low, purpose, traj high)) and
+ * Box-Muller.  mom: device double[2][Nt][L][L]; R: device complex FP64. */
+qedhmc_status qedhmc_heatbath(qedhmc_t h, uint64_t traj_index, double *mom,
+                              double *R);
+
+/* One HQMC trajectory: heat bath, eta = M^dag R, n_steps leapfrog steps of
+ * length traj_len / n_steps with a fresh solve (from x = 0) at every theta,
+ * Metropolis with u from Philox.  theta_inout: device double[2][Nt][L][L],
+ * overwritten by the proposal on acceptance, unchanged on rejection. */
+qedhmc_status qedhmc_hmc_trajectory(qedhmc_t h, double *theta_inout,
+                                    uint64_t traj_index, int32_t n_steps,
+                                    double traj_len, double tol, int32_t maxit,
+                                    qedhmc_precision prec, qedhmc_precond pc,
+                                    qedhmc_traj_result *out);
+
+/* Kernel timing for measurement (not part of the method).  qedhmc_profile
+ * with every > 0 brackets every every-th launch of the timed kernels with
+ * HIP events on the handle's stream and clears the accumulators; every = 0
+ * turns it off.  qedhmc_profile_read returns, for kernel class k
+ * (QEDHMC_K_*), the number of timed launches and their summed duration in
+ * milliseconds, after synchronising the stream. */
+typedef enum {
+    QEDHMC_K_MDAGM_FP32 = 0,   /* fused M^dag M, complex FP32 */
+    QEDHMC_K_MDAGM_FP64 = 1,   /* fused M^dag M, complex FP64 */
+    QEDHMC_K_FORCE = 2,        /* fermion force kernel (either precision) */
+    QEDHMC_K_COUNT = 3
+} qedhmc_kernel_class;
+
+qedhmc_status qedhmc_profile(qedhmc_t h, int32_t every);
+qedhmc_status qedhmc_profile_read(qedhmc_t h, int32_t kernel_class,
+                                  int64_t *count, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QEDHMC_H */

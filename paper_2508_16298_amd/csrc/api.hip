@@ -1,0 +1,362 @@
+// C ABI of libqedhmc: handle lifetime, argument checks, and the host-side
+// orchestration of the trajectory (Methods, HQMC steps (i)-(iv)).
+#include <cmath>
+#include <cstring>
+
+#include "qedhmc_internal.h"
+
+namespace qh {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+qedhmc_status hip_fail(hipError_t e, const char* what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return QEDHMC_EHIP;
+}
+
+static qedhmc_status einval(const char* msg) {
+    g_err = msg;
+    return QEDHMC_EINVAL;
+}
+
+int prof_begin(qedhmc_ctx* h, int cls) {
+    if (h->prof_every <= 0 || !h->prof_ready) return -1;
+    if ((h->prof_seen[cls]++ % h->prof_every) != 0) return -1;
+    if (h->prof_pending == 64 && prof_drain(h) != QEDHMC_OK) return -1;
+    const int k = h->prof_pending++;
+    h->prof_cls[k] = cls;
+    (void)hipEventRecord(h->prof_ev[k][0], h->stream);
+    return k;
+}
+
+void prof_end(qedhmc_ctx* h, int slot) {
+    if (slot >= 0) (void)hipEventRecord(h->prof_ev[slot][1], h->stream);
+}
+
+qedhmc_status prof_drain(qedhmc_ctx* h) {
+    for (int k = 0; k < h->prof_pending; k++) {
+        QH_HIP(hipEventSynchronize(h->prof_ev[k][1]));
+        float ms = 0.f;
+        QH_HIP(hipEventElapsedTime(&ms, h->prof_ev[k][0], h->prof_ev[k][1]));
+        h->prof_count[h->prof_cls[k]]++;
+        h->prof_ms[h->prof_cls[k]] += ms;
+    }
+    h->prof_pending = 0;
+    return QEDHMC_OK;
+}
+
+}  // namespace qh
+
+using namespace qh;
+
+#define CHECK_H(h) \
+    if (!(h)) return einval("null handle")
+
+static size_t nsites(const qedhmc_ctx* h) { return (size_t)h->lat.Nt * h->lat.Vs; }
+
+static qedhmc_status check_prec(qedhmc_precision p) {
+    if (p != QEDHMC_FP64 && p != QEDHMC_FP32) return einval("bad precision");
+    return QEDHMC_OK;
+}
+
+extern "C" {
+
+const char* qedhmc_last_error(void) { return g_err.c_str(); }
+
+qedhmc_status qedhmc_init_lattice(const qedhmc_params* params, void* stream, qedhmc_t* out) {
+    if (!params || !out) return einval("null argument");
+    const qedhmc_params& p = *params;
+    if (p.L < 2 || p.L % 2 != 0) return einval("L must be even and >= 2");
+    if (p.L > 90) return einval("L > 90 is not supported");
+    if (p.Nt < 1) return einval("Nt must be >= 1");
+    if (!(p.dtau >= 0.0) || !(p.J > 0.0) || !std::isfinite(p.t) || !std::isfinite(p.K))
+        return einval("bad couplings (need dtau >= 0, J > 0, finite t and K)");
+    if ((size_t)p.L * p.L * p.Nt >= ((size_t)1 << 31)) return einval("lattice too large");
+    *out = nullptr;
+    qedhmc_ctx* h = new (std::nothrow) qedhmc_ctx;
+    if (!h) return QEDHMC_ENOMEM;
+    std::memset(h, 0, sizeof(*h));
+    h->p = p;
+    h->lat.L = p.L;
+    h->lat.Nt = p.Nt;
+    h->lat.Vs = p.L * p.L;
+    h->lat.hL = p.L / 2;
+    h->lat.ncell = h->lat.hL * h->lat.hL;
+    h->stream = (hipStream_t)stream;
+    hipError_t e = hipGetDevice(&h->device);
+    int lds = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "hipGetDevice / attribute");
+    }
+    h->max_lds = (size_t)lds;
+    const size_t N = nsites(h);
+    const size_t vec = N * sizeof(cplx<double>);
+    bool ok = true;
+    ok = ok && hipMalloc(&h->d_tables, sizeof(int32_t) * 3 * 2 * h->lat.Vs) == hipSuccess;
+    ok = ok && hipMalloc(&h->gauge64, 2 * N * sizeof(cplx<double>)) == hipSuccess;
+    ok = ok && hipMalloc(&h->gauge32, 2 * N * sizeof(cplx<float>)) == hipSuccess;
+    for (int k = 0; k < 12 && ok; k++) ok = hipMalloc(&h->ws[k], vec) == hipSuccess;
+    ok = ok && hipMalloc(&h->theta0, 2 * N * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc(&h->mom, 2 * N * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc(&h->force, 2 * N * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc(&h->force_b, 2 * N * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc(&h->partial, ((size_t)p.Nt + 2048) * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc(&h->scal, 64 * sizeof(double)) == hipSuccess;
+    ok = ok && hipHostMalloc(&h->h_pinned, 64 * sizeof(double), hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        qedhmc_destroy(h);
+        g_err = "device allocation failed";
+        return QEDHMC_ENOMEM;
+    }
+    qedhmc_status st = launch_bond_tables(h);
+    if (st == QEDHMC_OK) {
+        e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) st = hip_fail(e, "init sync");
+    }
+    if (st != QEDHMC_OK) {
+        qedhmc_destroy(h);
+        return st;
+    }
+    *out = h;
+    return QEDHMC_OK;
+}
+
+qedhmc_status qedhmc_destroy(qedhmc_t h) {
+    if (!h) return QEDHMC_OK;
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(h->d_tables);
+    (void)hipFree(h->gauge64);
+    (void)hipFree(h->gauge32);
+    for (int k = 0; k < 12; k++) (void)hipFree(h->ws[k]);
+    (void)hipFree(h->theta0);
+    (void)hipFree(h->mom);
+    (void)hipFree(h->force);
+    (void)hipFree(h->force_b);
+    (void)hipFree(h->partial);
+    (void)hipFree(h->scal);
+    if (h->h_pinned) (void)hipHostFree(h->h_pinned);
+    if (h->prof_ready)
+        for (int k = 0; k < 64; k++) {
+            (void)hipEventDestroy(h->prof_ev[k][0]);
+            (void)hipEventDestroy(h->prof_ev[k][1]);
+        }
+    delete h;
+    return QEDHMC_OK;
+}
+
+qedhmc_status qedhmc_profile(qedhmc_t h, int32_t every) {
+    CHECK_H(h);
+    if (every < 0) return einval("every must be >= 0");
+    if (every > 0 && !h->prof_ready) {
+        for (int k = 0; k < 64; k++) {
+            QH_HIP(hipEventCreate(&h->prof_ev[k][0]));
+            QH_HIP(hipEventCreate(&h->prof_ev[k][1]));
+        }
+        h->prof_ready = true;
+    }
+    QH_TRY(prof_drain(h));
+    h->prof_every = every;
+    for (int c = 0; c < QEDHMC_K_COUNT; c++) {
+        h->prof_seen[c] = 0;
+        h->prof_count[c] = 0;
+        h->prof_ms[c] = 0.0;
+    }
+    return QEDHMC_OK;
+}
+
+qedhmc_status qedhmc_profile_read(qedhmc_t h, int32_t cls, int64_t* count, double* total_ms) {
+    CHECK_H(h);
+    if (cls < 0 || cls >= QEDHMC_K_COUNT || !count || !total_ms) return einval("bad profile query");
+    QH_HIP(hipStreamSynchronize(h->stream));
+    QH_TRY(prof_drain(h));
+    *count = h->prof_count[cls];
+    *total_ms = h->prof_ms[cls];
+    return QEDHMC_OK;
+}
+
+qedhmc_status qedhmc_set_stream(qedhmc_t h, void* stream) {
+    CHECK_H(h);
+    h->stream = (hipStream_t)stream;
+    return QEDHMC_OK;
+}
+
+qedhmc_status qedhmc_get_bond_tables(qedhmc_t h, int32_t* host_out) {
+    CHECK_H(h);
+    if (!host_out) return einval("null output");
+    QH_HIP(hipMemcpyAsync(host_out, h->d_tables, sizeof(int32_t) * 3 * 2 * h->lat.Vs, hipMemcpyDeviceToHost,
+                          h->stream));
+    QH_HIP(hipStreamSynchronize(h->stream));
+    return QEDHMC_OK;
+}
+
+qedhmc_status qedhmc_apply_B(qedhmc_t h, const double* theta, int32_t tau, const void* in, void* out,
+                             qedhmc_precision prec) {
+    CHECK_H(h);
+    if (!theta || !in || !out) return einval("null pointer");
+    if (tau < 0 || tau >= h->lat.Nt) return einval("tau out of range");
+    QH_TRY(check_prec(prec));
+    QH_TRY(ensure_gauge(h, theta, prec));
+    return launch_apply_B(h, prec, tau, in, out);
+}
+
+qedhmc_status qedhmc_apply_M(qedhmc_t h, const double* theta, const void* in, void* out, int32_t dagger,
+                             qedhmc_precision prec) {
+    CHECK_H(h);
+    if (!theta || !in || !out) return einval("null pointer");
+    if (in == out) return einval("in and out alias");
+    QH_TRY(check_prec(prec));
+    QH_TRY(ensure_gauge(h, theta, prec));
+    return launch_apply_M(h, prec, in, out, dagger ? 1 : 0);
+}
+
+qedhmc_status qedhmc_apply_MdagM(qedhmc_t h, const double* theta, const void* in, void* out,
+                                 qedhmc_precision prec) {
+    CHECK_H(h);
+    if (!theta || !in || !out) return einval("null pointer");
+    if (in == out) return einval("in and out alias");
+    QH_TRY(check_prec(prec));
+    QH_TRY(ensure_gauge(h, theta, prec));
+    return launch_mdagm(h, prec, in, out, nullptr);
+}
+
+static qedhmc_status solve_at(qedhmc_ctx* h, const double* theta, const double* rhs, double* x, double tol,
+                              int32_t maxit, qedhmc_precision prec, int32_t* iters, double* rel, int* nrel) {
+    QH_TRY(ensure_gauge(h, theta, QEDHMC_FP64));
+    if (prec != QEDHMC_FP64) QH_TRY(ensure_gauge(h, theta, prec));
+    int it = 0, nr = 0;
+    double r = 0.0;
+    const qedhmc_status st = cg_solve_impl(h, rhs, x, tol, maxit, prec, &it, &r, &nr);
+    if (iters) *iters = it;
+    if (rel) *rel = r;
+    if (nrel) *nrel = nr;
+    if (st == QEDHMC_ENOCONV)
+        set_error("CG reached maxit=" + std::to_string(maxit) + " with true residual " + std::to_string(r));
+    return st;
+}
+
+qedhmc_status qedhmc_cg_solve(qedhmc_t h, const double* theta, const double* rhs, double* x, double tol,
+                              int32_t maxit, qedhmc_precision prec, qedhmc_precond pc, int32_t* iters,
+                              double* true_rel_resid) {
+    CHECK_H(h);
+    if (!theta || !rhs || !x) return einval("null pointer");
+    if (rhs == x) return einval("rhs and x alias");
+    if (!(tol > 0.0) || maxit < 1) return einval("need tol > 0 and maxit >= 1");
+    if (pc != QEDHMC_PC_NONE) return einval("unknown preconditioner");
+    QH_TRY(check_prec(prec));
+    return solve_at(h, theta, rhs, x, tol, maxit, prec, iters, true_rel_resid, nullptr);
+}
+
+qedhmc_status qedhmc_fermion_force(qedhmc_t h, const double* theta, const double* X, double* F,
+                                   qedhmc_precision prec) {
+    CHECK_H(h);
+    if (!theta || !X || !F) return einval("null pointer");
+    QH_TRY(check_prec(prec));
+    QH_TRY(ensure_gauge(h, theta, prec));
+    return launch_force(h, prec, X, F);
+}
+
+qedhmc_status qedhmc_bosonic_action_force(qedhmc_t h, const double* theta, double* S_B_host, double* F_B) {
+    CHECK_H(h);
+    if (!theta) return einval("null pointer");
+    QH_TRY(launch_bosonic(h, theta, F_B, h->scal + 40));
+    if (S_B_host) {
+        QH_HIP(hipMemcpyAsync(h->h_pinned, h->scal + 40, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        QH_HIP(hipStreamSynchronize(h->stream));
+        *S_B_host = h->h_pinned[0];
+    }
+    return QEDHMC_OK;
+}
+
+qedhmc_status qedhmc_heatbath(qedhmc_t h, uint64_t traj_index, double* mom, double* R) {
+    CHECK_H(h);
+    if (!mom || !R) return einval("null pointer");
+    return launch_heatbath(h, traj_index, mom, R);
+}
+
+qedhmc_status qedhmc_hmc_trajectory(qedhmc_t h, double* theta, uint64_t traj, int32_t n_steps, double traj_len,
+                                    double tol, int32_t maxit, qedhmc_precision prec, qedhmc_precond pc,
+                                    qedhmc_traj_result* out) {
+    CHECK_H(h);
+    if (!theta || !out) return einval("null pointer");
+    if (n_steps < 1 || !(traj_len > 0.0) || !(tol > 0.0) || maxit < 1) return einval("bad trajectory parameters");
+    if (pc != QEDHMC_PC_NONE) return einval("unknown preconditioner");
+    QH_TRY(check_prec(prec));
+    std::memset(out, 0, sizeof(*out));
+    const size_t N = nsites(h), nb = 2 * N;
+    const double dt = traj_len / n_steps;
+    double* sc = h->scal + 16;  // SB0 K0 SF0 SB1 K1 SF1 dH u acc scratch
+    double* R = (double*)h->ws[4];
+    double* eta = (double*)h->ws[5];
+    double* X = (double*)h->ws[6];
+    int it_total = 0, it_max = 0, nrel_total = 0, worst = 0;
+    double max_rel = 0.0;
+    auto solve = [&](const double* th) -> qedhmc_status {
+        int32_t it = 0;
+        double rel = 0.0;
+        int nr = 0;
+        const qedhmc_status st = solve_at(h, th, eta, X, tol, maxit, prec, &it, &rel, &nr);
+        if (st != QEDHMC_OK && st != QEDHMC_ENOCONV) return st;
+        if (st == QEDHMC_ENOCONV) worst = 2;
+        out->n_solves++;
+        it_total += it;
+        if (it > it_max) it_max = it;
+        if (rel > max_rel) max_rel = rel;
+        nrel_total += nr;
+        return QEDHMC_OK;
+    };
+
+    QH_HIP(hipMemcpyAsync(h->theta0, theta, nb * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    // (i) heat bath, eta = M^dag R
+    QH_TRY(launch_heatbath(h, traj, h->mom, R));
+    QH_TRY(ensure_gauge(h, theta, QEDHMC_FP64));
+    QH_TRY(launch_apply_M(h, QEDHMC_FP64, R, eta, 1));
+    // H at the start
+    QH_TRY(solve(theta));
+    QH_TRY(launch_dot_re(h, eta, X, 2 * N, sc + 2));
+    QH_TRY(launch_sumsq(h, h->mom, nb, sc + 1));
+    QH_TRY(launch_bosonic(h, theta, h->force_b, sc + 0));
+    QH_TRY(ensure_gauge(h, theta, prec));
+    QH_TRY(launch_force(h, prec, X, h->force));
+    // (ii) leapfrog
+    for (int n = 0; n < n_steps; n++) {
+        QH_TRY(launch_kick(h, h->mom, h->force, h->force_b, 0.5 * dt, nb));
+        QH_TRY(launch_drift(h, theta, h->mom, 2.0 * dt, nb));
+        QH_TRY(solve(theta));
+        QH_TRY(ensure_gauge(h, theta, prec));
+        QH_TRY(launch_force(h, prec, X, h->force));
+        QH_TRY(launch_bosonic(h, theta, h->force_b, sc + 3));
+        QH_TRY(launch_kick(h, h->mom, h->force, h->force_b, 0.5 * dt, nb));
+    }
+    // H at the end, (iii) Metropolis, restore on rejection
+    QH_TRY(launch_dot_re(h, eta, X, 2 * N, sc + 5));
+    QH_TRY(launch_sumsq(h, h->mom, nb, sc + 4));
+    QH_TRY(launch_metropolis(h, traj, sc));
+    QH_TRY(launch_restore(h, theta, h->theta0, sc, nb));
+    QH_HIP(hipMemcpyAsync(h->h_pinned, sc, 9 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    QH_HIP(hipStreamSynchronize(h->stream));
+    const double* v = h->h_pinned;
+    out->SB0 = v[0];
+    out->K0 = v[1];
+    out->SF0 = v[2];
+    out->SB1 = v[3];
+    out->K1 = v[4];
+    out->SF1 = v[5];
+    out->H0 = v[0] + v[1] + v[2];
+    out->H1 = v[3] + v[4] + v[5];
+    out->dH = v[6];
+    out->u = v[7];
+    out->accepted = v[8] != 0.0 ? 1 : 0;
+    out->cg_iters_total = it_total;
+    out->cg_iters_max = it_max;
+    out->status = worst;
+    out->reliable_updates = nrel_total;
+    out->max_true_resid = max_rel;
+    return QEDHMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,236 @@
+// Gauge-field side of the trajectory: compact action and force, Philox heat
+// bath, leapfrog kicks and drifts, FP64 reductions, Metropolis test.
+#include "qedhmc_internal.h"
+
+namespace qh {
+
+static constexpr int kGridR = 512;
+static constexpr int kBlockR = 256;
+
+__global__ void k_sum_partials(const double* __restrict__ part, int n, double* __restrict__ out) {
+    __shared__ double red[16];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) *out = s;
+}
+
+// ---------------------------------------------------------------------------
+// Compact gauge action (Results, L_B^c, integrated as dtau sum_tau):
+//   S_B = 1/(J dtau) sum_{d,tau,s} [1 - cos(theta_{d,tau+1,s} - theta_{d,tau,s})]
+//       + K dtau sum_{tau,s} cos Phi_{tau,s},
+//   Phi_{tau,s} = th_x(s) + th_y(s+x) - th_x(s+y) - th_y(s).
+// One thread per space-time site; the force on the two bonds leaving the
+// site is assembled from the two time-link terms and the two plaquettes each
+// bond borders.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double plaq(const double* __restrict__ th, const Lat& lt, int tau, int x, int y) {
+    const int L = lt.L, Vs = lt.Vs;
+    const int xp = x + 1 == L ? 0 : x + 1, yp = y + 1 == L ? 0 : y + 1;
+    const double* tx = th + (size_t)tau * Vs;
+    const double* ty = th + ((size_t)lt.Nt + tau) * Vs;
+    return tx[y * L + x] + ty[y * L + xp] - tx[yp * L + x] - ty[y * L + x];
+}
+
+__global__ void k_bosonic(Lat lt, double J, double K, double dtau, const double* __restrict__ th,
+                          double* __restrict__ F, double* __restrict__ part) {
+    __shared__ double red[16];
+    const double cj = 1.0 / (J * dtau), kd = K * dtau;
+    const size_t N = (size_t)lt.Nt * lt.Vs;
+    double s_act = 0.0;
+    for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N; n += (size_t)gridDim.x * blockDim.x) {
+        const int tau = (int)(n / lt.Vs), s = (int)(n - (size_t)tau * lt.Vs);
+        const int x = s % lt.L, y = s / lt.L;
+        const int tp = tau + 1 == lt.Nt ? 0 : tau + 1, tm = tau == 0 ? lt.Nt - 1 : tau - 1;
+        const int xm = x == 0 ? lt.L - 1 : x - 1, ym = y == 0 ? lt.L - 1 : y - 1;
+        const double P = plaq(th, lt, tau, x, y);
+        s_act += kd * cos(P);
+        double f[2];
+        for (int d = 0; d < 2; d++) {
+            const double* td = th + (size_t)d * N;
+            const double a = td[(size_t)tau * lt.Vs + s];
+            const double an = td[(size_t)tp * lt.Vs + s];
+            const double ap = td[(size_t)tm * lt.Vs + s];
+            s_act += cj * (1.0 - cos(an - a));
+            f[d] = cj * (sin(an - a) - sin(a - ap));
+        }
+        if (F) {
+            const double g0 = kd * sin(P);
+            const double gy = kd * sin(plaq(th, lt, tau, x, ym));  // plaquette below: bond is its top edge
+            const double gx = kd * sin(plaq(th, lt, tau, xm, y));  // plaquette to the left: bond is its right edge
+            F[(size_t)tau * lt.Vs + s] = f[0] + g0 - gy;
+            F[N + (size_t)tau * lt.Vs + s] = f[1] + gx - g0;
+        }
+    }
+    s_act = block_sum(s_act, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s_act;
+}
+
+qedhmc_status launch_bosonic(qedhmc_ctx* h, const double* theta, double* F_B, double* S_dev) {
+    double* part = (h->partial + h->lat.Nt + 1024);
+    hipLaunchKernelGGL(k_bosonic, dim3(kGridR), dim3(kBlockR), 0, h->stream, h->lat, h->p.J, h->p.K, h->p.dtau, theta,
+                       F_B, part);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, h->stream, (const double*)part, kGridR, S_dev);
+    QH_HIP(hipGetLastError());
+    return QEDHMC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11) and Box-Muller
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox10(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; r++) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+__device__ __forceinline__ double uniform53(uint32_t a, uint32_t b) {
+    return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * (1.0 / 9007199254740992.0);
+}
+
+// Counter (element, traj low, purpose, traj high), key (seed low, seed high).
+__device__ __forceinline__ void draw_block(uint64_t seed, uint64_t traj, uint32_t purpose, uint32_t elem,
+                                           uint32_t (&x)[4]) {
+    x[0] = elem;
+    x[1] = (uint32_t)traj;
+    x[2] = purpose;
+    x[3] = (uint32_t)(traj >> 32);
+    philox10(x, (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+__device__ __forceinline__ void gauss_pair(const uint32_t (&x)[4], double& g1, double& g2) {
+    const double u1 = uniform53(x[0], x[1]), u2 = uniform53(x[2], x[3]);
+    const double rad = sqrt(-2.0 * log(1.0 - u1));
+    double s, c;
+    sincos(2.0 * M_PI * u2, &s, &c);
+    g1 = rad * c;
+    g2 = rad * s;
+}
+
+// p ~ N(0, 1/2) per bond (pair 2k, 2k+1 from block k of purpose 1) and
+// R ~ Re, Im N(0, 1/2) per site (block k of purpose 2).
+__global__ void k_heatbath(uint64_t seed, uint64_t traj, size_t N, double* __restrict__ mom,
+                           cplx<double>* __restrict__ R) {
+    const double r2 = 0.70710678118654752440;
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < N; k += (size_t)gridDim.x * blockDim.x) {
+        uint32_t x[4];
+        double g1, g2;
+        draw_block(seed, traj, 1u, (uint32_t)k, x);
+        gauss_pair(x, g1, g2);
+        mom[2 * k] = r2 * g1;
+        mom[2 * k + 1] = r2 * g2;
+        draw_block(seed, traj, 2u, (uint32_t)k, x);
+        gauss_pair(x, g1, g2);
+        R[k] = mk<double>(r2 * g1, r2 * g2);
+    }
+}
+
+qedhmc_status launch_heatbath(qedhmc_ctx* h, uint64_t traj, double* mom, double* R) {
+    const size_t N = (size_t)h->lat.Nt * h->lat.Vs;
+    hipLaunchKernelGGL(k_heatbath, dim3(kGridR), dim3(kBlockR), 0, h->stream, h->p.seed, traj, N, mom,
+                       (cplx<double>*)R);
+    QH_HIP(hipGetLastError());
+    return QEDHMC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 reductions (fixed grid: deterministic)
+// ---------------------------------------------------------------------------
+__global__ void k_dot(const double* __restrict__ a, const double* __restrict__ b, size_t n,
+                      double* __restrict__ part) {
+    __shared__ double red[16];
+    double s = 0.0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        s += a[i] * b[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// Re <a, b> of complex vectors = sum over the interleaved reals of a*b (n reals)
+qedhmc_status launch_dot_re(qedhmc_ctx* h, const double* a, const double* b, size_t n, double* out_dev) {
+    double* part = (h->partial + h->lat.Nt + 1024);
+    hipLaunchKernelGGL(k_dot, dim3(kGridR), dim3(kBlockR), 0, h->stream, a, b, n, part);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, h->stream, (const double*)part, kGridR, out_dev);
+    QH_HIP(hipGetLastError());
+    return QEDHMC_OK;
+}
+
+qedhmc_status launch_sumsq(qedhmc_ctx* h, const double* a, size_t n, double* out_dev) {
+    return launch_dot_re(h, a, a, n, out_dev);
+}
+
+// ---------------------------------------------------------------------------
+// Leapfrog (Eq. leapfrog): p += c (F_F + F_B);  theta += c p
+// ---------------------------------------------------------------------------
+__global__ void k_kick(double* __restrict__ mom, const double* __restrict__ F, const double* __restrict__ Fb,
+                       double c, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        mom[i] += c * (F[i] + Fb[i]);
+}
+
+__global__ void k_drift(double* __restrict__ th, const double* __restrict__ mom, double c, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        th[i] += c * mom[i];
+}
+
+qedhmc_status launch_kick(qedhmc_ctx* h, double* mom, const double* F, const double* Fb, double c, size_t n) {
+    hipLaunchKernelGGL(k_kick, dim3(kGridR), dim3(kBlockR), 0, h->stream, mom, F, Fb, c, n);
+    QH_HIP(hipGetLastError());
+    return QEDHMC_OK;
+}
+
+qedhmc_status launch_drift(qedhmc_ctx* h, double* theta, const double* mom, double c, size_t n) {
+    hipLaunchKernelGGL(k_drift, dim3(kGridR), dim3(kBlockR), 0, h->stream, theta, mom, c, n);
+    QH_HIP(hipGetLastError());
+    return QEDHMC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Metropolis (step iii): scalar slots sc[0..5] = SB0, K0, SF0, SB1, K1, SF1;
+// writes sc[6] = dH, sc[7] = u, sc[8] = accepted (1/0).
+// ---------------------------------------------------------------------------
+__global__ void k_metropolis(uint64_t seed, uint64_t traj, double* __restrict__ sc) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double H0 = sc[0] + sc[1] + sc[2];
+    const double H1 = sc[3] + sc[4] + sc[5];
+    const double dH = H1 - H0;
+    uint32_t x[4];
+    draw_block(seed, traj, 3u, 0u, x);
+    const double u = uniform53(x[0], x[1]);
+    const bool acc = (dH <= 0.0) || (u < exp(-dH));
+    sc[6] = dH;
+    sc[7] = u;
+    sc[8] = acc ? 1.0 : 0.0;
+}
+
+qedhmc_status launch_metropolis(qedhmc_ctx* h, uint64_t traj, double* scal_dev) {
+    hipLaunchKernelGGL(k_metropolis, dim3(1), dim3(64), 0, h->stream, h->p.seed, traj, scal_dev);
+    QH_HIP(hipGetLastError());
+    return QEDHMC_OK;
+}
+
+__global__ void k_restore(double* __restrict__ th, const double* __restrict__ th0, const double* __restrict__ sc,
+                          size_t n) {
+    if (sc[8] != 0.0) return;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        th[i] = th0[i];
+}
+
+qedhmc_status launch_restore(qedhmc_ctx* h, double* theta, const double* theta0, const double* scal_dev, size_t n) {
+    hipLaunchKernelGGL(k_restore, dim3(kGridR), dim3(kBlockR), 0, h->stream, theta, theta0, scal_dev, n);
+    QH_HIP(hipGetLastError());
+    return QEDHMC_OK;
+}
+
+}  // namespace qh

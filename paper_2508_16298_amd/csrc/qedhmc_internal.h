@@ -1,0 +1,376 @@
+// Internal declarations shared by the HIP translation units of libqedhmc.
+//
+// Device data layouts
+//   theta    double [2][Nt][Vs]                 (caller's buffer)
+//   gauge    cplx<R> [2][Nt][Vs] = e^{i theta}  (handle workspace, one per
+//            working precision, rebuilt whenever theta changes)
+//   vectors  cplx<R> [Nt][Vs]
+//
+// Cell decomposition used by every lattice kernel: the L x L slice is tiled
+// by 2x2 cells (a, b) holding sites
+//   0: (2a, 2b)   1: (2a+1, 2b)   2: (2a, 2b+1)   3: (2a+1, 2b+1).
+// Bond families f0 (x-bonds leaving even x) and f2 (y-bonds leaving even y)
+// then lie inside a cell, and f1 / f3 join a cell to its +x / +y neighbour.
+// A thread keeps the four site values of its cells in registers; only the
+// f1 / f3 sweeps exchange values, through LDS.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "qedhmc.h"
+
+namespace qh {
+
+template <typename R>
+struct alignas(2 * sizeof(R)) cplx {
+    R re, im;
+};
+
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> mk(R a, R b) {
+    cplx<R> z;
+    z.re = a;
+    z.im = b;
+    return z;
+}
+
+// c v + h w
+template <typename R>
+__device__ __forceinline__ cplx<R> rv_plus_hw(R c, cplx<R> v, cplx<R> h, cplx<R> w) {
+    return mk<R>(c * v.re + (h.re * w.re - h.im * w.im), c * v.im + (h.re * w.im + h.im * w.re));
+}
+// c v + conj(h) w
+template <typename R>
+__device__ __forceinline__ cplx<R> rv_plus_hcw(R c, cplx<R> v, cplx<R> h, cplx<R> w) {
+    return mk<R>(c * v.re + (h.re * w.re + h.im * w.im), c * v.im + (h.re * w.im - h.im * w.re));
+}
+template <typename R>
+__device__ __forceinline__ cplx<R> cadd(cplx<R> a, cplx<R> b) { return mk<R>(a.re + b.re, a.im + b.im); }
+template <typename R>
+__device__ __forceinline__ cplx<R> csub(cplx<R> a, cplx<R> b) { return mk<R>(a.re - b.re, a.im - b.im); }
+template <typename R>
+__device__ __forceinline__ cplx<R> cscale(R s, cplx<R> a) { return mk<R>(s * a.re, s * a.im); }
+template <typename R>
+__device__ __forceinline__ cplx<R> cfma(R s, cplx<R> a, cplx<R> b) { return mk<R>(s * a.re + b.re, s * a.im + b.im); }
+
+// Lattice constants passed by value to every kernel.
+struct Lat {
+    int L, Nt, Vs, hL, ncell;  // hL = L/2, ncell = hL*hL
+};
+
+// Hopping coefficients of one bond factor: cosh/sinh of the half step h and
+// of the merged central step 2h (Eq. 24).
+template <typename R>
+struct Coef {
+    R c1, s1, c2, s2;
+};
+
+// Static geometry of one 2x2 cell (site indices inside a slice).
+struct CellGeo {
+    int s[4];                // own sites 0..3
+    int r0, r2;              // +x neighbour's sites 0 and 2
+    int l1, l3;              // -x neighbour's sites 1 and 3
+    int u0, u1;              // +y neighbour's sites 0 and 1
+    int d2, d3;              // -y neighbour's sites 2 and 3
+};
+
+__device__ __forceinline__ int wrap(int x, int L) { return x < 0 ? x + L : (x >= L ? x - L : x); }
+
+__device__ __forceinline__ CellGeo cell_geo(int cell, const Lat& lt) {
+    const int a = cell % lt.hL, b = cell / lt.hL, L = lt.L;
+    const int x0 = 2 * a, y0 = 2 * b;
+    CellGeo g;
+    g.s[0] = y0 * L + x0;
+    g.s[1] = g.s[0] + 1;
+    g.s[2] = g.s[0] + L;
+    g.s[3] = g.s[2] + 1;
+    const int xr = wrap(x0 + 2, L), xl = wrap(x0 - 1, L);
+    const int yu = wrap(y0 + 2, L), yd = wrap(y0 - 1, L);
+    g.r0 = y0 * L + xr;
+    g.r2 = (y0 + 1) * L + xr;
+    g.l1 = y0 * L + xl;
+    g.l3 = (y0 + 1) * L + xl;
+    g.u0 = yu * L + x0;
+    g.u1 = yu * L + x0 + 1;
+    g.d2 = yd * L + x0;
+    g.d3 = yd * L + x0 + 1;
+    return g;
+}
+
+// The twelve bond phases a cell needs for one slice, index -> (d, site):
+//   0,1  f0 bonds from sites 0, 2 (d=0)       pairs (0,1), (2,3)
+//   2,3  f1 bonds from sites 1, 3 (d=0)       pairs (1, r0), (3, r2)
+//   4,5  f2 bonds from sites 0, 1 (d=1)       pairs (0,2), (1,3)
+//   6,7  f3 bonds from sites 2, 3 (d=1)       pairs (2, u0), (3, u1)
+//   8,9  f1 bonds from l1, l3 (d=0)           pairs (l1, 0), (l3, 2)
+//   10,11 f3 bonds from d2, d3 (d=1)          pairs (d2, 0), (d3, 1)
+__device__ __forceinline__ void phase_index(const CellGeo& g, int Vs, int (&idx)[12]) {
+    idx[0] = g.s[0];
+    idx[1] = g.s[2];
+    idx[2] = g.s[1];
+    idx[3] = g.s[3];
+    idx[4] = Vs + g.s[0];
+    idx[5] = Vs + g.s[1];
+    idx[6] = Vs + g.s[2];
+    idx[7] = Vs + g.s[3];
+    idx[8] = g.l1;
+    idx[9] = g.l3;
+    idx[10] = Vs + g.d2;
+    idx[11] = Vs + g.d3;
+}
+
+// Load the scaled hopping terms h_k = sinh(a_k) e^{i theta_k} of one slice:
+// gauge is [2][Nt][Vs]; idx (from phase_index) packs d*Vs + s.
+template <typename R>
+__device__ __forceinline__ void load_hops(const cplx<R>* __restrict__ gauge, const Lat& lt, int tau,
+                                          const int (&idx)[12], const Coef<R>& co, cplx<R> (&h)[12]) {
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        const int id = idx[k];
+        const int d = id >= lt.Vs ? 1 : 0;
+        const int s = id - d * lt.Vs;
+        const cplx<R> e = gauge[((size_t)d * lt.Nt + tau) * lt.Vs + s];
+        const R sc = (k < 2) ? co.s2 : co.s1;
+        h[k] = mk<R>(sc * e.re, sc * e.im);
+    }
+}
+
+// In-cell factor of family f0 (merged central step, coefficients c2/h[0..1]).
+template <typename R>
+__device__ __forceinline__ void sweep_f0(cplx<R> (&v)[4], const cplx<R> (&h)[12], R c) {
+    const cplx<R> a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3];
+    v[0] = rv_plus_hw(c, a0, h[0], a1);
+    v[1] = rv_plus_hcw(c, a1, h[0], a0);
+    v[2] = rv_plus_hw(c, a2, h[1], a3);
+    v[3] = rv_plus_hcw(c, a3, h[1], a2);
+}
+// In-cell factor of family f2.
+template <typename R>
+__device__ __forceinline__ void sweep_f2(cplx<R> (&v)[4], const cplx<R> (&h)[12], R c) {
+    const cplx<R> a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3];
+    v[0] = rv_plus_hw(c, a0, h[4], a2);
+    v[2] = rv_plus_hcw(c, a2, h[4], a0);
+    v[1] = rv_plus_hw(c, a1, h[5], a3);
+    v[3] = rv_plus_hcw(c, a3, h[5], a1);
+}
+// Cross-cell factor of family f1 given the neighbours' (pre-sweep) values.
+template <typename R>
+__device__ __forceinline__ void sweep_f1(cplx<R> (&v)[4], const cplx<R> (&h)[12], R c, cplx<R> R0,
+                                         cplx<R> R2, cplx<R> L1, cplx<R> L3) {
+    const cplx<R> a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3];
+    v[1] = rv_plus_hw(c, a1, h[2], R0);
+    v[3] = rv_plus_hw(c, a3, h[3], R2);
+    v[0] = rv_plus_hcw(c, a0, h[8], L1);
+    v[2] = rv_plus_hcw(c, a2, h[9], L3);
+}
+// Cross-cell factor of family f3.
+template <typename R>
+__device__ __forceinline__ void sweep_f3(cplx<R> (&v)[4], const cplx<R> (&h)[12], R c, cplx<R> U0,
+                                         cplx<R> U1, cplx<R> D2, cplx<R> D3) {
+    const cplx<R> a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3];
+    v[2] = rv_plus_hw(c, a2, h[6], U0);
+    v[3] = rv_plus_hw(c, a3, h[7], U1);
+    v[0] = rv_plus_hcw(c, a0, h[10], D2);
+    v[1] = rv_plus_hcw(c, a1, h[11], D3);
+}
+
+// Per-thread cell set: thread t owns cells t, t + blockDim, ... (at most MC).
+template <typename R, int MC>
+struct Cells {
+    cplx<R> v[MC][4];
+};
+
+// LDS exchange buffers: NB buffers of Vs complex values each.  With NB = 2
+// consecutive cross sweeps alternate buffers, so one barrier per sweep is
+// enough (a buffer is rewritten only after a barrier that follows every read
+// of its previous contents).  With NB = 1 a second barrier closes each sweep.
+template <typename R, int NB>
+struct Xchg {
+    cplx<R>* buf;
+    int Vs;
+    int k;  // next buffer
+    __device__ cplx<R>* next() {
+        cplx<R>* b = buf + (size_t)(NB == 2 ? k : 0) * Vs;
+        k ^= 1;
+        return b;
+    }
+};
+
+template <int NB>
+__device__ __forceinline__ void xchg_close() {
+    if (NB == 1) __syncthreads();
+}
+
+// Apply one cross family (f1 if X, else f3) to all cells of this thread.
+template <typename R, int MC, int NB, bool X>
+__device__ __forceinline__ void cross_sweep(Cells<R, MC>& c, const cplx<R> (&h)[MC][12], const CellGeo (&g)[MC],
+                                            const bool (&own)[MC], R cc, Xchg<R, NB>& xb) {
+    cplx<R>* b = xb.next();
+#pragma unroll
+    for (int m = 0; m < MC; m++)
+        if (own[m]) {
+#pragma unroll
+            for (int q = 0; q < 4; q++) b[g[m].s[q]] = c.v[m][q];
+        }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < MC; m++)
+        if (own[m]) {
+            if (X)
+                sweep_f1(c.v[m], h[m], cc, b[g[m].r0], b[g[m].r2], b[g[m].l1], b[g[m].l3]);
+            else
+                sweep_f3(c.v[m], h[m], cc, b[g[m].u0], b[g[m].u1], b[g[m].d2], b[g[m].d3]);
+        }
+    xchg_close<NB>();
+}
+
+// B_tau on the cells of this thread: factors applied in the order
+// E3, E2, E1, E0(2h), E1, E2, E3 (the product is a palindrome).
+template <typename R, int MC, int NB>
+__device__ __forceinline__ void apply_B_cells(Cells<R, MC>& c, const cplx<R> (&h)[MC][12], const CellGeo (&g)[MC],
+                                              const bool (&own)[MC], const Coef<R>& co, Xchg<R, NB>& xb) {
+    cross_sweep<R, MC, NB, false>(c, h, g, own, co.c1, xb);
+#pragma unroll
+    for (int m = 0; m < MC; m++) sweep_f2(c.v[m], h[m], co.c1);
+    cross_sweep<R, MC, NB, true>(c, h, g, own, co.c1, xb);
+#pragma unroll
+    for (int m = 0; m < MC; m++) sweep_f0(c.v[m], h[m], co.c2);
+    cross_sweep<R, MC, NB, true>(c, h, g, own, co.c1, xb);
+#pragma unroll
+    for (int m = 0; m < MC; m++) sweep_f2(c.v[m], h[m], co.c1);
+    cross_sweep<R, MC, NB, false>(c, h, g, own, co.c1, xb);
+}
+
+template <typename R, int MC>
+__device__ __forceinline__ void load_cells(Cells<R, MC>& c, const cplx<R>* __restrict__ slice, const CellGeo (&g)[MC],
+                                           const bool (&own)[MC]) {
+#pragma unroll
+    for (int m = 0; m < MC; m++) {
+        if (own[m]) {
+#pragma unroll
+            for (int q = 0; q < 4; q++) c.v[m][q] = slice[g[m].s[q]];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; q++) c.v[m][q] = mk<R>(0, 0);
+        }
+    }
+}
+
+template <typename R, int MC>
+__device__ __forceinline__ void store_cells(const Cells<R, MC>& c, cplx<R>* __restrict__ slice, const CellGeo (&g)[MC],
+                                            const bool (&own)[MC]) {
+#pragma unroll
+    for (int m = 0; m < MC; m++)
+        if (own[m]) {
+#pragma unroll
+            for (int q = 0; q < 4; q++) slice[g[m].s[q]] = c.v[m][q];
+        }
+}
+
+// Fixed-order block reduction of one double per thread (deterministic for a
+// fixed block size).  red: LDS scratch of at least blockDim/64 doubles.
+__device__ __forceinline__ double block_sum(double x, double* red) {
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[w] = x;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int k = 0; k < nw; k++) s += red[k];
+    }
+    return s;  // valid in thread 0
+}
+
+}  // namespace qh
+
+// ---------------------------------------------------------------------------
+// Handle and host-side helpers
+// ---------------------------------------------------------------------------
+struct qedhmc_ctx {
+    qedhmc_params p;
+    qh::Lat lat;
+    hipStream_t stream;
+    int device;
+    size_t max_lds;
+    int32_t* d_tables;          // [4][Vs/2][3]
+    // working-precision gauge caches e^{i theta}
+    qh::cplx<double>* gauge64;
+    qh::cplx<float>* gauge32;
+    const double* gauge_src64;  // theta the caches were last built from (nullptr: stale)
+    const double* gauge_src32;
+    // workspace vectors
+    void* ws[12];               // general complex FP64-sized vectors
+    double* theta0;             // saved theta for Metropolis
+    double* mom;                // momenta
+    double* force;              // total force
+    double* force_b;            // bosonic force
+    double* partial;            // per-block partial sums (>= 4 * max blocks)
+    double* scal;               // device scalars
+    double* h_pinned;           // pinned host mirror of a few scalars
+    // sampled kernel timing (qedhmc_profile)
+    int prof_every;
+    int64_t prof_seen[QEDHMC_K_COUNT];
+    int64_t prof_count[QEDHMC_K_COUNT];
+    double prof_ms[QEDHMC_K_COUNT];
+    hipEvent_t prof_ev[64][2];
+    int prof_cls[64];
+    int prof_pending;
+    bool prof_ready;
+};
+
+namespace qh {
+
+void set_error(const std::string& msg);
+qedhmc_status hip_fail(hipError_t e, const char* what);
+
+#define QH_HIP(call)                                                  \
+    do {                                                              \
+        hipError_t _e = (call);                                       \
+        if (_e != hipSuccess) return ::qh::hip_fail(_e, #call);       \
+    } while (0)
+
+#define QH_TRY(call)                                                  \
+    do {                                                              \
+        qedhmc_status _s = (call);                                    \
+        if (_s != QEDHMC_OK) return _s;                               \
+    } while (0)
+
+template <typename R>
+Coef<R> coef_of(const qedhmc_params& p);
+
+// Sampled kernel timing around one launch (api.hip).  prof_begin returns the
+// event slot to close with prof_end, or -1 when this launch is not sampled.
+int prof_begin(qedhmc_ctx* h, int cls);
+void prof_end(qedhmc_ctx* h, int slot);
+qedhmc_status prof_drain(qedhmc_ctx* h);
+
+// Launch helpers implemented in lattice.hip
+qedhmc_status ensure_gauge(qedhmc_ctx* h, const double* theta, qedhmc_precision prec);
+qedhmc_status launch_apply_M(qedhmc_ctx* h, qedhmc_precision prec, const void* in, void* out, int dagger);
+qedhmc_status launch_apply_B(qedhmc_ctx* h, qedhmc_precision prec, int tau, const void* in, void* out);
+// out = M^dag M in; if pdot != nullptr the per-slice partials of Re<in, out>
+// are written to pdot[0..Nt).
+qedhmc_status launch_mdagm(qedhmc_ctx* h, qedhmc_precision prec, const void* in, void* out, double* pdot);
+qedhmc_status launch_force(qedhmc_ctx* h, qedhmc_precision prec, const double* X, double* F);
+qedhmc_status launch_bond_tables(qedhmc_ctx* h);
+
+// CG (cg.hip)
+qedhmc_status cg_solve_impl(qedhmc_ctx* h, const double* rhs, double* x, double tol, int maxit,
+                            qedhmc_precision prec, int* iters, double* true_rel, int* n_reliable);
+
+// Gauge-field and trajectory kernels (boson.hip)
+qedhmc_status launch_bosonic(qedhmc_ctx* h, const double* theta, double* F_B, double* S_dev);
+qedhmc_status launch_heatbath(qedhmc_ctx* h, uint64_t traj, double* mom, double* R);
+qedhmc_status launch_dot_re(qedhmc_ctx* h, const double* a, const double* b, size_t n, double* out_dev);
+qedhmc_status launch_sumsq(qedhmc_ctx* h, const double* a, size_t n, double* out_dev);
+qedhmc_status launch_kick(qedhmc_ctx* h, double* mom, const double* F, const double* Fb, double c, size_t n);
+qedhmc_status launch_drift(qedhmc_ctx* h, double* theta, const double* mom, double c, size_t n);
+qedhmc_status launch_metropolis(qedhmc_ctx* h, uint64_t traj, double* scal_dev);
+qedhmc_status launch_restore(qedhmc_ctx* h, double* theta, const double* theta0, const double* scal_dev, size_t n);
+
+}  // namespace qh

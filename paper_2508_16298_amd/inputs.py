@@ -37,21 +37,39 @@ class Workload:
     tol: float = 1e-10
     precision: str = "fp64"
     n_traj: int = 1
+    theta: str = "hot"          # "hot": uniform [0, 2 pi); "pi_noise": pi flux + N(0, sigma^2)
+    sigma: float = 0.0
+    theta_seed: int = 0
     chains: List[int] = field(default_factory=list)
 
     @property
     def N(self) -> int:
         return self.L * self.L * self.Nt
 
+    def initial_theta(self) -> np.ndarray:
+        if self.theta == "hot":
+            return hot_start_theta(self.L, self.Nt, self.theta_seed or self.seed)
+        if self.theta == "pi_noise":
+            return noisy_pi_flux_theta(self.L, self.Nt, self.sigma, self.theta_seed or self.seed)
+        raise ValueError(self.theta)
 
-# The five workloads of the hot path (lattice sizes, couplings, CG residual,
-# trajectory shape).  Trajectory length is 1 everywhere.
+
+# The workloads of the hot path (lattice sizes, couplings, CG residual,
+# trajectory shape).  Trajectory length is 1 everywhere.  From L = 12 up a
+# hot start sits next to det M = 0: the fermion force diverges within the
+# first leapfrog step and the trajectory is meaningless, so trajectories at
+# those sizes start from pi flux plus Gaussian noise (sigma 0.3), the stand-in
+# for a thermalised configuration; hot starts remain the first-solve workloads
+# ("*_hot").
 WORKLOADS = {
     "cpu_small": Workload("cpu_small", L=6, Nt=10, seed=1001, n_steps=10, tol=1e-10),
     "fp64_l12": Workload("fp64_l12", L=12, Nt=120, seed=1002, n_steps=20, tol=1e-10,
-                         n_traj=20),
+                         n_traj=20, theta="pi_noise", sigma=0.3, theta_seed=1012),
+    "fp64_l12_hot": Workload("fp64_l12_hot", L=12, Nt=120, seed=1002, n_steps=20, tol=1e-10),
     "mixed_l24": Workload("mixed_l24", L=24, Nt=240, seed=1003, n_steps=20, tol=1e-8,
-                          precision="mixed"),
+                          precision="mixed", theta="pi_noise", sigma=0.3, theta_seed=1013),
+    "mixed_l24_hot": Workload("mixed_l24_hot", L=24, Nt=240, seed=1003, n_steps=20, tol=1e-8,
+                              precision="mixed"),
     "batched_chains": Workload("batched_chains", L=0, Nt=0, seed=1004, n_steps=20,
                                tol=1e-8, precision="mixed"),
     "learned_l66": Workload("learned_l66", L=66, Nt=660, seed=1005, n_steps=20, tol=1e-8,

@@ -1,0 +1,258 @@
+"""ctypes binding of libqedhmc (the C ABI in include/qedhmc.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+kernels of libqedhmc.so.  torch provides device memory and the current HIP
+stream.  The library is loaded on first use and a missing or unloadable
+library raises -- there is no CPU fallback.
+
+Layouts (torch tensors on the GPU, contiguous)
+  theta   float64     (2, Nt, L, L)   [d, tau, y, x]
+  vector  complex128  (Nt, L, L)      FP64 path
+          complex64   (Nt, L, L)      FP32 apply calls
+"""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqedhmc.so")
+
+OK, EINVAL, ENOCONV, EHIP, ENOMEM, EUNSUPPORTED = range(6)
+K_MDAGM_FP32, K_MDAGM_FP64, K_FORCE = range(3)
+FP64, FP32 = 0, 1
+PC_NONE = 0
+
+_PREC = {"fp64": FP64, "fp32": FP32, "mixed": FP32, FP64: FP64, FP32: FP32}
+
+
+class QedhmcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"qedhmc status {status}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("L", C.c_int32), ("Nt", C.c_int32), ("dtau", C.c_double), ("t", C.c_double),
+                ("J", C.c_double), ("K", C.c_double), ("seed", C.c_uint64)]
+
+
+class TrajResult(C.Structure):
+    _fields_ = [("dH", C.c_double), ("H0", C.c_double), ("H1", C.c_double), ("SB0", C.c_double),
+                ("SB1", C.c_double), ("SF0", C.c_double), ("SF1", C.c_double), ("K0", C.c_double),
+                ("K1", C.c_double), ("u", C.c_double), ("accepted", C.c_int32),
+                ("n_solves", C.c_int32), ("cg_iters_total", C.c_int32),
+                ("cg_iters_max", C.c_int32), ("status", C.c_int32),
+                ("reliable_updates", C.c_int32), ("max_true_resid", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_P = C.c_void_p
+
+
+def load():
+    """Load libqedhmc.so (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                           "or python -m paper_2508_16298_amd.build")
+    L = C.CDLL(LIB_PATH)
+    st = C.c_int
+    sig = {
+        "qedhmc_init_lattice": [C.POINTER(Params), _P, C.POINTER(_P)],
+        "qedhmc_destroy": [_P],
+        "qedhmc_set_stream": [_P, _P],
+        "qedhmc_get_bond_tables": [_P, _P],
+        "qedhmc_apply_B": [_P, _P, C.c_int32, _P, _P, C.c_int],
+        "qedhmc_apply_M": [_P, _P, _P, _P, C.c_int32, C.c_int],
+        "qedhmc_apply_MdagM": [_P, _P, _P, _P, C.c_int],
+        "qedhmc_cg_solve": [_P, _P, _P, _P, C.c_double, C.c_int32, C.c_int, C.c_int,
+                            C.POINTER(C.c_int32), C.POINTER(C.c_double)],
+        "qedhmc_fermion_force": [_P, _P, _P, _P, C.c_int],
+        "qedhmc_bosonic_action_force": [_P, _P, C.POINTER(C.c_double), _P],
+        "qedhmc_heatbath": [_P, C.c_uint64, _P, _P],
+        "qedhmc_profile": [_P, C.c_int32],
+        "qedhmc_profile_read": [_P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
+        "qedhmc_hmc_trajectory": [_P, _P, C.c_uint64, C.c_int32, C.c_double, C.c_double, C.c_int32,
+                                  C.c_int, C.c_int, C.POINTER(TrajResult)],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = st
+    L.qedhmc_last_error.argtypes = []
+    L.qedhmc_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def last_error():
+    return load().qedhmc_last_error().decode()
+
+
+def _check(status, allow=(OK,)):
+    if status not in allow:
+        raise QedhmcError(status, last_error())
+    return status
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream_handle():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Lattice:
+    """A qedhmc handle (qedhmc_init_lattice) bound to torch's current stream."""
+
+    def __init__(self, L, Nt, dtau=0.1, t=1.0, J=1.0, K=1.0, seed=0):
+        import torch
+        self.L, self.Nt = int(L), int(Nt)
+        self.params = Params(self.L, self.Nt, dtau, t, J, K, seed)
+        self._torch = torch
+        h = _P()
+        _check(load().qedhmc_init_lattice(C.byref(self.params), _stream_handle(), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().qedhmc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- helpers -----------------------------------------------------------
+    @property
+    def N(self):
+        return self.L * self.L * self.Nt
+
+    def _sync_stream(self):
+        _check(load().qedhmc_set_stream(self.h, _stream_handle()))
+
+    def _vec(self, prec):
+        dt = self._torch.complex128 if _PREC[prec] == FP64 else self._torch.complex64
+        return self._torch.empty((self.Nt, self.L, self.L), dtype=dt, device="cuda")
+
+    def _check_theta(self, theta):
+        assert theta.is_cuda and theta.dtype == self._torch.float64 and theta.is_contiguous()
+        assert theta.numel() == 2 * self.N, theta.shape
+
+    def _check_vec(self, v, prec):
+        dt = self._torch.complex128 if _PREC[prec] == FP64 else self._torch.complex64
+        assert v.is_cuda and v.dtype == dt and v.is_contiguous(), (v.dtype, dt)
+        assert v.numel() == self.N, v.shape
+
+    # -- the C ABI ---------------------------------------------------------
+    def get_bond_tables(self):
+        import numpy as np
+        out = np.zeros((4, self.L * self.L // 2, 3), dtype=np.int32)
+        self._sync_stream()
+        _check(load().qedhmc_get_bond_tables(self.h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def apply_B(self, theta, tau, v, prec="fp64", out=None):
+        self._check_theta(theta)
+        dt = self._torch.complex128 if _PREC[prec] == FP64 else self._torch.complex64
+        assert v.is_cuda and v.dtype == dt and v.numel() == self.L * self.L
+        out = self._torch.empty_like(v) if out is None else out
+        self._sync_stream()
+        _check(load().qedhmc_apply_B(self.h, _ptr(theta), int(tau), _ptr(v), _ptr(out), _PREC[prec]))
+        return out
+
+    def apply_M(self, theta, v, dagger=False, prec="fp64", out=None):
+        self._check_theta(theta)
+        self._check_vec(v, prec)
+        out = self._vec(prec) if out is None else out
+        self._sync_stream()
+        _check(load().qedhmc_apply_M(self.h, _ptr(theta), _ptr(v), _ptr(out), int(bool(dagger)),
+                                     _PREC[prec]))
+        return out
+
+    def apply_MdagM(self, theta, v, prec="fp64", out=None):
+        self._check_theta(theta)
+        self._check_vec(v, prec)
+        out = self._vec(prec) if out is None else out
+        self._sync_stream()
+        _check(load().qedhmc_apply_MdagM(self.h, _ptr(theta), _ptr(v), _ptr(out), _PREC[prec]))
+        return out
+
+    def cg_solve(self, theta, rhs, tol=1e-10, maxit=1_000_000, prec="fp64", x=None):
+        """Returns (x, status, iters, true_rel_resid); status OK or ENOCONV."""
+        self._check_theta(theta)
+        self._check_vec(rhs, "fp64")
+        x = self._vec("fp64") if x is None else x
+        it = C.c_int32(0)
+        rel = C.c_double(0.0)
+        self._sync_stream()
+        st = _check(load().qedhmc_cg_solve(self.h, _ptr(theta), _ptr(rhs), _ptr(x), float(tol), int(maxit),
+                                           _PREC[prec], PC_NONE, C.byref(it), C.byref(rel)),
+                    allow=(OK, ENOCONV))
+        return x, st, it.value, rel.value
+
+    def fermion_force(self, theta, X, prec="fp64", out=None):
+        self._check_theta(theta)
+        self._check_vec(X, "fp64")
+        out = self._torch.empty_like(theta) if out is None else out
+        self._sync_stream()
+        _check(load().qedhmc_fermion_force(self.h, _ptr(theta), _ptr(X), _ptr(out), _PREC[prec]))
+        return out
+
+    def bosonic_action_force(self, theta, force=True):
+        self._check_theta(theta)
+        S = C.c_double(0.0)
+        F = self._torch.empty_like(theta) if force else None
+        self._sync_stream()
+        _check(load().qedhmc_bosonic_action_force(self.h, _ptr(theta), C.byref(S),
+                                                  _ptr(F) if force else None))
+        return S.value, F
+
+    def heatbath(self, traj):
+        mom = self._torch.empty((2, self.Nt, self.L, self.L), dtype=self._torch.float64, device="cuda")
+        R = self._vec("fp64")
+        self._sync_stream()
+        _check(load().qedhmc_heatbath(self.h, int(traj), _ptr(mom), _ptr(R)))
+        return mom, R
+
+    def hmc_trajectory(self, theta, traj, n_steps, traj_len=1.0, tol=1e-10, maxit=1_000_000,
+                       prec="fp64"):
+        """theta is updated in place (proposal on acceptance); returns the result dict."""
+        self._check_theta(theta)
+        res = TrajResult()
+        self._sync_stream()
+        _check(load().qedhmc_hmc_trajectory(self.h, _ptr(theta), int(traj), int(n_steps),
+                                            float(traj_len), float(tol), int(maxit), _PREC[prec],
+                                            PC_NONE, C.byref(res)))
+        return res.as_dict()
+
+
+    def profile(self, every):
+        """Time every every-th launch of the timed kernels with HIP events (0: off)."""
+        self._sync_stream()
+        _check(load().qedhmc_profile(self.h, int(every)))
+
+    def profile_read(self, kernel_class):
+        """(count, total_ms) of the timed launches of one kernel class."""
+        n = C.c_int64(0)
+        ms = C.c_double(0.0)
+        _check(load().qedhmc_profile_read(self.h, int(kernel_class), C.byref(n), C.byref(ms)))
+        return n.value, ms.value
+
+
+def init_lattice(L, Nt, **kw):
+    return Lattice(L, Nt, **kw)

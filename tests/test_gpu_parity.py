@@ -1,0 +1,256 @@
+"""GPU parity: every C-ABI call of libqedhmc against the CPU oracle on the
+same seeded inputs.
+
+Bars (FP64): 1e-10 relative (2-norm) on vectors and forces, 1e-12 on the
+gauge action; bond tables bytewise.  FP32 apply calls: 1e-6 relative.
+Solves are compared through what is unique: the true residual (recomputed by
+the oracle) and the distance to the oracle's solution, bounded by the
+residuals and the smallest eigenvalue of M^dag M where that is computable.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2508_16298_amd import inputs
+from paper_2508_16298_amd import qedhmc as Q
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    a = np.asarray(a).reshape(-1)
+    b = np.asarray(b).reshape(-1)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _dev(x, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+LATS = [(2, 3), (4, 1), (4, 2), (6, 10), (8, 5), (12, 120), (24, 240), (66, 12)]
+
+
+@pytest.mark.parametrize("L", [2, 4, 6, 12, 24, 66])
+def test_bond_tables_bytewise(L):
+    with Q.Lattice(L, 2) as lat:
+        assert np.array_equal(lat.get_bond_tables(), O.bond_tables(L))
+
+
+@pytest.mark.parametrize("L,Nt", [(2, 2), (6, 3), (24, 2), (66, 2)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_apply_B(L, Nt, prec):
+    p = O.lat(L, Nt)
+    th = inputs.hot_start_theta(L, Nt, seed=100 + L)
+    v = inputs.gauss_cvec(L, Nt, seed=200 + L)
+    cdt = torch.complex128 if prec == "fp64" else torch.complex64
+    tol = 1e-12 if prec == "fp64" else 2e-6
+    with Q.Lattice(L, Nt) as lat:
+        thd = _dev(th)
+        for tau in range(Nt):
+            out = lat.apply_B(thd, tau, _dev(v[tau], cdt), prec)
+            ref = O.apply_B(p, th, tau, v[tau])
+            assert _rel(_host(out), ref) < tol, (tau, _rel(_host(out), ref))
+
+
+@pytest.mark.parametrize("L,Nt", LATS)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("dagger", [False, True])
+def test_apply_M(L, Nt, prec, dagger):
+    p = O.lat(L, Nt)
+    th = inputs.hot_start_theta(L, Nt, seed=300 + L)
+    v = inputs.gauss_cvec(L, Nt, seed=400 + L)
+    cdt = torch.complex128 if prec == "fp64" else torch.complex64
+    tol = 1e-12 if prec == "fp64" else 2e-6
+    with Q.Lattice(L, Nt) as lat:
+        out = lat.apply_M(_dev(th), _dev(v, cdt), dagger=dagger, prec=prec)
+        ref = O.apply_M(p, th, v, dagger)
+        assert _rel(_host(out), ref) < tol
+
+
+@pytest.mark.parametrize("L,Nt", LATS)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_apply_MdagM(L, Nt, prec):
+    p = O.lat(L, Nt)
+    th = inputs.hot_start_theta(L, Nt, seed=500 + L)
+    v = inputs.gauss_cvec(L, Nt, seed=600 + L)
+    cdt = torch.complex128 if prec == "fp64" else torch.complex64
+    tol = 1e-12 if prec == "fp64" else 3e-6
+    with Q.Lattice(L, Nt) as lat:
+        out = lat.apply_MdagM(_dev(th), _dev(v, cdt), prec=prec)
+        ref = O.apply_MdagM(p, th, v)
+        assert _rel(_host(out), ref) < tol
+
+
+def test_apply_MdagM_pi_flux_and_free():
+    """Structured gauge fields (pi flux, zero field) through the same kernels."""
+    L, Nt = 8, 16
+    p = O.lat(L, Nt)
+    v = inputs.gauss_cvec(L, Nt, seed=7)
+    with Q.Lattice(L, Nt) as lat:
+        for th in (inputs.pi_flux_theta(L, Nt), np.zeros((2, Nt, L, L))):
+            out = lat.apply_MdagM(_dev(th), _dev(v))
+            assert _rel(_host(out), O.apply_MdagM(p, th, v)) < 1e-12
+
+
+@pytest.mark.parametrize("L,Nt", [(2, 3), (4, 1), (6, 10), (12, 120), (24, 240), (66, 12)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-6)])
+def test_fermion_force(L, Nt, prec, tol):
+    p = O.lat(L, Nt)
+    th = inputs.hot_start_theta(L, Nt, seed=700 + L)
+    X = inputs.gauss_cvec(L, Nt, seed=800 + L)
+    with Q.Lattice(L, Nt) as lat:
+        F = lat.fermion_force(_dev(th), _dev(X), prec=prec)
+        ref = O.fermion_force(p, th, X)
+        assert _rel(_host(F), ref) < tol, _rel(_host(F), ref)
+
+
+@pytest.mark.parametrize("L,Nt", [(2, 3), (4, 1), (6, 10), (24, 240)])
+def test_bosonic_action_and_force(L, Nt):
+    p = O.lat(L, Nt, J=1.3, K=0.7)
+    th = inputs.hot_start_theta(L, Nt, seed=900 + L)
+    with Q.Lattice(L, Nt, J=1.3, K=0.7) as lat:
+        S, F = lat.bosonic_action_force(_dev(th))
+        assert abs(S - O.bosonic_action(p, th)) < 1e-12 * abs(O.bosonic_action(p, th))
+        assert _rel(_host(F), O.bosonic_force(p, th)) < 1e-12
+
+
+@pytest.mark.parametrize("L,Nt", [(2, 3), (6, 10), (12, 40)])
+def test_heatbath_matches_oracle_streams(L, Nt):
+    p = O.lat(L, Nt)
+    with Q.Lattice(L, Nt, seed=4242) as lat:
+        for traj in (0, 7, (1 << 33) + 5):
+            mom, R = lat.heatbath(traj)
+            mref, Rref = O.heatbath(p, 4242, traj)
+            assert np.abs(_host(mom) - mref).max() < 1e-13
+            assert np.abs(_host(R) - Rref).max() < 1e-13
+
+
+def _lam_min(p, th):
+    return np.linalg.eigvalsh(O.dense_MdagM(p, th))[0]
+
+
+@pytest.mark.parametrize("L,Nt,seed", [(6, 10, 1001), (4, 6, 11), (2, 3, 12)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_cg_solve_small(L, Nt, seed, prec):
+    p = O.lat(L, Nt)
+    th = inputs.hot_start_theta(L, Nt, seed)
+    R = inputs.gauss_cvec(L, Nt, seed + 1)
+    eta = O.apply_M(p, th, R, dagger=True).reshape(Nt, L, L)
+    tol = 1e-10
+    with Q.Lattice(L, Nt) as lat:
+        x, st, it, rel = lat.cg_solve(_dev(th), _dev(eta), tol=tol, prec=prec)
+        xg = _host(x)
+    assert st == Q.OK and rel <= tol and it > 0
+    true = np.linalg.norm(eta.reshape(-1) - O.apply_MdagM(p, th, xg).reshape(-1)) / np.linalg.norm(eta)
+    assert true <= 1.01 * tol, true
+    Xo, sto, ito, relo = O.cg_solve(p, th, eta, tol=tol)
+    bound = (rel + relo) * np.linalg.norm(eta) / _lam_min(p, th)
+    assert np.linalg.norm(xg.reshape(-1) - Xo.reshape(-1)) <= 1.01 * bound + 1e-14
+    if prec == "fp64":
+        assert abs(it - ito) <= max(2, ito // 50), (it, ito)
+
+
+def test_cg_edge_cases():
+    L, Nt = 4, 4
+    th = inputs.hot_start_theta(L, Nt, 5)
+    with Q.Lattice(L, Nt) as lat:
+        # zero right-hand side: x = 0, no iterations
+        x, st, it, rel = lat.cg_solve(_dev(th), _dev(np.zeros((Nt, L, L), complex)))
+        assert st == Q.OK and it == 0 and np.abs(_host(x)).max() == 0
+        # maxit reached: ENOCONV, partial x written
+        eta = inputs.gauss_cvec(L, Nt, 6)
+        x, st, it, rel = lat.cg_solve(_dev(th), _dev(eta), tol=1e-14, maxit=3)
+        assert st == Q.ENOCONV and it == 3 and rel > 1e-14 and np.abs(_host(x)).max() > 0
+        with pytest.raises(Q.QedhmcError):
+            lat.cg_solve(_dev(th), _dev(eta), tol=-1.0)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-8)])
+def test_cg_solve_at_full_sizes(prec, tol):
+    """L=12, Nt=120 and L=24, Nt=240 from a hot start (the hardest first
+    solve, 1.6e4 and 1.5e5 iterations): the true residual of the GPU solve,
+    recomputed by the oracle."""
+    for (L, Nt, seed) in ((12, 120, 1002), (24, 240, 1003)):
+        if prec == "fp64" and L == 24:
+            continue
+        p = O.lat(L, Nt)
+        th = inputs.hot_start_theta(L, Nt, seed)
+        R = inputs.gauss_cvec(L, Nt, seed + 1)
+        eta = O.apply_M(p, th, R, dagger=True).reshape(Nt, L, L)
+        with Q.Lattice(L, Nt) as lat:
+            x, st, it, rel = lat.cg_solve(_dev(th), _dev(eta), tol=tol, prec=prec)
+            xg = _host(x)
+        print(f"L={L} Nt={Nt} {prec}: {it} iterations, true residual {rel:.3e}", flush=True)
+        assert st == Q.OK and rel <= tol
+        true = np.linalg.norm(eta.reshape(-1) - O.apply_MdagM(p, th, xg).reshape(-1)) / np.linalg.norm(eta)
+        assert true <= 1.05 * tol, true
+        # eta = M^dag R  =>  eta^dag X = R^dag R up to the solve error
+        assert abs(np.vdot(eta.reshape(-1), xg.reshape(-1)).real / np.vdot(R, R).real - 1) < 1e-3
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_trajectory_small_vs_oracle(prec):
+    """One 10-step trajectory of length 1 at L=6, Nt=10 (seed 1001)."""
+    L, Nt, seed = 6, 10, 1001
+    p = O.lat(L, Nt)
+    th = inputs.hot_start_theta(L, Nt, seed)
+    tol = 1e-10
+    th_o, ro, *_ = O.hmc_trajectory(p, th, seed=seed, traj=0, n_steps=10, traj_len=1.0, tol=tol)
+    with Q.Lattice(L, Nt, seed=seed) as lat:
+        thd = _dev(th)
+        rg = lat.hmc_trajectory(thd, traj=0, n_steps=10, traj_len=1.0, tol=tol, prec=prec)
+        th_g = _host(thd)
+    print({k: (rg[k], ro[k]) for k in ("dH", "H0", "H1", "accepted", "cg_iters_total")}, flush=True)
+    assert rg["n_solves"] == 11 and rg["status"] == 0
+    for k in ("SB0", "K0"):
+        assert abs(rg[k] - ro[k]) <= 1e-12 * abs(ro[k])
+    assert abs(rg["SF0"] - ro["SF0"]) <= 1e-8 * abs(ro["SF0"])
+    gap = 1e-7 if prec == "fp64" else 1e-5
+    assert abs(rg["dH"] - ro["dH"]) <= gap * max(1.0, abs(ro["H0"])) * 1e-2 + gap
+    assert rg["u"] == pytest.approx(ro["u"], abs=1e-15)
+    if abs(ro["dH"] + np.log(ro["u"])) > 10 * gap:
+        assert rg["accepted"] == ro["accepted"]
+        if ro["accepted"]:
+            assert np.abs(th_g - th_o).max() < 1e3 * gap
+        else:
+            assert np.array_equal(th_g, th)
+
+
+def test_trajectory_mixed_matches_fp64_at_workload_size():
+    """L=24, Nt=240, 20 leapfrog steps of length 1, CG residual 1e-8 (the
+    benchmark workload): mixed path vs FP64 path on the GPU from identical
+    theta and heat bath.  dH within 1e-6 |H0|, and the forces of the two
+    paths on the FP64 solution within 1e-6."""
+    wl = inputs.WORKLOADS["mixed_l24"]
+    th = wl.initial_theta()
+    out, thf = {}, {}
+    with Q.Lattice(wl.L, wl.Nt, seed=wl.seed) as lat:
+        for prec in ("fp64", "fp32"):
+            thd = _dev(th)
+            out[prec] = lat.hmc_trajectory(thd, traj=0, n_steps=wl.n_steps, traj_len=wl.traj_len,
+                                           tol=wl.tol, prec=prec)
+            thf[prec] = _host(thd)
+            print(prec, out[prec], flush=True)
+        # force kernels on one solution
+        R = inputs.gauss_cvec(wl.L, wl.Nt, 5)
+        p = O.lat(wl.L, wl.Nt)
+        eta = O.apply_M(p, th, R, dagger=True).reshape(wl.Nt, wl.L, wl.L)
+        x, st, it, rel = lat.cg_solve(_dev(th), _dev(eta), tol=1e-10, prec="fp64")
+        F64 = _host(lat.fermion_force(_dev(th), x, prec="fp64"))
+        F32 = _host(lat.fermion_force(_dev(th), x, prec="fp32"))
+    a, b = out["fp64"], out["fp32"]
+    assert a["status"] == 0 and b["status"] == 0
+    assert a["max_true_resid"] <= wl.tol and b["max_true_resid"] <= wl.tol
+    assert abs(a["H0"] - b["H0"]) <= 1e-6 * abs(a["H0"])
+    assert abs(a["dH"] - b["dH"]) <= 1e-6 * abs(a["H0"])
+    assert a["accepted"] == b["accepted"]
+    assert _rel(F32, F64) < 1e-6
