@@ -174,16 +174,19 @@ qedhmc_status qedhmc_hmc_trajectory(qedhmc_t h, double *theta_inout,
                                     qedhmc_traj_result *out);
 
 /* Kernel timing for measurement (not part of the method).  qedhmc_profile
- * with every > 0 brackets every every-th launch of the timed kernels with
- * HIP events on the handle's stream and clears the accumulators; every = 0
- * turns it off.  qedhmc_profile_read returns, for kernel class k
- * (QEDHMC_K_*), the number of timed launches and their summed duration in
- * milliseconds, after synchronising the stream. */
+ * with every > 0 times every every-th launch of the timed kernel classes
+ * with the start and end events of the dispatch itself
+ * (hipExtLaunchKernelGGL) and clears the accumulators; every = 0 turns it
+ * off.  qedhmc_profile_read returns, for kernel class k (QEDHMC_K_*), the
+ * number of timed launches and their summed duration in milliseconds, after
+ * synchronising the stream. */
 typedef enum {
-    QEDHMC_K_MDAGM_FP32 = 0,   /* fused M^dag M, complex FP32 */
-    QEDHMC_K_MDAGM_FP64 = 1,   /* fused M^dag M, complex FP64 */
+    QEDHMC_K_MDAGM_FP32 = 0,   /* standalone fused M^dag M, complex FP32 */
+    QEDHMC_K_MDAGM_FP64 = 1,   /* standalone fused M^dag M, complex FP64 */
     QEDHMC_K_FORCE = 2,        /* fermion force kernel (either precision) */
-    QEDHMC_K_COUNT = 3
+    QEDHMC_K_CG_FP32 = 3,      /* one fused CG iteration (M^dag M + updates), FP32 */
+    QEDHMC_K_CG_FP64 = 4,      /* one fused CG iteration, FP64 */
+    QEDHMC_K_COUNT = 5
 } qedhmc_kernel_class;
 
 qedhmc_status qedhmc_profile(qedhmc_t h, int32_t every);

@@ -21,18 +21,15 @@ static qedhmc_status einval(const char* msg) {
     return QEDHMC_EINVAL;
 }
 
-int prof_begin(qedhmc_ctx* h, int cls) {
-    if (h->prof_every <= 0 || !h->prof_ready) return -1;
-    if ((h->prof_seen[cls]++ % h->prof_every) != 0) return -1;
-    if (h->prof_pending == 64 && prof_drain(h) != QEDHMC_OK) return -1;
+bool prof_sample(qedhmc_ctx* h, int cls, hipEvent_t& e0, hipEvent_t& e1) {
+    if (h->prof_every <= 0 || !h->prof_ready) return false;
+    if ((h->prof_seen[cls]++ % h->prof_every) != 0) return false;
+    if (h->prof_pending == 64 && prof_drain(h) != QEDHMC_OK) return false;
     const int k = h->prof_pending++;
     h->prof_cls[k] = cls;
-    (void)hipEventRecord(h->prof_ev[k][0], h->stream);
-    return k;
-}
-
-void prof_end(qedhmc_ctx* h, int slot) {
-    if (slot >= 0) (void)hipEventRecord(h->prof_ev[slot][1], h->stream);
+    e0 = h->prof_ev[k][0];
+    e1 = h->prof_ev[k][1];
+    return true;
 }
 
 qedhmc_status prof_drain(qedhmc_ctx* h) {
@@ -100,12 +97,13 @@ qedhmc_status qedhmc_init_lattice(const qedhmc_params* params, void* stream, qed
     ok = ok && hipMalloc(&h->gauge64, 2 * N * sizeof(cplx<double>)) == hipSuccess;
     ok = ok && hipMalloc(&h->gauge32, 2 * N * sizeof(cplx<float>)) == hipSuccess;
     for (int k = 0; k < 12 && ok; k++) ok = hipMalloc(&h->ws[k], vec) == hipSuccess;
+    ok = ok && hipMalloc(&h->cg_arena, 7 * vec) == hipSuccess;
     ok = ok && hipMalloc(&h->theta0, 2 * N * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc(&h->mom, 2 * N * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc(&h->force, 2 * N * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc(&h->force_b, 2 * N * sizeof(double)) == hipSuccess;
-    ok = ok && hipMalloc(&h->partial, ((size_t)p.Nt + 2048) * sizeof(double)) == hipSuccess;
-    ok = ok && hipMalloc(&h->scal, 64 * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc(&h->partial, ((size_t)6 * p.Nt + 4096) * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc(&h->scal, 128 * sizeof(double)) == hipSuccess;
     ok = ok && hipHostMalloc(&h->h_pinned, 64 * sizeof(double), hipHostMallocDefault) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
@@ -133,6 +131,7 @@ qedhmc_status qedhmc_destroy(qedhmc_t h) {
     (void)hipFree(h->gauge64);
     (void)hipFree(h->gauge32);
     for (int k = 0; k < 12; k++) (void)hipFree(h->ws[k]);
+    (void)hipFree(h->cg_arena);
     (void)hipFree(h->theta0);
     (void)hipFree(h->mom);
     (void)hipFree(h->force);
@@ -263,9 +262,9 @@ qedhmc_status qedhmc_fermion_force(qedhmc_t h, const double* theta, const double
 qedhmc_status qedhmc_bosonic_action_force(qedhmc_t h, const double* theta, double* S_B_host, double* F_B) {
     CHECK_H(h);
     if (!theta) return einval("null pointer");
-    QH_TRY(launch_bosonic(h, theta, F_B, h->scal + 40));
+    QH_TRY(launch_bosonic(h, theta, F_B, h->scal + 100));
     if (S_B_host) {
-        QH_HIP(hipMemcpyAsync(h->h_pinned, h->scal + 40, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        QH_HIP(hipMemcpyAsync(h->h_pinned, h->scal + 100, sizeof(double), hipMemcpyDeviceToHost, h->stream));
         QH_HIP(hipStreamSynchronize(h->stream));
         *S_B_host = h->h_pinned[0];
     }
@@ -289,7 +288,7 @@ qedhmc_status qedhmc_hmc_trajectory(qedhmc_t h, double* theta, uint64_t traj, in
     std::memset(out, 0, sizeof(*out));
     const size_t N = nsites(h), nb = 2 * N;
     const double dt = traj_len / n_steps;
-    double* sc = h->scal + 16;  // SB0 K0 SF0 SB1 K1 SF1 dH u acc scratch
+    double* sc = h->scal + 64;  // SB0 K0 SF0 SB1 K1 SF1 dH u acc
     double* R = (double*)h->ws[4];
     double* eta = (double*)h->ws[5];
     double* X = (double*)h->ws[6];

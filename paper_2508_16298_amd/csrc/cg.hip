@@ -1,342 +1,627 @@
-// Conjugate gradient on O = M^dag M (Methods, Eq. pCG), started from x = 0.
+// Conjugate gradient on O = M^dag M (Methods, Eq. pCG), started from x = 0,
+// one kernel launch per iteration.
 //
-// Every scalar of the recursion (alpha, beta, |r|^2) lives on the device and
-// is reduced in FP64 in a fixed order, so a solve is bitwise reproducible for
-// a given launch shape.  A device stop flag turns the remaining iterations of
-// a launched chunk into no-ops once |r| <= tol |rhs|, so the host only reads
-// the flag once per chunk.
+// The recursion is CG in the Chronopoulos-Gear form (one global reduction
+// phase per iteration, both inner products together):
+//   beta_i  = gamma_i / gamma_{i-1}            (0 on the first iteration)
+//   alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1})
+//   p_i = r_i + beta_i p_{i-1},  s_i = w_i + beta_i s_{i-1}     (s = O p)
+//   x_{i+1} = x_i + alpha_i p_i,  r_{i+1} = r_i - alpha_i s_i
+//   w_{i+1} = O r_{i+1},  gamma_{i+1} = <r,r>,  delta_{i+1} = <w,r>
+// mathematically the same iterates as Eq. pCG without preconditioner.
+// A launch boundary is the only grid-wide synchronisation: every workgroup
+// (one per time slice) reduces the per-slice partials of the previous launch
+// in a fixed order (bitwise reproducible), recomputes the recurrences on the
+// two neighbouring slices it needs for the stencil, and applies O to its
+// slice.  r, s and w alternate between two buffers by iteration parity; the
+// device scalars alternate between two slots by launch parity, so no launch
+// reads what a concurrent workgroup writes.
 //
-// Mixed precision (QEDHMC_FP32): r, p and O p are complex FP32 and the matvec
-// runs in FP32; x accumulates in FP64.  The residual is recomputed in FP64 as
-// r = rhs - O x and copied into the FP32 r, with p kept (a reliable update,
-// Sleijpen and van der Vorst 1996), whenever the recursive residual has
-// dropped by a factor 10 since the last update, at least every 50
-// iterations, and when it reaches the target.  The solve ends when that FP64
-// true residual meets tol.  Updating once per decade keeps the gap between
-// the FP32 recursion and the true residual far below the residual itself, so
-// replacing r does not disturb the conjugacy of the directions.
+// Stop and pause: an iteration that finds gamma_i <= tol^2 |rhs|^2 turns
+// itself and all later launches into no-ops (the host reads the flag once per
+// chunk).  The mixed path (complex-FP32 r, p, s, w, O; FP64 x and reductions)
+// also pauses when gamma has fallen by 100 since the last reliable update or
+// 50 iterations have passed (Sleijpen and van der Vorst 1996): then
+// r = rhs - O x is recomputed with the FP64 operator and copied into the FP32
+// recursion, w = O r and s = O p are recomputed (s is otherwise only a
+// recurrence and drifts; the drift turns the denominator <p, O p> =
+// delta - beta gamma / alpha negative on ill-conditioned systems) and the
+// iteration resumes with p kept.  A denominator that is not positive forces
+// the same update with a restart (beta = 0).  At a stop the FP64 true
+// residual decides: converged, or resume (the FP64 path restarts with p = r,
+// as the oracle does).
+#include <cstdlib>
+
 #include "qedhmc_internal.h"
 
 namespace qh {
 
-// Device scalar slots (h->scal)
+// Scalar slot layout (two slots of 16 doubles, by launch parity)
 enum {
-    S_RR = 0,      // current |r|^2 of the recursion
-    S_ALPHA = 1,
-    S_BETA = 2,
-    S_B2 = 3,      // |rhs|^2
-    S_DONE = 4,    // 1: recursive residual reached the target
-    S_TARGET = 5,  // tol^2 |rhs|^2
-    S_ITERS = 6,   // iterations performed
-    S_TRUE = 7,    // last true |r|^2
-    S_RRUPD = 8,   // |r|^2 at the last reliable update (mixed path)
-    S_RRPREV = 9,  // |r|^2 before the last recursive update (for beta after a replacement)
-    S_ITUPD = 10,  // iteration count at the last reliable update
+    S_GPREV = 0,   // gamma_{i-1}
+    S_APREV = 1,   // alpha_{i-1}
+    S_ITERS = 2,   // completed iterations i
+    S_DONE = 3,    // 0 running, 1 stop (target reached / converged), 2 pause for a reliable update,
+                   // 3 pause with restart (non-positive <p, O p>), 4 breakdown (non-finite)
+    S_FIRST = 4,   // 1: next iteration starts a new direction sequence (beta = 0)
+    S_B2 = 5,      // |rhs|^2 (FP64); < 0 until the first iteration sets it
+    S_TARGET = 6,  // tol^2 |rhs|^2
+    S_RRUPD = 7,   // gamma at the last reliable update
+    S_ITUPD = 8,   // iteration of the last reliable update
+    S_TRUE = 9,    // last FP64 true |r|^2
+    S_GCUR = 10,   // gamma_i of the current state
+    S_NSLOT = 16,
 };
-// S_DONE values: 0 running, 1 target reached, 2 paused for a reliable update
-static constexpr double kDelta2 = 0.01;  // (factor 10)^-2
+static constexpr double kDecade2 = 0.01;  // pause when gamma fell by 10^2 (|r| by 10)
+static constexpr int kCap = 50;           // ... or after 50 iterations
 
-static constexpr int kGridV = 512;   // blocks of the vector kernels (fixed: deterministic sums)
-static constexpr int kBlockV = 256;
-
-// partial slots in h->partial: [0, Nt) per-slice partials of <p, Op>, then
-// kGridV partials of the vector kernels (see part_vec)
-static double* part_dot(qedhmc_ctx* h) { return h->partial; }
-static double* part_vec(qedhmc_ctx* h) { return h->partial + h->lat.Nt; }
-
-__global__ void k_finish_sum(const double* __restrict__ part, int n, double* __restrict__ out) {
-    __shared__ double red[16];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) *out = s;
-}
-
-// r = rhs (in working precision), p = r, x = 0; partial |rhs|^2
 template <typename R>
-__global__ void k_cg_init(const cplx<double>* __restrict__ rhs, cplx<R>* __restrict__ r, cplx<R>* __restrict__ p,
-                          cplx<double>* __restrict__ x, size_t n, double* __restrict__ part) {
-    __shared__ double red[16];
-    double s = 0.0;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const cplx<double> b = rhs[i];
-        const cplx<R> br = mk<R>((R)b.re, (R)b.im);
-        r[i] = br;
-        p[i] = br;
-        x[i] = mk<double>(0.0, 0.0);
-        s += b.re * b.re + b.im * b.im;
-    }
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
+struct CgBufs {
+    cplx<R>* r[2];
+    cplx<R>* s[2];
+    cplx<R>* w[2];
+    cplx<R>* p;
+    cplx<double>* x;
+    const cplx<double>* rhs;
+    const cplx<double>* Ox;  // FP64 O x for the true residual
+    double* part;            // [2][Nt][3] per-slice partials (gamma, delta, aux)
+};
 
-__global__ void k_cg_setup(double* __restrict__ sc, const double* __restrict__ part, int n, double tol2) {
-    __shared__ double red[16];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
-    s = block_sum(s, red);
+// Block reduction of three doubles in a fixed order; result valid in thread 0.
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* red) {
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+        c += __shfl_xor(c, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        red[3 * wv] = a;
+        red[3 * wv + 1] = b;
+        red[3 * wv + 2] = c;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        sc[S_B2] = s;
-        sc[S_RR] = s;
-        sc[S_TARGET] = tol2 * s;
-        sc[S_DONE] = (s <= tol2 * s) ? 1.0 : 0.0;
-        sc[S_ITERS] = 0.0;
-        sc[S_RRUPD] = s;
-        sc[S_RRPREV] = s;
-        sc[S_ITUPD] = 0.0;
+        const int nw = (blockDim.x + 63) >> 6;
+        double sa = 0, sb = 0, sc = 0;
+        for (int k = 0; k < nw; k++) {
+            sa += red[3 * k];
+            sb += red[3 * k + 1];
+            sc += red[3 * k + 2];
+        }
+        a = sa;
+        b = sb;
+        c = sc;
     }
 }
 
-// alpha = |r|^2 / <p, Op> (0 once the stop flag is up)
-__global__ void k_cg_alpha(double* __restrict__ sc, const double* __restrict__ part, int n) {
-    __shared__ double red[16];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) sc[S_ALPHA] = sc[S_DONE] != 0.0 ? 0.0 : sc[S_RR] / s;
+// Sum of the Nt partial triples of one parity, broadcast to every thread.
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int Nt, double* red, double* bc,
+                                                double& g, double& d, double& aux) {
+    double a = 0, b = 0, c = 0;
+    for (int t = threadIdx.x; t < Nt; t += blockDim.x) {
+        a += part[3 * t];
+        b += part[3 * t + 1];
+        c += part[3 * t + 2];
+    }
+    block_sum3(a, b, c, red);
+    if (threadIdx.x == 0) {
+        bc[0] = a;
+        bc[1] = b;
+        bc[2] = c;
+    }
+    __syncthreads();
+    g = bc[0];
+    d = bc[1];
+    aux = bc[2];
 }
 
-// x += alpha p; r -= alpha Op; partial |r|^2
-template <typename R>
-__global__ void k_cg_update(double* __restrict__ sc, cplx<double>* __restrict__ x, cplx<R>* __restrict__ r,
-                            const cplx<R>* __restrict__ p, const cplx<R>* __restrict__ q, size_t n,
-                            double* __restrict__ part) {
-    __shared__ double red[16];
-    const double alpha = sc[S_ALPHA];
-    const bool live = sc[S_DONE] == 0.0;
-    const R ar = (R)alpha;
+template <typename R, int MC>
+__device__ __forceinline__ double dot_cells(const Cells<R, MC>& a, const Cells<R, MC>& b, const bool (&own)[MC]) {
     double s = 0.0;
-    if (live) {
-        for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-            const cplx<R> pi = p[i];
-            cplx<double> xi = x[i];
-            xi.re += alpha * (double)pi.re;
-            xi.im += alpha * (double)pi.im;
-            x[i] = xi;
-            cplx<R> ri = r[i];
-            const cplx<R> qi = q[i];
-            ri.re -= ar * qi.re;
-            ri.im -= ar * qi.im;
-            r[i] = ri;
-            s += (double)ri.re * (double)ri.re + (double)ri.im * (double)ri.im;
+#pragma unroll
+    for (int m = 0; m < MC; m++)
+        if (own[m])
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+                s += (double)a.v[m][q].re * (double)b.v[m][q].re + (double)a.v[m][q].im * (double)b.v[m][q].im;
+    return s;
+}
+
+// Common per-block setup for the slice kernels.
+template <int MC>
+struct SliceCtx {
+    int tau, tm, tp;
+    CellGeo g[MC];
+    bool own[MC];
+    int idx[MC][12];
+};
+
+template <int MC>
+__device__ __forceinline__ void slice_ctx(const Lat& lt, SliceCtx<MC>& c) {
+    c.tau = blockIdx.x;
+    c.tm = c.tau == 0 ? lt.Nt - 1 : c.tau - 1;
+    c.tp = c.tau == lt.Nt - 1 ? 0 : c.tau + 1;
+#pragma unroll
+    for (int m = 0; m < MC; m++) {
+        const int cell = threadIdx.x + m * blockDim.x;
+        c.own[m] = cell < lt.ncell;
+        c.g[m] = cell_geo(c.own[m] ? cell : 0, lt);
+        phase_index(c.g[m], lt.Vs, c.idx[m]);
+    }
+}
+
+template <typename R, int MC>
+__device__ __forceinline__ void hops_of(const cplx<R>* __restrict__ gauge, const Lat& lt, int tau,
+                                        const int (&idx)[MC][12], const Coef<R>& co, cplx<R> (&h)[MC][12]) {
+#pragma unroll
+    for (int m = 0; m < MC; m++) load_hops(gauge, lt, tau, idx[m], co, h[m]);
+}
+
+// c = (R)(a - b) (b may be null); sq += |a - b|^2 in FP64 over owned cells
+template <typename R, int MC>
+__device__ __forceinline__ void load_cvt(Cells<R, MC>& c, const cplx<double>* __restrict__ a,
+                                         const cplx<double>* __restrict__ b, const CellGeo (&g)[MC],
+                                         const bool (&own)[MC], double& sq) {
+#pragma unroll
+    for (int m = 0; m < MC; m++)
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            double re = 0, im = 0;
+            if (own[m]) {
+                const cplx<double> x = a[g[m].s[q]];
+                re = x.re;
+                im = x.im;
+                if (b) {
+                    const cplx<double> y = b[g[m].s[q]];
+                    re -= y.re;
+                    im -= y.im;
+                }
+            }
+            sq += re * re + im * im;
+            c.v[m][q] = mk<R>((R)re, (R)im);
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Start: r_0 = rhs, w_0 = O r_0, x = p = s = 0, partials of iteration 0,
+// slot 0 initialised.
+// ---------------------------------------------------------------------------
+template <typename R, int MC, int NB, int BS>
+__global__ __launch_bounds__(BS) void k_cg_start(Lat lt, CgBufs<R> B, const cplx<R>* __restrict__ gauge, Coef<R> co,
+                                                 double* __restrict__ scal) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cplx<R>* buf2 = reinterpret_cast<cplx<R>*>(smem);
+    double* red = reinterpret_cast<double*>(smem + (size_t)NB * 2 * lt.Vs * sizeof(cplx<R>));
+    SliceCtx<MC> c;
+    slice_ctx<MC>(lt, c);
+    const size_t Vs = lt.Vs;
+    cplx<R> hm[MC][12], ht[MC][12];
+    hops_of<R, MC>(gauge, lt, c.tm, c.idx, co, hm);
+    hops_of<R, MC>(gauge, lt, c.tau, c.idx, co, ht);
+    Cells<R, MC> vm, vt, vn, w;
+    double b2 = 0.0, dummy = 0.0;
+    load_cvt<R, MC>(vm, B.rhs + c.tm * Vs, nullptr, c.g, c.own, dummy);
+    load_cvt<R, MC>(vt, B.rhs + c.tau * Vs, nullptr, c.g, c.own, b2);
+    load_cvt<R, MC>(vn, B.rhs + c.tp * Vs, nullptr, c.g, c.own, dummy);
+    Cells<R, MC> zero;
+    Cells<double, MC> zx;
+#pragma unroll
+    for (int m = 0; m < MC; m++)
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            zero.v[m][q] = mk<R>(0, 0);
+            zx.v[m][q] = mk<double>(0, 0);
+        }
+    store_cells<R, MC>(vt, B.r[0] + c.tau * Vs, c.g, c.own);
+    store_cells<R, MC>(zero, B.s[0] + c.tau * Vs, c.g, c.own);
+    store_cells<R, MC>(zero, B.p + c.tau * Vs, c.g, c.own);
+    store_cells<double, MC>(zx, B.x + c.tau * Vs, c.g, c.own);
+    const Cells<R, MC> r0 = vt;
+    mdagm_cells<R, MC, NB>(vm, vt, vn, hm, ht, c.g, c.own, co, c.tau == 0 ? R(-1) : R(1),
+                           c.tau == lt.Nt - 1 ? R(-1) : R(1), buf2, lt.Vs, w);
+    store_cells<R, MC>(w, B.w[0] + c.tau * Vs, c.g, c.own);
+    double gg = dot_cells<R, MC>(r0, r0, c.own), dd = dot_cells<R, MC>(w, r0, c.own);
+    block_sum3(gg, dd, b2, red);
+    if (threadIdx.x == 0) {
+        double* pt = B.part + 3 * (size_t)c.tau;  // parity 0
+        pt[0] = gg;
+        pt[1] = dd;
+        pt[2] = b2;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < S_NSLOT) {
+        double v = 0.0;
+        if (threadIdx.x == S_FIRST) v = 1.0;
+        if (threadIdx.x == S_B2) v = -1.0;
+        if (threadIdx.x == S_GPREV || threadIdx.x == S_APREV) v = 1.0;
+        scal[threadIdx.x] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One CG iteration.  kpar: launch parity (slot in = kpar, slot out = kpar^1).
+// ---------------------------------------------------------------------------
+template <typename R, int MC, int NB, int BS>
+__global__ __launch_bounds__(BS) void k_cg_iter(Lat lt, CgBufs<R> B, const cplx<R>* __restrict__ gauge, Coef<R> co,
+                                                double* __restrict__ scal, int kpar, double tol2, int mixed) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cplx<R>* buf2 = reinterpret_cast<cplx<R>*>(smem);
+    double* red = reinterpret_cast<double*>(smem + (size_t)NB * 2 * lt.Vs * sizeof(cplx<R>));
+    double* bc = red + 64;
+    const double* sin_ = scal + S_NSLOT * kpar;
+    double* sout = scal + S_NSLOT * (kpar ^ 1);
+    if (sin_[S_DONE] != 0.0) {
+        if (blockIdx.x == 0 && threadIdx.x < S_NSLOT) sout[threadIdx.x] = sin_[threadIdx.x];
+        return;
+    }
+    const int it = (int)sin_[S_ITERS];
+    const int ip = it & 1, nx = ip ^ 1;
+    SliceCtx<MC> c;
+    slice_ctx<MC>(lt, c);
+    const size_t Vs = lt.Vs;
+
+    // raw loads first (independent of the scalars)
+    Cells<R, MC> wm, wt, wn, sm, st, sn, rm, rt, rn, pp;
+    load_cells<R, MC>(wm, B.w[ip] + c.tm * Vs, c.g, c.own);
+    load_cells<R, MC>(wt, B.w[ip] + c.tau * Vs, c.g, c.own);
+    load_cells<R, MC>(wn, B.w[ip] + c.tp * Vs, c.g, c.own);
+    load_cells<R, MC>(sm, B.s[ip] + c.tm * Vs, c.g, c.own);
+    load_cells<R, MC>(st, B.s[ip] + c.tau * Vs, c.g, c.own);
+    load_cells<R, MC>(sn, B.s[ip] + c.tp * Vs, c.g, c.own);
+    load_cells<R, MC>(rm, B.r[ip] + c.tm * Vs, c.g, c.own);
+    load_cells<R, MC>(rt, B.r[ip] + c.tau * Vs, c.g, c.own);
+    load_cells<R, MC>(rn, B.r[ip] + c.tp * Vs, c.g, c.own);
+    load_cells<R, MC>(pp, B.p + c.tau * Vs, c.g, c.own);
+    cplx<R> hm[MC][12], ht[MC][12];
+    hops_of<R, MC>(gauge, lt, c.tm, c.idx, co, hm);
+    hops_of<R, MC>(gauge, lt, c.tau, c.idx, co, ht);
+
+    double gam, del, aux;
+    reduce_partials(B.part + 3 * (size_t)lt.Nt * ip, lt.Nt, red, bc, gam, del, aux);
+    double b2 = sin_[S_B2], target = sin_[S_TARGET], rrupd = sin_[S_RRUPD];
+    if (b2 < 0.0) {  // first iteration of the solve: the start kernel left |rhs|^2 partials in aux
+        b2 = aux;
+        target = tol2 * aux;
+        rrupd = gam;
+    }
+    int stop = 0;
+    if (!isfinite(gam) || !isfinite(del))
+        stop = 4;  // breakdown: non-finite recursion
+    else if (gam <= target)
+        stop = 1;
+    else if (mixed && (gam <= kDecade2 * rrupd || it - (int)sin_[S_ITUPD] >= kCap))
+        stop = 2;
+    if (stop) {
+        if (blockIdx.x == 0 && threadIdx.x < S_NSLOT) {
+            double v = sin_[threadIdx.x];
+            if (threadIdx.x == S_DONE) v = (double)stop;
+            if (threadIdx.x == S_B2) v = b2;
+            if (threadIdx.x == S_TARGET) v = target;
+            if (threadIdx.x == S_RRUPD) v = rrupd;
+            if (threadIdx.x == S_GCUR) v = gam;
+            sout[threadIdx.x] = v;
+        }
+        return;
+    }
+    const bool first = sin_[S_FIRST] != 0.0;
+    const double beta = first ? 0.0 : gam / sin_[S_GPREV];
+    const double den = first ? del : del - beta * gam / sin_[S_APREV];  // <p_i, O p_i>
+    if (!(den > 0.0)) {
+        if (blockIdx.x == 0 && threadIdx.x < S_NSLOT) {
+            double v = sin_[threadIdx.x];
+            if (threadIdx.x == S_DONE) v = 3.0;
+            if (threadIdx.x == S_B2) v = b2;
+            if (threadIdx.x == S_TARGET) v = target;
+            if (threadIdx.x == S_RRUPD) v = rrupd;
+            if (threadIdx.x == S_GCUR) v = gam;
+            sout[threadIdx.x] = v;
+        }
+        return;
+    }
+    const double alpha = gam / den;
+    const R b = (R)beta, a = (R)alpha;
+
+    // s_i = w_i + beta s_{i-1};  r_{i+1} = r_i - alpha s_i on the three slices
+#pragma unroll
+    for (int m = 0; m < MC; m++)
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            sm.v[m][q] = cfma(b, sm.v[m][q], wm.v[m][q]);
+            st.v[m][q] = cfma(b, st.v[m][q], wt.v[m][q]);
+            sn.v[m][q] = cfma(b, sn.v[m][q], wn.v[m][q]);
+            pp.v[m][q] = cfma(b, pp.v[m][q], rt.v[m][q]);  // p_i = r_i + beta p_{i-1}
+            rm.v[m][q] = cfma(-a, sm.v[m][q], rm.v[m][q]);
+            rt.v[m][q] = cfma(-a, st.v[m][q], rt.v[m][q]);
+            rn.v[m][q] = cfma(-a, sn.v[m][q], rn.v[m][q]);
+        }
+    store_cells<R, MC>(st, B.s[nx] + c.tau * Vs, c.g, c.own);
+    store_cells<R, MC>(rt, B.r[nx] + c.tau * Vs, c.g, c.own);
+    store_cells<R, MC>(pp, B.p + c.tau * Vs, c.g, c.own);
+    // x_{i+1} = x_i + alpha p_i in FP64
+#pragma unroll
+    for (int m = 0; m < MC; m++)
+        if (c.own[m])
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                cplx<double>* xp = B.x + c.tau * Vs + c.g[m].s[q];
+                cplx<double> xv = *xp;
+                xv.re += alpha * (double)pp.v[m][q].re;
+                xv.im += alpha * (double)pp.v[m][q].im;
+                *xp = xv;
+            }
+    const Cells<R, MC> rnew = rt;
+    Cells<R, MC> w;
+    mdagm_cells<R, MC, NB>(rm, rt, rn, hm, ht, c.g, c.own, co, c.tau == 0 ? R(-1) : R(1),
+                           c.tau == lt.Nt - 1 ? R(-1) : R(1), buf2, lt.Vs, w);
+    store_cells<R, MC>(w, B.w[nx] + c.tau * Vs, c.g, c.own);
+    double gg = dot_cells<R, MC>(rnew, rnew, c.own), dd = dot_cells<R, MC>(w, rnew, c.own), zz = 0.0;
+    block_sum3(gg, dd, zz, red);
+    if (threadIdx.x == 0) {
+        double* pt = B.part + 3 * ((size_t)lt.Nt * nx + c.tau);
+        pt[0] = gg;
+        pt[1] = dd;
+        pt[2] = 0.0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < S_NSLOT) {
+        double v = sin_[threadIdx.x];
+        if (threadIdx.x == S_GPREV) v = gam;
+        if (threadIdx.x == S_APREV) v = alpha;
+        if (threadIdx.x == S_ITERS) v = (double)(it + 1);
+        if (threadIdx.x == S_FIRST) v = 0.0;
+        if (threadIdx.x == S_B2) v = b2;
+        if (threadIdx.x == S_TARGET) v = target;
+        if (threadIdx.x == S_RRUPD) v = rrupd;
+        if (threadIdx.x == S_GCUR) v = gam;
+        sout[threadIdx.x] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reliable update / true residual: r_i = rhs - O x (FP64 O x given), w_i =
+// O r_i in the working precision, partials of iteration i replaced; aux gets
+// the FP64 |rhs - O x|^2.  Slot kpar is only read.
+// ---------------------------------------------------------------------------
+template <typename R, int MC, int NB, int BS>
+__global__ __launch_bounds__(BS) void k_cg_replace(Lat lt, CgBufs<R> B, const cplx<R>* __restrict__ gauge,
+                                                   Coef<R> co, const double* __restrict__ scal, int kpar) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cplx<R>* buf2 = reinterpret_cast<cplx<R>*>(smem);
+    double* red = reinterpret_cast<double*>(smem + (size_t)NB * 2 * lt.Vs * sizeof(cplx<R>));
+    const int it = (int)scal[S_NSLOT * kpar + S_ITERS];
+    const int ip = it & 1;
+    SliceCtx<MC> c;
+    slice_ctx<MC>(lt, c);
+    const size_t Vs = lt.Vs;
+    cplx<R> hm[MC][12], ht[MC][12];
+    hops_of<R, MC>(gauge, lt, c.tm, c.idx, co, hm);
+    hops_of<R, MC>(gauge, lt, c.tau, c.idx, co, ht);
+    Cells<R, MC> vm, vt, vn, w;
+    double t2 = 0.0, dummy = 0.0;
+    load_cvt<R, MC>(vm, B.rhs + c.tm * Vs, B.Ox + c.tm * Vs, c.g, c.own, dummy);
+    load_cvt<R, MC>(vt, B.rhs + c.tau * Vs, B.Ox + c.tau * Vs, c.g, c.own, t2);
+    load_cvt<R, MC>(vn, B.rhs + c.tp * Vs, B.Ox + c.tp * Vs, c.g, c.own, dummy);
+    store_cells<R, MC>(vt, B.r[ip] + c.tau * Vs, c.g, c.own);
+    const Cells<R, MC> r0 = vt;
+    const R em = c.tau == 0 ? R(-1) : R(1), et = c.tau == lt.Nt - 1 ? R(-1) : R(1);
+    mdagm_cells<R, MC, NB>(vm, vt, vn, hm, ht, c.g, c.own, co, em, et, buf2, lt.Vs, w);
+    store_cells<R, MC>(w, B.w[ip] + c.tau * Vs, c.g, c.own);
+    // s_{i-1} = O p_{i-1}, recomputed
+    Cells<R, MC> pm, pt_, pn, sp;
+    load_cells<R, MC>(pm, B.p + c.tm * Vs, c.g, c.own);
+    load_cells<R, MC>(pt_, B.p + c.tau * Vs, c.g, c.own);
+    load_cells<R, MC>(pn, B.p + c.tp * Vs, c.g, c.own);
+    __syncthreads();  // LDS exchange buffers are reused
+    mdagm_cells<R, MC, NB>(pm, pt_, pn, hm, ht, c.g, c.own, co, em, et, buf2, lt.Vs, sp);
+    store_cells<R, MC>(sp, B.s[ip] + c.tau * Vs, c.g, c.own);
+    double gg = dot_cells<R, MC>(r0, r0, c.own), dd = dot_cells<R, MC>(w, r0, c.own);
+    block_sum3(gg, dd, t2, red);
+    if (threadIdx.x == 0) {
+        double* pt = B.part + 3 * ((size_t)lt.Nt * ip + c.tau);
+        pt[0] = gg;
+        pt[1] = dd;
+        pt[2] = t2;
+    }
+}
+
+// After k_cg_replace: true |r|^2 into the slot; converged -> stop flag 1;
+// otherwise clear the flag and resume (restart: beta = 0 on the next
+// iteration, the FP64 path's p = r).
+__global__ void k_cg_check(double* __restrict__ scal, int kpar, const double* __restrict__ part, int Nt,
+                           int restart) {
+    __shared__ double red[64];
+    double* sl = scal + S_NSLOT * kpar;
+    const int ip = ((int)sl[S_ITERS]) & 1;
+    const double* pt = part + 3 * (size_t)Nt * ip;
+    double a = 0, b = 0, c = 0;
+    for (int t = threadIdx.x; t < Nt; t += blockDim.x) {
+        a += pt[3 * t];
+        c += pt[3 * t + 2];
+    }
+    block_sum3(a, b, c, red);
+    if (threadIdx.x == 0) {
+        sl[S_TRUE] = c;
+        if (c <= sl[S_TARGET]) {
+            sl[S_DONE] = 1.0;
+        } else {
+            sl[S_DONE] = 0.0;
+            if (restart) sl[S_FIRST] = 1.0;
+            sl[S_ITUPD] = sl[S_ITERS];
+            sl[S_RRUPD] = a;
         }
     }
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// beta = |r_new|^2 / |r|^2; stop flag when |r_new|^2 <= target.  Mixed path:
-// pause flag (before p is updated) when |r| fell by 10 since the last reliable
-// update or 50 iterations have passed since it.
-__global__ void k_cg_beta(double* __restrict__ sc, const double* __restrict__ part, int n, int mixed) {
-    __shared__ double red[16];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) {
-        if (sc[S_DONE] == 0.0) {
-            const double prev = sc[S_RR];
-            sc[S_RRPREV] = prev;
-            sc[S_BETA] = s / prev;
-            sc[S_RR] = s;
-            sc[S_ITERS] += 1.0;
-            if (s <= sc[S_TARGET])
-                sc[S_DONE] = 1.0;
-            else if (mixed && (s <= kDelta2 * sc[S_RRUPD] || sc[S_ITERS] - sc[S_ITUPD] >= 50.0))
-                sc[S_DONE] = 2.0;
-        }
-    }
-}
-
-// p = r + beta p
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
 template <typename R>
-__global__ void k_cg_p(const double* __restrict__ sc, const cplx<R>* __restrict__ r, cplx<R>* __restrict__ p,
-                       size_t n) {
-    if (sc[S_DONE] != 0.0) return;
-    const R b = (R)sc[S_BETA];
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const cplx<R> ri = r[i], pi = p[i];
-        p[i] = mk<R>(ri.re + b * pi.re, ri.im + b * pi.im);
-    }
-}
-
-// True residual in FP64: r64 = rhs - Ox; r (working precision) = r64; partial |r64|^2.
-// restart != 0 also sets p = r (used when the recursion stopped but the true
-// residual is still above tol).
-template <typename R>
-__global__ void k_cg_true(const cplx<double>* __restrict__ rhs, const cplx<double>* __restrict__ Ox,
-                          cplx<R>* __restrict__ r, cplx<R>* __restrict__ p, int restart, size_t n,
-                          double* __restrict__ part) {
-    __shared__ double red[16];
-    double s = 0.0;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const cplx<double> b = rhs[i], o = Ox[i];
-        const double re = b.re - o.re, im = b.im - o.im;
-        const cplx<R> rr = mk<R>((R)re, (R)im);
-        r[i] = rr;
-        if (restart) p[i] = rr;
-        s += re * re + im * im;
-    }
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
-
-// After a true-residual recomputation: |r|^2 <- true value and the stop flag
-// is cleared.  complete != 0 finishes the interrupted iteration: beta is
-// recomputed against the replaced residual, beta = |r_true|^2 / |r_prev|^2,
-// for the p update that follows.
-__global__ void k_cg_after_true(double* __restrict__ sc, const double* __restrict__ part, int n, int complete) {
-    __shared__ double red[16];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) {
-        sc[S_TRUE] = s;
-        sc[S_RR] = s;
-        sc[S_RRUPD] = s;
-        sc[S_ITUPD] = sc[S_ITERS];
-        if (complete) sc[S_BETA] = s / sc[S_RRPREV];
-        sc[S_DONE] = 0.0;
-    }
-}
-
-__global__ void k_cg_fix_beta(double* __restrict__ sc) {
-    if (threadIdx.x == 0) sc[S_BETA] = sc[S_TRUE] / sc[S_RRPREV];
-}
-
-template <typename R>
-__global__ void k_cg_copy(const cplx<R>* __restrict__ a, cplx<R>* __restrict__ b, size_t n) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        b[i] = a[i];
-}
-
-template <typename R>
-static qedhmc_status cg_iterations(qedhmc_ctx* h, qedhmc_precision prec, double* x, cplx<R>* r, cplx<R>* p,
-                                   cplx<R>* q, int count) {
+static CgBufs<R> bufs_of(qedhmc_ctx* h, const double* rhs, double* x) {
+    CgBufs<R> B;
     const size_t N = (size_t)h->lat.Nt * h->lat.Vs;
-    double* sc = h->scal;
-    double* pd = part_dot(h);
-    double* pv = part_vec(h);
-    for (int k = 0; k < count; k++) {
-        QH_TRY(launch_mdagm(h, prec, p, q, pd));
-        hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, h->stream, sc, pd, h->lat.Nt);
-        hipLaunchKernelGGL(k_cg_update<R>, dim3(kGridV), dim3(kBlockV), 0, h->stream, sc, (cplx<double>*)x, r,
-                           (const cplx<R>*)p, (const cplx<R>*)q, N, pv);
-        hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, h->stream, sc, pv, kGridV, prec != QEDHMC_FP64 ? 1 : 0);
-        hipLaunchKernelGGL(k_cg_p<R>, dim3(kGridV), dim3(kBlockV), 0, h->stream, (const double*)sc,
-                           (const cplx<R>*)r, p, N);
+    cplx<R>* base = reinterpret_cast<cplx<R>*>(h->cg_arena);
+    B.r[0] = base;
+    B.r[1] = base + N;
+    B.s[0] = base + 2 * N;
+    B.s[1] = base + 3 * N;
+    B.w[0] = base + 4 * N;
+    B.w[1] = base + 5 * N;
+    B.p = base + 6 * N;
+    B.x = reinterpret_cast<cplx<double>*>(x);
+    B.rhs = reinterpret_cast<const cplx<double>*>(rhs);
+    B.Ox = reinterpret_cast<const cplx<double>*>(h->ws[3]);
+    B.part = h->partial;
+    return B;
+}
+
+template <typename R>
+static const cplx<R>* gauge_for(qedhmc_ctx* h) {
+    if constexpr (sizeof(R) == 8)
+        return h->gauge64;
+    else
+        return h->gauge32;
+}
+
+template <typename R, typename F>
+static qedhmc_status with_shape(qedhmc_ctx* h, F&& f) {
+    const Lat& lt = h->lat;
+    const int mc = lt.ncell <= 1024 ? 1 : 2;
+    int nt = ((((lt.ncell + mc - 1) / mc) + 63) / 64) * 64;
+    if (nt < 64) nt = 64;
+    const size_t red = 128 * sizeof(double);
+    const bool two = 4 * (size_t)lt.Vs * sizeof(cplx<R>) + red <= h->max_lds;
+    auto go = [&]<int MC, int BS>() -> qedhmc_status {
+        if (two) return f.template operator()<MC, 2, BS>(nt, 4 * (size_t)lt.Vs * sizeof(cplx<R>) + red);
+        return f.template operator()<MC, 1, BS>(nt, 2 * (size_t)lt.Vs * sizeof(cplx<R>) + red);
+    };
+    if (mc == 2) return go.template operator()<2, 576>();
+    if (nt <= 256) return go.template operator()<1, 256>();
+    if (nt <= 512) return go.template operator()<1, 512>();
+    return go.template operator()<1, 1024>();
+}
+
+template <typename K>
+static qedhmc_status lds_attr(qedhmc_ctx* h, K kern, size_t bytes) {
+    if (bytes > h->max_lds) {
+        set_error("lattice too large for LDS on this device");
+        return QEDHMC_EUNSUPPORTED;
     }
+    if (bytes > 65536)
+        QH_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    return QEDHMC_OK;
+}
+
+template <typename R>
+static qedhmc_status launch_start(qedhmc_ctx* h, const CgBufs<R>& B) {
+    return with_shape<R>(h, [&]<int MC, int NB, int BS>(int nt, size_t lds) -> qedhmc_status {
+        QH_TRY(lds_attr(h, k_cg_start<R, MC, NB, BS>, lds));
+        hipLaunchKernelGGL((k_cg_start<R, MC, NB, BS>), dim3(h->lat.Nt), dim3(nt), lds, h->stream, h->lat, B,
+                           gauge_for<R>(h), coef_of<R>(h->p), h->scal);
+        QH_HIP(hipGetLastError());
+        return QEDHMC_OK;
+    });
+}
+
+template <typename R>
+static qedhmc_status launch_iters(qedhmc_ctx* h, const CgBufs<R>& B, int& kpar, int count, double tol2, int mixed) {
+    return with_shape<R>(h, [&]<int MC, int NB, int BS>(int nt, size_t lds) -> qedhmc_status {
+        QH_TRY(lds_attr(h, k_cg_iter<R, MC, NB, BS>, lds));
+        const Coef<R> co = coef_of<R>(h->p);
+        const cplx<R>* g = gauge_for<R>(h);
+        const int cls = sizeof(R) == 4 ? QEDHMC_K_CG_FP32 : QEDHMC_K_CG_FP64;
+        for (int k = 0; k < count; k++) {
+            hipEvent_t e0, e1;
+            if (prof_sample(h, cls, e0, e1))
+                hipExtLaunchKernelGGL((k_cg_iter<R, MC, NB, BS>), dim3(h->lat.Nt), dim3(nt), lds, h->stream, e0, e1,
+                                      0, h->lat, B, g, co, h->scal, kpar, tol2, mixed);
+            else
+                hipLaunchKernelGGL((k_cg_iter<R, MC, NB, BS>), dim3(h->lat.Nt), dim3(nt), lds, h->stream, h->lat, B,
+                                   g, co, h->scal, kpar, tol2, mixed);
+            kpar ^= 1;
+        }
+        QH_HIP(hipGetLastError());
+        return QEDHMC_OK;
+    });
+}
+
+template <typename R>
+static qedhmc_status launch_true(qedhmc_ctx* h, const CgBufs<R>& B, const double* x, int kpar, int restart) {
+    QH_TRY(launch_mdagm(h, QEDHMC_FP64, x, h->ws[3], nullptr));
+    QH_TRY(with_shape<R>(h, [&]<int MC, int NB, int BS>(int nt, size_t lds) -> qedhmc_status {
+        QH_TRY(lds_attr(h, k_cg_replace<R, MC, NB, BS>, lds));
+        hipLaunchKernelGGL((k_cg_replace<R, MC, NB, BS>), dim3(h->lat.Nt), dim3(nt), lds, h->stream, h->lat, B,
+                           gauge_for<R>(h), coef_of<R>(h->p), (const double*)h->scal, kpar);
+        QH_HIP(hipGetLastError());
+        return QEDHMC_OK;
+    }));
+    hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(256), 0, h->stream, h->scal, kpar, (const double*)h->partial,
+                       h->lat.Nt, restart);
     QH_HIP(hipGetLastError());
     return QEDHMC_OK;
 }
 
-// Recompute the true residual in FP64 into r.  mode 0: only replace r;
-// mode 1: restart (p = r); mode 2: replace r and finish the interrupted
-// iteration with p = r + beta p.
-template <typename R>
-static qedhmc_status cg_true_resid(qedhmc_ctx* h, const double* rhs, const double* x, cplx<R>* r, cplx<R>* p,
-                                   int mode) {
-    const size_t N = (size_t)h->lat.Nt * h->lat.Vs;
-    double* Ox = (double*)h->ws[3];
-    double* pv = part_vec(h);
-    QH_TRY(launch_mdagm(h, QEDHMC_FP64, x, Ox, nullptr));
-    hipLaunchKernelGGL(k_cg_true<R>, dim3(kGridV), dim3(kBlockV), 0, h->stream, (const cplx<double>*)rhs,
-                       (const cplx<double>*)Ox, r, p, mode == 1 ? 1 : 0, N, pv);
-    hipLaunchKernelGGL(k_cg_after_true, dim3(1), dim3(256), 0, h->stream, h->scal, pv, kGridV, mode == 2 ? 1 : 0);
-    if (mode == 2)
-        hipLaunchKernelGGL(k_cg_p<R>, dim3(kGridV), dim3(kBlockV), 0, h->stream, (const double*)h->scal,
-                           (const cplx<R>*)r, p, N);
-    QH_HIP(hipGetLastError());
-    return QEDHMC_OK;
-}
-
-static qedhmc_status read_scal(qedhmc_ctx* h) {
-    QH_HIP(hipMemcpyAsync(h->h_pinned, h->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+static qedhmc_status read_slot(qedhmc_ctx* h, int kpar) {
+    QH_HIP(hipMemcpyAsync(h->h_pinned, h->scal + S_NSLOT * kpar, S_NSLOT * sizeof(double), hipMemcpyDeviceToHost,
+                          h->stream));
     QH_HIP(hipStreamSynchronize(h->stream));
-    return QEDHMC_OK;
-}
-
-// True residual into r (no change of p), its relative norm on the host.
-template <typename R>
-static qedhmc_status read_true(qedhmc_ctx* h, const double* rhs, const double* x, cplx<R>* r, cplx<R>* p, int mode,
-                               double b2, double& rel) {
-    QH_TRY(cg_true_resid<R>(h, rhs, x, r, p, mode));
-    QH_TRY(read_scal(h));
-    rel = std::sqrt(h->h_pinned[S_TRUE] / b2);
-    return QEDHMC_OK;
-}
-
-// Continue after a failed convergence check whose true residual is in r:
-// mixed -> finish the iteration (beta against the replaced residual, then
-// p = r + beta p); FP64 -> restart with p = r.
-template <typename R>
-static qedhmc_status cg_continue(qedhmc_ctx* h, cplx<R>* r, cplx<R>* p, bool mixed) {
-    const size_t N = (size_t)h->lat.Nt * h->lat.Vs;
-    if (mixed) {
-        hipLaunchKernelGGL(k_cg_fix_beta, dim3(1), dim3(64), 0, h->stream, h->scal);
-        hipLaunchKernelGGL(k_cg_p<R>, dim3(kGridV), dim3(kBlockV), 0, h->stream, (const double*)h->scal,
-                           (const cplx<R>*)r, p, N);
-    } else {
-        hipLaunchKernelGGL(k_cg_copy<R>, dim3(kGridV), dim3(kBlockV), 0, h->stream, (const cplx<R>*)r, p, N);
-    }
-    QH_HIP(hipGetLastError());
     return QEDHMC_OK;
 }
 
 template <typename R>
 static qedhmc_status cg_t(qedhmc_ctx* h, const double* rhs, double* x, double tol, int maxit, qedhmc_precision prec,
                           int* iters, double* true_rel, int* n_reliable) {
-    const size_t N = (size_t)h->lat.Nt * h->lat.Vs;
-    cplx<R>* r = (cplx<R>*)h->ws[0];
-    cplx<R>* p = (cplx<R>*)h->ws[1];
-    cplx<R>* q = (cplx<R>*)h->ws[2];
     const bool mixed = prec != QEDHMC_FP64;
-    const int kChunk = 50;  // host check period (the mixed path pauses itself at least every 50)
-    int nrel = 0;
-
-    // FP64 rhs -> working precision before the ensure_gauge of the caller's theta
-    hipLaunchKernelGGL(k_cg_init<R>, dim3(kGridV), dim3(kBlockV), 0, h->stream, (const cplx<double>*)rhs, r, p,
-                       (cplx<double>*)x, N, part_vec(h));
-    hipLaunchKernelGGL(k_cg_setup, dim3(1), dim3(256), 0, h->stream, h->scal, part_vec(h), kGridV, tol * tol);
-    QH_HIP(hipGetLastError());
-    QH_TRY(read_scal(h));
-    const double b2 = h->h_pinned[S_B2];
-    if (b2 == 0.0) {
-        if (iters) *iters = 0;
-        if (true_rel) *true_rel = 0.0;
-        if (n_reliable) *n_reliable = 0;
-        return QEDHMC_OK;
-    }
-    int it = 0;
+    const CgBufs<R> B = bufs_of<R>(h, rhs, x);
+    // chunk of launches between host checks; the mixed path pauses itself at
+    // most every kCap + 1 launches
+    const int chunk = mixed ? kCap + 1 : 64;
+    int kpar = 0, nrel = 0, it = 0, stalled = 0, last_it = -1;
     double rel = 1.0;
-    bool converged = false;
+    bool converged = false, broken = false;
+    static const bool trace = std::getenv("QEDHMC_CG_TRACE") != nullptr;
+    QH_TRY(launch_start<R>(h, B));
     while (true) {
         const int left = maxit - it;
-        if (left > 0) QH_TRY(cg_iterations<R>(h, prec, x, r, p, q, left < kChunk ? left : kChunk));
-        QH_TRY(read_scal(h));
+        if (left > 0) QH_TRY(launch_iters<R>(h, B, kpar, left < chunk ? left : chunk, tol * tol, mixed ? 1 : 0));
+        QH_TRY(read_slot(h, kpar));
         it = (int)h->h_pinned[S_ITERS];
         const double flag = h->h_pinned[S_DONE];
-        if (flag == 1.0 || it >= maxit) {
-            // true residual check (FP64).  Not yet converged: the FP64 path
-            // restarts from it (p = r); the mixed path keeps p and finishes the
-            // interrupted iteration (a reliable update).
-            QH_TRY(read_true(h, rhs, x, r, p, 0, b2, rel));
-            nrel++;
-            if (rel <= tol) {
-                converged = true;
-                break;
-            }
-            if (it >= maxit) break;
-            QH_TRY(cg_continue<R>(h, r, p, mixed));
-        } else if (flag == 2.0) {
-            // reliable update at the pause: replace r, keep p, finish the iteration
-            QH_TRY(cg_true_resid<R>(h, rhs, x, r, p, 2));
-            nrel++;
+        if (flag == 0.0 && it < maxit) continue;
+        if (flag == 4.0) {
+            broken = true;
+            set_error("CG breakdown: non-finite inner products after " + std::to_string(it) + " iterations");
+            break;
         }
+        // every stop / pause must be followed by progress, else give up
+        stalled = (it == last_it) ? stalled + 1 : 0;
+        last_it = it;
+        if (stalled >= 3) {
+            set_error("CG made no progress across reliable updates at iteration " + std::to_string(it));
+            break;
+        }
+        // stop, pause or maxit: FP64 true residual decides
+        QH_TRY(launch_true<R>(h, B, x, kpar, (!mixed || flag == 3.0) ? 1 : 0));
+        nrel++;
+        QH_TRY(read_slot(h, kpar));
+        const double b2 = h->h_pinned[S_B2];
+        rel = b2 > 0.0 ? std::sqrt(h->h_pinned[S_TRUE] / b2) : 0.0;
+        if (trace)
+            std::fprintf(stderr, "cg it=%d flag=%g true_rel=%.3e gamma=%.3e\n", it, flag, rel, h->h_pinned[S_GCUR]);
+        if (!std::isfinite(rel)) {
+            broken = true;
+            set_error("CG breakdown: non-finite true residual after " + std::to_string(it) + " iterations");
+            break;
+        }
+        if (h->h_pinned[S_DONE] == 1.0) {
+            converged = true;
+            break;
+        }
+        if (it >= maxit) break;
     }
     if (iters) *iters = it;
     if (true_rel) *true_rel = rel;
     if (n_reliable) *n_reliable = nrel;
+    if (broken) return QEDHMC_ENOCONV;
     return converged ? QEDHMC_OK : QEDHMC_ENOCONV;
 }
 

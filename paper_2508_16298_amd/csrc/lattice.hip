@@ -170,19 +170,17 @@ __global__ __launch_bounds__(BS) void k_apply_M(Lat lt, int dagger, const cplx<R
 }
 
 // ---------------------------------------------------------------------------
-// Fused out = M^dag M in, slice by slice:
-//   out_tau = in_tau - eps_{tau-1} B_{tau-1} in_{tau-1}
-//           + B_tau (B_tau in_tau - eps_tau in_{tau+1})
-// (three B applications per slice; the definition M^dag (M in) expanded with
-// eps^2 = 1).  Optionally writes the slice partial of Re <in, out>.
+// Fused out = M^dag M in, slice by slice (mdagm_cells: three B applications,
+// the first two together).  Optionally writes the slice partial of
+// Re <in, out>.
 // ---------------------------------------------------------------------------
 template <typename R, int MC, int NB, int BS>
 __global__ __launch_bounds__(BS) void k_mdagm(Lat lt, const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
-                                                const cplx<R>* __restrict__ gauge, Coef<R> co,
-                                                double* __restrict__ pdot) {
+                                              const cplx<R>* __restrict__ gauge, Coef<R> co,
+                                              double* __restrict__ pdot) {
     extern __shared__ __align__(16) unsigned char smem[];
-    Xchg<R, NB> xb{reinterpret_cast<cplx<R>*>(smem), lt.Vs, 0};
-    double* red = reinterpret_cast<double*>(smem + (size_t)NB * lt.Vs * sizeof(cplx<R>));
+    cplx<R>* buf2 = reinterpret_cast<cplx<R>*>(smem);
+    double* red = reinterpret_cast<double*>(smem + (size_t)NB * 2 * lt.Vs * sizeof(cplx<R>));
     const int tau = blockIdx.x, Nt = lt.Nt;
     const int tm = tau == 0 ? Nt - 1 : tau - 1, tp = tau == Nt - 1 ? 0 : tau + 1;
     const R eps_m = tau == 0 ? R(-1) : R(1);
@@ -192,43 +190,25 @@ __global__ __launch_bounds__(BS) void k_mdagm(Lat lt, const cplx<R>* __restrict_
     bool own[MC];
     int idx[MC][12];
     my_cells<MC>(lt, g, own, idx);
-    cplx<R> hp[MC][12];
-    Cells<R, MC> a, vt, vn;
-    load_hops_all<R, MC>(gauge, lt, tm, idx, co, hp);
-    load_cells<R, MC>(a, in + (size_t)tm * lt.Vs, g, own);
+    cplx<R> hm[MC][12], ht[MC][12];
+    Cells<R, MC> vm, vt, vn, o;
+    load_hops_all<R, MC>(gauge, lt, tm, idx, co, hm);
+    load_hops_all<R, MC>(gauge, lt, tau, idx, co, ht);
+    load_cells<R, MC>(vm, in + (size_t)tm * lt.Vs, g, own);
     load_cells<R, MC>(vt, in + (size_t)tau * lt.Vs, g, own);
     load_cells<R, MC>(vn, in + (size_t)tp * lt.Vs, g, own);
-
-    apply_B_cells<R, MC, NB>(a, hp, g, own, co, xb);  // a = B_{tau-1} in_{tau-1}
-    Cells<R, MC> acc, t;
-#pragma unroll
-    for (int m = 0; m < MC; m++)
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-            acc.v[m][q] = cfma(-eps_m, a.v[m][q], vt.v[m][q]);
-            t.v[m][q] = vt.v[m][q];
-        }
-    load_hops_all<R, MC>(gauge, lt, tau, idx, co, hp);
-    apply_B_cells<R, MC, NB>(t, hp, g, own, co, xb);  // t = B_tau in_tau
-#pragma unroll
-    for (int m = 0; m < MC; m++)
-#pragma unroll
-        for (int q = 0; q < 4; q++) t.v[m][q] = cfma(-eps_t, vn.v[m][q], t.v[m][q]);
-    apply_B_cells<R, MC, NB>(t, hp, g, own, co, xb);  // t = B_tau (B_tau in_tau - eps in_{tau+1})
-    double dot = 0.0;
-#pragma unroll
-    for (int m = 0; m < MC; m++)
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-            acc.v[m][q] = cadd(acc.v[m][q], t.v[m][q]);
-            if (own[m])
-                dot += (double)vt.v[m][q].re * (double)acc.v[m][q].re +
-                       (double)vt.v[m][q].im * (double)acc.v[m][q].im;
-        }
-    store_cells<R, MC>(acc, out + (size_t)tau * lt.Vs, g, own);
+    mdagm_cells<R, MC, NB>(vm, vt, vn, hm, ht, g, own, co, eps_m, eps_t, buf2, lt.Vs, o);
+    store_cells<R, MC>(o, out + (size_t)tau * lt.Vs, g, own);
     if (pdot) {
-        const double s = block_sum(dot, red);
-        if (threadIdx.x == 0) pdot[tau] = s;
+        double dot = 0.0;
+#pragma unroll
+        for (int m = 0; m < MC; m++)
+            if (own[m])
+#pragma unroll
+                for (int q = 0; q < 4; q++)
+                    dot += (double)vt.v[m][q].re * (double)o.v[m][q].re + (double)vt.v[m][q].im * (double)o.v[m][q].im;
+        const double sum = block_sum(dot, red);
+        if (threadIdx.x == 0) pdot[tau] = sum;
     }
 }
 
@@ -451,15 +431,19 @@ template <typename R>
 static qedhmc_status mdagm_t(qedhmc_ctx* h, const void* in, void* out, double* pdot) {
     const Shape s = shape_of(h->lat);
     const size_t red = 32 * sizeof(double);
-    const bool two = 2 * h->lat.Vs * sizeof(cplx<R>) + red <= h->max_lds;
+    const bool two = 4 * h->lat.Vs * sizeof(cplx<R>) + red <= h->max_lds;
     return dispatch_shape(s, [&]<int MC, int BS>() -> qedhmc_status {
         auto run = [&]<int NB>() -> qedhmc_status {
-            const size_t lds = (size_t)NB * h->lat.Vs * sizeof(cplx<R>) + red;
+            const size_t lds = (size_t)NB * 2 * h->lat.Vs * sizeof(cplx<R>) + red;
             QH_TRY(allow_lds(h, k_mdagm<R, MC, NB, BS>, lds));
-            const int slot = prof_begin(h, sizeof(R) == 4 ? QEDHMC_K_MDAGM_FP32 : QEDHMC_K_MDAGM_FP64);
-            hipLaunchKernelGGL((k_mdagm<R, MC, NB, BS>), dim3(h->lat.Nt), dim3(s.nt), lds, h->stream, h->lat,
-                               (const cplx<R>*)in, (cplx<R>*)out, gauge_of<R>(h), coef_of<R>(h->p), pdot);
-            prof_end(h, slot);
+            hipEvent_t e0, e1;
+            if (prof_sample(h, sizeof(R) == 4 ? QEDHMC_K_MDAGM_FP32 : QEDHMC_K_MDAGM_FP64, e0, e1))
+                hipExtLaunchKernelGGL((k_mdagm<R, MC, NB, BS>), dim3(h->lat.Nt), dim3(s.nt), lds, h->stream, e0, e1,
+                                      0, h->lat, (const cplx<R>*)in, (cplx<R>*)out, gauge_of<R>(h),
+                                      coef_of<R>(h->p), pdot);
+            else
+                hipLaunchKernelGGL((k_mdagm<R, MC, NB, BS>), dim3(h->lat.Nt), dim3(s.nt), lds, h->stream, h->lat,
+                                   (const cplx<R>*)in, (cplx<R>*)out, gauge_of<R>(h), coef_of<R>(h->p), pdot);
             QH_HIP(hipGetLastError());
             return QEDHMC_OK;
         };
@@ -522,10 +506,13 @@ static qedhmc_status force_t(qedhmc_ctx* h, const void* X, const void* Y, double
     return dispatch_shape(s, [&]<int MC, int BS>() -> qedhmc_status {
         const size_t lds = (size_t)2 * h->lat.Vs * sizeof(cplx<R>);
         QH_TRY(allow_lds(h, k_force<R, MC, BS>, lds));
-        const int slot = prof_begin(h, QEDHMC_K_FORCE);
-        hipLaunchKernelGGL((k_force<R, MC, BS>), dim3(h->lat.Nt), dim3(s.nt), lds, h->stream, h->lat,
-                           (const cplx<R>*)X, (const cplx<R>*)Y, gauge_of<R>(h), coef_of<R>(h->p), F);
-        prof_end(h, slot);
+        hipEvent_t e0, e1;
+        if (prof_sample(h, QEDHMC_K_FORCE, e0, e1))
+            hipExtLaunchKernelGGL((k_force<R, MC, BS>), dim3(h->lat.Nt), dim3(s.nt), lds, h->stream, e0, e1, 0,
+                                  h->lat, (const cplx<R>*)X, (const cplx<R>*)Y, gauge_of<R>(h), coef_of<R>(h->p), F);
+        else
+            hipLaunchKernelGGL((k_force<R, MC, BS>), dim3(h->lat.Nt), dim3(s.nt), lds, h->stream, h->lat,
+                               (const cplx<R>*)X, (const cplx<R>*)Y, gauge_of<R>(h), coef_of<R>(h->p), F);
         QH_HIP(hipGetLastError());
         return QEDHMC_OK;
     });

@@ -15,6 +15,7 @@
 // f1 / f3 sweeps exchange values, through LDS.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstdint>
 #include <cstdio>
@@ -244,6 +245,101 @@ __device__ __forceinline__ void apply_B_cells(Cells<R, MC>& c, const cplx<R> (&h
     cross_sweep<R, MC, NB, false>(c, h, g, own, co.c1, xb);
 }
 
+// Two independent cross sweeps (vector a with hops ha, vector b with hops
+// hb) sharing one LDS round trip: a uses the first Vs entries of the buffer
+// and b the next Vs.  Buffers of 2 Vs values alternate as in Xchg (NB = 2) or
+// are closed by a second barrier (NB = 1).
+template <typename R, int MC, int NB, bool X>
+__device__ __forceinline__ void cross_sweep2(Cells<R, MC>& a, const cplx<R> (&ha)[MC][12], Cells<R, MC>& b,
+                                             const cplx<R> (&hb)[MC][12], const CellGeo (&g)[MC],
+                                             const bool (&own)[MC], R cc, cplx<R>* buf2, int Vs, int& k) {
+    cplx<R>* ba = buf2 + (size_t)(NB == 2 ? k : 0) * 2 * Vs;
+    cplx<R>* bb = ba + Vs;
+    k ^= 1;
+#pragma unroll
+    for (int m = 0; m < MC; m++)
+        if (own[m]) {
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                ba[g[m].s[q]] = a.v[m][q];
+                bb[g[m].s[q]] = b.v[m][q];
+            }
+        }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < MC; m++)
+        if (own[m]) {
+            if (X) {
+                sweep_f1(a.v[m], ha[m], cc, ba[g[m].r0], ba[g[m].r2], ba[g[m].l1], ba[g[m].l3]);
+                sweep_f1(b.v[m], hb[m], cc, bb[g[m].r0], bb[g[m].r2], bb[g[m].l1], bb[g[m].l3]);
+            } else {
+                sweep_f3(a.v[m], ha[m], cc, ba[g[m].u0], ba[g[m].u1], ba[g[m].d2], ba[g[m].d3]);
+                sweep_f3(b.v[m], hb[m], cc, bb[g[m].u0], bb[g[m].u1], bb[g[m].d2], bb[g[m].d3]);
+            }
+        }
+    if (NB == 1) __syncthreads();
+}
+
+// B_{tau-1} a and B_tau b applied together (Eq. 24 factor order on both).
+template <typename R, int MC, int NB>
+__device__ __forceinline__ void apply_B2_cells(Cells<R, MC>& a, const cplx<R> (&ha)[MC][12], Cells<R, MC>& b,
+                                               const cplx<R> (&hb)[MC][12], const CellGeo (&g)[MC],
+                                               const bool (&own)[MC], const Coef<R>& co, cplx<R>* buf2, int Vs,
+                                               int& k) {
+    cross_sweep2<R, MC, NB, false>(a, ha, b, hb, g, own, co.c1, buf2, Vs, k);
+#pragma unroll
+    for (int m = 0; m < MC; m++) {
+        sweep_f2(a.v[m], ha[m], co.c1);
+        sweep_f2(b.v[m], hb[m], co.c1);
+    }
+    cross_sweep2<R, MC, NB, true>(a, ha, b, hb, g, own, co.c1, buf2, Vs, k);
+#pragma unroll
+    for (int m = 0; m < MC; m++) {
+        sweep_f0(a.v[m], ha[m], co.c2);
+        sweep_f0(b.v[m], hb[m], co.c2);
+    }
+    cross_sweep2<R, MC, NB, true>(a, ha, b, hb, g, own, co.c1, buf2, Vs, k);
+#pragma unroll
+    for (int m = 0; m < MC; m++) {
+        sweep_f2(a.v[m], ha[m], co.c1);
+        sweep_f2(b.v[m], hb[m], co.c1);
+    }
+    cross_sweep2<R, MC, NB, false>(a, ha, b, hb, g, own, co.c1, buf2, Vs, k);
+}
+
+// Fused M^dag M on the cells of slice tau given the cells of the input at
+// tau-1 (vm), tau (vt), tau+1 (vn) and the hops of slices tau-1 (hm) and tau
+// (ht):
+//   out = vt - eps_{tau-1} B_{tau-1} vm + B_tau (B_tau vt - eps_tau vn),
+// the definition M^dag (M v) expanded with eps^2 = 1 (eps_{Nt-1} = -1 at the
+// antiperiodic corner, +1 elsewhere).  B_{tau-1} vm and B_tau vt run together.
+// vm is consumed.  buf2: LDS of NB * 2 * Vs values.
+template <typename R, int MC, int NB>
+__device__ __forceinline__ void mdagm_cells(Cells<R, MC>& vm, const Cells<R, MC>& vt, const Cells<R, MC>& vn,
+                                            const cplx<R> (&hm)[MC][12], const cplx<R> (&ht)[MC][12],
+                                            const CellGeo (&g)[MC], const bool (&own)[MC], const Coef<R>& co,
+                                            R eps_m, R eps_t, cplx<R>* buf2, int Vs, Cells<R, MC>& out) {
+    int k = 0;
+    Cells<R, MC> t = vt;
+    apply_B2_cells<R, MC, NB>(vm, hm, t, ht, g, own, co, buf2, Vs, k);
+#pragma unroll
+    for (int m = 0; m < MC; m++)
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            out.v[m][q] = cfma(-eps_m, vm.v[m][q], vt.v[m][q]);
+            t.v[m][q] = cfma(-eps_t, vn.v[m][q], t.v[m][q]);
+        }
+    // third B_tau on t: reuse the pair sweep with a dummy second vector
+    // would double the LDS traffic, so use the single-vector form on the
+    // first half of the pair buffers.
+    Xchg<R, NB> xb{buf2, 2 * Vs, k};
+    apply_B_cells<R, MC, NB>(t, ht, g, own, co, xb);
+#pragma unroll
+    for (int m = 0; m < MC; m++)
+#pragma unroll
+        for (int q = 0; q < 4; q++) out.v[m][q] = cadd(out.v[m][q], t.v[m][q]);
+}
+
 template <typename R, int MC>
 __device__ __forceinline__ void load_cells(Cells<R, MC>& c, const cplx<R>* __restrict__ slice, const CellGeo (&g)[MC],
                                            const bool (&own)[MC]) {
@@ -305,12 +401,13 @@ struct qedhmc_ctx {
     const double* gauge_src32;
     // workspace vectors
     void* ws[12];               // general complex FP64-sized vectors
+    void* cg_arena;             // 7 complex FP64-sized vectors of the fused CG (r, s, w ping-pong, p)
     double* theta0;             // saved theta for Metropolis
     double* mom;                // momenta
     double* force;              // total force
     double* force_b;            // bosonic force
-    double* partial;            // per-block partial sums (>= 4 * max blocks)
-    double* scal;               // device scalars
+    double* partial;            // per-block partial sums: [2][Nt][3] for CG, then 2048 more
+    double* scal;               // device scalars: [0,32) CG slots, [64,80) trajectory, [100] action
     double* h_pinned;           // pinned host mirror of a few scalars
     // sampled kernel timing (qedhmc_profile)
     int prof_every;
@@ -319,6 +416,7 @@ struct qedhmc_ctx {
     double prof_ms[QEDHMC_K_COUNT];
     hipEvent_t prof_ev[64][2];
     int prof_cls[64];
+    bool prof_used[64];
     int prof_pending;
     bool prof_ready;
 };
@@ -343,10 +441,10 @@ qedhmc_status hip_fail(hipError_t e, const char* what);
 template <typename R>
 Coef<R> coef_of(const qedhmc_params& p);
 
-// Sampled kernel timing around one launch (api.hip).  prof_begin returns the
-// event slot to close with prof_end, or -1 when this launch is not sampled.
-int prof_begin(qedhmc_ctx* h, int cls);
-void prof_end(qedhmc_ctx* h, int slot);
+// Sampled kernel timing (api.hip).  prof_sample returns true when this launch
+// of class cls is to be timed and hands out the start/stop events to pass to
+// hipExtLaunchKernelGGL, which records them around the dispatch itself.
+bool prof_sample(qedhmc_ctx* h, int cls, hipEvent_t& e0, hipEvent_t& e1);
 qedhmc_status prof_drain(qedhmc_ctx* h);
 
 // Launch helpers implemented in lattice.hip

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqedhmc.so")
 
 OK, EINVAL, ENOCONV, EHIP, ENOMEM, EUNSUPPORTED = range(6)
-K_MDAGM_FP32, K_MDAGM_FP64, K_FORCE = range(3)
+K_MDAGM_FP32, K_MDAGM_FP64, K_FORCE, K_CG_FP32, K_CG_FP64 = range(5)
 FP64, FP32 = 0, 1
 PC_NONE = 0
 

@@ -254,3 +254,35 @@ def test_trajectory_mixed_matches_fp64_at_workload_size():
     assert abs(a["dH"] - b["dH"]) <= 1e-6 * abs(a["H0"])
     assert a["accepted"] == b["accepted"]
     assert _rel(F32, F64) < 1e-6
+
+
+def test_fp64_chain_matches_oracle_golden():
+    """The FP64 workload at L=12, Nt=120: 20 chained trajectories (20 leapfrog
+    steps, CG 1e-10) from pi flux + N(0, 0.3^2), RNG seed 1002, against the
+    oracle's chain stored in tests/golden/fp64_l12_trajectories.json (written
+    by tests/golden/make_fp64_l12_golden.py from the oracle alone).  dH per
+    trajectory within 1e-4 (the CG tolerance bounds the solution error to
+    ~1e-8 relative; the MD amplifies it over 20 steps), identical accept /
+    reject decisions, identical chain (theta checksums)."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "fp64_l12_trajectories.json")))
+    wl = inputs.WORKLOADS["fp64_l12"]
+    assert (gold["L"], gold["Nt"], gold["seed"], gold["theta_seed"]) == (wl.L, wl.Nt, wl.seed, wl.theta_seed)
+    th = _dev(wl.initial_theta())
+    worst = 0.0
+    with Q.Lattice(wl.L, wl.Nt, seed=wl.seed) as lat:
+        for k, ref in enumerate(gold["trajectories"]):
+            r = lat.hmc_trajectory(th, traj=k, n_steps=wl.n_steps, traj_len=wl.traj_len, tol=wl.tol, prec="fp64")
+            thh = _host(th)
+            d = abs(r["dH"] - ref["dH"])
+            worst = max(worst, d)
+            print(k, f"dH gpu {r['dH']:.9f} oracle {ref['dH']:.9f} |diff| {d:.2e} acc {r['accepted']} "
+                  f"{ref['accepted']} iters {r['cg_iters_total']} {ref['cg_iters_total']}", flush=True)
+            assert r["status"] == 0 and r["max_true_resid"] <= wl.tol
+            assert r["u"] == pytest.approx(ref["u"], abs=1e-15)
+            assert d <= 1e-4, (k, r["dH"], ref["dH"])
+            assert r["accepted"] == ref["accepted"], k
+            assert abs(thh.sum() - ref["theta_sum"]) <= 1e-9 * abs(ref["theta_sumsq"]) ** 0.5 * thh.size ** 0.5
+            assert abs((thh ** 2).sum() - ref["theta_sumsq"]) <= 1e-8 * ref["theta_sumsq"]
+    print("worst |dH gpu - dH oracle| =", worst, flush=True)
