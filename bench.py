@@ -9,10 +9,16 @@ relative residual 1e-8, mixed precision (complex-FP32 matvecs and force, FP64
 solution, reliable updates and reductions).  One step = one trajectory of the
 chain: heat bath, 21 solves, 21 forces, leapfrog, Metropolis.
 
-Prints one JSON line.  The roofline block is for the dominant kernel (the
-fused FP32 M^dag M): algorithmic bytes per launch = 24 B per site (v in, out
-written, one FP32 angle per bond) / its average duration, timed with HIP
-events on the handle's stream over the timed region (every 8th launch).
+Prints one JSON line.  The roofline block is for the dominant kernel, the
+fused CG iteration k_cg_iter (one launch per iteration: recurrences, x update,
+M^dag M, inner products).  Its algorithmic bytes per site are, in the mixed
+path, r, w, s, p read (4 x 8 B), two FP32 angles (8 B), x read and written
+(2 x 16 B, FP64) and r, s, p, w written (4 x 8 B): 104 B per site (176 B in
+FP64).  Its duration is the start/end event pair of every 8th dispatch
+(hipExtLaunchKernelGGL) over the timed region.  The metric's M^dag M
+bandwidth is measured after the timed region on the standalone fused
+M^dag M kernel at 24 B per site (v in, out written, two FP32 angles; 48 B in
+FP64), 200 back-to-back launches, every dispatch timed the same way.
 The CPU baseline is the plain FP64 oracle on a bounded sample (a fixed
 number of CG iterations plus one force at the same lattice), scaled to the
 trajectory's measured CG iteration count.
@@ -110,15 +116,29 @@ def main():
         traj += 1
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    kcls = Q.K_MDAGM_FP32 if prec != "fp64" else Q.K_MDAGM_FP64
+    kcls = Q.K_CG_FP32 if prec != "fp64" else Q.K_CG_FP64
     n_k, ms_k = lat.profile_read(kcls)
     lat.profile(0)
 
+    # standalone fused M^dag M on the same lattice (the metric's matvec)
+    cdt = torch.complex64 if prec != "fp64" else torch.complex128
+    vin = torch.from_numpy(inputs.gauss_cvec(wl.L, wl.Nt, 99)).to(cdt).cuda()
+    vout = torch.empty_like(vin)
+    mv_prec = "fp32" if prec != "fp64" else "fp64"
+    lat.apply_MdagM(theta, vin, prec=mv_prec, out=vout)
+    lat.profile(1)
+    for _ in range(200):
+        lat.apply_MdagM(theta, vin, prec=mv_prec, out=vout)
+    n_mv, ms_mv = lat.profile_read(Q.K_MDAGM_FP32 if prec != "fp64" else Q.K_MDAGM_FP64)
+    lat.profile(0)
+
     N = wl.L * wl.L * wl.Nt
-    bytes_per_site = 24 if prec != "fp64" else 48
-    alg_bytes = bytes_per_site * N
+    mv_bytes = (24 if prec != "fp64" else 48) * N
+    mv_us = 1e3 * ms_mv / max(n_mv, 1)
+    mv_gbs = mv_bytes / (mv_us * 1e-6) / 1e9 if n_mv else None
+    it_bytes = (104 if prec != "fp64" else 176) * N
     avg_ms = ms_k / max(n_k, 1)
-    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9 if n_k else None
+    achieved = it_bytes / (avg_ms * 1e-3) / 1e9 if n_k else None
     s_per_traj = elapsed / a.steps
     cg_total = sum(r["cg_iters_total"] for r in results) // a.steps
     n_solves = results[-1]["n_solves"]
@@ -143,19 +163,22 @@ def main():
             "L": wl.L, "Nt": wl.Nt, "sites": N, "n_steps": wl.n_steps, "tol": wl.tol,
             "precision": prec,
         },
-        "matvec_gbs": achieved,
+        "matvec_gbs": mv_gbs,
+        "matvec": {"kernel": f"k_mdagm<{'float' if prec != 'fp64' else 'double'}> (standalone fused M^dag M)",
+                   "avg_launch_us": mv_us, "alg_bytes_per_launch": mv_bytes, "gbs": mv_gbs,
+                   "frac_of_hbm_peak": (mv_gbs / HBM_PEAK_GBS) if mv_gbs else None, "launches": n_mv},
         "cg_iters_per_traj": cg_total,
         "traj": [{k: r[k] for k in ("dH", "accepted", "cg_iters_total", "cg_iters_max",
                                     "reliable_updates", "max_true_resid", "status")} for r in results],
         "roofline": {
             "bound": "hbm",
-            "kernel": f"k_mdagm<{'float' if prec != 'fp64' else 'double'}> (fused M^dag M)",
+            "kernel": f"k_cg_iter<{'float' if prec != 'fp64' else 'double'}> (one fused CG iteration)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
             "traffic": None,
-            "alg_bytes_per_launch": alg_bytes,
+            "alg_bytes_per_launch": it_bytes,
             "avg_launch_us": avg_ms * 1e3,
             "timed_launches": n_k,
         },

@@ -102,7 +102,7 @@ qedhmc_status qedhmc_init_lattice(const qedhmc_params* params, void* stream, qed
     ok = ok && hipMalloc(&h->mom, 2 * N * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc(&h->force, 2 * N * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc(&h->force_b, 2 * N * sizeof(double)) == hipSuccess;
-    ok = ok && hipMalloc(&h->partial, ((size_t)6 * p.Nt + 4096) * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc(&h->partial, ((size_t)12 * p.Nt + 4096) * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc(&h->scal, 128 * sizeof(double)) == hipSuccess;
     ok = ok && hipHostMalloc(&h->h_pinned, 64 * sizeof(double), hipHostMallocDefault) == hipSuccess;
     if (!ok) {

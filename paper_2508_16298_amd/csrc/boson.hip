@@ -67,7 +67,7 @@ __global__ void k_bosonic(Lat lt, double J, double K, double dtau, const double*
 }
 
 qedhmc_status launch_bosonic(qedhmc_ctx* h, const double* theta, double* F_B, double* S_dev) {
-    double* part = (h->partial + h->lat.Nt + 1024);
+    double* part = (h->partial + 12 * (size_t)h->lat.Nt);
     hipLaunchKernelGGL(k_bosonic, dim3(kGridR), dim3(kBlockR), 0, h->stream, h->lat, h->p.J, h->p.K, h->p.dtau, theta,
                        F_B, part);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, h->stream, (const double*)part, kGridR, S_dev);
@@ -159,7 +159,7 @@ __global__ void k_dot(const double* __restrict__ a, const double* __restrict__ b
 
 // Re <a, b> of complex vectors = sum over the interleaved reals of a*b (n reals)
 qedhmc_status launch_dot_re(qedhmc_ctx* h, const double* a, const double* b, size_t n, double* out_dev) {
-    double* part = (h->partial + h->lat.Nt + 1024);
+    double* part = (h->partial + 12 * (size_t)h->lat.Nt);
     hipLaunchKernelGGL(k_dot, dim3(kGridR), dim3(kBlockR), 0, h->stream, a, b, n, part);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, h->stream, (const double*)part, kGridR, out_dev);
     QH_HIP(hipGetLastError());

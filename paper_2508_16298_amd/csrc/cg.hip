@@ -1,14 +1,23 @@
 // Conjugate gradient on O = M^dag M (Methods, Eq. pCG), started from x = 0,
 // one kernel launch per iteration.
 //
-// The recursion is CG in the Chronopoulos-Gear form (one global reduction
-// phase per iteration, both inner products together):
+// The recursion is CG with a single global reduction phase per iteration
+// (the Chronopoulos-Gear arrangement: s = O p carried as a recurrence):
 //   beta_i  = gamma_i / gamma_{i-1}            (0 on the first iteration)
-//   alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1})
 //   p_i = r_i + beta_i p_{i-1},  s_i = w_i + beta_i s_{i-1}     (s = O p)
+//   alpha_i = gamma_i / <p_i, s_i>
 //   x_{i+1} = x_i + alpha_i p_i,  r_{i+1} = r_i - alpha_i s_i
-//   w_{i+1} = O r_{i+1},  gamma_{i+1} = <r,r>,  delta_{i+1} = <w,r>
-// mathematically the same iterates as Eq. pCG without preconditioner.
+//   w_{i+1} = O r_{i+1}
+// mathematically the same iterates as Eq. pCG without preconditioner.  The
+// denominator is expanded over vectors the previous launch already holds,
+//   <p_i, s_i> = <r_i,w_i> + beta_i (<r_i,s_{i-1}> + <p_{i-1},w_i>)
+//                + beta_i^2 <p_{i-1},s_{i-1}>,
+// so one launch computes all five inner products of the next iteration
+// together.  (The textbook Chronopoulos-Gear denominator
+// delta - beta gamma / alpha_{i-1} leans on an orthogonality identity that
+// FP32 rounding breaks: in emulation it needed 15-23% more iterations and
+// diverged on ill-conditioned systems, while the expansion tracks the
+// two-reduction form iteration for iteration.)
 // A launch boundary is the only grid-wide synchronisation: every workgroup
 // (one per time slice) reduces the per-slice partials of the previous launch
 // in a fixed order (bitwise reproducible), recomputes the recurrences on the
@@ -52,6 +61,9 @@ enum {
     S_GCUR = 10,   // gamma_i of the current state
     S_NSLOT = 16,
 };
+// Per-slice partials of one parity: <r,r>, <w,r>, <r,s>, <p,w>, <p,s>, aux
+// (aux: |rhs|^2 from the start kernel, the FP64 true |r|^2 from a reliable update)
+static constexpr int kNP = 6;
 static constexpr double kDecade2 = 0.01;  // pause when gamma fell by 10^2 (|r| by 10)
 static constexpr int kCap = 50;           // ... or after 50 iterations
 
@@ -64,57 +76,56 @@ struct CgBufs {
     cplx<double>* x;
     const cplx<double>* rhs;
     const cplx<double>* Ox;  // FP64 O x for the true residual
-    double* part;            // [2][Nt][3] per-slice partials (gamma, delta, aux)
+    double* part;            // [2][Nt][kNP] per-slice partials, see kNP
 };
 
-// Block reduction of three doubles in a fixed order; result valid in thread 0.
-__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* red) {
-    for (int off = 32; off > 0; off >>= 1) {
-        a += __shfl_xor(a, off, 64);
-        b += __shfl_xor(b, off, 64);
-        c += __shfl_xor(c, off, 64);
-    }
+// Block reduction of K doubles in a fixed order; result valid in thread 0.
+// red: LDS scratch of at least K * 16 doubles.
+template <int K>
+__device__ __forceinline__ void block_sumk(double (&v)[K], double* red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < K; k++) v[k] += __shfl_xor(v[k], off, 64);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     __syncthreads();
-    if (lane == 0) {
-        red[3 * wv] = a;
-        red[3 * wv + 1] = b;
-        red[3 * wv + 2] = c;
-    }
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < K; k++) red[K * wv + k] = v[k];
     __syncthreads();
     if (threadIdx.x == 0) {
         const int nw = (blockDim.x + 63) >> 6;
-        double sa = 0, sb = 0, sc = 0;
-        for (int k = 0; k < nw; k++) {
-            sa += red[3 * k];
-            sb += red[3 * k + 1];
-            sc += red[3 * k + 2];
-        }
-        a = sa;
-        b = sb;
-        c = sc;
+#pragma unroll
+        for (int k = 0; k < K; k++) v[k] = 0.0;
+        for (int w = 0; w < nw; w++)
+#pragma unroll
+            for (int k = 0; k < K; k++) v[k] += red[K * w + k];
     }
 }
 
-// Sum of the Nt partial triples of one parity, broadcast to every thread.
+// Sum of the Nt partial tuples of one parity, broadcast to every thread.
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int Nt, double* red, double* bc,
-                                                double& g, double& d, double& aux) {
-    double a = 0, b = 0, c = 0;
-    for (int t = threadIdx.x; t < Nt; t += blockDim.x) {
-        a += part[3 * t];
-        b += part[3 * t + 1];
-        c += part[3 * t + 2];
-    }
-    block_sum3(a, b, c, red);
-    if (threadIdx.x == 0) {
-        bc[0] = a;
-        bc[1] = b;
-        bc[2] = c;
-    }
+                                                double (&out)[kNP]) {
+    double v[kNP];
+#pragma unroll
+    for (int k = 0; k < kNP; k++) v[k] = 0.0;
+    for (int t = threadIdx.x; t < Nt; t += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < kNP; k++) v[k] += part[kNP * t + k];
+    block_sumk<kNP>(v, red);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < kNP; k++) bc[k] = v[k];
     __syncthreads();
-    g = bc[0];
-    d = bc[1];
-    aux = bc[2];
+#pragma unroll
+    for (int k = 0; k < kNP; k++) out[k] = bc[k];
+}
+
+__device__ __forceinline__ void write_partials(double* __restrict__ pt, double (&v)[kNP], double* red) {
+    block_sumk<kNP>(v, red);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < kNP; k++) pt[k] = v[k];
 }
 
 template <typename R, int MC>
@@ -222,14 +233,8 @@ __global__ __launch_bounds__(BS) void k_cg_start(Lat lt, CgBufs<R> B, const cplx
     mdagm_cells<R, MC, NB>(vm, vt, vn, hm, ht, c.g, c.own, co, c.tau == 0 ? R(-1) : R(1),
                            c.tau == lt.Nt - 1 ? R(-1) : R(1), buf2, lt.Vs, w);
     store_cells<R, MC>(w, B.w[0] + c.tau * Vs, c.g, c.own);
-    double gg = dot_cells<R, MC>(r0, r0, c.own), dd = dot_cells<R, MC>(w, r0, c.own);
-    block_sum3(gg, dd, b2, red);
-    if (threadIdx.x == 0) {
-        double* pt = B.part + 3 * (size_t)c.tau;  // parity 0
-        pt[0] = gg;
-        pt[1] = dd;
-        pt[2] = b2;
-    }
+    double v[kNP] = {dot_cells<R, MC>(r0, r0, c.own), dot_cells<R, MC>(w, r0, c.own), 0.0, 0.0, 0.0, b2};
+    write_partials(B.part + kNP * (size_t)c.tau, v, red);  // parity 0
     if (blockIdx.x == 0 && threadIdx.x < S_NSLOT) {
         double v = 0.0;
         if (threadIdx.x == S_FIRST) v = 1.0;
@@ -248,7 +253,7 @@ __global__ __launch_bounds__(BS) void k_cg_iter(Lat lt, CgBufs<R> B, const cplx<
     extern __shared__ __align__(16) unsigned char smem[];
     cplx<R>* buf2 = reinterpret_cast<cplx<R>*>(smem);
     double* red = reinterpret_cast<double*>(smem + (size_t)NB * 2 * lt.Vs * sizeof(cplx<R>));
-    double* bc = red + 64;
+    double* bc = red + kNP * 16;
     const double* sin_ = scal + S_NSLOT * kpar;
     double* sout = scal + S_NSLOT * (kpar ^ 1);
     if (sin_[S_DONE] != 0.0) {
@@ -277,8 +282,9 @@ __global__ __launch_bounds__(BS) void k_cg_iter(Lat lt, CgBufs<R> B, const cplx<
     hops_of<R, MC>(gauge, lt, c.tm, c.idx, co, hm);
     hops_of<R, MC>(gauge, lt, c.tau, c.idx, co, ht);
 
-    double gam, del, aux;
-    reduce_partials(B.part + 3 * (size_t)lt.Nt * ip, lt.Nt, red, bc, gam, del, aux);
+    double pr[kNP];
+    reduce_partials(B.part + kNP * (size_t)lt.Nt * ip, lt.Nt, red, bc, pr);
+    const double gam = pr[0], del = pr[1], aux = pr[5];
     double b2 = sin_[S_B2], target = sin_[S_TARGET], rrupd = sin_[S_RRUPD];
     if (b2 < 0.0) {  // first iteration of the solve: the start kernel left |rhs|^2 partials in aux
         b2 = aux;
@@ -306,7 +312,7 @@ __global__ __launch_bounds__(BS) void k_cg_iter(Lat lt, CgBufs<R> B, const cplx<
     }
     const bool first = sin_[S_FIRST] != 0.0;
     const double beta = first ? 0.0 : gam / sin_[S_GPREV];
-    const double den = first ? del : del - beta * gam / sin_[S_APREV];  // <p_i, O p_i>
+    const double den = first ? del : del + beta * (pr[2] + pr[3]) + beta * beta * pr[4];  // <p_i, s_i>
     if (!(den > 0.0)) {
         if (blockIdx.x == 0 && threadIdx.x < S_NSLOT) {
             double v = sin_[threadIdx.x];
@@ -355,14 +361,10 @@ __global__ __launch_bounds__(BS) void k_cg_iter(Lat lt, CgBufs<R> B, const cplx<
     mdagm_cells<R, MC, NB>(rm, rt, rn, hm, ht, c.g, c.own, co, c.tau == 0 ? R(-1) : R(1),
                            c.tau == lt.Nt - 1 ? R(-1) : R(1), buf2, lt.Vs, w);
     store_cells<R, MC>(w, B.w[nx] + c.tau * Vs, c.g, c.own);
-    double gg = dot_cells<R, MC>(rnew, rnew, c.own), dd = dot_cells<R, MC>(w, rnew, c.own), zz = 0.0;
-    block_sum3(gg, dd, zz, red);
-    if (threadIdx.x == 0) {
-        double* pt = B.part + 3 * ((size_t)lt.Nt * nx + c.tau);
-        pt[0] = gg;
-        pt[1] = dd;
-        pt[2] = 0.0;
-    }
+    double v[kNP] = {dot_cells<R, MC>(rnew, rnew, c.own), dot_cells<R, MC>(w, rnew, c.own),
+                     dot_cells<R, MC>(rnew, st, c.own), dot_cells<R, MC>(pp, w, c.own),
+                     dot_cells<R, MC>(pp, st, c.own), 0.0};
+    write_partials(B.part + kNP * ((size_t)lt.Nt * nx + c.tau), v, red);
     if (blockIdx.x == 0 && threadIdx.x < S_NSLOT) {
         double v = sin_[threadIdx.x];
         if (threadIdx.x == S_GPREV) v = gam;
@@ -414,14 +416,10 @@ __global__ __launch_bounds__(BS) void k_cg_replace(Lat lt, CgBufs<R> B, const cp
     __syncthreads();  // LDS exchange buffers are reused
     mdagm_cells<R, MC, NB>(pm, pt_, pn, hm, ht, c.g, c.own, co, em, et, buf2, lt.Vs, sp);
     store_cells<R, MC>(sp, B.s[ip] + c.tau * Vs, c.g, c.own);
-    double gg = dot_cells<R, MC>(r0, r0, c.own), dd = dot_cells<R, MC>(w, r0, c.own);
-    block_sum3(gg, dd, t2, red);
-    if (threadIdx.x == 0) {
-        double* pt = B.part + 3 * ((size_t)lt.Nt * ip + c.tau);
-        pt[0] = gg;
-        pt[1] = dd;
-        pt[2] = t2;
-    }
+    double v[kNP] = {dot_cells<R, MC>(r0, r0, c.own), dot_cells<R, MC>(w, r0, c.own),
+                     dot_cells<R, MC>(r0, sp, c.own), dot_cells<R, MC>(pt_, w, c.own),
+                     dot_cells<R, MC>(pt_, sp, c.own), t2};
+    write_partials(B.part + kNP * ((size_t)lt.Nt * ip + c.tau), v, red);
 }
 
 // After k_cg_replace: true |r|^2 into the slot; converged -> stop flag 1;
@@ -429,16 +427,12 @@ __global__ __launch_bounds__(BS) void k_cg_replace(Lat lt, CgBufs<R> B, const cp
 // iteration, the FP64 path's p = r).
 __global__ void k_cg_check(double* __restrict__ scal, int kpar, const double* __restrict__ part, int Nt,
                            int restart) {
-    __shared__ double red[64];
+    __shared__ double red[kNP * 16 + 16];
     double* sl = scal + S_NSLOT * kpar;
     const int ip = ((int)sl[S_ITERS]) & 1;
-    const double* pt = part + 3 * (size_t)Nt * ip;
-    double a = 0, b = 0, c = 0;
-    for (int t = threadIdx.x; t < Nt; t += blockDim.x) {
-        a += pt[3 * t];
-        c += pt[3 * t + 2];
-    }
-    block_sum3(a, b, c, red);
+    double pr[kNP];
+    reduce_partials(part + kNP * (size_t)Nt * ip, Nt, red, red + kNP * 16, pr);
+    const double a = pr[0], c = pr[5];
     if (threadIdx.x == 0) {
         sl[S_TRUE] = c;
         if (c <= sl[S_TARGET]) {
@@ -488,7 +482,7 @@ static qedhmc_status with_shape(qedhmc_ctx* h, F&& f) {
     const int mc = lt.ncell <= 1024 ? 1 : 2;
     int nt = ((((lt.ncell + mc - 1) / mc) + 63) / 64) * 64;
     if (nt < 64) nt = 64;
-    const size_t red = 128 * sizeof(double);
+    const size_t red = (kNP * 16 + 16) * sizeof(double);
     const bool two = 4 * (size_t)lt.Vs * sizeof(cplx<R>) + red <= h->max_lds;
     auto go = [&]<int MC, int BS>() -> qedhmc_status {
         if (two) return f.template operator()<MC, 2, BS>(nt, 4 * (size_t)lt.Vs * sizeof(cplx<R>) + red);

@@ -406,7 +406,7 @@ struct qedhmc_ctx {
     double* mom;                // momenta
     double* force;              // total force
     double* force_b;            // bosonic force
-    double* partial;            // per-block partial sums: [2][Nt][3] for CG, then 2048 more
+    double* partial;            // per-block partial sums: [2][Nt][6] for CG, then 4096 more
     double* scal;               // device scalars: [0,32) CG slots, [64,80) trajectory, [100] action
     double* h_pinned;           // pinned host mirror of a few scalars
     // sampled kernel timing (qedhmc_profile)
