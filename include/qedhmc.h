@@ -73,7 +73,12 @@ typedef enum {
  * FP64 reductions. */
 typedef enum { QEDHMC_FP64 = 0, QEDHMC_FP32 = 1 } qedhmc_precision;
 
-typedef enum { QEDHMC_PC_NONE = 0 } qedhmc_precond;
+/* Preconditioner of the CG solve.  QEDHMC_PC_PAPER: the paper's fixed
+ * preconditioner P = G^dag G (Methods, "CG method and preconditioner";
+ * Fig. 3): G the truncated inverse of the forward IC(0) factor of M^dag M at
+ * pi flux on an 8 x 8 x 24 build lattice (0 <= dtau <= 6, |g| >= 1e-3),
+ * tiled over the lattice per x parity; built on first use. */
+typedef enum { QEDHMC_PC_NONE = 0, QEDHMC_PC_PAPER = 1 } qedhmc_precond;
 
 /* Lattice, couplings and the seed of the trajectory random streams.
  * L even, 2 <= L <= 90; Nt >= 1. */
@@ -140,6 +145,19 @@ qedhmc_status qedhmc_cg_solve(qedhmc_t h, const double *theta,
                               qedhmc_precond pc, int32_t *iters,
                               double *true_rel_resid);
 
+/* The paper's preconditioner stencil for x parity 0 or 1 (built on first
+ * use): up to capacity taps into host double out[capacity][5] as
+ * (dtau, dx, dy, Re g, Im g), meaning G[(tau,x,y),(tau-dtau, x+dx, y+dy)] = g
+ * for rows of that parity (times -1 when tau - dtau wraps below 0); *count
+ * receives the number of taps.  Methods, "CG method and preconditioner". */
+qedhmc_status qedhmc_precond_taps(qedhmc_t h, int32_t parity, int32_t *count,
+                                  double *out, int32_t capacity);
+
+/* out = P in = G^dag (G in) with the paper's preconditioner; in/out device
+ * complex vectors of the given precision; must not alias. */
+qedhmc_status qedhmc_apply_precond(qedhmc_t h, const void *in, void *out,
+                                   qedhmc_precision prec);
+
 /* F = -dS_F/dtheta with S_F = eta^dag (M^dag M)^{-1} eta, given the solve
  * X = (M^dag M)^{-1} eta (SM SI):  F_{b,tau} = 2 Re[Yt_tau^dag dB_tau X_tau],
  * Y = M X, Yt_tau = -Y_{tau+1} (tau < Nt-1), Yt_{Nt-1} = +Y_0.
@@ -186,7 +204,9 @@ typedef enum {
     QEDHMC_K_FORCE = 2,        /* fermion force kernel (either precision) */
     QEDHMC_K_CG_FP32 = 3,      /* one fused CG iteration (M^dag M + updates), FP32 */
     QEDHMC_K_CG_FP64 = 4,      /* one fused CG iteration, FP64 */
-    QEDHMC_K_COUNT = 5
+    QEDHMC_K_PCG_MV_FP32 = 5,  /* M^dag M + inner products of a PCG iteration, FP32 */
+    QEDHMC_K_PCG_MV_FP64 = 6,  /* the same, FP64 */
+    QEDHMC_K_COUNT = 7
 } qedhmc_kernel_class;
 
 qedhmc_status qedhmc_profile(qedhmc_t h, int32_t every);

@@ -12,8 +12,9 @@ the reading followed here, step by step:
 1. O_pi = M^dag M on a small build lattice L0 x L0 x Nt0 at pi flux
    (theta_x = 0, theta_y = pi x: flux pi through every plaquette).
 2. Forward IC(0) in the natural order n = tau*Vs + s: O_pi ~ L L^dag with L
-   lower triangular on the sparsity pattern of O_pi (a diagonal shift of the
-   matrix when a pivot is not positive).
+   lower triangular on the sparsity pattern of O_pi, the entries with
+   |O| > 1e-12 max|O| (a diagonal shift of the matrix when a pivot is not
+   positive).
 3. G = L^{-1} exactly, by triangular solves (the series is meant to
    approximate this).
 4. From an interior site of a bulk slice, one per x parity (the pi-flux unit
@@ -41,7 +42,7 @@ def ic0_forward(A):
     triangular on the lower pattern of A.  Returns (L, shift) where shift is
     the diagonal shift (fraction of diag(A)) that made every pivot positive."""
     n = A.shape[0]
-    pattern = np.abs(A) > 0
+    pattern = np.abs(A) > 1e-12 * np.abs(A).max()
     shift = 0.0
     while True:
         As = A + shift * np.diag(np.diag(A))
@@ -62,6 +63,8 @@ def ic0_forward(A):
         if ok:
             return L, shift
         shift = 1e-3 if shift == 0.0 else 2 * shift
+        if shift > 1.0:
+            raise ValueError("IC(0) pivots stay non-positive")
 
 
 def build_stencil(L0=8, Nt0=24, dtau=0.1, t=1.0, cap=6, thresh=1e-3, tau0=None):
@@ -121,11 +124,18 @@ def apply_P(taps, r):
 
 
 def dense_G(taps, L, Nt):
-    N = L * L * Nt
+    """G as a dense matrix, scattered entry by entry from the taps (a second,
+    loop-based reading of the definition used by apply_G)."""
+    Vs = L * L
+    N = Vs * Nt
     G = np.zeros((N, N), dtype=complex)
-    e = np.zeros((Nt, L, L), dtype=complex)
-    for k in range(N):
-        e[:] = 0
-        e.reshape(-1)[k] = 1
-        G[:, k] = apply_G(taps, e).reshape(-1)
+    for tau in range(Nt):
+        for y in range(L):
+            for x in range(L):
+                row = tau * Vs + y * L + x
+                for dt, dx, dy, g in taps[x % 2]:
+                    ts = tau - dt
+                    sign = -1.0 if ts < 0 else 1.0
+                    col = (ts % Nt) * Vs + ((y + dy) % L) * L + (x + dx) % L
+                    G[row, col] += sign * g
     return G

@@ -72,9 +72,8 @@ qedhmc_status qedhmc_init_lattice(const qedhmc_params* params, void* stream, qed
         return einval("bad couplings (need dtau >= 0, J > 0, finite t and K)");
     if ((size_t)p.L * p.L * p.Nt >= ((size_t)1 << 31)) return einval("lattice too large");
     *out = nullptr;
-    qedhmc_ctx* h = new (std::nothrow) qedhmc_ctx;
+    qedhmc_ctx* h = new (std::nothrow) qedhmc_ctx{};
     if (!h) return QEDHMC_ENOMEM;
-    std::memset(h, 0, sizeof(*h));
     h->p = p;
     h->lat.L = p.L;
     h->lat.Nt = p.Nt;
@@ -132,6 +131,8 @@ qedhmc_status qedhmc_destroy(qedhmc_t h) {
     (void)hipFree(h->gauge32);
     for (int k = 0; k < 12; k++) (void)hipFree(h->ws[k]);
     (void)hipFree(h->cg_arena);
+    if (h->pc_dev64) (void)hipFree(h->pc_dev64);
+    if (h->pc_dev32) (void)hipFree(h->pc_dev32);
     (void)hipFree(h->theta0);
     (void)hipFree(h->mom);
     (void)hipFree(h->force);
@@ -224,12 +225,14 @@ qedhmc_status qedhmc_apply_MdagM(qedhmc_t h, const double* theta, const void* in
 }
 
 static qedhmc_status solve_at(qedhmc_ctx* h, const double* theta, const double* rhs, double* x, double tol,
-                              int32_t maxit, qedhmc_precision prec, int32_t* iters, double* rel, int* nrel) {
+                              int32_t maxit, qedhmc_precision prec, qedhmc_precond pc, int32_t* iters, double* rel,
+                              int* nrel) {
     QH_TRY(ensure_gauge(h, theta, QEDHMC_FP64));
     if (prec != QEDHMC_FP64) QH_TRY(ensure_gauge(h, theta, prec));
     int it = 0, nr = 0;
     double r = 0.0;
-    const qedhmc_status st = cg_solve_impl(h, rhs, x, tol, maxit, prec, &it, &r, &nr);
+    const qedhmc_status st = pc == QEDHMC_PC_PAPER ? pcg_solve_impl(h, rhs, x, tol, maxit, prec, &it, &r, &nr)
+                                                   : cg_solve_impl(h, rhs, x, tol, maxit, prec, &it, &r, &nr);
     if (iters) *iters = it;
     if (rel) *rel = r;
     if (nrel) *nrel = nr;
@@ -245,9 +248,34 @@ qedhmc_status qedhmc_cg_solve(qedhmc_t h, const double* theta, const double* rhs
     if (!theta || !rhs || !x) return einval("null pointer");
     if (rhs == x) return einval("rhs and x alias");
     if (!(tol > 0.0) || maxit < 1) return einval("need tol > 0 and maxit >= 1");
-    if (pc != QEDHMC_PC_NONE) return einval("unknown preconditioner");
+    if (pc != QEDHMC_PC_NONE && pc != QEDHMC_PC_PAPER) return einval("unknown preconditioner");
     QH_TRY(check_prec(prec));
-    return solve_at(h, theta, rhs, x, tol, maxit, prec, iters, true_rel_resid, nullptr);
+    return solve_at(h, theta, rhs, x, tol, maxit, prec, pc, iters, true_rel_resid, nullptr);
+}
+
+qedhmc_status qedhmc_precond_taps(qedhmc_t h, int32_t parity, int32_t* count, double* out, int32_t capacity) {
+    CHECK_H(h);
+    if (!count || (parity != 0 && parity != 1) || capacity < 0 || (capacity > 0 && !out))
+        return einval("bad stencil query");
+    QH_TRY(ensure_paper_precond(h));
+    const auto& t = h->pc_taps[parity];
+    *count = (int32_t)t.size();
+    for (int32_t k = 0; k < capacity && k < (int32_t)t.size(); k++) {
+        out[5 * k] = t[k].dt;
+        out[5 * k + 1] = t[k].dx;
+        out[5 * k + 2] = t[k].dy;
+        out[5 * k + 3] = t[k].gre;
+        out[5 * k + 4] = t[k].gim;
+    }
+    return QEDHMC_OK;
+}
+
+qedhmc_status qedhmc_apply_precond(qedhmc_t h, const void* in, void* out, qedhmc_precision prec) {
+    CHECK_H(h);
+    if (!in || !out) return einval("null pointer");
+    if (in == out) return einval("in and out alias");
+    QH_TRY(check_prec(prec));
+    return launch_apply_precond(h, prec, in, out);
 }
 
 qedhmc_status qedhmc_fermion_force(qedhmc_t h, const double* theta, const double* X, double* F,
@@ -283,7 +311,7 @@ qedhmc_status qedhmc_hmc_trajectory(qedhmc_t h, double* theta, uint64_t traj, in
     CHECK_H(h);
     if (!theta || !out) return einval("null pointer");
     if (n_steps < 1 || !(traj_len > 0.0) || !(tol > 0.0) || maxit < 1) return einval("bad trajectory parameters");
-    if (pc != QEDHMC_PC_NONE) return einval("unknown preconditioner");
+    if (pc != QEDHMC_PC_NONE && pc != QEDHMC_PC_PAPER) return einval("unknown preconditioner");
     QH_TRY(check_prec(prec));
     std::memset(out, 0, sizeof(*out));
     const size_t N = nsites(h), nb = 2 * N;
@@ -298,7 +326,7 @@ qedhmc_status qedhmc_hmc_trajectory(qedhmc_t h, double* theta, uint64_t traj, in
         int32_t it = 0;
         double rel = 0.0;
         int nr = 0;
-        const qedhmc_status st = solve_at(h, th, eta, X, tol, maxit, prec, &it, &rel, &nr);
+        const qedhmc_status st = solve_at(h, th, eta, X, tol, maxit, prec, pc, &it, &rel, &nr);
         if (st != QEDHMC_OK && st != QEDHMC_ENOCONV) return st;
         if (st == QEDHMC_ENOCONV) worst = 2;
         out->n_solves++;

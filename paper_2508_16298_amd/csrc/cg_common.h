@@ -1,0 +1,207 @@
+// Device and host helpers shared by the CG solvers (cg.hip, pcg.hip).
+#pragma once
+#include <cmath>
+#include <cstdlib>
+
+#include "qedhmc_internal.h"
+
+namespace qh {
+
+// Scalar slot layout (two slots of 16 doubles, by launch parity)
+enum {
+    S_GPREV = 0,   // gamma_{i-1}
+    S_APREV = 1,   // alpha_{i-1}
+    S_ITERS = 2,   // completed iterations i
+    S_DONE = 3,    // 0 running, 1 stop (target reached / converged), 2 pause for a reliable update,
+                   // 3 pause with restart (non-positive <p, O p>), 4 breakdown (non-finite)
+    S_FIRST = 4,   // 1: next iteration starts a new direction sequence (beta = 0)
+    S_B2 = 5,      // |rhs|^2 (FP64); < 0 until the first iteration sets it
+    S_TARGET = 6,  // tol^2 |rhs|^2
+    S_RRUPD = 7,   // gamma at the last reliable update
+    S_ITUPD = 8,   // iteration of the last reliable update
+    S_TRUE = 9,    // last FP64 true |r|^2
+    S_GCUR = 10,   // gamma_i of the current state
+    S_NSLOT = 16,
+};
+// Per-slice partials of one parity: <r,r>, <w,r>, <r,s>, <p,w>, <p,s>, aux
+// (aux: |rhs|^2 from the start kernel, the FP64 true |r|^2 from a reliable update)
+static constexpr int kNP = 6;
+static constexpr double kDecade2 = 0.01;  // pause when gamma fell by 10^2 (|r| by 10)
+static constexpr int kCap = 50;           // ... or after 50 iterations
+
+template <typename R>
+struct CgBufs {
+    cplx<R>* r[2];
+    cplx<R>* s[2];
+    cplx<R>* w[2];
+    cplx<R>* p;
+    cplx<double>* x;
+    const cplx<double>* rhs;
+    const cplx<double>* Ox;  // FP64 O x for the true residual
+    double* part;            // [2][Nt][kNP] per-slice partials, see kNP
+};
+
+// Block reduction of K doubles in a fixed order; result valid in thread 0.
+// red: LDS scratch of at least K * 16 doubles.
+template <int K>
+__device__ __forceinline__ void block_sumk(double (&v)[K], double* red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < K; k++) v[k] += __shfl_xor(v[k], off, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < K; k++) red[K * wv + k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+        for (int k = 0; k < K; k++) v[k] = 0.0;
+        for (int w = 0; w < nw; w++)
+#pragma unroll
+            for (int k = 0; k < K; k++) v[k] += red[K * w + k];
+    }
+}
+
+// Sum of the Nt partial tuples of one parity, broadcast to every thread.
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int Nt, double* red, double* bc,
+                                                double (&out)[kNP]) {
+    double v[kNP];
+#pragma unroll
+    for (int k = 0; k < kNP; k++) v[k] = 0.0;
+    for (int t = threadIdx.x; t < Nt; t += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < kNP; k++) v[k] += part[kNP * t + k];
+    block_sumk<kNP>(v, red);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < kNP; k++) bc[k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kNP; k++) out[k] = bc[k];
+}
+
+__device__ __forceinline__ void write_partials(double* __restrict__ pt, double (&v)[kNP], double* red) {
+    block_sumk<kNP>(v, red);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < kNP; k++) pt[k] = v[k];
+}
+
+template <typename R, int MC>
+__device__ __forceinline__ double dot_cells(const Cells<R, MC>& a, const Cells<R, MC>& b, const bool (&own)[MC]) {
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < MC; m++)
+        if (own[m])
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+                s += (double)a.v[m][q].re * (double)b.v[m][q].re + (double)a.v[m][q].im * (double)b.v[m][q].im;
+    return s;
+}
+
+// Common per-block setup for the slice kernels.
+template <int MC>
+struct SliceCtx {
+    int tau, tm, tp;
+    CellGeo g[MC];
+    bool own[MC];
+    int idx[MC][12];
+};
+
+template <int MC>
+__device__ __forceinline__ void slice_ctx(const Lat& lt, SliceCtx<MC>& c) {
+    c.tau = blockIdx.x;
+    c.tm = c.tau == 0 ? lt.Nt - 1 : c.tau - 1;
+    c.tp = c.tau == lt.Nt - 1 ? 0 : c.tau + 1;
+#pragma unroll
+    for (int m = 0; m < MC; m++) {
+        const int cell = threadIdx.x + m * blockDim.x;
+        c.own[m] = cell < lt.ncell;
+        c.g[m] = cell_geo(c.own[m] ? cell : 0, lt);
+        phase_index(c.g[m], lt.Vs, c.idx[m]);
+    }
+}
+
+template <typename R, int MC>
+__device__ __forceinline__ void hops_of(const cplx<R>* __restrict__ gauge, const Lat& lt, int tau,
+                                        const int (&idx)[MC][12], const Coef<R>& co, cplx<R> (&h)[MC][12]) {
+#pragma unroll
+    for (int m = 0; m < MC; m++) load_hops(gauge, lt, tau, idx[m], co, h[m]);
+}
+
+// c = (R)(a - b) (b may be null); sq += |a - b|^2 in FP64 over owned cells
+template <typename R, int MC>
+__device__ __forceinline__ void load_cvt(Cells<R, MC>& c, const cplx<double>* __restrict__ a,
+                                         const cplx<double>* __restrict__ b, const CellGeo (&g)[MC],
+                                         const bool (&own)[MC], double& sq) {
+#pragma unroll
+    for (int m = 0; m < MC; m++)
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            double re = 0, im = 0;
+            if (own[m]) {
+                const cplx<double> x = a[g[m].s[q]];
+                re = x.re;
+                im = x.im;
+                if (b) {
+                    const cplx<double> y = b[g[m].s[q]];
+                    re -= y.re;
+                    im -= y.im;
+                }
+            }
+            sq += re * re + im * im;
+            c.v[m][q] = mk<R>((R)re, (R)im);
+        }
+}
+
+
+template <typename R>
+inline const cplx<R>* gauge_for(qedhmc_ctx* h) {
+    if constexpr (sizeof(R) == 8)
+        return h->gauge64;
+    else
+        return h->gauge32;
+}
+
+template <typename R, typename F>
+inline qedhmc_status with_shape(qedhmc_ctx* h, F&& f) {
+    const Lat& lt = h->lat;
+    const int mc = lt.ncell <= 1024 ? 1 : 2;
+    int nt = ((((lt.ncell + mc - 1) / mc) + 63) / 64) * 64;
+    if (nt < 64) nt = 64;
+    const size_t red = (kNP * 16 + 16) * sizeof(double);
+    const bool two = 4 * (size_t)lt.Vs * sizeof(cplx<R>) + red <= h->max_lds;
+    auto go = [&]<int MC, int BS>() -> qedhmc_status {
+        if (two) return f.template operator()<MC, 2, BS>(nt, 4 * (size_t)lt.Vs * sizeof(cplx<R>) + red);
+        return f.template operator()<MC, 1, BS>(nt, 2 * (size_t)lt.Vs * sizeof(cplx<R>) + red);
+    };
+    if (mc == 2) return go.template operator()<2, 576>();
+    if (nt <= 256) return go.template operator()<1, 256>();
+    if (nt <= 512) return go.template operator()<1, 512>();
+    return go.template operator()<1, 1024>();
+}
+
+template <typename K>
+inline qedhmc_status lds_attr(qedhmc_ctx* h, K kern, size_t bytes) {
+    if (bytes > h->max_lds) {
+        set_error("lattice too large for LDS on this device");
+        return QEDHMC_EUNSUPPORTED;
+    }
+    if (bytes > 65536)
+        QH_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    return QEDHMC_OK;
+}
+
+
+inline qedhmc_status read_slot(qedhmc_ctx* h, int kpar) {
+    QH_HIP(hipMemcpyAsync(h->h_pinned, h->scal + S_NSLOT * kpar, S_NSLOT * sizeof(double), hipMemcpyDeviceToHost,
+                          h->stream));
+    QH_HIP(hipStreamSynchronize(h->stream));
+    return QEDHMC_OK;
+}
+
+
+}  // namespace qh

@@ -1,0 +1,616 @@
+// The paper's preconditioner (Methods, "CG method and preconditioner"; the
+// banded structure of Fig. 3) and CG preconditioned with it.
+//
+// Construction (once per handle, on first use), following the paper's recipe
+// as read for this build:
+//   1. O_pi = M^dag M at pi flux (theta_x = 0, theta_y = pi x) on a build
+//      lattice of kBuildL x kBuildL x kBuildNt, assembled column by column by
+//      the library's own FP64 M^dag M kernel applied to unit vectors;
+//   2. forward IC(0) on the host in the natural order n = tau*Vs + s,
+//      O_pi ~ L L^dag on the pattern of O_pi (|O| > 1e-12 max|O|), with a
+//      diagonal shift if a pivot is not positive;
+//   3. the rows of G = L^{-1} at an interior site of a bulk slice, one per x
+//      parity (the pi-flux unit cell), by one triangular solve each;
+//   4. taps (dtau, dx, dy, g) with 0 <= dtau <= kCapTau and |g| >= kThresh.
+// Application: G[(tau,s),(tau-dtau, s+ds)] = g_{x(s) mod 2}(dtau, ds), with
+// -1 when tau-dtau wraps (antiperiodic), and P = G^dag G as two stencil
+// passes.  P is Hermitian positive definite whenever G is non-singular.
+//
+// PCG, one iteration = four launches (every read of a neighbouring slice
+// crosses a launch boundary, so no buffer is read and written in one launch):
+//   k_pcg_upd   partial sums -> beta, alpha (single reduction phase as in the
+//               unpreconditioned solver, denominator <p,s> expanded);
+//               p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s
+//   k_pc_apply  t = G r
+//   k_pc_apply  u = G^dag t
+//   k_pcg_mv    w = O u and the partials <r,r>, <r,u>, <w,u>, <u,s>, <p,w>, <p,s>
+// with gamma = <r, P r>; stopping and reliable updates on |r| as in cg.hip.
+#include <algorithm>
+#include <vector>
+
+#include "cg_common.h"
+
+namespace qh {
+
+static constexpr int kBuildL = 8;
+static constexpr int kBuildNt = 24;
+static constexpr int kCapTau = 6;
+static constexpr double kThresh = 1e-3;
+static constexpr int kNP7 = 7;  // PCG partials: <r,r>, <r,u>, <w,u>, <u,s>, <p,w>, <p,s>, unused
+
+template <typename R>
+struct PTap {
+    int dt, dx, dy, pad;
+    cplx<R> g;
+};
+
+// ---------------------------------------------------------------------------
+// Builder
+// ---------------------------------------------------------------------------
+__global__ void k_unit(cplx<double>* __restrict__ e, size_t n, size_t k) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        e[i] = mk<double>(i == k ? 1.0 : 0.0, 0.0);
+}
+
+static qedhmc_status build_paper_precond(qedhmc_ctx* h) {
+    qedhmc_params bp = h->p;
+    bp.L = kBuildL;
+    bp.Nt = kBuildNt;
+    qedhmc_ctx* b = nullptr;
+    QH_TRY(qedhmc_init_lattice(&bp, h->stream, &b));
+    const int L0 = kBuildL, Vs = L0 * L0, n = Vs * kBuildNt;
+    std::vector<double> th(2 * (size_t)n, 0.0);
+    for (int tau = 0; tau < kBuildNt; tau++)
+        for (int y = 0; y < L0; y++)
+            for (int x = 0; x < L0; x++) th[(size_t)(kBuildNt + tau) * Vs + y * L0 + x] = M_PI * x;
+    double *dth = nullptr, *dcols = nullptr, *de = nullptr;
+    std::vector<cplx<double>> O((size_t)n * n);  // column-major: O[k * n + i] = O_ik
+    qedhmc_status st = QEDHMC_OK;
+    auto fail = [&](hipError_t e, const char* w) { st = hip_fail(e, w); };
+    hipError_t e = hipMalloc(&dth, th.size() * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&dcols, (size_t)n * n * sizeof(cplx<double>));
+    if (e == hipSuccess) e = hipMalloc(&de, (size_t)n * sizeof(cplx<double>));
+    if (e == hipSuccess) e = hipMemcpyAsync(dth, th.data(), th.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) fail(e, "preconditioner build allocation");
+    if (st == QEDHMC_OK) st = ensure_gauge(b, dth, QEDHMC_FP64);
+    for (int k = 0; k < n && st == QEDHMC_OK; k++) {
+        hipLaunchKernelGGL(k_unit, dim3(8), dim3(256), 0, h->stream, (cplx<double>*)de, (size_t)n, (size_t)k);
+        st = launch_mdagm(b, QEDHMC_FP64, de, dcols + (size_t)2 * k * n, nullptr);
+    }
+    if (st == QEDHMC_OK) {
+        e = hipMemcpyAsync(O.data(), dcols, O.size() * sizeof(cplx<double>), hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) fail(e, "preconditioner build copy");
+    }
+    (void)hipFree(dth);
+    (void)hipFree(dcols);
+    (void)hipFree(de);
+    qedhmc_destroy(b);
+    if (st != QEDHMC_OK) return st;
+
+    // IC(0), left-looking, dense storage of the lower factor (column-major)
+    double omax = 0.0;
+    for (const auto& z : O) omax = std::max(omax, std::hypot(z.re, z.im));
+    const double cut = 1e-12 * omax;
+    std::vector<cplx<double>> Lf((size_t)n * n, mk<double>(0.0, 0.0));
+    double shift = 0.0;
+    for (;;) {
+        bool ok = true;
+        std::fill(Lf.begin(), Lf.end(), mk<double>(0.0, 0.0));
+        for (int k = 0; k < n && ok; k++) {
+            // col[i] = A_ik - sum_{j<k} L_ij conj(L_kj), i >= k
+            std::vector<cplx<double>> col(n - k);
+            for (int i = k; i < n; i++) {
+                cplx<double> a = O[(size_t)k * n + i];
+                if (i == k) a.re += shift * O[(size_t)k * n + k].re;
+                double sr = 0.0, si = 0.0;
+                for (int j = 0; j < k; j++) {
+                    const cplx<double> lij = Lf[(size_t)j * n + i], lkj = Lf[(size_t)j * n + k];
+                    sr += lij.re * lkj.re + lij.im * lkj.im;
+                    si += lij.im * lkj.re - lij.re * lkj.im;
+                }
+                col[i - k] = mk<double>(a.re - sr, a.im - si);
+            }
+            const double piv = col[0].re;
+            if (!(piv > 0.0)) {
+                ok = false;
+                break;
+            }
+            const double d = std::sqrt(piv);
+            Lf[(size_t)k * n + k] = mk<double>(d, 0.0);
+            for (int i = k + 1; i < n; i++) {
+                const cplx<double> a = O[(size_t)k * n + i];
+                if (std::hypot(a.re, a.im) > cut) Lf[(size_t)k * n + i] = mk<double>(col[i - k].re / d, col[i - k].im / d);
+            }
+        }
+        if (ok) break;
+        shift = shift == 0.0 ? 1e-3 : 2 * shift;
+        if (shift > 1.0) {
+            set_error("preconditioner: IC(0) pivots stay non-positive");
+            return QEDHMC_EUNSUPPORTED;
+        }
+    }
+    // rows of G = L^{-1}: x^T L = e_n0^T  <=>  L^T x = e_n0 (back substitution)
+    const int tau0 = kBuildNt / 2 + 4, y0 = L0 / 2;
+    for (int par = 0; par < 2; par++) {
+        const int x0 = L0 / 2 + par, n0 = tau0 * Vs + y0 * L0 + x0;
+        std::vector<cplx<double>> xr(n, mk<double>(0.0, 0.0));
+        for (int i = n0; i >= 0; i--) {
+            double re = (i == n0) ? 1.0 : 0.0, im = 0.0;
+            for (int j = i + 1; j <= n0; j++) {
+                const cplx<double> lji = Lf[(size_t)i * n + j], xj = xr[j];
+                re -= lji.re * xj.re - lji.im * xj.im;
+                im -= lji.re * xj.im + lji.im * xj.re;
+            }
+            const cplx<double> lii = Lf[(size_t)i * n + i];  // real positive
+            xr[i] = mk<double>(re / lii.re, im / lii.re);
+        }
+        auto& taps = h->pc_taps[par];
+        taps.clear();
+        for (int m = 0; m <= n0; m++) {
+            const double mag = std::hypot(xr[m].re, xr[m].im);
+            if (!(mag >= kThresh)) continue;
+            const int tm = m / Vs, sm = m % Vs;
+            const int dt = tau0 - tm;
+            if (dt < 0 || dt > kCapTau) continue;
+            const int dx = ((sm % L0 - x0 + L0 / 2) % L0 + L0) % L0 - L0 / 2;
+            const int dy = ((sm / L0 - y0 + L0 / 2) % L0 + L0) % L0 - L0 / 2;
+            taps.push_back({dt, dx, dy, xr[m].re, xr[m].im});
+        }
+        std::sort(taps.begin(), taps.end(), [](const HostTap& a, const HostTap& b) {
+            if (a.dt != b.dt) return a.dt < b.dt;
+            if (a.dy != b.dy) return a.dy < b.dy;
+            return a.dx < b.dx;
+        });
+    }
+    h->pc_shift = shift;
+    // device copies in both precisions: [parity 0 taps][parity 1 taps]
+    const size_t nt = h->pc_taps[0].size() + h->pc_taps[1].size();
+    std::vector<PTap<double>> t64;
+    std::vector<PTap<float>> t32;
+    for (int par = 0; par < 2; par++)
+        for (const auto& t : h->pc_taps[par]) {
+            t64.push_back({t.dt, t.dx, t.dy, 0, mk<double>(t.gre, t.gim)});
+            t32.push_back({t.dt, t.dx, t.dy, 0, mk<float>((float)t.gre, (float)t.gim)});
+        }
+    QH_HIP(hipMalloc(&h->pc_dev64, nt * sizeof(PTap<double>)));
+    QH_HIP(hipMalloc(&h->pc_dev32, nt * sizeof(PTap<float>)));
+    QH_HIP(hipMemcpyAsync(h->pc_dev64, t64.data(), nt * sizeof(PTap<double>), hipMemcpyHostToDevice, h->stream));
+    QH_HIP(hipMemcpyAsync(h->pc_dev32, t32.data(), nt * sizeof(PTap<float>), hipMemcpyHostToDevice, h->stream));
+    QH_HIP(hipStreamSynchronize(h->stream));
+    h->pc_ready = true;
+    return QEDHMC_OK;
+}
+
+qedhmc_status ensure_paper_precond(qedhmc_ctx* h) {
+    if (h->pc_ready) return QEDHMC_OK;
+    return build_paper_precond(h);
+}
+
+// ---------------------------------------------------------------------------
+// Stencil application.  Grid (Nt, 2 parities, chunks); a block handles sites
+// of one x parity of one slice, so every thread walks the same tap list.
+//   G:     out(tau,y,x) = sum_{taps[x%2]} g in(tau-dt, y+dy, x+dx) [-1 if tau-dt < 0]
+//   G^dag: out(tau,y,x) = sum_{p'} sum_{taps[p'], (x-dx)%2 == p'} conj(g)
+//                         in(tau+dt, y-dy, x-dx) [-1 if tau+dt >= Nt]
+// stop (nullable): a scalar slot's stop flag; non-zero makes the launch a no-op.
+// ---------------------------------------------------------------------------
+template <typename R, bool DAG>
+__global__ __launch_bounds__(256) void k_pc_apply(Lat lt, const PTap<R>* __restrict__ taps, int n0, int n1,
+                                                  const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
+                                                  const double* __restrict__ stop) {
+    if (stop && *stop != 0.0) return;
+    const int tau = blockIdx.x, par = blockIdx.y;
+    const int half = lt.Vs / 2;
+    const int k = blockIdx.z * blockDim.x + threadIdx.x;
+    if (k >= half) return;
+    const int L = lt.L, Nt = lt.Nt;
+    const int y = k / lt.hL, x = 2 * (k - y * lt.hL) + par;
+    R ar = 0, ai = 0;
+    if (!DAG) {
+        const PTap<R>* tp = taps + (par ? n0 : 0);
+        const int nt = par ? n1 : n0;
+        for (int j = 0; j < nt; j++) {
+            const PTap<R> t = tp[j];
+            int ts = tau - t.dt;
+            const R sg = ts < 0 ? R(-1) : R(1);
+            if (ts < 0) ts += Nt;
+            int ys = y + t.dy, xs = x + t.dx;
+            ys = ys < 0 ? ys + L : (ys >= L ? ys - L : ys);
+            xs = xs < 0 ? xs + L : (xs >= L ? xs - L : xs);
+            const cplx<R> v = in[(size_t)ts * lt.Vs + ys * L + xs];
+            ar += sg * (t.g.re * v.re - t.g.im * v.im);
+            ai += sg * (t.g.re * v.im + t.g.im * v.re);
+        }
+    } else {
+        for (int pp = 0; pp < 2; pp++) {
+            const PTap<R>* tp = taps + (pp ? n0 : 0);
+            const int nt = pp ? n1 : n0;
+            for (int j = 0; j < nt; j++) {
+                const PTap<R> t = tp[j];
+                if (((par - t.dx) & 1) != pp) continue;
+                int ts = tau + t.dt;
+                const R sg = ts >= Nt ? R(-1) : R(1);
+                if (ts >= Nt) ts -= Nt;
+                int ys = y - t.dy, xs = x - t.dx;
+                ys = ys < 0 ? ys + L : (ys >= L ? ys - L : ys);
+                xs = xs < 0 ? xs + L : (xs >= L ? xs - L : xs);
+                const cplx<R> v = in[(size_t)ts * lt.Vs + ys * L + xs];
+                ar += sg * (t.g.re * v.re + t.g.im * v.im);
+                ai += sg * (t.g.re * v.im - t.g.im * v.re);
+            }
+        }
+    }
+    out[(size_t)tau * lt.Vs + y * L + x] = mk<R>(ar, ai);
+}
+
+template <typename R>
+static const PTap<R>* taps_for(qedhmc_ctx* h) {
+    if constexpr (sizeof(R) == 8)
+        return (const PTap<double>*)h->pc_dev64;
+    else
+        return (const PTap<float>*)h->pc_dev32;
+}
+
+template <typename R, bool DAG>
+static qedhmc_status launch_pc(qedhmc_ctx* h, const cplx<R>* in, cplx<R>* out, const double* stop) {
+    const int half = h->lat.Vs / 2;
+    const dim3 grid(h->lat.Nt, 2, (half + 255) / 256);
+    hipLaunchKernelGGL((k_pc_apply<R, DAG>), grid, dim3(256), 0, h->stream, h->lat, taps_for<R>(h),
+                       (int)h->pc_taps[0].size(), (int)h->pc_taps[1].size(), in, out, stop);
+    QH_HIP(hipGetLastError());
+    return QEDHMC_OK;
+}
+
+// z = G^dag (G r); tmp: scratch vector of the same precision
+template <typename R>
+static qedhmc_status apply_P_t(qedhmc_ctx* h, const cplx<R>* r, cplx<R>* z, cplx<R>* tmp, const double* stop) {
+    QH_TRY((launch_pc<R, false>(h, r, tmp, stop)));
+    return launch_pc<R, true>(h, tmp, z, stop);
+}
+
+qedhmc_status launch_apply_precond(qedhmc_ctx* h, qedhmc_precision prec, const void* in, void* out) {
+    QH_TRY(ensure_paper_precond(h));
+    if (prec == QEDHMC_FP64)
+        return apply_P_t<double>(h, (const cplx<double>*)in, (cplx<double>*)out, (cplx<double>*)h->ws[9], nullptr);
+    return apply_P_t<float>(h, (const cplx<float>*)in, (cplx<float>*)out, (cplx<float>*)h->ws[9], nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// PCG kernels
+// ---------------------------------------------------------------------------
+template <typename R>
+struct PcgBufs {
+    cplx<R>* r;
+    cplx<R>* p;
+    cplx<R>* s;
+    cplx<R>* u;
+    cplx<R>* w;
+    cplx<R>* t;
+    cplx<double>* x;
+    const cplx<double>* rhs;
+    const cplx<double>* Ox;
+    double* part;   // [Nt][kNP7]
+    double* partb;  // [Nt]: |rhs|^2 or the FP64 true |r|^2
+};
+
+// r = rhs, x = p = s = 0; partb = |rhs|^2 per slice
+template <typename R>
+__global__ __launch_bounds__(256) void k_pcg_start(Lat lt, PcgBufs<R> B) {
+    __shared__ double red[64];
+    const size_t base = (size_t)blockIdx.x * lt.Vs;
+    double b2 = 0.0;
+    for (int k = threadIdx.x; k < lt.Vs; k += blockDim.x) {
+        const cplx<double> b = B.rhs[base + k];
+        B.r[base + k] = mk<R>((R)b.re, (R)b.im);
+        B.p[base + k] = mk<R>(0, 0);
+        B.s[base + k] = mk<R>(0, 0);
+        B.x[base + k] = mk<double>(0, 0);
+        b2 += b.re * b.re + b.im * b.im;
+    }
+    double v[1] = {b2};
+    block_sumk<1>(v, red);
+    if (threadIdx.x == 0) B.partb[blockIdx.x] = v[0];
+}
+
+// slot 0 from the |rhs|^2 partials
+__global__ void k_pcg_init_slot(double* __restrict__ scal, const double* __restrict__ partb, int Nt, double tol2) {
+    __shared__ double red[64];
+    double v[1] = {0.0};
+    for (int t = threadIdx.x; t < Nt; t += blockDim.x) v[0] += partb[t];
+    block_sumk<1>(v, red);
+    if (threadIdx.x < S_NSLOT) {
+        double val = 0.0;
+        if (threadIdx.x == S_FIRST || threadIdx.x == S_GPREV || threadIdx.x == S_APREV) val = 1.0;
+        scal[threadIdx.x] = val;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        scal[S_B2] = v[0];
+        scal[S_TARGET] = tol2 * v[0];
+        scal[S_RRUPD] = v[0];
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void reduce_k(const double* __restrict__ part, int Nt, double* red, double* bc,
+                                         double (&out)[K]) {
+    double v[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) v[k] = 0.0;
+    for (int t = threadIdx.x; t < Nt; t += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < K; k++) v[k] += part[K * t + k];
+    block_sumk<K>(v, red);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < K; k++) bc[k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; k++) out[k] = bc[k];
+}
+
+// One slice per block: scalars from the partials, then the elementwise update.
+template <typename R>
+__global__ __launch_bounds__(256) void k_pcg_upd(Lat lt, PcgBufs<R> B, double* __restrict__ scal, int kpar,
+                                                 int mixed) {
+    __shared__ double red[kNP7 * 16 + 16];
+    const double* sin_ = scal + S_NSLOT * kpar;
+    double* sout = scal + S_NSLOT * (kpar ^ 1);
+    if (sin_[S_DONE] != 0.0) {
+        if (blockIdx.x == 0 && threadIdx.x < S_NSLOT) sout[threadIdx.x] = sin_[threadIdx.x];
+        return;
+    }
+    double pr[kNP7];
+    reduce_k<kNP7>(B.part, lt.Nt, red, red + kNP7 * 16, pr);
+    const double rr = pr[0], gam = pr[1], del = pr[2];
+    const int it = (int)sin_[S_ITERS];
+    int stop = 0;
+    double alpha = 0.0, beta = 0.0;
+    const bool first = sin_[S_FIRST] != 0.0;
+    if (!isfinite(rr) || !isfinite(gam) || !isfinite(del))
+        stop = 4;
+    else if (rr <= sin_[S_TARGET])
+        stop = 1;
+    else if (mixed && (rr <= kDecade2 * sin_[S_RRUPD] || it - (int)sin_[S_ITUPD] >= kCap))
+        stop = 2;
+    else {
+        beta = first ? 0.0 : gam / sin_[S_GPREV];
+        const double den = first ? del : del + beta * (pr[3] + pr[4]) + beta * beta * pr[5];
+        if (!(den > 0.0))
+            stop = 3;
+        else
+            alpha = gam / den;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < S_NSLOT) {
+        double v = sin_[threadIdx.x];
+        if (stop) {
+            if (threadIdx.x == S_DONE) v = (double)stop;
+            if (threadIdx.x == S_GCUR) v = rr;
+        } else {
+            if (threadIdx.x == S_GPREV) v = gam;
+            if (threadIdx.x == S_APREV) v = alpha;
+            if (threadIdx.x == S_ITERS) v = (double)(it + 1);
+            if (threadIdx.x == S_FIRST) v = 0.0;
+            if (threadIdx.x == S_GCUR) v = rr;
+        }
+        sout[threadIdx.x] = v;
+    }
+    if (stop) return;
+    const R a = (R)alpha, b = (R)beta;
+    const size_t base = (size_t)blockIdx.x * lt.Vs;
+    for (int k = threadIdx.x; k < lt.Vs; k += blockDim.x) {
+        const size_t i = base + k;
+        const cplx<R> pn = cfma(b, B.p[i], B.u[i]);
+        const cplx<R> sn = cfma(b, B.s[i], B.w[i]);
+        B.p[i] = pn;
+        B.s[i] = sn;
+        cplx<double> xv = B.x[i];
+        xv.re += alpha * (double)pn.re;
+        xv.im += alpha * (double)pn.im;
+        B.x[i] = xv;
+        B.r[i] = cfma(-a, sn, B.r[i]);
+    }
+}
+
+// w = O u (own slice) and the partials of the next iteration
+template <typename R, int MC, int NB, int BS>
+__global__ __launch_bounds__(BS) void k_pcg_mv(Lat lt, PcgBufs<R> B, const cplx<R>* __restrict__ gauge, Coef<R> co,
+                                               const double* __restrict__ stop) {
+    if (stop && *stop != 0.0) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    cplx<R>* buf2 = reinterpret_cast<cplx<R>*>(smem);
+    double* red = reinterpret_cast<double*>(smem + (size_t)NB * 2 * lt.Vs * sizeof(cplx<R>));
+    SliceCtx<MC> c;
+    slice_ctx<MC>(lt, c);
+    const size_t Vs = lt.Vs;
+    cplx<R> hm[MC][12], ht[MC][12];
+    hops_of<R, MC>(gauge, lt, c.tm, c.idx, co, hm);
+    hops_of<R, MC>(gauge, lt, c.tau, c.idx, co, ht);
+    Cells<R, MC> um, ut, un, rt, pt, st, w;
+    load_cells<R, MC>(um, B.u + c.tm * Vs, c.g, c.own);
+    load_cells<R, MC>(ut, B.u + c.tau * Vs, c.g, c.own);
+    load_cells<R, MC>(un, B.u + c.tp * Vs, c.g, c.own);
+    load_cells<R, MC>(rt, B.r + c.tau * Vs, c.g, c.own);
+    load_cells<R, MC>(pt, B.p + c.tau * Vs, c.g, c.own);
+    load_cells<R, MC>(st, B.s + c.tau * Vs, c.g, c.own);
+    const Cells<R, MC> u0 = ut;
+    mdagm_cells<R, MC, NB>(um, ut, un, hm, ht, c.g, c.own, co, c.tau == 0 ? R(-1) : R(1),
+                           c.tau == lt.Nt - 1 ? R(-1) : R(1), buf2, lt.Vs, w);
+    store_cells<R, MC>(w, B.w + c.tau * Vs, c.g, c.own);
+    double v[kNP7] = {dot_cells<R, MC>(rt, rt, c.own), dot_cells<R, MC>(rt, u0, c.own),
+                      dot_cells<R, MC>(w, u0, c.own),  dot_cells<R, MC>(u0, st, c.own),
+                      dot_cells<R, MC>(pt, w, c.own),  dot_cells<R, MC>(pt, st, c.own), 0.0};
+    block_sumk<kNP7>(v, red);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < kNP7; k++) B.part[kNP7 * (size_t)c.tau + k] = v[k];
+}
+
+// r = rhs - O x from the FP64 O x; partb = FP64 |rhs - O x|^2 per slice
+template <typename R>
+__global__ __launch_bounds__(256) void k_pcg_rep(Lat lt, PcgBufs<R> B) {
+    __shared__ double red[64];
+    const size_t base = (size_t)blockIdx.x * lt.Vs;
+    double t2 = 0.0;
+    for (int k = threadIdx.x; k < lt.Vs; k += blockDim.x) {
+        const cplx<double> b = B.rhs[base + k], o = B.Ox[base + k];
+        const double re = b.re - o.re, im = b.im - o.im;
+        B.r[base + k] = mk<R>((R)re, (R)im);
+        t2 += re * re + im * im;
+    }
+    double v[1] = {t2};
+    block_sumk<1>(v, red);
+    if (threadIdx.x == 0) B.partb[blockIdx.x] = v[0];
+}
+
+// After a replacement and a fresh u, w and partials: converged -> stop 1;
+// otherwise resume (restart sets beta = 0 on the next iteration).
+__global__ void k_pcg_check(double* __restrict__ scal, int kpar, const double* __restrict__ part,
+                            const double* __restrict__ partb, int Nt, int restart) {
+    __shared__ double red[64];
+    double v[2] = {0.0, 0.0};
+    for (int t = threadIdx.x; t < Nt; t += blockDim.x) {
+        v[0] += partb[t];
+        v[1] += part[kNP7 * t];
+    }
+    block_sumk<2>(v, red);
+    if (threadIdx.x == 0) {
+        double* sl = scal + S_NSLOT * kpar;
+        sl[S_TRUE] = v[0];
+        if (v[0] <= sl[S_TARGET]) {
+            sl[S_DONE] = 1.0;
+        } else {
+            sl[S_DONE] = 0.0;
+            if (restart) sl[S_FIRST] = 1.0;
+            sl[S_ITUPD] = sl[S_ITERS];
+            sl[S_RRUPD] = v[1];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host driver
+// ---------------------------------------------------------------------------
+template <typename R>
+static PcgBufs<R> pbufs_of(qedhmc_ctx* h, const double* rhs, double* x) {
+    PcgBufs<R> B;
+    const size_t N = (size_t)h->lat.Nt * h->lat.Vs;
+    cplx<R>* base = reinterpret_cast<cplx<R>*>(h->cg_arena);
+    B.r = base;
+    B.p = base + N;
+    B.s = base + 2 * N;
+    B.u = base + 3 * N;
+    B.w = base + 4 * N;
+    B.t = base + 5 * N;
+    B.x = reinterpret_cast<cplx<double>*>(x);
+    B.rhs = reinterpret_cast<const cplx<double>*>(rhs);
+    B.Ox = reinterpret_cast<const cplx<double>*>(h->ws[3]);
+    B.part = h->partial;
+    B.partb = h->partial + kNP7 * (size_t)h->lat.Nt;
+    return B;
+}
+
+template <typename R>
+static qedhmc_status launch_mv(qedhmc_ctx* h, const PcgBufs<R>& B, const double* stop, bool timed) {
+    return with_shape<R>(h, [&]<int MC, int NB, int BS>(int nt, size_t lds) -> qedhmc_status {
+        QH_TRY(lds_attr(h, k_pcg_mv<R, MC, NB, BS>, lds));
+        hipEvent_t e0, e1;
+        const int cls = sizeof(R) == 4 ? QEDHMC_K_PCG_MV_FP32 : QEDHMC_K_PCG_MV_FP64;
+        if (timed && prof_sample(h, cls, e0, e1))
+            hipExtLaunchKernelGGL((k_pcg_mv<R, MC, NB, BS>), dim3(h->lat.Nt), dim3(nt), lds, h->stream, e0, e1, 0,
+                                  h->lat, B, gauge_for<R>(h), coef_of<R>(h->p), stop);
+        else
+            hipLaunchKernelGGL((k_pcg_mv<R, MC, NB, BS>), dim3(h->lat.Nt), dim3(nt), lds, h->stream, h->lat, B,
+                               gauge_for<R>(h), coef_of<R>(h->p), stop);
+        QH_HIP(hipGetLastError());
+        return QEDHMC_OK;
+    });
+}
+
+// u = P r, w = O u, partials (stop: nullable slot flag)
+template <typename R>
+static qedhmc_status pcg_tail(qedhmc_ctx* h, const PcgBufs<R>& B, const double* stop) {
+    QH_TRY(apply_P_t<R>(h, B.r, B.u, B.t, stop));
+    return launch_mv<R>(h, B, stop, stop != nullptr);
+}
+
+template <typename R>
+static qedhmc_status pcg_t(qedhmc_ctx* h, const double* rhs, double* x, double tol, int maxit, qedhmc_precision prec,
+                           int* iters, double* true_rel, int* n_reliable) {
+    QH_TRY(ensure_paper_precond(h));
+    const bool mixed = prec != QEDHMC_FP64;
+    const PcgBufs<R> B = pbufs_of<R>(h, rhs, x);
+    const int Nt = h->lat.Nt;
+    const int chunk = mixed ? kCap + 1 : 64;
+    int kpar = 0, nrel = 0, it = 0, stalled = 0, last_it = -1;
+    double rel = 1.0;
+    bool converged = false, broken = false;
+    hipLaunchKernelGGL(k_pcg_start<R>, dim3(Nt), dim3(256), 0, h->stream, h->lat, B);
+    hipLaunchKernelGGL(k_pcg_init_slot, dim3(1), dim3(256), 0, h->stream, h->scal, (const double*)B.partb, Nt,
+                       tol * tol);
+    QH_HIP(hipGetLastError());
+    QH_TRY(pcg_tail<R>(h, B, nullptr));
+    while (true) {
+        const int left = maxit - it;
+        const int n = left < chunk ? left : chunk;
+        for (int k = 0; k < n; k++) {
+            hipLaunchKernelGGL(k_pcg_upd<R>, dim3(Nt), dim3(256), 0, h->stream, h->lat, B, h->scal, kpar,
+                               mixed ? 1 : 0);
+            kpar ^= 1;
+            QH_TRY(pcg_tail<R>(h, B, h->scal + S_NSLOT * kpar + S_DONE));
+        }
+        QH_HIP(hipGetLastError());
+        QH_TRY(read_slot(h, kpar));
+        it = (int)h->h_pinned[S_ITERS];
+        const double flag = h->h_pinned[S_DONE];
+        if (flag == 0.0 && it < maxit) continue;
+        if (flag == 4.0) {
+            broken = true;
+            set_error("PCG breakdown: non-finite inner products after " + std::to_string(it) + " iterations");
+            break;
+        }
+        stalled = (it == last_it) ? stalled + 1 : 0;
+        last_it = it;
+        if (stalled >= 3) {
+            set_error("PCG made no progress across reliable updates at iteration " + std::to_string(it));
+            break;
+        }
+        // FP64 true residual; r replaced, s = O p refreshed, u, w and partials recomputed
+        QH_TRY(launch_mdagm(h, QEDHMC_FP64, x, h->ws[3], nullptr));
+        hipLaunchKernelGGL(k_pcg_rep<R>, dim3(Nt), dim3(256), 0, h->stream, h->lat, B);
+        QH_HIP(hipGetLastError());
+        QH_TRY(launch_mdagm(h, prec == QEDHMC_FP64 ? QEDHMC_FP64 : QEDHMC_FP32, B.p, B.s, nullptr));
+        QH_TRY(pcg_tail<R>(h, B, nullptr));
+        hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(256), 0, h->stream, h->scal, kpar, (const double*)B.part,
+                           (const double*)B.partb, Nt, (!mixed || flag == 3.0) ? 1 : 0);
+        QH_HIP(hipGetLastError());
+        nrel++;
+        QH_TRY(read_slot(h, kpar));
+        const double b2 = h->h_pinned[S_B2];
+        rel = b2 > 0.0 ? std::sqrt(h->h_pinned[S_TRUE] / b2) : 0.0;
+        if (!std::isfinite(rel)) {
+            broken = true;
+            set_error("PCG breakdown: non-finite true residual after " + std::to_string(it) + " iterations");
+            break;
+        }
+        if (h->h_pinned[S_DONE] == 1.0) {
+            converged = true;
+            break;
+        }
+        if (it >= maxit) break;
+    }
+    if (iters) *iters = it;
+    if (true_rel) *true_rel = rel;
+    if (n_reliable) *n_reliable = nrel;
+    if (broken) return QEDHMC_ENOCONV;
+    return converged ? QEDHMC_OK : QEDHMC_ENOCONV;
+}
+
+qedhmc_status pcg_solve_impl(qedhmc_ctx* h, const double* rhs, double* x, double tol, int maxit,
+                             qedhmc_precision prec, int* iters, double* true_rel, int* n_reliable) {
+    if (prec == QEDHMC_FP64) return pcg_t<double>(h, rhs, x, tol, maxit, prec, iters, true_rel, n_reliable);
+    return pcg_t<float>(h, rhs, x, tol, maxit, prec, iters, true_rel, n_reliable);
+}
+
+}  // namespace qh

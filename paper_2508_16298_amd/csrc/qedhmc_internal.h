@@ -20,6 +20,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "qedhmc.h"
 
@@ -387,6 +388,12 @@ __device__ __forceinline__ double block_sum(double x, double* red) {
 // ---------------------------------------------------------------------------
 // Handle and host-side helpers
 // ---------------------------------------------------------------------------
+// One tap of the paper's preconditioner stencil (host copy, FP64).
+struct HostTap {
+    int dt, dx, dy;
+    double gre, gim;
+};
+
 struct qedhmc_ctx {
     qedhmc_params p;
     qh::Lat lat;
@@ -419,6 +426,12 @@ struct qedhmc_ctx {
     bool prof_used[64];
     int prof_pending;
     bool prof_ready;
+    // the paper's preconditioner (built on first use)
+    bool pc_ready;
+    double pc_shift;
+    std::vector<HostTap> pc_taps[2];  // per x parity
+    void* pc_dev64;                   // device taps, FP64 and FP32
+    void* pc_dev32;
 };
 
 namespace qh {
@@ -457,9 +470,13 @@ qedhmc_status launch_mdagm(qedhmc_ctx* h, qedhmc_precision prec, const void* in,
 qedhmc_status launch_force(qedhmc_ctx* h, qedhmc_precision prec, const double* X, double* F);
 qedhmc_status launch_bond_tables(qedhmc_ctx* h);
 
-// CG (cg.hip)
+// CG (cg.hip) and preconditioned CG (pcg.hip)
 qedhmc_status cg_solve_impl(qedhmc_ctx* h, const double* rhs, double* x, double tol, int maxit,
                             qedhmc_precision prec, int* iters, double* true_rel, int* n_reliable);
+qedhmc_status pcg_solve_impl(qedhmc_ctx* h, const double* rhs, double* x, double tol, int maxit,
+                             qedhmc_precision prec, int* iters, double* true_rel, int* n_reliable);
+qedhmc_status ensure_paper_precond(qedhmc_ctx* h);
+qedhmc_status launch_apply_precond(qedhmc_ctx* h, qedhmc_precision prec, const void* in, void* out);
 
 // Gauge-field and trajectory kernels (boson.hip)
 qedhmc_status launch_bosonic(qedhmc_ctx* h, const double* theta, double* F_B, double* S_dev);

@@ -17,9 +17,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqedhmc.so")
 
 OK, EINVAL, ENOCONV, EHIP, ENOMEM, EUNSUPPORTED = range(6)
-K_MDAGM_FP32, K_MDAGM_FP64, K_FORCE, K_CG_FP32, K_CG_FP64 = range(5)
+K_MDAGM_FP32, K_MDAGM_FP64, K_FORCE, K_CG_FP32, K_CG_FP64, K_PCG_MV_FP32, K_PCG_MV_FP64 = range(7)
 FP64, FP32 = 0, 1
-PC_NONE = 0
+PC_NONE, PC_PAPER = 0, 1
+_PC = {None: PC_NONE, "none": PC_NONE, "paper": PC_PAPER, PC_NONE: PC_NONE, PC_PAPER: PC_PAPER}
 
 _PREC = {"fp64": FP64, "fp32": FP32, "mixed": FP32, FP64: FP64, FP32: FP32}
 
@@ -74,6 +75,8 @@ def load():
         "qedhmc_fermion_force": [_P, _P, _P, _P, C.c_int],
         "qedhmc_bosonic_action_force": [_P, _P, C.POINTER(C.c_double), _P],
         "qedhmc_heatbath": [_P, C.c_uint64, _P, _P],
+        "qedhmc_precond_taps": [_P, C.c_int32, C.POINTER(C.c_int32), _P, C.c_int32],
+        "qedhmc_apply_precond": [_P, _P, _P, C.c_int],
         "qedhmc_profile": [_P, C.c_int32],
         "qedhmc_profile_read": [_P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
         "qedhmc_hmc_trajectory": [_P, _P, C.c_uint64, C.c_int32, C.c_double, C.c_double, C.c_int32,
@@ -192,8 +195,27 @@ class Lattice:
         _check(load().qedhmc_apply_MdagM(self.h, _ptr(theta), _ptr(v), _ptr(out), _PREC[prec]))
         return out
 
-    def cg_solve(self, theta, rhs, tol=1e-10, maxit=1_000_000, prec="fp64", x=None):
-        """Returns (x, status, iters, true_rel_resid); status OK or ENOCONV."""
+    def precond_taps(self, parity):
+        """The paper's preconditioner stencil of one x parity: float64 (n, 5) rows
+        (dtau, dx, dy, Re g, Im g)."""
+        import numpy as np
+        n = C.c_int32(0)
+        _check(load().qedhmc_precond_taps(self.h, int(parity), C.byref(n), None, 0))
+        out = np.zeros((n.value, 5))
+        _check(load().qedhmc_precond_taps(self.h, int(parity), C.byref(n), out.ctypes.data_as(C.c_void_p),
+                                          n.value))
+        return out
+
+    def apply_precond(self, v, prec="fp64", out=None):
+        self._check_vec(v, prec)
+        out = self._vec(prec) if out is None else out
+        self._sync_stream()
+        _check(load().qedhmc_apply_precond(self.h, _ptr(v), _ptr(out), _PREC[prec]))
+        return out
+
+    def cg_solve(self, theta, rhs, tol=1e-10, maxit=1_000_000, prec="fp64", x=None, precond=None):
+        """Returns (x, status, iters, true_rel_resid); status OK or ENOCONV.
+        precond: None or "paper"."""
         self._check_theta(theta)
         self._check_vec(rhs, "fp64")
         x = self._vec("fp64") if x is None else x
@@ -201,7 +223,7 @@ class Lattice:
         rel = C.c_double(0.0)
         self._sync_stream()
         st = _check(load().qedhmc_cg_solve(self.h, _ptr(theta), _ptr(rhs), _ptr(x), float(tol), int(maxit),
-                                           _PREC[prec], PC_NONE, C.byref(it), C.byref(rel)),
+                                           _PREC[prec], _PC[precond], C.byref(it), C.byref(rel)),
                     allow=(OK, ENOCONV))
         return x, st, it.value, rel.value
 
@@ -230,14 +252,14 @@ class Lattice:
         return mom, R
 
     def hmc_trajectory(self, theta, traj, n_steps, traj_len=1.0, tol=1e-10, maxit=1_000_000,
-                       prec="fp64"):
+                       prec="fp64", precond=None):
         """theta is updated in place (proposal on acceptance); returns the result dict."""
         self._check_theta(theta)
         res = TrajResult()
         self._sync_stream()
         _check(load().qedhmc_hmc_trajectory(self.h, _ptr(theta), int(traj), int(n_steps),
                                             float(traj_len), float(tol), int(maxit), _PREC[prec],
-                                            PC_NONE, C.byref(res)))
+                                            _PC[precond], C.byref(res)))
         return res.as_dict()
 
 

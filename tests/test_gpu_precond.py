@@ -1,0 +1,125 @@
+"""GPU parity of the paper's preconditioner path: the library's stencil
+against the oracle twin (same recipe, independent code: 1e-10), P = G^dag G
+applied on the GPU against the oracle (FP64 1e-12, FP32 5e-6), and CG
+preconditioned with it (true residual recomputed by the oracle, solution
+unchanged, iterations cut)."""
+import functools
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from oracle import precond as PC
+from paper_2508_16298_amd import inputs
+from paper_2508_16298_amd import qedhmc as Q
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(x, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    a, b = np.asarray(a).reshape(-1), np.asarray(b).reshape(-1)
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@functools.lru_cache(maxsize=1)
+def _oracle_taps():
+    return PC.build_stencil(8, 24)[0]
+
+
+def test_stencil_matches_oracle_twin():
+    taps = _oracle_taps()
+    with Q.Lattice(8, 4) as lat:
+        for par in (0, 1):
+            g = lat.precond_taps(par)
+            o = np.array([(e[0], e[1], e[2], e[3].real, e[3].imag) for e in taps[par]])
+            print(par, len(g), len(o), flush=True)
+            assert g.shape == o.shape
+            assert np.array_equal(g[:, :3], o[:, :3])
+            assert np.abs(g[:, 3:] - o[:, 3:]).max() < 1e-10
+
+
+@pytest.mark.parametrize("L,Nt", [(8, 16), (12, 30), (24, 240)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 5e-6)])
+def test_apply_precond_matches_oracle(L, Nt, prec, tol):
+    taps = _oracle_taps()
+    v = inputs.gauss_cvec(L, Nt, 31 + L)
+    cdt = torch.complex128 if prec == "fp64" else torch.complex64
+    with Q.Lattice(L, Nt) as lat:
+        out = _host(lat.apply_precond(_dev(v, cdt), prec=prec))
+    assert _rel(out, PC.apply_P(taps, v)) < tol
+
+
+@pytest.mark.parametrize("which", ["pi", "noisy", "hot"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_pcg_small_vs_oracle(which, prec):
+    L, Nt = 8, 40
+    p = O.lat(L, Nt)
+    th = {"pi": inputs.pi_flux_theta(L, Nt), "noisy": inputs.noisy_pi_flux_theta(L, Nt, 0.3, 5),
+          "hot": inputs.hot_start_theta(L, Nt, 5)}[which]
+    eta = O.apply_M(p, th, inputs.gauss_cvec(L, Nt, 7), dagger=True).reshape(Nt, L, L)
+    tol = 1e-10
+    taps = _oracle_taps()
+    Xo, _, ito, relo = O.cg_solve(p, th, eta, tol=tol,
+                                  precond=lambda r: PC.apply_P(taps, r.reshape(Nt, L, L)).reshape(-1))
+    with Q.Lattice(L, Nt) as lat:
+        x0, st0, it0, rel0 = lat.cg_solve(_dev(th), _dev(eta), tol=tol, prec=prec)
+        x, st, it, rel = lat.cg_solve(_dev(th), _dev(eta), tol=tol, prec=prec, precond="paper")
+        xg = _host(x)
+    print(which, prec, "iterations none", it0, "paper", it, "oracle paper", ito, flush=True)
+    assert st == Q.OK and rel <= tol
+    true = np.linalg.norm(eta.reshape(-1) - O.apply_MdagM(p, th, xg).reshape(-1)) / np.linalg.norm(eta)
+    assert true <= 1.05 * tol
+    assert it < 0.6 * it0
+    lam = np.linalg.eigvalsh(O.dense_MdagM(p, th))[0]
+    assert np.linalg.norm(xg.reshape(-1) - Xo.reshape(-1)) <= 1.01 * (rel + relo) * np.linalg.norm(eta) / lam
+    if prec == "fp64":
+        assert abs(it - ito) <= max(2, ito // 20), (it, ito)
+
+
+@pytest.mark.parametrize("wl_name", ["mixed_l24", "mixed_l24_hot"])
+def test_pcg_full_size(wl_name):
+    wl = inputs.WORKLOADS[wl_name]
+    p = O.lat(wl.L, wl.Nt)
+    th = wl.initial_theta()
+    R = inputs.gauss_cvec(wl.L, wl.Nt, wl.seed + 1)
+    eta = O.apply_M(p, th, R, dagger=True).reshape(wl.Nt, wl.L, wl.L)
+    with Q.Lattice(wl.L, wl.Nt) as lat:
+        x0, st0, it0, rel0 = lat.cg_solve(_dev(th), _dev(eta), tol=wl.tol, prec="fp32")
+        x, st, it, rel = lat.cg_solve(_dev(th), _dev(eta), tol=wl.tol, prec="fp32", precond="paper")
+        xg, x0g = _host(x), _host(x0)
+    print(wl_name, "iterations none", it0, "paper", it, flush=True)
+    assert st == Q.OK and rel <= wl.tol
+    true = np.linalg.norm(eta.reshape(-1) - O.apply_MdagM(p, th, xg).reshape(-1)) / np.linalg.norm(eta)
+    assert true <= 1.05 * wl.tol
+    assert it < it0
+
+
+def test_trajectory_with_and_without_preconditioner():
+    """Same chain step with and without P (benchmark workload): the solves
+    differ only within the CG tolerance, so dH agrees to 1e-6 |H0|."""
+    wl = inputs.WORKLOADS["mixed_l24"]
+    th = wl.initial_theta()
+    out = {}
+    with Q.Lattice(wl.L, wl.Nt, seed=wl.seed) as lat:
+        for pc in (None, "paper"):
+            thd = _dev(th)
+            out[pc] = lat.hmc_trajectory(thd, 0, wl.n_steps, wl.traj_len, wl.tol, prec="fp32", precond=pc)
+            print(pc, out[pc], flush=True)
+    a, b = out[None], out["paper"]
+    assert b["status"] == 0 and b["max_true_resid"] <= wl.tol
+    assert abs(a["dH"] - b["dH"]) <= 1e-6 * abs(a["H0"])
+    assert a["accepted"] == b["accepted"]
+    assert b["cg_iters_total"] < a["cg_iters_total"]
