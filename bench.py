@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="mixed_l24")
     ap.add_argument("--prec", default=None, help="override: fp64 or mixed")
+    ap.add_argument("--precond", default="none", choices=["none", "paper"],
+                    help="CG preconditioner: none, or the paper's G^dag G stencil")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=200, help="oracle CG iterations in the CPU sample")
     ap.add_argument("--profile-every", type=int, default=8)
@@ -96,14 +98,15 @@ def main():
     # load every kernel once (code objects, LDS attributes) before timing
     v = torch.zeros((wl.Nt, wl.L, wl.L), dtype=torch.complex128, device="cuda")
     v[0, 0, 0] = 1.0
-    lat.cg_solve(theta, v, tol=1e-3, maxit=50, prec=prec)
+    pc = None if a.precond == "none" else a.precond
+    lat.cg_solve(theta, v, tol=1e-3, maxit=50, prec=prec, precond=pc)
     lat.fermion_force(theta, v, prec=prec)
     lat.bosonic_action_force(theta)
     torch.cuda.synchronize()
 
     traj = 0
     for _ in range(a.warmup):
-        lat.hmc_trajectory(theta, traj, wl.n_steps, wl.traj_len, wl.tol, prec=prec)
+        lat.hmc_trajectory(theta, traj, wl.n_steps, wl.traj_len, wl.tol, prec=prec, precond=pc)
         traj += 1
     torch.cuda.synchronize()
 
@@ -112,7 +115,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(a.steps):
-        results.append(lat.hmc_trajectory(theta, traj, wl.n_steps, wl.traj_len, wl.tol, prec=prec))
+        results.append(lat.hmc_trajectory(theta, traj, wl.n_steps, wl.traj_len, wl.tol, prec=prec, precond=pc))
         traj += 1
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -161,7 +164,7 @@ def main():
                          f"theta {wl.theta}{' sigma %g' % wl.sigma if wl.sigma else ''}, {wl.n_steps} leapfrog steps, length {wl.traj_len}, "
                          f"CG true residual {wl.tol}, {'mixed FP32/FP64' if prec != 'fp64' else 'FP64'}"),
             "L": wl.L, "Nt": wl.Nt, "sites": N, "n_steps": wl.n_steps, "tol": wl.tol,
-            "precision": prec,
+            "precision": prec, "preconditioner": a.precond,
         },
         "matvec_gbs": mv_gbs,
         "matvec": {"kernel": f"k_mdagm<{'float' if prec != 'fp64' else 'double'}> (standalone fused M^dag M)",

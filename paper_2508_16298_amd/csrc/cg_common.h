@@ -13,7 +13,9 @@ enum {
     S_APREV = 1,   // alpha_{i-1}
     S_ITERS = 2,   // completed iterations i
     S_DONE = 3,    // 0 running, 1 stop (target reached / converged), 2 pause for a reliable update,
-                   // 3 pause with restart (non-positive <p, O p>), 4 breakdown (non-finite)
+                   // 3 pause with restart (non-positive <p, O p>), 4 breakdown (non-finite);
+                   // the batched driver adds 4 final failure, 5 verified convergence,
+                   // 6 iteration budget used (true residual pending)
     S_FIRST = 4,   // 1: next iteration starts a new direction sequence (beta = 0)
     S_B2 = 5,      // |rhs|^2 (FP64); < 0 until the first iteration sets it
     S_TARGET = 6,  // tol^2 |rhs|^2
@@ -21,6 +23,9 @@ enum {
     S_ITUPD = 8,   // iteration of the last reliable update
     S_TRUE = 9,    // last FP64 true |r|^2
     S_GCUR = 10,   // gamma_i of the current state
+    S_STALL = 11,  // batched driver: consecutive updates without progress
+    S_LASTUP = 12, // batched driver: 1 + iteration of the last update (0: none)
+    S_NREL = 13,   // batched driver: updates so far
     S_NSLOT = 16,
 };
 // Per-slice partials of one parity: <r,r>, <w,r>, <r,s>, <p,w>, <p,s>, aux
@@ -112,8 +117,8 @@ struct SliceCtx {
 };
 
 template <int MC>
-__device__ __forceinline__ void slice_ctx(const Lat& lt, SliceCtx<MC>& c) {
-    c.tau = blockIdx.x;
+__device__ __forceinline__ void slice_ctx(const Lat& lt, SliceCtx<MC>& c, int tau) {
+    c.tau = tau;
     c.tm = c.tau == 0 ? lt.Nt - 1 : c.tau - 1;
     c.tp = c.tau == lt.Nt - 1 ? 0 : c.tau + 1;
 #pragma unroll

@@ -422,7 +422,7 @@ __global__ __launch_bounds__(BS) void k_pcg_mv(Lat lt, PcgBufs<R> B, const cplx<
     cplx<R>* buf2 = reinterpret_cast<cplx<R>*>(smem);
     double* red = reinterpret_cast<double*>(smem + (size_t)NB * 2 * lt.Vs * sizeof(cplx<R>));
     SliceCtx<MC> c;
-    slice_ctx<MC>(lt, c);
+    slice_ctx<MC>(lt, c, blockIdx.x);
     const size_t Vs = lt.Vs;
     cplx<R> hm[MC][12], ht[MC][12];
     hops_of<R, MC>(gauge, lt, c.tm, c.idx, co, hm);
