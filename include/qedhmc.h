@@ -191,6 +191,68 @@ qedhmc_status qedhmc_hmc_trajectory(qedhmc_t h, double *theta_inout,
                                     qedhmc_precision prec, qedhmc_precond pc,
                                     qedhmc_traj_result *out);
 
+/* ------------------------------------------------------------------------
+ * Batched chains: many independent Markov chains, each on its own lattice
+ * (sizes may differ), advanced together on one device.  Every chain runs
+ * exactly the single-lattice trajectory of qedhmc_hmc_trajectory (same
+ * heat bath streams from its own seed, same leapfrog, same Metropolis); the
+ * chains' CG solves share each kernel launch (one launch performs one
+ * iteration of every chain still running), with per-chain scalars,
+ * reliable updates and stopping.  Methods, "HQMC algorithm"; the batching
+ * itself is not in the paper.
+ *
+ * Layout: all chains' arrays are concatenated in chain order.  theta_all,
+ * momenta and forces: double, chain c at offset theta_off[c] (2*Nt*L*L
+ * doubles per chain); complex vectors: chain c at complex offset vec_off[c]
+ * (Nt*L*L elements).  The offsets come from qedhmc_batch_layout.
+ *
+ * Limits: every lattice must fit one workgroup per time slice with at most
+ * two 2x2 cells per thread (L <= 44; QEDHMC_EUNSUPPORTED otherwise).
+ * Preconditioning is not offered on batches. */
+typedef struct qedhmc_batch *qedhmc_batch_t;
+
+/* Create n_chains handles from params[0..n_chains-1] (each validated as by
+ * qedhmc_init_lattice) on one stream, and pick the tile shape of the batched
+ * CG kernels by timing every candidate on these lattices.  Synchronises the
+ * stream.  On failure nothing is left allocated and *out is NULL. */
+qedhmc_status qedhmc_batch_create(const qedhmc_params *params,
+                                  int32_t n_chains, void *stream,
+                                  qedhmc_batch_t *out);
+qedhmc_status qedhmc_batch_destroy(qedhmc_batch_t b);
+
+/* Offsets into the concatenated arrays, host int64[n_chains + 1] each; the
+ * last entry is the total length. */
+qedhmc_status qedhmc_batch_layout(qedhmc_batch_t b, int64_t *theta_off,
+                                  int64_t *vec_off);
+
+/* The tile shape the autotuner chose for the CG recursion in precision
+ * prec (cells per thread, threads per workgroup, LDS exchange buffers) and
+ * the measured time per batched CG iteration of each of the four candidate
+ * shapes in microseconds (host float[4]; 0 for a candidate that does not
+ * fit). */
+qedhmc_status qedhmc_batch_tile(qedhmc_batch_t b, qedhmc_precision prec,
+                                int32_t *cells_per_thread, int32_t *threads,
+                                int32_t *exchange_buffers, float *us_per_iter);
+
+/* Solve M^dag M x_c = rhs_c for every chain c at once (as qedhmc_cg_solve
+ * without preconditioner).  theta_all, rhs_all, x_all: device, concatenated;
+ * iters, true_rel: host arrays of n_chains.  QEDHMC_ENOCONV when any chain
+ * did not converge (every x still written). */
+qedhmc_status qedhmc_batch_cg_solve(qedhmc_batch_t b, const double *theta_all,
+                                    const double *rhs_all, double *x_all,
+                                    double tol, int32_t maxit,
+                                    qedhmc_precision prec, int32_t *iters,
+                                    double *true_rel);
+
+/* One trajectory of every chain (as qedhmc_hmc_trajectory with
+ * QEDHMC_PC_NONE).  theta_all: device, concatenated, updated per chain on
+ * acceptance; out: host array of n_chains results. */
+qedhmc_status qedhmc_batch_trajectory(qedhmc_batch_t b, double *theta_all,
+                                      uint64_t traj_index, int32_t n_steps,
+                                      double traj_len, double tol,
+                                      int32_t maxit, qedhmc_precision prec,
+                                      qedhmc_traj_result *out);
+
 /* Kernel timing for measurement (not part of the method).  qedhmc_profile
  * with every > 0 times every every-th launch of the timed kernel classes
  * with the start and end events of the dispatch itself

@@ -118,3 +118,13 @@ def chain_sizes(n_chains: int = 64, seed: int = 1004, sizes=(8, 12, 16, 20)) -> 
     """Linear sizes of independent chains, drawn uniformly from ``sizes``."""
     rng = np.random.default_rng(seed)
     return [int(x) for x in rng.choice(np.asarray(sizes), size=n_chains)]
+
+
+def batched_chain_inputs(n_chains: int = 64, seed: int = 1004, sigma: float = 0.3):
+    """The batched-chains workload: sizes (L, 10 L) with L drawn from
+    8/12/16/20, starting angles pi flux plus N(0, sigma^2) noise, and one
+    heat-bath seed per chain."""
+    sizes = [(L, 10 * L) for L in chain_sizes(n_chains, seed)]
+    seeds = [seed * 1000 + c for c in range(n_chains)]
+    thetas = [noisy_pi_flux_theta(L, Nt, sigma, s) for (L, Nt), s in zip(sizes, seeds)]
+    return sizes, thetas, seeds

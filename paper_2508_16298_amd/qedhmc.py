@@ -81,6 +81,14 @@ def load():
         "qedhmc_profile_read": [_P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
         "qedhmc_hmc_trajectory": [_P, _P, C.c_uint64, C.c_int32, C.c_double, C.c_double, C.c_int32,
                                   C.c_int, C.c_int, C.POINTER(TrajResult)],
+        "qedhmc_batch_create": [C.POINTER(Params), C.c_int32, _P, C.POINTER(_P)],
+        "qedhmc_batch_destroy": [_P],
+        "qedhmc_batch_layout": [_P, _P, _P],
+        "qedhmc_batch_tile": [_P, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                              _P],
+        "qedhmc_batch_cg_solve": [_P, _P, _P, _P, C.c_double, C.c_int32, C.c_int, _P, _P],
+        "qedhmc_batch_trajectory": [_P, _P, C.c_uint64, C.c_int32, C.c_double, C.c_double, C.c_int32,
+                                    C.c_int, _P],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -274,6 +282,97 @@ class Lattice:
         ms = C.c_double(0.0)
         _check(load().qedhmc_profile_read(self.h, int(kernel_class), C.byref(n), C.byref(ms)))
         return n.value, ms.value
+
+
+class Batch:
+    """Independent chains on lattices of different sizes, advanced together
+    (qedhmc_batch_create); bound to torch's current stream at creation.
+
+    Concatenated layouts: theta_all float64 (theta_off[-1],) with chain c at
+    theta_off[c] in (2, Nt_c, L_c, L_c) order; vectors complex128
+    (vec_off[-1],) with chain c at vec_off[c]."""
+
+    def __init__(self, sizes, dtau=0.1, t=1.0, J=1.0, K=1.0, seeds=None):
+        import numpy as np
+        import torch
+        self._torch = torch
+        self.sizes = [(int(L), int(Nt)) for L, Nt in sizes]
+        n = len(self.sizes)
+        seeds = list(range(n)) if seeds is None else [int(s) for s in seeds]
+        arr = (Params * n)(*[Params(L, Nt, dtau, t, J, K, sd) for (L, Nt), sd in zip(self.sizes, seeds)])
+        self.params = arr
+        h = _P()
+        _check(load().qedhmc_batch_create(arr, n, _stream_handle(), C.byref(h)))
+        self.h = h
+        self.theta_off = np.zeros(n + 1, dtype=np.int64)
+        self.vec_off = np.zeros(n + 1, dtype=np.int64)
+        _check(load().qedhmc_batch_layout(self.h, self.theta_off.ctypes.data_as(C.c_void_p),
+                                          self.vec_off.ctypes.data_as(C.c_void_p)))
+
+    @property
+    def n(self):
+        return len(self.sizes)
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().qedhmc_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def theta_view(self, theta_all, c):
+        L, Nt = self.sizes[c]
+        return theta_all[self.theta_off[c]:self.theta_off[c + 1]].view(2, Nt, L, L)
+
+    def vec_view(self, v_all, c):
+        L, Nt = self.sizes[c]
+        return v_all[self.vec_off[c]:self.vec_off[c + 1]].view(Nt, L, L)
+
+    def tile(self, prec="fp32"):
+        """(cells_per_thread, threads, exchange_buffers, us_per_iter[4]) chosen by the autotuner."""
+        import numpy as np
+        mc, nt, nb = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+        us = np.zeros(4, dtype=np.float32)
+        _check(load().qedhmc_batch_tile(self.h, _PREC[prec], C.byref(mc), C.byref(nt), C.byref(nb),
+                                        us.ctypes.data_as(C.c_void_p)))
+        return mc.value, nt.value, nb.value, us
+
+    def _check_all(self, t, n, dtype):
+        assert t.is_cuda and t.dtype == dtype and t.is_contiguous() and t.numel() == n, (t.shape, t.dtype)
+
+    def cg_solve(self, theta_all, rhs_all, tol=1e-10, maxit=1_000_000, prec="fp64", x_all=None):
+        """Returns (x_all, status, iters[n], true_rel[n])."""
+        import numpy as np
+        torch = self._torch
+        self._check_all(theta_all, int(self.theta_off[-1]), torch.float64)
+        self._check_all(rhs_all, int(self.vec_off[-1]), torch.complex128)
+        x_all = torch.empty_like(rhs_all) if x_all is None else x_all
+        it = np.zeros(self.n, dtype=np.int32)
+        rel = np.zeros(self.n)
+        st = _check(load().qedhmc_batch_cg_solve(self.h, _ptr(theta_all), _ptr(rhs_all), _ptr(x_all),
+                                                 float(tol), int(maxit), _PREC[prec],
+                                                 it.ctypes.data_as(C.c_void_p),
+                                                 rel.ctypes.data_as(C.c_void_p)),
+                    allow=(OK, ENOCONV))
+        return x_all, st, it, rel
+
+    def trajectory(self, theta_all, traj, n_steps, traj_len=1.0, tol=1e-10, maxit=1_000_000, prec="fp64"):
+        """theta_all updated per chain in place; returns a list of result dicts."""
+        self._check_all(theta_all, int(self.theta_off[-1]), self._torch.float64)
+        res = (TrajResult * self.n)()
+        _check(load().qedhmc_batch_trajectory(self.h, _ptr(theta_all), int(traj), int(n_steps),
+                                              float(traj_len), float(tol), int(maxit), _PREC[prec], res))
+        return [r.as_dict() for r in res]
 
 
 def init_lattice(L, Nt, **kw):
