@@ -125,6 +125,24 @@ def batched_chain_inputs(n_chains: int = 64, seed: int = 1004, sigma: float = 0.
     8/12/16/20, starting angles pi flux plus N(0, sigma^2) noise, and one
     heat-bath seed per chain."""
     sizes = [(L, 10 * L) for L in chain_sizes(n_chains, seed)]
-    seeds = [seed * 1000 + c for c in range(n_chains)]
+    seeds = [4000 + c for c in range(n_chains)]
     thetas = [noisy_pi_flux_theta(L, Nt, sigma, s) for (L, Nt), s in zip(sizes, seeds)]
     return sizes, thetas, seeds
+
+
+NET_CHANNELS = (6, 32, 32, 32, 32, 32, 2)
+
+
+def net_init_weights(seed: int, ch=NET_CHANNELS):
+    """Initial weights of the preconditioner network: per layer W of shape
+    (Cout, Cin, 27) drawn N(0, 2 / (27 Cin)) (the last layer scaled by 0.1)
+    and zero biases."""
+    rng = np.random.default_rng(seed)
+    params = []
+    for l in range(len(ch) - 1):
+        cin, cout = ch[l], ch[l + 1]
+        W = rng.normal(0.0, np.sqrt(2.0 / (27 * cin)), size=(cout, cin, 27))
+        if l == len(ch) - 2:
+            W *= 0.1
+        params.append((W, np.zeros(cout)))
+    return params
