@@ -47,7 +47,51 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=200, help="oracle CG iterations in the CPU sample")
     ap.add_argument("--profile-every", type=int, default=8)
+    ap.add_argument("--solve-only", type=int, default=0, metavar="MAXIT",
+                    help="counter runs: one solve of MAXIT iterations plus 200 standalone M^dag M "
+                         "launches on the workload instead of trajectories (same kernels and launch shapes)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="counter calibration: 5 device copies of 256 MiB (torch copy kernel)")
     return ap.parse_args()
+
+
+def run_copy_calibration():
+    """A plain copy of known size, for scaling the HBM byte counters
+    (FETCH_SIZE, WRITE_SIZE) of the profiler: each launch reads and writes
+    exactly 256 MiB."""
+    import torch
+    n = 64 * 2 ** 20
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n,
+                                           "launches": 5}}), flush=True)
+
+
+def run_solve_only(a):
+    """One mixed-precision solve of a fixed iteration count on the workload
+    (k_cg_iter in the trajectory's launch shape) and 200 standalone M^dag M
+    launches; prints the iteration count."""
+    import torch
+    from paper_2508_16298_amd import inputs
+    from paper_2508_16298_amd import qedhmc as Q
+    wl = inputs.WORKLOADS[a.workload]
+    prec = a.prec or wl.precision
+    theta = torch.from_numpy(wl.initial_theta()).cuda()
+    with Q.Lattice(wl.L, wl.Nt, dtau=wl.dtau, t=wl.t, J=wl.J, K=wl.K, seed=wl.seed) as lat:
+        _, R = lat.heatbath(0)
+        eta = lat.apply_M(theta, R, dagger=True)
+        x, st, it, rel = lat.cg_solve(theta, eta, tol=1e-30, maxit=a.solve_only, prec=prec)
+        cdt = torch.complex64 if prec != "fp64" else torch.complex128
+        vin = torch.from_numpy(inputs.gauss_cvec(wl.L, wl.Nt, 99)).to(cdt).cuda()
+        vout = torch.empty_like(vin)
+        for _ in range(200):
+            lat.apply_MdagM(theta, vin, prec="fp32" if prec != "fp64" else "fp64", out=vout)
+        torch.cuda.synchronize()
+    print(json.dumps({"solve_only": {"workload": wl.name, "iterations": it, "true_rel": rel,
+                                     "matvec_launches": 200}}), flush=True)
 
 
 def cpu_baseline(wl, total_cg_iters, n_solves, n_iter):
@@ -79,12 +123,81 @@ def cpu_baseline(wl, total_cg_iters, n_solves, n_iter):
     }
 
 
+def run_batched(a):
+    """--workload batched_chains: 64 independent chains, L drawn from
+    8/12/16/20 (seed 1004), Nt = 10 L, chain c with heat-bath seed 4000 + c,
+    pi flux plus noise, mixed precision, 20 leapfrog steps, CG residual 1e-8;
+    one step = one trajectory of every chain; value = sites x trajectories
+    per second.  The roofline block is the batched CG iteration k_b_cg_iter at the
+    autotuned tile shape, timed by the autotuner with events around 24
+    back-to-back launches with every chain active (104 B per site of every
+    chain, as k_cg_iter)."""
+    import numpy as np
+    import torch
+    from paper_2508_16298_amd import inputs
+    from paper_2508_16298_amd import qedhmc as Q
+
+    wl = inputs.WORKLOADS["batched_chains"]
+    prec = a.prec or wl.precision
+    sizes, ths, seeds = inputs.batched_chain_inputs()
+    theta = torch.from_numpy(np.concatenate([t.reshape(-1) for t in ths])).cuda()
+    b = Q.Batch(sizes, dtau=wl.dtau, t=wl.t, J=wl.J, K=wl.K, seeds=seeds)
+    traj = 0
+    for _ in range(a.warmup):
+        b.trajectory(theta, traj, wl.n_steps, wl.traj_len, wl.tol, prec=prec)
+        traj += 1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for _ in range(a.steps):
+        results.append(b.trajectory(theta, traj, wl.n_steps, wl.traj_len, wl.tol, prec=prec))
+        traj += 1
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    mc, nt, nb, us = b.tile("fp32" if prec != "fp64" else "fp64")
+    shape_idx = {(1, 2): 0, (2, 2): 1, (1, 1): 2, (2, 1): 3}[(mc, nb)]
+    N = sum(L * L * Nt for L, Nt in sizes)
+    it_bytes = (104 if prec != "fp64" else 176) * N
+    it_us = float(us[shape_idx])
+    achieved = it_bytes / (it_us * 1e-6) / 1e9
+    s_per = elapsed / a.steps
+    per_chain_iters = [sum(r[c]["cg_iters_total"] for r in results) / a.steps for c in range(len(sizes))]
+    out = {
+        "metric": "lattice-site updates per s, 64 batched chains of uneven L (one update = one space-time "
+                  "site advanced by one trajectory)",
+        "value": N / s_per, "unit": "site-updates/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": 1e3 * s_per, "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
+        "dtype": "c64+f64" if prec != "fp64" else "c128", "data": "synthetic",
+        "config": {"workload": (f"batched_chains: {len(sizes)} chains, L in {sorted(set(L for L, _ in sizes))}, "
+                                f"Nt = 10 L, {N} sites, theta pi flux + N(0, 0.3^2), {wl.n_steps} leapfrog "
+                                f"steps, CG true residual {wl.tol}, {prec}"),
+                   "chains": len(sizes), "sites": N, "precision": prec},
+        "chain_traj_per_s": len(sizes) / s_per,
+        "cg_iters_per_chain_traj": {"mean": float(np.mean(per_chain_iters)), "max": float(np.max(per_chain_iters))},
+        "accept_rate": float(np.mean([r[c]["accepted"] for r in results for c in range(len(sizes))])),
+        "tile": {"cells_per_thread": mc, "threads": nt, "exchange_buffers": nb,
+                 "us_per_iter_candidates": [float(x) for x in us]},
+        "roofline": {"bound": "hbm", "kernel": "k_b_cg_iter (batched fused CG iteration, all chains)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_launch": it_bytes, "avg_launch_us": it_us, "timed_launches": "24, best of 2"},
+    }
+    b.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {a.gpus} is not supported (this path has no "
               "multi-GPU sharding; see DESIGN.md for how it would shard along tau)", file=sys.stderr)
         sys.exit(2)
+    if a.copy_calibration:
+        return run_copy_calibration()
+    if a.workload == "batched_chains":
+        return run_batched(a)
+    if a.solve_only:
+        return run_solve_only(a)
     import torch
     from paper_2508_16298_amd import inputs
     from paper_2508_16298_amd import qedhmc as Q

@@ -12,7 +12,9 @@ template <typename R, int MC, int NB, int BS>
 __global__ __launch_bounds__(BS) void k_cg_start(Lat lt, CgBufs<R> B, const cplx<R>* __restrict__ gauge, Coef<R> co,
                                                  double* __restrict__ scal) {
     extern __shared__ __align__(16) unsigned char smem[];
-    cg_start_body<R, MC, NB>(lt, B, gauge, co, scal, blockIdx.x, blockIdx.x == 0, smem);
+    const int tau = slice_of_block(blockIdx.x, lt.Nt);
+    if (tau < 0) return;
+    cg_start_body<R, MC, NB>(lt, B, gauge, co, scal, tau, tau == 0, smem);
 }
 
 template <typename R, int MC, int NB, int BS>
@@ -20,14 +22,18 @@ __global__ __launch_bounds__(BS) void k_cg_iter(Lat lt, CgBufs<R> B, const cplx<
                                                 double* __restrict__ scal, int kpar, int ipar, double tol2,
                                                 int mixed) {
     extern __shared__ __align__(16) unsigned char smem[];
-    cg_iter_body<R, MC, NB>(lt, B, gauge, co, scal, kpar, ipar, tol2, mixed, blockIdx.x, blockIdx.x == 0, smem);
+    const int tau = slice_of_block(blockIdx.x, lt.Nt);
+    if (tau < 0) return;
+    cg_iter_body<R, MC, NB>(lt, B, gauge, co, scal, kpar, ipar, tol2, mixed, tau, tau == 0, smem);
 }
 
 template <typename R, int MC, int NB, int BS>
 __global__ __launch_bounds__(BS) void k_cg_replace(Lat lt, CgBufs<R> B, const cplx<R>* __restrict__ gauge,
                                                    Coef<R> co, const double* __restrict__ scal, int kpar) {
     extern __shared__ __align__(16) unsigned char smem[];
-    cg_replace_body<R, MC, NB>(lt, B, gauge, co, scal, kpar, blockIdx.x, smem);
+    const int tau = slice_of_block(blockIdx.x, lt.Nt);
+    if (tau < 0) return;
+    cg_replace_body<R, MC, NB>(lt, B, gauge, co, scal, kpar, tau, smem);
 }
 
 __global__ void k_cg_check(double* __restrict__ scal, int kpar, const double* __restrict__ part, int Nt,
@@ -63,7 +69,7 @@ template <typename R>
 static qedhmc_status launch_start(qedhmc_ctx* h, const CgBufs<R>& B) {
     return with_shape<R>(h, [&]<int MC, int NB, int BS>(int nt, size_t lds) -> qedhmc_status {
         QH_TRY(lds_attr(h, k_cg_start<R, MC, NB, BS>, lds));
-        hipLaunchKernelGGL((k_cg_start<R, MC, NB, BS>), dim3(h->lat.Nt), dim3(nt), lds, h->stream, h->lat, B,
+        hipLaunchKernelGGL((k_cg_start<R, MC, NB, BS>), dim3(slice_grid(h->lat.Nt)), dim3(nt), lds, h->stream, h->lat, B,
                            gauge_for<R>(h), coef_of<R>(h->p), h->scal);
         QH_HIP(hipGetLastError());
         return QEDHMC_OK;
@@ -82,10 +88,10 @@ static qedhmc_status launch_iters(qedhmc_ctx* h, const CgBufs<R>& B, int& kpar, 
             hipEvent_t e0, e1;
             const int ipar = (it0 + k) & 1;
             if (prof_sample(h, cls, e0, e1))
-                hipExtLaunchKernelGGL((k_cg_iter<R, MC, NB, BS>), dim3(h->lat.Nt), dim3(nt), lds, h->stream, e0, e1,
+                hipExtLaunchKernelGGL((k_cg_iter<R, MC, NB, BS>), dim3(slice_grid(h->lat.Nt)), dim3(nt), lds, h->stream, e0, e1,
                                       0, h->lat, B, g, co, h->scal, kpar, ipar, tol2, mixed);
             else
-                hipLaunchKernelGGL((k_cg_iter<R, MC, NB, BS>), dim3(h->lat.Nt), dim3(nt), lds, h->stream, h->lat, B,
+                hipLaunchKernelGGL((k_cg_iter<R, MC, NB, BS>), dim3(slice_grid(h->lat.Nt)), dim3(nt), lds, h->stream, h->lat, B,
                                    g, co, h->scal, kpar, ipar, tol2, mixed);
             kpar ^= 1;
         }
@@ -99,7 +105,7 @@ static qedhmc_status launch_true(qedhmc_ctx* h, const CgBufs<R>& B, const double
     QH_TRY(launch_mdagm(h, QEDHMC_FP64, x, h->ws[3], nullptr));
     QH_TRY(with_shape<R>(h, [&]<int MC, int NB, int BS>(int nt, size_t lds) -> qedhmc_status {
         QH_TRY(lds_attr(h, k_cg_replace<R, MC, NB, BS>, lds));
-        hipLaunchKernelGGL((k_cg_replace<R, MC, NB, BS>), dim3(h->lat.Nt), dim3(nt), lds, h->stream, h->lat, B,
+        hipLaunchKernelGGL((k_cg_replace<R, MC, NB, BS>), dim3(slice_grid(h->lat.Nt)), dim3(nt), lds, h->stream, h->lat, B,
                            gauge_for<R>(h), coef_of<R>(h->p), (const double*)h->scal, kpar);
         QH_HIP(hipGetLastError());
         return QEDHMC_OK;

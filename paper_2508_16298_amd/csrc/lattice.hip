@@ -140,7 +140,8 @@ __global__ __launch_bounds__(BS) void k_apply_M(Lat lt, int dagger, const cplx<R
                                                   Coef<R> co) {
     extern __shared__ __align__(16) unsigned char smem[];
     Xchg<R, NB> xb{reinterpret_cast<cplx<R>*>(smem), lt.Vs, 0};
-    const int tau = blockIdx.x, Nt = lt.Nt;
+    const int tau = slice_of_block(blockIdx.x, lt.Nt), Nt = lt.Nt;
+    if (tau < 0) return;
     int src, bsl;
     R sgn;
     if (!dagger) {
@@ -181,7 +182,8 @@ __global__ __launch_bounds__(BS) void k_mdagm(Lat lt, const cplx<R>* __restrict_
     extern __shared__ __align__(16) unsigned char smem[];
     cplx<R>* buf2 = reinterpret_cast<cplx<R>*>(smem);
     double* red = reinterpret_cast<double*>(smem + (size_t)NB * 2 * lt.Vs * sizeof(cplx<R>));
-    const int tau = blockIdx.x, Nt = lt.Nt;
+    const int tau = slice_of_block(blockIdx.x, lt.Nt), Nt = lt.Nt;
+    if (tau < 0) return;
     const int tm = tau == 0 ? Nt - 1 : tau - 1, tp = tau == Nt - 1 ? 0 : tau + 1;
     const R eps_m = tau == 0 ? R(-1) : R(1);
     const R eps_t = tau == Nt - 1 ? R(-1) : R(1);
@@ -320,7 +322,8 @@ __global__ __launch_bounds__(BS) void k_force(Lat lt, const cplx<R>* __restrict_
     extern __shared__ __align__(16) unsigned char smem[];
     cplx<R>* bu = reinterpret_cast<cplx<R>*>(smem);
     cplx<R>* bw = bu + lt.Vs;
-    const int tau = blockIdx.x, Nt = lt.Nt;
+    const int tau = slice_of_block(blockIdx.x, lt.Nt), Nt = lt.Nt;
+    if (tau < 0) return;
     const int tn = tau == Nt - 1 ? 0 : tau + 1;
     const R sg = tau == Nt - 1 ? R(1) : R(-1);
 
@@ -438,11 +441,11 @@ static qedhmc_status mdagm_t(qedhmc_ctx* h, const void* in, void* out, double* p
             QH_TRY(allow_lds(h, k_mdagm<R, MC, NB, BS>, lds));
             hipEvent_t e0, e1;
             if (prof_sample(h, sizeof(R) == 4 ? QEDHMC_K_MDAGM_FP32 : QEDHMC_K_MDAGM_FP64, e0, e1))
-                hipExtLaunchKernelGGL((k_mdagm<R, MC, NB, BS>), dim3(h->lat.Nt), dim3(s.nt), lds, h->stream, e0, e1,
+                hipExtLaunchKernelGGL((k_mdagm<R, MC, NB, BS>), dim3(slice_grid(h->lat.Nt)), dim3(s.nt), lds, h->stream, e0, e1,
                                       0, h->lat, (const cplx<R>*)in, (cplx<R>*)out, gauge_of<R>(h),
                                       coef_of<R>(h->p), pdot);
             else
-                hipLaunchKernelGGL((k_mdagm<R, MC, NB, BS>), dim3(h->lat.Nt), dim3(s.nt), lds, h->stream, h->lat,
+                hipLaunchKernelGGL((k_mdagm<R, MC, NB, BS>), dim3(slice_grid(h->lat.Nt)), dim3(s.nt), lds, h->stream, h->lat,
                                    (const cplx<R>*)in, (cplx<R>*)out, gauge_of<R>(h), coef_of<R>(h->p), pdot);
             QH_HIP(hipGetLastError());
             return QEDHMC_OK;
@@ -463,7 +466,7 @@ static qedhmc_status M_t(qedhmc_ctx* h, const void* in, void* out, int dagger) {
         auto run = [&]<int NB>() -> qedhmc_status {
             const size_t lds = (size_t)NB * h->lat.Vs * sizeof(cplx<R>);
             QH_TRY(allow_lds(h, k_apply_M<R, MC, NB, BS>, lds));
-            hipLaunchKernelGGL((k_apply_M<R, MC, NB, BS>), dim3(h->lat.Nt), dim3(s.nt), lds, h->stream, h->lat,
+            hipLaunchKernelGGL((k_apply_M<R, MC, NB, BS>), dim3(slice_grid(h->lat.Nt)), dim3(s.nt), lds, h->stream, h->lat,
                                dagger, (const cplx<R>*)in, (cplx<R>*)out, gauge_of<R>(h), coef_of<R>(h->p));
             QH_HIP(hipGetLastError());
             return QEDHMC_OK;
@@ -508,10 +511,10 @@ static qedhmc_status force_t(qedhmc_ctx* h, const void* X, const void* Y, double
         QH_TRY(allow_lds(h, k_force<R, MC, BS>, lds));
         hipEvent_t e0, e1;
         if (prof_sample(h, QEDHMC_K_FORCE, e0, e1))
-            hipExtLaunchKernelGGL((k_force<R, MC, BS>), dim3(h->lat.Nt), dim3(s.nt), lds, h->stream, e0, e1, 0,
+            hipExtLaunchKernelGGL((k_force<R, MC, BS>), dim3(slice_grid(h->lat.Nt)), dim3(s.nt), lds, h->stream, e0, e1, 0,
                                   h->lat, (const cplx<R>*)X, (const cplx<R>*)Y, gauge_of<R>(h), coef_of<R>(h->p), F);
         else
-            hipLaunchKernelGGL((k_force<R, MC, BS>), dim3(h->lat.Nt), dim3(s.nt), lds, h->stream, h->lat,
+            hipLaunchKernelGGL((k_force<R, MC, BS>), dim3(slice_grid(h->lat.Nt)), dim3(s.nt), lds, h->stream, h->lat,
                                (const cplx<R>*)X, (const cplx<R>*)Y, gauge_of<R>(h), coef_of<R>(h->p), F);
         QH_HIP(hipGetLastError());
         return QEDHMC_OK;

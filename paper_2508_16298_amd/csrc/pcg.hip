@@ -421,8 +421,10 @@ __global__ __launch_bounds__(BS) void k_pcg_mv(Lat lt, PcgBufs<R> B, const cplx<
     extern __shared__ __align__(16) unsigned char smem[];
     cplx<R>* buf2 = reinterpret_cast<cplx<R>*>(smem);
     double* red = reinterpret_cast<double*>(smem + (size_t)NB * 2 * lt.Vs * sizeof(cplx<R>));
+    const int tau = slice_of_block(blockIdx.x, lt.Nt);
+    if (tau < 0) return;
     SliceCtx<MC> c;
-    slice_ctx<MC>(lt, c, blockIdx.x);
+    slice_ctx<MC>(lt, c, tau);
     const size_t Vs = lt.Vs;
     cplx<R> hm[MC][12], ht[MC][12];
     hops_of<R, MC>(gauge, lt, c.tm, c.idx, co, hm);
@@ -518,10 +520,10 @@ static qedhmc_status launch_mv(qedhmc_ctx* h, const PcgBufs<R>& B, const double*
         hipEvent_t e0, e1;
         const int cls = sizeof(R) == 4 ? QEDHMC_K_PCG_MV_FP32 : QEDHMC_K_PCG_MV_FP64;
         if (timed && prof_sample(h, cls, e0, e1))
-            hipExtLaunchKernelGGL((k_pcg_mv<R, MC, NB, BS>), dim3(h->lat.Nt), dim3(nt), lds, h->stream, e0, e1, 0,
+            hipExtLaunchKernelGGL((k_pcg_mv<R, MC, NB, BS>), dim3(slice_grid(h->lat.Nt)), dim3(nt), lds, h->stream, e0, e1, 0,
                                   h->lat, B, gauge_for<R>(h), coef_of<R>(h->p), stop);
         else
-            hipLaunchKernelGGL((k_pcg_mv<R, MC, NB, BS>), dim3(h->lat.Nt), dim3(nt), lds, h->stream, h->lat, B,
+            hipLaunchKernelGGL((k_pcg_mv<R, MC, NB, BS>), dim3(slice_grid(h->lat.Nt)), dim3(nt), lds, h->stream, h->lat, B,
                                gauge_for<R>(h), coef_of<R>(h->p), stop);
         QH_HIP(hipGetLastError());
         return QEDHMC_OK;

@@ -63,6 +63,19 @@ struct Lat {
     int L, Nt, Vs, hL, ncell;  // hL = L/2, ncell = hL*hL
 };
 
+// Slice of a workgroup in the one-slice-per-workgroup kernels.  Workgroups
+// are dealt to the eight XCDs round robin (workgroup i runs on XCD i mod 8),
+// and every stencil kernel reads the tau -+ 1 neighbours of its slice; dealing
+// the slices out in eight contiguous ranges keeps a slice and its neighbours
+// on one XCD, so the neighbour reads hit that XCD's L2.  Grids have
+// slice_grid(Nt) workgroups; the surplus ones get -1 and exit at once.
+__host__ __device__ __forceinline__ int slice_grid(int Nt) { return 8 * ((Nt + 7) / 8); }
+__device__ __forceinline__ int slice_of_block(int b, int Nt) {
+    const int per = (Nt + 7) >> 3;
+    const int tau = (b & 7) * per + (b >> 3);
+    return tau < Nt ? tau : -1;
+}
+
 // Hopping coefficients of one bond factor: cosh/sinh of the half step h and
 // of the merged central step 2h (Eq. 24).
 template <typename R>
