@@ -253,6 +253,71 @@ qedhmc_status qedhmc_batch_trajectory(qedhmc_batch_t b, double *theta_all,
                                       int32_t maxit, qedhmc_precision prec,
                                       qedhmc_traj_result *out);
 
+/* ------------------------------------------------------------------------
+ * Learned preconditioner (not in the paper; its fixed preconditioner of
+ * Methods, "CG method and preconditioner", is the fallback): a network
+ * z = N(theta, r) of six 3x3x3 convolutions over the (tau, y, x) lattice,
+ * channels 6 -> 32 -> 32 -> 32 -> 32 -> 32 -> 2, SiLU after every layer but
+ * the last.  Input channels per site: cos, sin of theta on the +x and +y
+ * bonds leaving it and Re, Im of r / s, s = |r| / sqrt(N); output
+ * z = s (o_0 + i o_1).  Padding periodic in x, y and tau, except that the
+ * first layer's residual channels change sign when they wrap in tau.
+ *
+ * Parameters (host float array of qedhmc_net_param_count() entries): per
+ * layer in order, W[Cout][Cin][27] with tap k = 9 (dt + 1) + 3 (dy + 1) +
+ * (dx + 1) reading the input at (tau + dt, y + dy, x + dx), then b[Cout].
+ * A network is bound to one lattice handle (its stream and sizes); copy the
+ * parameters to use them on another lattice. */
+typedef struct qedhmc_net *qedhmc_net_t;
+
+/* Arithmetic of the network: FP32 on the vector ALUs throughout, or BF16
+ * MFMA products (BF16 weights and activations, FP32 accumulation) for the
+ * four 32 -> 32 layers with the first and last layers in FP32.  Training
+ * runs in FP32 (FP32 master weights and Adam moments). */
+typedef enum { QEDHMC_NET_FP32 = 0, QEDHMC_NET_BF16 = 1 } qedhmc_net_arith;
+
+int64_t qedhmc_net_param_count(void);
+/* Allocate a network on lattice h with all parameters zero. */
+qedhmc_status qedhmc_net_create(qedhmc_t h, qedhmc_net_t *out);
+qedhmc_status qedhmc_net_destroy(qedhmc_net_t n);
+/* Copy parameters in / out (host layout above; count must match). */
+qedhmc_status qedhmc_net_set_params(qedhmc_net_t n, const float *host,
+                                    int64_t count);
+qedhmc_status qedhmc_net_get_params(qedhmc_net_t n, float *host,
+                                    int64_t count);
+/* Zero the Adam moments and step counter. */
+qedhmc_status qedhmc_net_reset_optimizer(qedhmc_net_t n);
+
+/* z = N(theta, r); r, z: device complex FP64 [Nt][L][L]. */
+qedhmc_status qedhmc_net_apply(qedhmc_net_t n, const double *theta,
+                               const double *r, double *z,
+                               qedhmc_net_arith arith);
+
+/* One training step on the triple (theta, r, e), e the solution of
+ * M^dag M e = r: loss = |N(theta, r) - e|^2 / |e|^2 into *loss (host), the
+ * gradient of the loss into grad_host (host float array in the parameter
+ * layout, nullable; the gradient before the update), then one Adam step
+ * (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr).  FP32 arithmetic
+ * only (QEDHMC_EUNSUPPORTED otherwise). */
+qedhmc_status qedhmc_net_train_step(qedhmc_net_t n, const double *theta,
+                                    const double *r, const double *e,
+                                    double lr, qedhmc_net_arith arith,
+                                    double *loss, float *grad_host);
+
+/* Flexible CG on M^dag M x = rhs preconditioned by the network (Notay's
+ * flexible CG: alpha = <p, r> / <p, O p>, beta = -<O p, z'> / <p, O p>),
+ * from x = 0, stopping on the FP64 true residual |rhs - O x| / |rhs| <= tol.
+ * The residual judges the network: when |r| has fallen by less than 10 %
+ * over the last 10 iterations the solve continues with the fallback
+ * preconditioner (QEDHMC_PC_PAPER or QEDHMC_PC_NONE) and *switched_at
+ * (host, nullable) receives that iteration (-1 if the network kept it).
+ * All vectors FP64 complex on the device.  ENOCONV as for qedhmc_cg_solve. */
+qedhmc_status qedhmc_fcg_solve(qedhmc_net_t n, const double *theta,
+                               const double *rhs, double *x, double tol,
+                               int32_t maxit, qedhmc_net_arith arith,
+                               qedhmc_precond fallback, int32_t *iters,
+                               double *true_rel_resid, int32_t *switched_at);
+
 /* Kernel timing for measurement (not part of the method).  qedhmc_profile
  * with every > 0 times every every-th launch of the timed kernel classes
  * with the start and end events of the dispatch itself

@@ -34,9 +34,9 @@ confirms with the true residual |rhs - O x| / |rhs| <= tol (restarting from
 the true residual if it is not met).
 
 The residual judges the network: when |r| has fallen by less than a factor
-0.9 over the last 10 iterations, the solve continues with the fallback
-preconditioner (the paper's, or none), restarting its directions from the
-current residual.
+0.9 over the last 10 iterations, or the network's direction is not one of
+descent (<p, O p> <= 0), the solve continues with the fallback preconditioner
+(the paper's, or none), restarting its directions from the current residual.
 """
 import numpy as np
 
@@ -219,10 +219,13 @@ def fcg_solve(apply_O, precond, rhs, tol=1e-10, maxit=10000, fallback=None):
     while True:
         pc = precond if switched < 0 else fallback
         p = pc(r)
+        just_switched = False
         while it < maxit and np.linalg.norm(r) > tol * nb:
             s = apply_O(p)
             ps = np.vdot(p, s).real
             if not ps > 0:
+                if switched < 0:  # no descent direction: the network is unusable here
+                    switched, just_switched = it, True
                 break
             alpha = np.vdot(p, r) / ps
             x = x + alpha * p
@@ -231,12 +234,12 @@ def fcg_solve(apply_O, precond, rhs, tol=1e-10, maxit=10000, fallback=None):
             hist.append(np.linalg.norm(r))
             if (switched < 0 and len(hist) > JUDGE_WINDOW
                     and hist[-1] > JUDGE_FACTOR * hist[-1 - JUDGE_WINDOW]):
-                switched = it
+                switched, just_switched = it, True
                 break
             zn = pc(r)
             beta = -np.vdot(s, zn) / ps
             p = zn + beta * p
-        if switched == it:
+        if just_switched:
             continue
         true = np.linalg.norm(rhs - apply_O(x)) / nb
         stalls = stalls + 1 if it == last else 0

@@ -1,0 +1,109 @@
+// Shared declarations of the learned-preconditioner kernels (net.hip,
+// netmfma.hip).
+#pragma once
+#include <cstdint>
+
+#include "qedhmc_internal.h"
+
+struct qedhmc_net;
+
+namespace qh {
+
+static constexpr int kNetLayers = 6;
+static constexpr int kNetCh[kNetLayers + 1] = {6, 32, 32, 32, 32, 32, 2};
+static constexpr int kWChunk = 1024;     // output sites per weight-gradient partial
+static constexpr int kJudgeWindow = 10;  // flexible CG: iterations the residual judge looks back
+static constexpr double kJudgeFactor = 0.9;
+
+struct NetGeo {
+    int L, Nt, Vs, N;
+};
+
+__device__ __forceinline__ void site_of(const NetGeo& g, int n, int& tau, int& y, int& x) {
+    tau = n / g.Vs;
+    const int s = n - tau * g.Vs;
+    y = s / g.L;
+    x = s - y * g.L;
+}
+
+// neighbour tau + dt; sg = -1 where it wraps (the antiperiodic sign of the
+// first layer's residual channels)
+__device__ __forceinline__ int wrap_tau(int t, int Nt, float& sg) {
+    sg = 1.0f;
+    if (t < 0) {
+        t += Nt;
+        sg = -1.0f;
+    } else if (t >= Nt) {
+        t -= Nt;
+        sg = -1.0f;
+    }
+    return t;
+}
+
+__device__ __forceinline__ float silu_f(float a) { return a / (1.0f + expf(-a)); }
+__device__ __forceinline__ float dsilu_f(float a) {
+    const float s = 1.0f / (1.0f + expf(-a));
+    return s * (1.0f + a * (1.0f - s));
+}
+
+// BF16 storage as the upper half of an FP32 word, rounded to nearest even
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ float to_f32(float v) { return v; }
+__device__ __forceinline__ float to_f32(uint16_t v) { return bf16_to_f32(v); }
+template <typename T>
+__device__ __forceinline__ T from_f32(float v);
+template <>
+__device__ __forceinline__ float from_f32<float>(float v) {
+    return v;
+}
+template <>
+__device__ __forceinline__ uint16_t from_f32<uint16_t>(float v) {
+    return f32_to_bf16(v);
+}
+
+qedhmc_status launch_first_bf16(const NetGeo& g, hipStream_t st, const cplx<float>* g32, const double* r,
+                                const double* rr, const float* W, const float* b, uint16_t* out);
+qedhmc_status launch_last_bf16(const NetGeo& g, hipStream_t st, const uint16_t* in, const float* W, const float* b,
+                               float* out);
+
+// BF16 forward of the network (MFMA for the 32 -> 32 layers); leaves the
+// two output channels in FP32 where the FP32 forward leaves them
+qedhmc_status net_forward_bf16(qedhmc_net* n, const double* r);
+// number of BF16 weight elements the MFMA layers keep (fragment order)
+size_t net_bf16_weight_elems();
+
+}  // namespace qh
+
+// Network state bound to one lattice handle (its stream, sizes and caches).
+struct qedhmc_net {
+    qedhmc_ctx* h = nullptr;
+    qh::NetGeo g{};
+    size_t woff[qh::kNetLayers], boff[qh::kNetLayers], nparam = 0;
+    float* params = nullptr;  // FP32 master, device layout
+    float* grads = nullptr;
+    float* adam_m = nullptr;
+    float* adam_v = nullptr;
+    int adam_t = 0;
+    uint16_t* wbf = nullptr;   // BF16 weights of the hidden layers in MFMA fragment order
+    bool wbf_ready = false;
+    // activations: act[l] = input of layer l (l >= 1), [N][32]; pre[l] pre-activation of layer l
+    float* act[qh::kNetLayers + 1] = {};
+    float* pre[qh::kNetLayers] = {};
+    float* gbuf[2] = {nullptr, nullptr};
+    float* wpart = nullptr;  // weight-gradient partials
+    uint16_t* actb[2] = {nullptr, nullptr};  // BF16 ping-pong activations (inference)
+    double* dscal = nullptr;  // [0] |r|^2, [1] |e|^2, [8..12) reductions
+    double* dpart = nullptr;  // reduction partials
+    double* hpin = nullptr;   // pinned host scalars
+    bool train_ready = false;
+    // flexible CG vectors (complex FP64)
+    qh::cplx<double>* fr = nullptr;
+    qh::cplx<double>* fp = nullptr;
+    qh::cplx<double>* fs = nullptr;
+    qh::cplx<double>* fz = nullptr;
+};

@@ -81,6 +81,15 @@ def load():
         "qedhmc_profile_read": [_P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
         "qedhmc_hmc_trajectory": [_P, _P, C.c_uint64, C.c_int32, C.c_double, C.c_double, C.c_int32,
                                   C.c_int, C.c_int, C.POINTER(TrajResult)],
+        "qedhmc_net_create": [_P, C.POINTER(_P)],
+        "qedhmc_net_destroy": [_P],
+        "qedhmc_net_set_params": [_P, _P, C.c_int64],
+        "qedhmc_net_get_params": [_P, _P, C.c_int64],
+        "qedhmc_net_reset_optimizer": [_P],
+        "qedhmc_net_apply": [_P, _P, _P, _P, C.c_int],
+        "qedhmc_net_train_step": [_P, _P, _P, _P, C.c_double, C.c_int, C.POINTER(C.c_double), _P],
+        "qedhmc_fcg_solve": [_P, _P, _P, _P, C.c_double, C.c_int32, C.c_int, C.c_int, C.POINTER(C.c_int32),
+                             C.POINTER(C.c_double), C.POINTER(C.c_int32)],
         "qedhmc_batch_create": [C.POINTER(Params), C.c_int32, _P, C.POINTER(_P)],
         "qedhmc_batch_destroy": [_P],
         "qedhmc_batch_layout": [_P, _P, _P],
@@ -94,6 +103,8 @@ def load():
         fn = getattr(L, name)
         fn.argtypes = args
         fn.restype = st
+    L.qedhmc_net_param_count.argtypes = []
+    L.qedhmc_net_param_count.restype = C.c_int64
     L.qedhmc_last_error.argtypes = []
     L.qedhmc_last_error.restype = C.c_char_p
     _lib = L
@@ -373,6 +384,110 @@ class Batch:
         _check(load().qedhmc_batch_trajectory(self.h, _ptr(theta_all), int(traj), int(n_steps),
                                               float(traj_len), float(tol), int(maxit), _PREC[prec], res))
         return [r.as_dict() for r in res]
+
+
+NET_FP32, NET_BF16 = 0, 1
+_ARITH = {"fp32": NET_FP32, "bf16": NET_BF16, NET_FP32: NET_FP32, NET_BF16: NET_BF16}
+
+
+class Net:
+    """The learned preconditioner (qedhmc_net_*) bound to a Lattice.
+
+    Parameters travel as a flat float32 array in the C layout (per layer
+    W[Cout][Cin][27] then b[Cout]); ``pack``/``unpack`` convert from/to a list
+    of (W, b) numpy pairs."""
+
+    def __init__(self, lat):
+        self.lat = lat
+        h = _P()
+        lat._sync_stream()
+        _check(load().qedhmc_net_create(lat.h, C.byref(h)))
+        self.h = h
+        self.count = int(load().qedhmc_net_param_count())
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().qedhmc_net_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @staticmethod
+    def pack(params):
+        import numpy as np
+        return np.concatenate([np.concatenate([W.reshape(-1), b.reshape(-1)]) for W, b in params]).astype(np.float32)
+
+    @staticmethod
+    def unpack(flat, channels=(6, 32, 32, 32, 32, 32, 2)):
+        out, o = [], 0
+        for l in range(len(channels) - 1):
+            ci, co = channels[l], channels[l + 1]
+            W = flat[o:o + co * ci * 27].reshape(co, ci, 27)
+            o += co * ci * 27
+            b = flat[o:o + co]
+            o += co
+            out.append((W, b))
+        return out
+
+    def set_params(self, params):
+        import numpy as np
+        flat = params if isinstance(params, np.ndarray) else self.pack(params)
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        assert flat.size == self.count
+        _check(load().qedhmc_net_set_params(self.h, flat.ctypes.data_as(C.c_void_p), self.count))
+
+    def get_params(self):
+        import numpy as np
+        flat = np.zeros(self.count, dtype=np.float32)
+        _check(load().qedhmc_net_get_params(self.h, flat.ctypes.data_as(C.c_void_p), self.count))
+        return flat
+
+    def reset_optimizer(self):
+        _check(load().qedhmc_net_reset_optimizer(self.h))
+
+    def apply(self, theta, r, arith="fp32", out=None):
+        self.lat._check_theta(theta)
+        self.lat._check_vec(r, "fp64")
+        out = self.lat._vec("fp64") if out is None else out
+        self.lat._sync_stream()
+        _check(load().qedhmc_net_apply(self.h, _ptr(theta), _ptr(r), _ptr(out), _ARITH[arith]))
+        return out
+
+    def train_step(self, theta, r, e, lr=1e-3, arith="fp32", want_grad=False):
+        """Returns (loss, grad) with grad the flat float32 gradient (or None)."""
+        import numpy as np
+        self.lat._check_theta(theta)
+        self.lat._check_vec(r, "fp64")
+        self.lat._check_vec(e, "fp64")
+        loss = C.c_double(0.0)
+        grad = np.zeros(self.count, dtype=np.float32) if want_grad else None
+        self.lat._sync_stream()
+        _check(load().qedhmc_net_train_step(self.h, _ptr(theta), _ptr(r), _ptr(e), float(lr), _ARITH[arith],
+                                            C.byref(loss),
+                                            grad.ctypes.data_as(C.c_void_p) if want_grad else None))
+        return loss.value, grad
+
+    def fcg_solve(self, theta, rhs, tol=1e-10, maxit=100_000, arith="bf16", fallback="paper", x=None):
+        """Returns (x, status, iters, true_rel, switched_at)."""
+        self.lat._check_theta(theta)
+        self.lat._check_vec(rhs, "fp64")
+        x = self.lat._vec("fp64") if x is None else x
+        it, rel, sw = C.c_int32(0), C.c_double(0.0), C.c_int32(0)
+        self.lat._sync_stream()
+        st = _check(load().qedhmc_fcg_solve(self.h, _ptr(theta), _ptr(rhs), _ptr(x), float(tol), int(maxit),
+                                            _ARITH[arith], _PC[fallback], C.byref(it), C.byref(rel),
+                                            C.byref(sw)), allow=(OK, ENOCONV))
+        return x, st, it.value, rel.value, sw.value
 
 
 def init_lattice(L, Nt, **kw):

@@ -1,0 +1,153 @@
+"""The learned preconditioner on the GPU against its oracle (oracle/net.py):
+forward pass in FP32 and BF16, loss and gradients of a training step, the
+Adam update, and flexible CG with the residual judge and fallback."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from oracle import net as NN
+from paper_2508_16298_amd import inputs
+from paper_2508_16298_amd import qedhmc as Q
+
+pytestmark = pytest.mark.gpu
+
+# lattices spanning a ragged last tile of the MFMA kernel (N not a multiple of 256)
+SIZES = [(4, 6), (6, 10), (8, 5), (2, 3)]
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    a = np.asarray(a).reshape(-1)
+    b = np.asarray(b).reshape(-1)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _params(seed, bias=0.1):
+    """Initial weights with nonzero biases (so the bias path is exercised);
+    rounded to FP32, the precision the library stores."""
+    rng = np.random.default_rng(seed + 1)
+    out = []
+    for W, b in inputs.net_init_weights(seed):
+        out.append((W.astype(np.float32).astype(np.float64),
+                    rng.normal(0.0, bias, size=b.shape).astype(np.float32).astype(np.float64)))
+    return out
+
+
+def _case(L, Nt, seed):
+    th = inputs.noisy_pi_flux_theta(L, Nt, 0.3, seed)
+    r = inputs.gauss_cvec(L, Nt, seed + 1)
+    return th, r
+
+
+@pytest.mark.parametrize("L,Nt", SIZES)
+def test_net_forward_fp32_and_bf16(L, Nt):
+    th, r = _case(L, Nt, 300 + L)
+    params = _params(7)
+    zo = NN.forward(params, th, r)
+    with Q.Lattice(L, Nt) as lat, Q.Net(lat) as net:
+        net.set_params(params)
+        assert np.array_equal(net.get_params(), Q.Net.pack(params))
+        z32 = _host(net.apply(_dev(th), _dev(r), arith="fp32"))
+        zbf = _host(net.apply(_dev(th), _dev(r), arith="bf16"))
+    e32, ebf = _rel(z32, zo), _rel(zbf, zo)
+    print(f"L={L} Nt={Nt}: fp32 {e32:.2e}  bf16 {ebf:.2e}", flush=True)
+    assert e32 <= 1e-5
+    assert ebf <= 3e-2
+
+
+def test_net_forward_zero_residual():
+    L, Nt = 4, 4
+    th, _ = _case(L, Nt, 5)
+    with Q.Lattice(L, Nt) as lat, Q.Net(lat) as net:
+        net.set_params(_params(8))
+        z = _host(net.apply(_dev(th), _dev(np.zeros((Nt, L, L), complex))))
+    assert np.abs(z).max() == 0.0  # s = 0 scales the output to zero
+
+
+@pytest.mark.parametrize("L,Nt", [(4, 6), (6, 10)])
+def test_net_train_step_gradients_and_adam(L, Nt):
+    th, r = _case(L, Nt, 400 + L)
+    e = inputs.gauss_cvec(L, Nt, 401 + L)
+    params = _params(9)
+    loss_o, grads_o = NN.loss_and_grads(params, th, r, e)
+    lr = 1e-3
+    with Q.Lattice(L, Nt) as lat, Q.Net(lat) as net:
+        net.set_params(params)
+        loss, g = net.train_step(_dev(th), _dev(r), _dev(e), lr=lr, want_grad=True)
+        newp = net.get_params()
+    print(f"loss gpu {loss:.10f} oracle {loss_o:.10f}", flush=True)
+    assert abs(loss - loss_o) <= 1e-5 * loss_o
+    gl = Q.Net.unpack(g)
+    for l, ((gW, gb), (oW, ob)) in enumerate(zip(gl, grads_o)):
+        eW, eb = _rel(gW, oW), _rel(gb, ob)
+        print(f"layer {l}: dW {eW:.2e} db {eb:.2e}", flush=True)
+        assert eW <= 1e-4 and eb <= 1e-4
+    # Adam's first step from the GPU's own gradient, in FP64
+    ref, _ = NN.adam_step(params, [(gW.astype(np.float64), gb.astype(np.float64)) for gW, gb in gl],
+                          NN.adam_init(params), lr=lr)
+    assert _rel(newp, Q.Net.pack(ref)) <= 1e-6
+
+
+def test_net_training_reduces_the_loss():
+    """A few hundred FP32 steps on one triple drive the loss down."""
+    L, Nt = 4, 8
+    th, r = _case(L, Nt, 501)
+    p = O.lat(L, Nt)
+    e = np.linalg.solve(O.dense_MdagM(p, th), r.reshape(-1)).reshape(Nt, L, L)
+    with Q.Lattice(L, Nt) as lat, Q.Net(lat) as net:
+        net.set_params(_params(10, bias=0.0))
+        thd, rd, ed = _dev(th), _dev(r), _dev(e)
+        first, _ = net.train_step(thd, rd, ed, lr=2e-3)
+        for _ in range(300):
+            last, _ = net.train_step(thd, rd, ed, lr=2e-3)
+    print(f"loss {first:.4f} -> {last:.4f}", flush=True)
+    assert last < 0.5 * first
+
+
+@pytest.mark.parametrize("fallback", ["none", "paper"])
+def test_fcg_untrained_network_falls_back(fallback):
+    """An untrained network is a useless preconditioner: the residual judge
+    hands the solve to the fallback, which converges; the solution is the
+    dense one.  The oracle's flexible CG with the same network and the
+    identity fallback switches at the same iteration."""
+    L, Nt = 4, 6
+    th, _ = _case(L, Nt, 601)
+    p = O.lat(L, Nt)
+    eta = O.apply_M(p, th, inputs.gauss_cvec(L, Nt, 602), dagger=True).reshape(Nt, L, L)
+    params = _params(11)
+    with Q.Lattice(L, Nt) as lat, Q.Net(lat) as net:
+        net.set_params(params)
+        x, st, it, rel, sw = net.fcg_solve(_dev(th), _dev(eta), tol=1e-10, arith="fp32", fallback=fallback)
+        xg = _host(x)
+    print(f"{fallback}: {it} iterations, switched at {sw}, true residual {rel:.2e}", flush=True)
+    assert st == Q.OK and rel <= 1e-10 and sw > 0
+    xd = np.linalg.solve(O.dense_MdagM(p, th), eta.reshape(-1))
+    assert np.linalg.norm(xg.reshape(-1) - xd) <= 1e-7 * np.linalg.norm(xd)
+    if fallback == "none":
+        Ofn = lambda v: O.apply_MdagM(p, th, v).reshape(Nt, L, L)
+        xo, ok, ito, relo, swo = NN.fcg_solve(Ofn, lambda r: NN.forward(params, th, r), eta, tol=1e-10)
+        assert ok and sw == swo and abs(it - ito) <= 3, (it, ito, sw, swo)
+
+
+def test_fcg_zero_network_falls_back_at_once():
+    """All parameters zero: z = 0 gives no descent direction, the solve
+    falls back at iteration 0, and with the fallback 'none' it is plain CG."""
+    L, Nt = 4, 6
+    th, _ = _case(L, Nt, 701)
+    p = O.lat(L, Nt)
+    eta = O.apply_M(p, th, inputs.gauss_cvec(L, Nt, 702), dagger=True).reshape(Nt, L, L)
+    with Q.Lattice(L, Nt) as lat, Q.Net(lat) as net:
+        # parameters all zero: z = 0, no descent direction -> fallback at iteration 0
+        x, st, it, rel, sw = net.fcg_solve(_dev(th), _dev(eta), tol=1e-10, arith="bf16", fallback="none")
+        _, sto, ito, relo = lat.cg_solve(_dev(th), _dev(eta), tol=1e-10)
+    assert st == Q.OK and sw == 0 and rel <= 1e-10
+    assert abs(it - ito) <= 2, (it, ito)
