@@ -186,6 +186,99 @@ def run_batched(a):
     print(json.dumps(out), flush=True)
 
 
+def run_learned(a):
+    """--workload learned_l66: the learned preconditioner.  Training: the
+    network (initial weights seed 1005) is trained with Adam (lr 1e-3, FP32)
+    on triples (theta, eta, X) from mixed-precision CG solves (residual 1e-8)
+    at L=24, Nt=240 -- theta pi flux + N(0, 0.3^2) noise (seeds 5000+k), eta =
+    M^dag R -- cycling over the triples.  Evaluation at L=66, Nt=660 (theta pi
+    flux + noise, seed 1005; eta = M^dag R from the heat bath), true residual
+    1e-8: CG iterations and seconds for no preconditioner and the paper's
+    (mixed precision, fused kernels) and for flexible CG with the trained
+    network (BF16 MFMA, fallback the paper's; FP64 vectors).  value = seconds
+    of the learned solve.  The roofline block is the BF16 MFMA conv layer
+    (2 x 27 x 32 x 32 flop per site) timed by dispatch events during the
+    learned solve."""
+    import numpy as np
+    import torch
+    from paper_2508_16298_amd import inputs
+    from paper_2508_16298_amd import qedhmc as Q
+
+    wl = inputs.WORKLOADS["learned_l66"]
+    n_train_theta = int(os.environ.get("QEDHMC_NET_TRIPLES", "8"))
+    n_steps = int(os.environ.get("QEDHMC_NET_STEPS", "400"))
+    Lt, Ntt = 24, 240
+    out = {}
+    t0 = time.perf_counter()
+    with Q.Lattice(Lt, Ntt, dtau=wl.dtau, t=wl.t, J=wl.J, K=wl.K, seed=5000) as lt, Q.Net(lt) as net:
+        triples = []
+        for k in range(n_train_theta):
+            th = torch.from_numpy(inputs.noisy_pi_flux_theta(Lt, Ntt, 0.3, 5000 + k)).cuda()
+            R = torch.from_numpy(inputs.gauss_cvec(Lt, Ntt, 5100 + k)).cuda()
+            eta = lt.apply_M(th, R, dagger=True)
+            X, st, it, rel = lt.cg_solve(th, eta, tol=1e-8, prec="fp32")
+            triples.append((th, eta, X))
+        t_data = time.perf_counter() - t0
+        net.set_params(inputs.net_init_weights(wl.seed))
+        losses = []
+        t1 = time.perf_counter()
+        for s in range(n_steps):
+            th, eta, X = triples[s % len(triples)]
+            loss, _ = net.train_step(th, eta, X, lr=1e-3)
+            losses.append(loss)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t1
+        params = net.get_params()
+    out["training"] = {"lattice": f"L={Lt} Nt={Ntt}", "triples": n_train_theta, "steps": n_steps,
+                       "loss_first": losses[0], "loss_last_avg": float(np.mean(losses[-len(triples):])),
+                       "data_s": t_data, "train_s": t_train, "ms_per_step": 1e3 * t_train / max(n_steps, 1)}
+    L, Nt = wl.L, wl.Nt
+    th_np = inputs.noisy_pi_flux_theta(L, Nt, 0.3, wl.seed)
+    with Q.Lattice(L, Nt, dtau=wl.dtau, t=wl.t, J=wl.J, K=wl.K, seed=wl.seed) as lat, Q.Net(lat) as net:
+        theta = torch.from_numpy(th_np).cuda()
+        _, R = lat.heatbath(0)
+        eta = lat.apply_M(theta, R, dagger=True)
+        net.set_params(params)
+        res = {}
+        for name, pc in (("none", None), ("paper", "paper")):
+            lat.cg_solve(theta, eta, tol=1e-3, maxit=20, prec="fp32", precond=pc)  # load kernels / build P
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, st, it, rel = lat.cg_solve(theta, eta, tol=wl.tol, prec="fp32", precond=pc)
+            torch.cuda.synchronize()
+            res[name] = {"iterations": it, "s": time.perf_counter() - t, "true_rel": rel, "status": st}
+        net.fcg_solve(theta, eta, tol=1e-2, maxit=3, arith="bf16", fallback="paper")
+        lat.profile(1)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, st, it, rel, sw = net.fcg_solve(theta, eta, tol=wl.tol, arith="bf16", fallback="paper")
+        torch.cuda.synchronize()
+        res["learned"] = {"iterations": it, "s": time.perf_counter() - t, "true_rel": rel, "status": st,
+                          "switched_at": sw}
+        n_k, ms_k = lat.profile_read(Q.K_NET_MFMA)
+        lat.profile(0)
+    N = L * L * Nt
+    flops = 2.0 * 27 * 32 * 32 * N
+    avg_ms = ms_k / max(n_k, 1)
+    achieved = flops / (avg_ms * 1e-3) / 1e12 if n_k else None
+    line = {
+        "metric": "seconds to true residual 1e-8 at L=66 Nt=660, flexible CG with the learned preconditioner",
+        "value": res["learned"]["s"], "unit": "s/solve", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": 1e3 * res["learned"]["s"], "higher_is_better": False, "scaling": "strong",
+        "vs_baseline": None, "dtype": "bf16 (network) + f64 (FCG)", "data": "synthetic",
+        "config": {"workload": (f"learned_l66: L={L} Nt={Nt} ({N} sites), theta pi flux + N(0, 0.3^2) seed "
+                                f"{wl.seed}, eta = M^dag R, tol {wl.tol}; network trained at L={Lt} Nt={Ntt}"),
+                   "sites": N},
+        "solves": res,
+        **out,
+        "roofline": {"bound": "mfma", "kernel": "k_conv_mfma<true> (one 32->32 3x3x3 layer, BF16 MFMA)",
+                     "achieved": achieved, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": (achieved / 2500.0) if achieved else None, "traffic": None,
+                     "alg_flops_per_launch": flops, "avg_launch_us": avg_ms * 1e3, "timed_launches": n_k},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -196,6 +289,8 @@ def main():
         return run_copy_calibration()
     if a.workload == "batched_chains":
         return run_batched(a)
+    if a.workload == "learned_l66":
+        return run_learned(a)
     if a.solve_only:
         return run_solve_only(a)
     import torch

@@ -333,7 +333,9 @@ typedef enum {
     QEDHMC_K_CG_FP64 = 4,      /* one fused CG iteration, FP64 */
     QEDHMC_K_PCG_MV_FP32 = 5,  /* M^dag M + inner products of a PCG iteration, FP32 */
     QEDHMC_K_PCG_MV_FP64 = 6,  /* the same, FP64 */
-    QEDHMC_K_COUNT = 7
+    QEDHMC_K_NET_MFMA = 7,     /* one 32 -> 32 network layer, BF16 MFMA */
+    QEDHMC_K_NET_FP32 = 8,     /* one 32 -> 32 network layer, FP32 */
+    QEDHMC_K_COUNT = 9
 } qedhmc_kernel_class;
 
 qedhmc_status qedhmc_profile(qedhmc_t h, int32_t every);

@@ -442,8 +442,15 @@ static qedhmc_status fwd_layer_f32(qedhmc_net* n, int l, const double* r, const 
     const double* rr = n->dscal;
     if (l == 0)
         hipLaunchKernelGGL((k_conv_fwd<6, 32, true, true, float, float>), grid, blk, 0, st, g, in, g32, rc, rr, W, b, pre, act);
-    else if (l < kNetLayers - 1)
-        hipLaunchKernelGGL((k_conv_fwd<32, 32, false, true, float, float>), grid, blk, 0, st, g, in, g32, rc, rr, W, b, pre, act);
+    else if (l < kNetLayers - 1) {
+        hipEvent_t e0, e1;
+        if (prof_sample(n->h, QEDHMC_K_NET_FP32, e0, e1))
+            hipExtLaunchKernelGGL((k_conv_fwd<32, 32, false, true, float, float>), grid, blk, 0, st, e0, e1, 0, g, in,
+                                  g32, rc, rr, W, b, pre, act);
+        else
+            hipLaunchKernelGGL((k_conv_fwd<32, 32, false, true, float, float>), grid, blk, 0, st, g, in, g32, rc, rr,
+                               W, b, pre, act);
+    }
     else
         hipLaunchKernelGGL((k_conv_fwd<32, 2, false, false, float, float>), grid, blk, 0, st, g, in, g32, rc, rr, W, b, pre, act);
     QH_HIP(hipGetLastError());

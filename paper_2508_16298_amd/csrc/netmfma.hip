@@ -120,9 +120,15 @@ qedhmc_status net_forward_bf16(qedhmc_net* n, const double* r) {
     const int blocks = (g.N + kSitesPerBlock - 1) / kSitesPerBlock;
     for (int hl = 0; hl < kHidden; hl++) {
         const int l = hl + 1;
-        hipLaunchKernelGGL((k_conv_mfma<true>), dim3(blocks), dim3(256), 0, st, g, (const uint16_t*)n->actb[cur],
-                           (const uint16_t*)(n->wbf + (size_t)hl * kFrag * 8), (const float*)(n->params + n->boff[l]),
-                           n->actb[cur ^ 1]);
+        hipEvent_t e0, e1;
+        if (prof_sample(n->h, QEDHMC_K_NET_MFMA, e0, e1))
+            hipExtLaunchKernelGGL((k_conv_mfma<true>), dim3(blocks), dim3(256), 0, st, e0, e1, 0, g,
+                                  (const uint16_t*)n->actb[cur], (const uint16_t*)(n->wbf + (size_t)hl * kFrag * 8),
+                                  (const float*)(n->params + n->boff[l]), n->actb[cur ^ 1]);
+        else
+            hipLaunchKernelGGL((k_conv_mfma<true>), dim3(blocks), dim3(256), 0, st, g, (const uint16_t*)n->actb[cur],
+                               (const uint16_t*)(n->wbf + (size_t)hl * kFrag * 8),
+                               (const float*)(n->params + n->boff[l]), n->actb[cur ^ 1]);
         QH_HIP(hipGetLastError());
         cur ^= 1;
     }

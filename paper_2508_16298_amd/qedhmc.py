@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqedhmc.so")
 
 OK, EINVAL, ENOCONV, EHIP, ENOMEM, EUNSUPPORTED = range(6)
-K_MDAGM_FP32, K_MDAGM_FP64, K_FORCE, K_CG_FP32, K_CG_FP64, K_PCG_MV_FP32, K_PCG_MV_FP64 = range(7)
+(K_MDAGM_FP32, K_MDAGM_FP64, K_FORCE, K_CG_FP32, K_CG_FP64, K_PCG_MV_FP32, K_PCG_MV_FP64, K_NET_MFMA,
+ K_NET_FP32) = range(9)
 FP64, FP32 = 0, 1
 PC_NONE, PC_PAPER = 0, 1
 _PC = {None: PC_NONE, "none": PC_NONE, "paper": PC_PAPER, PC_NONE: PC_NONE, PC_PAPER: PC_PAPER}
