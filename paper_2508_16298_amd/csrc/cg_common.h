@@ -51,12 +51,10 @@ struct CgBufs {
 template <int K>
 __device__ __forceinline__ void block_sumk(double (&v)[K], double* red) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-        for (int k = 0; k < K; k++) v[k] += __shfl_xor(v[k], off, 64);
+    for (int k = 0; k < K; k++) v[k] = wave_sum_f64(v[k]);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     __syncthreads();
-    if (lane == 0)
+    if (lane == 63)
 #pragma unroll
         for (int k = 0; k < K; k++) red[K * wv + k] = v[k];
     __syncthreads();

@@ -380,13 +380,34 @@ __device__ __forceinline__ void store_cells(const Cells<R, MC>& c, cplx<R>* __re
         }
 }
 
+// Wavefront sum of one double through DPP lane moves (no LDS round trips):
+// pairs, quads, half rows, rows, then rows 0+1 into row 1 and rows 0..3 into
+// row 3.  Fixed order; the total is valid in lane 63.  Every lane of the
+// wavefront must take part.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+    v += dpp_f64<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141, 0xF>(v);  // row_half_mirror
+    v += dpp_f64<0x140, 0xF>(v);  // row_mirror
+    v += dpp_f64<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_f64<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
 // Fixed-order block reduction of one double per thread (deterministic for a
 // fixed block size).  red: LDS scratch of at least blockDim/64 doubles.
 __device__ __forceinline__ double block_sum(double x, double* red) {
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    x = wave_sum_f64(x);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     __syncthreads();
-    if (lane == 0) red[w] = x;
+    if (lane == 63) red[w] = x;
     __syncthreads();
     double s = 0.0;
     if (threadIdx.x == 0) {
