@@ -145,6 +145,11 @@ qedhmc_status qedhmc_destroy(qedhmc_t h) {
             (void)hipEventDestroy(h->prof_ev[k][0]);
             (void)hipEventDestroy(h->prof_ev[k][1]);
         }
+    for (auto& a : h->cg_graph)
+        for (auto& b : a)
+            for (auto& g : b)
+                if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     delete h;
     return QEDHMC_OK;
 }

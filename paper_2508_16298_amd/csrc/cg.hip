@@ -100,6 +100,55 @@ static qedhmc_status launch_iters(qedhmc_ctx* h, const CgBufs<R>& B, int& kpar, 
     });
 }
 
+// One chunk of `count` iteration launches from launch parity kpar and buffer
+// parity ipar0, replayed from a graph captured the first time this
+// (buffers, tolerance, precision, chunk) combination is seen.
+template <typename R>
+static qedhmc_status launch_iters_graph(qedhmc_ctx* h, const CgBufs<R>& B, int kpar, int ipar0, int count,
+                                        double tol2, int mixed) {
+    qedhmc_ctx::CgGraph& gr = h->cg_graph[sizeof(R) == 8 ? 1 : 0][kpar][ipar0];
+    if (gr.exec && (gr.x != B.x || gr.rhs != B.rhs || gr.tol2 != tol2 || gr.mixed != mixed || gr.count != count)) {
+        QH_HIP(hipGraphExecDestroy(gr.exec));
+        gr.exec = nullptr;
+    }
+    if (!gr.exec) {
+        if (!h->cap_stream) QH_HIP(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+        // kernel attributes before the capture
+        QH_TRY(with_shape<R>(h, [&]<int MC, int NB, int BS>(int nt, size_t lds) -> qedhmc_status {
+            return lds_attr(h, k_cg_iter<R, MC, NB, BS>, lds);
+        }));
+        hipStream_t user = h->stream;
+        const int prof = h->prof_every;
+        h->stream = h->cap_stream;
+        h->prof_every = 0;  // no event launches inside a graph
+        hipGraph_t g = nullptr;
+        qedhmc_status st = QEDHMC_OK;
+        hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            int kp = kpar;
+            st = launch_iters<R>(h, B, kp, ipar0, count, tol2, mixed);
+            e = hipStreamEndCapture(h->cap_stream, &g);
+        }
+        h->stream = user;
+        h->prof_every = prof;
+        if (st != QEDHMC_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        QH_HIP(e);
+        e = hipGraphInstantiate(&gr.exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        QH_HIP(e);
+        gr.x = B.x;
+        gr.rhs = B.rhs;
+        gr.tol2 = tol2;
+        gr.mixed = mixed;
+        gr.count = count;
+    }
+    QH_HIP(hipGraphLaunch(gr.exec, h->stream));
+    return QEDHMC_OK;
+}
+
 template <typename R>
 static qedhmc_status launch_true(qedhmc_ctx* h, const CgBufs<R>& B, const double* x, int kpar, int restart) {
     QH_TRY(launch_mdagm(h, QEDHMC_FP64, x, h->ws[3], nullptr));
@@ -128,10 +177,20 @@ static qedhmc_status cg_t(qedhmc_ctx* h, const double* rhs, double* x, double to
     double rel = 1.0;
     bool converged = false, broken = false;
     static const bool trace = std::getenv("QEDHMC_CG_TRACE") != nullptr;
+    static const bool no_graph = std::getenv("QEDHMC_NO_GRAPH") != nullptr;
     QH_TRY(launch_start<R>(h, B));
     while (true) {
         const int left = maxit - it;
-        if (left > 0) QH_TRY(launch_iters<R>(h, B, kpar, it, left < chunk ? left : chunk, tol * tol, mixed ? 1 : 0));
+        // full chunks replay a captured graph; with kernel timing on, every
+        // 8th chunk is launched directly so its dispatches can carry events
+        const bool timed = h->prof_every > 0 && (h->cg_chunks % 8) == 0;
+        h->cg_chunks++;
+        if (left >= chunk && !no_graph && !timed) {
+            QH_TRY(launch_iters_graph<R>(h, B, kpar, it & 1, chunk, tol * tol, mixed ? 1 : 0));
+            if (chunk & 1) kpar ^= 1;
+        } else if (left > 0) {
+            QH_TRY(launch_iters<R>(h, B, kpar, it, left < chunk ? left : chunk, tol * tol, mixed ? 1 : 0));
+        }
         QH_TRY(read_slot(h, kpar));
         it = (int)h->h_pinned[S_ITERS];
         const double flag = h->h_pinned[S_DONE];

@@ -460,6 +460,18 @@ struct qedhmc_ctx {
     bool prof_used[64];
     int prof_pending;
     bool prof_ready;
+    // CG chunks captured into graphs: [R is double][launch parity][buffer
+    // parity]; captured on a private stream (capture needs a non-null
+    // stream) and launched on the handle's stream
+    struct CgGraph {
+        hipGraphExec_t exec;
+        const void* x;
+        const void* rhs;
+        double tol2;
+        int mixed, count;
+    } cg_graph[2][2][2];
+    hipStream_t cap_stream;
+    int64_t cg_chunks;
     // the paper's preconditioner (built on first use)
     bool pc_ready;
     double pc_shift;
