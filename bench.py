@@ -14,8 +14,9 @@ fused CG iteration k_cg_iter (one launch per iteration: recurrences, x update,
 M^dag M, inner products).  Its algorithmic bytes per site are, in the mixed
 path, r, w, s, p read (4 x 8 B), two FP32 angles (8 B), x read and written
 (2 x 16 B, FP64) and r, s, p, w written (4 x 8 B): 104 B per site (176 B in
-FP64).  Its duration is the start/end event pair of every 8th dispatch
-(hipExtLaunchKernelGGL) over the timed region.  The metric's M^dag M
+FP64).  Its duration comes from event pairs around every 8th graph replay of
+51 back-to-back iteration launches (a replay holds nothing else) over the
+timed region; `traffic` is the counter-measured HBM bytes per launch.  The metric's M^dag M
 bandwidth is measured after the timed region on the standalone fused
 M^dag M kernel at 24 B per site (v in, out written, two FP32 angles; 48 B in
 FP64), 200 back-to-back launches, every dispatch timed the same way.
@@ -33,6 +34,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+# HBM bytes per launch of the fused CG iteration from rocprofv3 counters
+# (profiles/k_cg_iter_mixed_l24_hbm_counters.md): FETCH_SIZE and WRITE_SIZE in
+# KiB, scaled by the copy-kernel calibration (x2.0 and x1.0).  Valid for the
+# kernel as measured there; set to None whenever k_cg_iter changes.
+CG_ITER_COUNTER_BYTES = {"fp32": (4637.5 * 2.0 + 6491.4 * 1.0) * 1024, "fp64": None}
 
 
 def parse():
@@ -388,7 +395,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": None,
+            "traffic": CG_ITER_COUNTER_BYTES["fp32" if prec != "fp64" else "fp64"],
             "alg_bytes_per_launch": it_bytes,
             "avg_launch_us": avg_ms * 1e3,
             "timed_launches": n_k,

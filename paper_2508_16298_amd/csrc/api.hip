@@ -21,23 +21,26 @@ static qedhmc_status einval(const char* msg) {
     return QEDHMC_EINVAL;
 }
 
-bool prof_sample(qedhmc_ctx* h, int cls, hipEvent_t& e0, hipEvent_t& e1) {
+bool prof_sample_n(qedhmc_ctx* h, int cls, int n, hipEvent_t& e0, hipEvent_t& e1) {
     if (h->prof_every <= 0 || !h->prof_ready) return false;
     if ((h->prof_seen[cls]++ % h->prof_every) != 0) return false;
     if (h->prof_pending == 64 && prof_drain(h) != QEDHMC_OK) return false;
     const int k = h->prof_pending++;
     h->prof_cls[k] = cls;
+    h->prof_weight[k] = n;
     e0 = h->prof_ev[k][0];
     e1 = h->prof_ev[k][1];
     return true;
 }
+
+bool prof_sample(qedhmc_ctx* h, int cls, hipEvent_t& e0, hipEvent_t& e1) { return prof_sample_n(h, cls, 1, e0, e1); }
 
 qedhmc_status prof_drain(qedhmc_ctx* h) {
     for (int k = 0; k < h->prof_pending; k++) {
         QH_HIP(hipEventSynchronize(h->prof_ev[k][1]));
         float ms = 0.f;
         QH_HIP(hipEventElapsedTime(&ms, h->prof_ev[k][0], h->prof_ev[k][1]));
-        h->prof_count[h->prof_cls[k]]++;
+        h->prof_count[h->prof_cls[k]] += h->prof_weight[k];
         h->prof_ms[h->prof_cls[k]] += ms;
     }
     h->prof_pending = 0;

@@ -145,7 +145,13 @@ static qedhmc_status launch_iters_graph(qedhmc_ctx* h, const CgBufs<R>& B, int k
         gr.mixed = mixed;
         gr.count = count;
     }
+    // kernel timing: an event pair around the whole replay (the replay is
+    // nothing but `count` back-to-back launches of the iteration kernel)
+    hipEvent_t e0, e1;
+    const bool timed = prof_sample_n(h, sizeof(R) == 4 ? QEDHMC_K_CG_FP32 : QEDHMC_K_CG_FP64, count, e0, e1);
+    if (timed) QH_HIP(hipEventRecord(e0, h->stream));
     QH_HIP(hipGraphLaunch(gr.exec, h->stream));
+    if (timed) QH_HIP(hipEventRecord(e1, h->stream));
     return QEDHMC_OK;
 }
 
@@ -181,11 +187,8 @@ static qedhmc_status cg_t(qedhmc_ctx* h, const double* rhs, double* x, double to
     QH_TRY(launch_start<R>(h, B));
     while (true) {
         const int left = maxit - it;
-        // full chunks replay a captured graph; with kernel timing on, every
-        // 8th chunk is launched directly so its dispatches can carry events
-        const bool timed = h->prof_every > 0 && (h->cg_chunks % 8) == 0;
-        h->cg_chunks++;
-        if (left >= chunk && !no_graph && !timed) {
+        // full chunks replay a captured graph
+        if (left >= chunk && !no_graph) {
             QH_TRY(launch_iters_graph<R>(h, B, kpar, it & 1, chunk, tol * tol, mixed ? 1 : 0));
             if (chunk & 1) kpar ^= 1;
         } else if (left > 0) {

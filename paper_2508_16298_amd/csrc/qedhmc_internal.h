@@ -457,6 +457,7 @@ struct qedhmc_ctx {
     double prof_ms[QEDHMC_K_COUNT];
     hipEvent_t prof_ev[64][2];
     int prof_cls[64];
+    int prof_weight[64];  // launches covered by the event pair
     bool prof_used[64];
     int prof_pending;
     bool prof_ready;
@@ -471,7 +472,6 @@ struct qedhmc_ctx {
         int mixed, count;
     } cg_graph[2][2][2];
     hipStream_t cap_stream;
-    int64_t cg_chunks;
     // the paper's preconditioner (built on first use)
     bool pc_ready;
     double pc_shift;
@@ -504,6 +504,8 @@ Coef<R> coef_of(const qedhmc_params& p);
 // of class cls is to be timed and hands out the start/stop events to pass to
 // hipExtLaunchKernelGGL, which records them around the dispatch itself.
 bool prof_sample(qedhmc_ctx* h, int cls, hipEvent_t& e0, hipEvent_t& e1);
+// the same for an event pair around n launches of the class (a graph replay)
+bool prof_sample_n(qedhmc_ctx* h, int cls, int n, hipEvent_t& e0, hipEvent_t& e1);
 qedhmc_status prof_drain(qedhmc_ctx* h);
 
 // Launch helpers implemented in lattice.hip
