@@ -190,7 +190,41 @@ def run_batched(a):
                      "alg_bytes_per_launch": it_bytes, "avg_launch_us": it_us, "timed_launches": "24, best of 2"},
     }
     b.close()
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batched(wl, sizes, ths, per_chain_iters, a.cpu_iters)
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_batched(wl, sizes, ths, per_chain_iters, n_iter):
+    """Oracle (plain FP64 C, one thread) on a bounded sample: n_iter CG
+    iterations and one fermion + gauge force on one chain of each lattice size
+    in the batch; every chain's trajectory is then costed at its measured CG
+    iteration count and N_md + 1 forces.  Reported in site-updates/s."""
+    import oracle as O
+    from paper_2508_16298_amd import inputs
+    per_size = {}
+    t_sample = 0.0
+    for c, (L, Nt) in enumerate(sizes):
+        if L in per_size:
+            continue
+        p = O.lat(L, Nt, wl.dtau, wl.t, wl.J, wl.K)
+        th = ths[c]
+        eta = O.apply_M(p, th, inputs.gauss_cvec(L, Nt, 77), dagger=True)
+        t0 = time.perf_counter()
+        X, st, it, rel = O.cg_solve(p, th, eta, tol=1e-30, maxit=n_iter)
+        t1 = time.perf_counter()
+        O.fermion_force(p, th, X)
+        O.bosonic_force(p, th)
+        t2 = time.perf_counter()
+        per_size[L] = ((t1 - t0) / max(it, 1), t2 - t1)
+        t_sample += t2 - t0
+    est = sum(per_size[L][0] * per_chain_iters[c] + per_size[L][1] * (wl.n_steps + 1)
+              for c, (L, Nt) in enumerate(sizes))
+    N = sum(L * L * Nt for L, Nt in sizes)
+    return {"value": N / est, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle FP64 CG, {n_iter} iterations + one fermion and gauge force per lattice size "
+                       f"{sorted(per_size)} ({t_sample:.1f} s); every chain costed at its measured CG iterations "
+                       f"and {wl.n_steps + 1} forces (extrapolation, single thread)")}
 
 
 def run_learned(a):
@@ -283,7 +317,45 @@ def run_learned(a):
                      "frac": (achieved / 2500.0) if achieved else None, "traffic": None,
                      "alg_flops_per_launch": flops, "avg_launch_us": avg_ms * 1e3, "timed_launches": n_k},
     }
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_learned(res["learned"]["iterations"], res["learned"]["switched_at"],
+                                                    params, L, Nt)
     print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_learned(iters, switched, flat_params, L, Nt):
+    """Oracle (FP64 numpy network, plain C M^dag M, numpy preconditioner
+    twin) on a bounded sample: one network application, one M^dag M and one
+    preconditioner application on an 8 x 8 x 80 lattice, scaled per site to
+    the evaluation lattice and to the learned solve's iterations (network
+    iterations until the switch, the paper's preconditioner after it)."""
+    import numpy as np
+    import oracle as O
+    from oracle import net as NN
+    from oracle import precond as PC
+    from paper_2508_16298_amd import inputs
+    from paper_2508_16298_amd import qedhmc as Q
+    Ls, Nts = 8, 80
+    th = inputs.noisy_pi_flux_theta(Ls, Nts, 0.3, 1)
+    r = inputs.gauss_cvec(Ls, Nts, 2)
+    params = [(W.astype(np.float64), b.astype(np.float64)) for W, b in Q.Net.unpack(flat_params)]
+    p = O.lat(Ls, Nts)
+    t0 = time.perf_counter()
+    NN.forward(params, th, r)
+    t1 = time.perf_counter()
+    O.apply_MdagM(p, th, r)
+    t2 = time.perf_counter()
+    taps, _ = PC.build_stencil()
+    t3 = time.perf_counter()
+    PC.apply_P(taps, r)
+    t4 = time.perf_counter()
+    scale = (L * L * Nt) / (Ls * Ls * Nts)
+    n_net = iters if switched < 0 else switched
+    est = scale * (n_net * (t1 - t0) + iters * (t2 - t1) + (iters - n_net) * (t4 - t3))
+    return {"value": est, "unit": "s/solve", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle FP64 network forward ({t1 - t0:.2f} s), M^dag M ({t2 - t1:.3f} s) and paper "
+                       f"preconditioner ({t4 - t3:.2f} s) on L={Ls} Nt={Nts}, scaled per site to L={L} Nt={Nt} and "
+                       f"to {iters} iterations ({n_net} with the network) (extrapolation)")}
 
 
 def main():
