@@ -238,6 +238,7 @@ static qedhmc_status cg_t(qedhmc_ctx* h, const double* rhs, double* x, double to
 
 qedhmc_status cg_solve_impl(qedhmc_ctx* h, const double* rhs, double* x, double tol, int maxit,
                             qedhmc_precision prec, int* iters, double* true_rel, int* n_reliable) {
+    if (h->lat.ncell > 1024) return cg2_solve_impl(h, rhs, x, tol, maxit, prec, iters, true_rel, n_reliable);
     if (prec == QEDHMC_FP64) return cg_t<double>(h, rhs, x, tol, maxit, prec, iters, true_rel, n_reliable);
     return cg_t<float>(h, rhs, x, tol, maxit, prec, iters, true_rel, n_reliable);
 }

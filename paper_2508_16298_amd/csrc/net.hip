@@ -98,10 +98,26 @@ __global__ __launch_bounds__(256) void k_conv_fwd(NetGeo g, const TIN* __restric
             }
         }
     }
+    if (pre)
 #pragma unroll
-    for (int co = 0; co < COUT; co++) {
-        if (pre) pre[(size_t)n * COUT + co] = acc[co];
-        act[(size_t)n * COUT + co] = from_f32<TOUT>(SILU ? silu_f(acc[co]) : acc[co]);
+        for (int co = 0; co < COUT; co++) pre[(size_t)n * COUT + co] = acc[co];
+    if constexpr (sizeof(TOUT) == 2 && COUT % 8 == 0) {
+        // BF16 out: eight channels per 16-byte store
+#pragma unroll
+        for (int c8 = 0; c8 < COUT; c8 += 8) {
+            uint32_t w[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const float v0 = SILU ? silu_f(acc[c8 + 2 * j]) : acc[c8 + 2 * j];
+                const float v1 = SILU ? silu_f(acc[c8 + 2 * j + 1]) : acc[c8 + 2 * j + 1];
+                w[j] = (uint32_t)f32_to_bf16(v0) | ((uint32_t)f32_to_bf16(v1) << 16);
+            }
+            *reinterpret_cast<uint4*>(act + (size_t)n * COUT + c8) = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    } else {
+#pragma unroll
+        for (int co = 0; co < COUT; co++)
+            act[(size_t)n * COUT + co] = from_f32<TOUT>(SILU ? silu_f(acc[co]) : acc[co]);
     }
 }
 

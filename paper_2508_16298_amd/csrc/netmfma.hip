@@ -7,8 +7,9 @@
 // block of the tap-shifted input (A) and a 32 x 16 block of that tap's
 // weights (B), so a tap costs two MFMAs per 16 sites and a layer 54.  The
 // layer's weights (27 taps x 2 column halves, 55 KB of BF16 in the MFMA B
-// fragment order) are staged once per workgroup in LDS; each wavefront keeps
-// one tap's two B fragments in registers while it runs four 16-site tiles,
+// fragment order) are staged once per workgroup of 16 wavefronts in LDS; each
+// wavefront keeps one tap's two B fragments in registers while it runs two
+// 16-site tiles (the fastest of the tilings timed at L=66),
 // and reads the A fragments straight from the channels-last activations
 // (one 16-byte load per lane: 8 channels of one site).  Neighbour reuse
 // across taps is left to L1/L2.
@@ -21,8 +22,9 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 static constexpr int kHidden = 4;             // 32 -> 32 layers (1..4, zero based)
 static constexpr int kFrag = 27 * 2 * 64;     // B fragments (16 bytes each) per layer
-static constexpr int kTiles = 4;              // 16-site tiles per wavefront
-static constexpr int kSitesPerBlock = 4 * 16 * kTiles;
+static constexpr int kTiles = 2;              // 16-site tiles per wavefront
+static constexpr int kBlock = 1024;           // threads per workgroup (16 wavefronts share the staged weights)
+static constexpr int kSitesPerBlock = (kBlock / 64) * 16 * kTiles;
 
 size_t net_bf16_weight_elems() { return (size_t)kHidden * kFrag * 8; }
 
@@ -44,7 +46,7 @@ __global__ void k_pack_bf16(const float* __restrict__ params, size_t w0, size_t 
 }
 
 template <bool SILU>
-__global__ __launch_bounds__(256) void k_conv_mfma(NetGeo g, const uint16_t* __restrict__ in,
+__global__ __launch_bounds__(kBlock) void k_conv_mfma(NetGeo g, const uint16_t* __restrict__ in,
                                                    const uint16_t* __restrict__ wfrag,
                                                    const float* __restrict__ bias, uint16_t* __restrict__ out) {
     __shared__ bf16x8 sW[kFrag];
@@ -122,11 +124,11 @@ qedhmc_status net_forward_bf16(qedhmc_net* n, const double* r) {
         const int l = hl + 1;
         hipEvent_t e0, e1;
         if (prof_sample(n->h, QEDHMC_K_NET_MFMA, e0, e1))
-            hipExtLaunchKernelGGL((k_conv_mfma<true>), dim3(blocks), dim3(256), 0, st, e0, e1, 0, g,
+            hipExtLaunchKernelGGL((k_conv_mfma<true>), dim3(blocks), dim3(kBlock), 0, st, e0, e1, 0, g,
                                   (const uint16_t*)n->actb[cur], (const uint16_t*)(n->wbf + (size_t)hl * kFrag * 8),
                                   (const float*)(n->params + n->boff[l]), n->actb[cur ^ 1]);
         else
-            hipLaunchKernelGGL((k_conv_mfma<true>), dim3(blocks), dim3(256), 0, st, g, (const uint16_t*)n->actb[cur],
+            hipLaunchKernelGGL((k_conv_mfma<true>), dim3(blocks), dim3(kBlock), 0, st, g, (const uint16_t*)n->actb[cur],
                                (const uint16_t*)(n->wbf + (size_t)hl * kFrag * 8),
                                (const float*)(n->params + n->boff[l]), n->actb[cur ^ 1]);
         QH_HIP(hipGetLastError());

@@ -530,19 +530,25 @@ static qedhmc_status launch_mv(qedhmc_ctx* h, const PcgBufs<R>& B, const double*
     });
 }
 
-// u = P r, w = O u, partials (stop: nullable slot flag)
+// u = P r, w = O u, partials (stop: nullable slot flag); with the identity
+// preconditioner u is r itself and only w = O r is launched
 template <typename R>
-static qedhmc_status pcg_tail(qedhmc_ctx* h, const PcgBufs<R>& B, const double* stop) {
-    QH_TRY(apply_P_t<R>(h, B.r, B.u, B.t, stop));
+static qedhmc_status pcg_tail(qedhmc_ctx* h, const PcgBufs<R>& B, const double* stop, bool identity) {
+    if (!identity) QH_TRY(apply_P_t<R>(h, B.r, B.u, B.t, stop));
     return launch_mv<R>(h, B, stop, stop != nullptr);
 }
 
+// identity = true: plain CG in the same two-launch form (update, then
+// M^dag M with the partials), the form used for lattices whose slices hold
+// more than 1024 cells: there the fused one-launch iteration would need two
+// cells per thread and more registers than a 576-thread workgroup has.
 template <typename R>
 static qedhmc_status pcg_t(qedhmc_ctx* h, const double* rhs, double* x, double tol, int maxit, qedhmc_precision prec,
-                           int* iters, double* true_rel, int* n_reliable) {
-    QH_TRY(ensure_paper_precond(h));
+                           int* iters, double* true_rel, int* n_reliable, bool identity) {
+    if (!identity) QH_TRY(ensure_paper_precond(h));
     const bool mixed = prec != QEDHMC_FP64;
-    const PcgBufs<R> B = pbufs_of<R>(h, rhs, x);
+    PcgBufs<R> B = pbufs_of<R>(h, rhs, x);
+    if (identity) B.u = B.r;
     const int Nt = h->lat.Nt;
     const int chunk = mixed ? kCap + 1 : 64;
     int kpar = 0, nrel = 0, it = 0, stalled = 0, last_it = -1;
@@ -552,7 +558,7 @@ static qedhmc_status pcg_t(qedhmc_ctx* h, const double* rhs, double* x, double t
     hipLaunchKernelGGL(k_pcg_init_slot, dim3(1), dim3(256), 0, h->stream, h->scal, (const double*)B.partb, Nt,
                        tol * tol);
     QH_HIP(hipGetLastError());
-    QH_TRY(pcg_tail<R>(h, B, nullptr));
+    QH_TRY(pcg_tail<R>(h, B, nullptr, identity));
     while (true) {
         const int left = maxit - it;
         const int n = left < chunk ? left : chunk;
@@ -560,7 +566,7 @@ static qedhmc_status pcg_t(qedhmc_ctx* h, const double* rhs, double* x, double t
             hipLaunchKernelGGL(k_pcg_upd<R>, dim3(Nt), dim3(256), 0, h->stream, h->lat, B, h->scal, kpar,
                                mixed ? 1 : 0);
             kpar ^= 1;
-            QH_TRY(pcg_tail<R>(h, B, h->scal + S_NSLOT * kpar + S_DONE));
+            QH_TRY(pcg_tail<R>(h, B, h->scal + S_NSLOT * kpar + S_DONE, identity));
         }
         QH_HIP(hipGetLastError());
         QH_TRY(read_slot(h, kpar));
@@ -583,7 +589,7 @@ static qedhmc_status pcg_t(qedhmc_ctx* h, const double* rhs, double* x, double t
         hipLaunchKernelGGL(k_pcg_rep<R>, dim3(Nt), dim3(256), 0, h->stream, h->lat, B);
         QH_HIP(hipGetLastError());
         QH_TRY(launch_mdagm(h, prec == QEDHMC_FP64 ? QEDHMC_FP64 : QEDHMC_FP32, B.p, B.s, nullptr));
-        QH_TRY(pcg_tail<R>(h, B, nullptr));
+        QH_TRY(pcg_tail<R>(h, B, nullptr, identity));
         hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(256), 0, h->stream, h->scal, kpar, (const double*)B.part,
                            (const double*)B.partb, Nt, (!mixed || flag == 3.0) ? 1 : 0);
         QH_HIP(hipGetLastError());
@@ -611,8 +617,14 @@ static qedhmc_status pcg_t(qedhmc_ctx* h, const double* rhs, double* x, double t
 
 qedhmc_status pcg_solve_impl(qedhmc_ctx* h, const double* rhs, double* x, double tol, int maxit,
                              qedhmc_precision prec, int* iters, double* true_rel, int* n_reliable) {
-    if (prec == QEDHMC_FP64) return pcg_t<double>(h, rhs, x, tol, maxit, prec, iters, true_rel, n_reliable);
-    return pcg_t<float>(h, rhs, x, tol, maxit, prec, iters, true_rel, n_reliable);
+    if (prec == QEDHMC_FP64) return pcg_t<double>(h, rhs, x, tol, maxit, prec, iters, true_rel, n_reliable, false);
+    return pcg_t<float>(h, rhs, x, tol, maxit, prec, iters, true_rel, n_reliable, false);
+}
+
+qedhmc_status cg2_solve_impl(qedhmc_ctx* h, const double* rhs, double* x, double tol, int maxit,
+                             qedhmc_precision prec, int* iters, double* true_rel, int* n_reliable) {
+    if (prec == QEDHMC_FP64) return pcg_t<double>(h, rhs, x, tol, maxit, prec, iters, true_rel, n_reliable, true);
+    return pcg_t<float>(h, rhs, x, tol, maxit, prec, iters, true_rel, n_reliable, true);
 }
 
 }  // namespace qh

@@ -523,6 +523,10 @@ qedhmc_status cg_solve_impl(qedhmc_ctx* h, const double* rhs, double* x, double 
                             qedhmc_precision prec, int* iters, double* true_rel, int* n_reliable);
 qedhmc_status pcg_solve_impl(qedhmc_ctx* h, const double* rhs, double* x, double tol, int maxit,
                              qedhmc_precision prec, int* iters, double* true_rel, int* n_reliable);
+// plain CG as two launches per iteration (update; M^dag M with partials), for
+// lattices with more than 1024 cells per slice
+qedhmc_status cg2_solve_impl(qedhmc_ctx* h, const double* rhs, double* x, double tol, int maxit,
+                             qedhmc_precision prec, int* iters, double* true_rel, int* n_reliable);
 qedhmc_status ensure_paper_precond(qedhmc_ctx* h);
 qedhmc_status launch_apply_precond(qedhmc_ctx* h, qedhmc_precision prec, const void* in, void* out);
 

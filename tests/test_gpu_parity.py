@@ -286,3 +286,24 @@ def test_fp64_chain_matches_oracle_golden():
             assert abs(thh.sum() - ref["theta_sum"]) <= 1e-9 * abs(ref["theta_sumsq"]) ** 0.5 * thh.size ** 0.5
             assert abs((thh ** 2).sum() - ref["theta_sumsq"]) <= 1e-8 * ref["theta_sumsq"]
     print("worst |dH gpu - dH oracle| =", worst, flush=True)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-8)])
+def test_cg_large_lattice_two_launch_path(prec, tol):
+    """L=66 has 1089 cells per slice (> 1024): the solver takes its
+    two-launch form.  True residual recomputed by the oracle; the FP64
+    iteration count matches the oracle's CG."""
+    L, Nt = 66, 12
+    p = O.lat(L, Nt)
+    th = inputs.noisy_pi_flux_theta(L, Nt, 0.3, 1066)
+    R = inputs.gauss_cvec(L, Nt, 1067)
+    eta = O.apply_M(p, th, R, dagger=True).reshape(Nt, L, L)
+    with Q.Lattice(L, Nt) as lat:
+        x, st, it, rel = lat.cg_solve(_dev(th), _dev(eta), tol=tol, prec=prec)
+        xg = _host(x)
+    true = np.linalg.norm(eta.reshape(-1) - O.apply_MdagM(p, th, xg).reshape(-1)) / np.linalg.norm(eta)
+    print(f"L=66 Nt=12 {prec}: {it} iterations, true residual {true:.2e}", flush=True)
+    assert st == Q.OK and rel <= tol and true <= 1.05 * tol
+    if prec == "fp64":
+        _, _, ito, _ = O.cg_solve(p, th, eta, tol=tol)
+        assert abs(it - ito) <= max(2, ito // 50), (it, ito)
