@@ -429,17 +429,20 @@ __global__ __launch_bounds__(BS) void k_pcg_mv(Lat lt, PcgBufs<R> B, const cplx<
     cplx<R> hm[MC][12], ht[MC][12];
     hops_of<R, MC>(gauge, lt, c.tm, c.idx, co, hm);
     hops_of<R, MC>(gauge, lt, c.tau, c.idx, co, ht);
-    Cells<R, MC> um, ut, un, rt, pt, st, w;
+    Cells<R, MC> um, ut, un, w;
     load_cells<R, MC>(um, B.u + c.tm * Vs, c.g, c.own);
     load_cells<R, MC>(ut, B.u + c.tau * Vs, c.g, c.own);
     load_cells<R, MC>(un, B.u + c.tp * Vs, c.g, c.own);
-    load_cells<R, MC>(rt, B.r + c.tau * Vs, c.g, c.own);
-    load_cells<R, MC>(pt, B.p + c.tau * Vs, c.g, c.own);
-    load_cells<R, MC>(st, B.s + c.tau * Vs, c.g, c.own);
-    const Cells<R, MC> u0 = ut;
     mdagm_cells<R, MC, NB>(um, ut, un, hm, ht, c.g, c.own, co, c.tau == 0 ? R(-1) : R(1),
                            c.tau == lt.Nt - 1 ? R(-1) : R(1), buf2, lt.Vs, w);
     store_cells<R, MC>(w, B.w + c.tau * Vs, c.g, c.own);
+    // the own-slice vectors of the inner products, read after the matvec so
+    // they are not live across it (fewer registers with two cells a thread)
+    Cells<R, MC> u0, rt, pt, st;
+    load_cells<R, MC>(u0, B.u + c.tau * Vs, c.g, c.own);
+    load_cells<R, MC>(rt, B.r + c.tau * Vs, c.g, c.own);
+    load_cells<R, MC>(pt, B.p + c.tau * Vs, c.g, c.own);
+    load_cells<R, MC>(st, B.s + c.tau * Vs, c.g, c.own);
     double v[kNP7] = {dot_cells<R, MC>(rt, rt, c.own), dot_cells<R, MC>(rt, u0, c.own),
                       dot_cells<R, MC>(w, u0, c.own),  dot_cells<R, MC>(u0, st, c.own),
                       dot_cells<R, MC>(pt, w, c.own),  dot_cells<R, MC>(pt, st, c.own), 0.0};
