@@ -183,7 +183,8 @@ static qedhmc_status cg_t(qedhmc_ctx* h, const double* rhs, double* x, double to
     double rel = 1.0;
     bool converged = false, broken = false;
     static const bool trace = std::getenv("QEDHMC_CG_TRACE") != nullptr;
-    static const bool no_graph = std::getenv("QEDHMC_NO_GRAPH") != nullptr;
+    // QEDHMC_NO_GRAPH (read per solve) launches every chunk directly
+    const bool no_graph = std::getenv("QEDHMC_NO_GRAPH") != nullptr;
     QH_TRY(launch_start<R>(h, B));
     while (true) {
         const int left = maxit - it;

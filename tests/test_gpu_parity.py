@@ -307,3 +307,35 @@ def test_cg_large_lattice_two_launch_path(prec, tol):
     if prec == "fp64":
         _, _, ito, _ = O.cg_solve(p, th, eta, tol=tol)
         assert abs(it - ito) <= max(2, ito // 50), (it, ito)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_cg_graph_replays_match_direct_launches(prec):
+    """Solves whose iteration chunks replay captured graphs give bitwise the
+    same solution, iteration count and residual as the same solves launched
+    directly, over several solves on one handle (graphs replayed many times,
+    with the reliable updates' eager launches and host reads in between)."""
+    import os
+    L, Nt = 12, 40
+    p = O.lat(L, Nt)
+    out = {}
+    with Q.Lattice(L, Nt) as lat:
+        for mode in ("graph", "direct", "graph"):
+            if mode == "direct":
+                os.environ["QEDHMC_NO_GRAPH"] = "1"
+            else:
+                os.environ.pop("QEDHMC_NO_GRAPH", None)
+            res = []
+            for seed in (11, 12, 13):
+                th = inputs.noisy_pi_flux_theta(L, Nt, 0.3, seed)
+                eta = O.apply_M(p, th, inputs.gauss_cvec(L, Nt, seed + 50), dagger=True).reshape(Nt, L, L)
+                x, st, it, rel = lat.cg_solve(_dev(th), _dev(eta), tol=1e-10 if prec == "fp64" else 1e-8,
+                                              prec=prec)
+                res.append((_host(x), st, it, rel))
+            out.setdefault(mode, []).append(res)
+    os.environ.pop("QEDHMC_NO_GRAPH", None)
+    ref = out["direct"][0]
+    for run in out["graph"]:
+        for (xg, sg, ig, rg), (xd, sd, id_, rd) in zip(run, ref):
+            assert sg == sd == Q.OK and ig == id_ and rg == rd
+            assert np.array_equal(xg, xd)
