@@ -226,7 +226,10 @@ qedhmc_status qedhmc_batch_layout(qedhmc_batch_t b, int64_t *theta_off,
                                   int64_t *vec_off);
 
 /* The tile shape the autotuner chose for the CG recursion in precision
- * prec (cells per thread, threads per workgroup, LDS exchange buffers) and
+ * prec (cells per thread, threads per workgroup, LDS exchange buffers; a
+ * workgroup runs threads / G consecutive time slices of one chain, G the
+ * smallest power of two from 16 up with G x cells per thread at least the
+ * slice's L^2 / 4 cells) and
  * the measured time per batched CG iteration of each of the four candidate
  * shapes in microseconds (host float[4]; 0 for a candidate that does not
  * fit). */

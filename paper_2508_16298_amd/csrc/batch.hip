@@ -50,9 +50,31 @@ struct ChainDev {
     int frozen;  // device: 1 once the solve of this chain is final
 };
 
+// A workgroup of kBS threads runs kBS / G consecutive slices tau0, tau0 + 1,
+// ... of one chain, a group of G threads per slice (G: the smallest power of
+// two from 16 up with G x cells per thread >= the slice's cells).  Groups past
+// the chain's last slice are padding: they take part in the barriers, own no
+// cell and write nothing.
 struct Blk {
-    int chain, tau;  // chain < 0: padding block
+    int chain, tau0, G;  // chain < 0: padding block
 };
+
+// This thread's group: its slice (an in-range stand-in for padding groups),
+// its exchange buffers (gbytes each, in group order) and the workgroup's
+// reduction scratch after the last group's buffers.
+__device__ __forceinline__ Tile blk_tile(const Blk& b, int Nt, unsigned char* smem, size_t gbytes, int& tau) {
+    const int g = (int)threadIdx.x / b.G;
+    tau = b.tau0 + g;
+    const bool valid = tau < Nt;
+    if (!valid) tau = b.tau0;
+    return Tile{(int)threadIdx.x - g * b.G, b.G, valid, smem + g * gbytes,
+                reinterpret_cast<double*>(smem + (size_t)(kBS / b.G) * gbytes)};
+}
+
+template <typename R, int NB>
+__device__ __forceinline__ size_t group_lds(const Lat& lt) {
+    return (size_t)NB * 2 * lt.Vs * sizeof(cplx<R>);
+}
 
 __device__ __forceinline__ bool needs_update(double done) {
     return done == 1.0 || done == 2.0 || done == 3.0 || done == 6.0;
@@ -68,8 +90,10 @@ __global__ __launch_bounds__(kBS) void k_b_cg_start(const ChainDev<R>* __restric
     const Blk b = blk[blockIdx.x];
     if (b.chain < 0) return;
     const ChainDev<R>& d = tab[b.chain];
-    cg_start_body<R, MC, NB>(d.lt, d.B, d.gauge, d.co, d.scal, b.tau, b.tau == 0, smem);
-    if (b.tau == 0 && threadIdx.x < kNRes) res[kNRes * b.chain + threadIdx.x] = 0.0;
+    int tau;
+    const Tile tl = blk_tile(b, d.lt.Nt, smem, group_lds<R, NB>(d.lt), tau);
+    cg_start_body<R, MC, NB>(d.lt, d.B, d.gauge, d.co, d.scal, tau, tl.valid && tau == 0, tl);
+    if (b.tau0 == 0 && threadIdx.x < kNRes) res[kNRes * b.chain + threadIdx.x] = 0.0;
 }
 
 template <typename R, int MC, int NB>
@@ -83,14 +107,17 @@ __global__ __launch_bounds__(kBS) void k_b_cg_iter(const ChainDev<R>* __restrict
     const int it = d.it0 + k;  // the iteration count if the chain ran every launch of this chunk
     if (it >= d.maxit) {
         // budget used: carry the state over, mark it for the final true residual
-        if (b.tau == 0 && threadIdx.x < S_NSLOT) {
+        if (b.tau0 == 0 && threadIdx.x < S_NSLOT) {
             double v = d.scal[S_NSLOT * kpar + threadIdx.x];
             if (threadIdx.x == S_DONE && v == 0.0) v = 6.0;
             d.scal[S_NSLOT * (kpar ^ 1) + threadIdx.x] = v;
         }
         return;
     }
-    cg_iter_body<R, MC, NB>(d.lt, d.B, d.gauge, d.co, d.scal, kpar, it & 1, tol2, d.mixed, b.tau, b.tau == 0, smem);
+    int tau;
+    const Tile tl = blk_tile(b, d.lt.Nt, smem, group_lds<R, NB>(d.lt), tau);
+    cg_iter_body<R, MC, NB>(d.lt, d.B, d.gauge, d.co, d.scal, kpar, it & 1, tol2, d.mixed, tau, tl.valid && tau == 0,
+                            tl);
 }
 
 // FP64 O x of the chains that stopped or paused
@@ -102,8 +129,10 @@ __global__ __launch_bounds__(kBS) void k_b_ox(const ChainDev<R>* __restrict__ ta
     if (b.chain < 0) return;
     const ChainDev<R>& d = tab[b.chain];
     if (d.frozen || !needs_update(d.scal[S_NSLOT * kpar + S_DONE])) return;
+    int tau;
+    const Tile tl = blk_tile(b, d.lt.Nt, smem, group_lds<double, NB>(d.lt), tau);
     SliceCtx<MC> c;
-    slice_ctx<MC>(d.lt, c, b.tau);
+    slice_ctx<MC>(d.lt, c, tau, tl);
     const size_t Vs = d.lt.Vs;
     cplx<double> hm[MC][12], ht[MC][12];
     hops_of<double, MC>(d.gauge64, d.lt, c.tm, c.idx, d.co64, hm);
@@ -113,7 +142,7 @@ __global__ __launch_bounds__(kBS) void k_b_ox(const ChainDev<R>* __restrict__ ta
     load_cells<double, MC>(vt, d.B.x + c.tau * Vs, c.g, c.own);
     load_cells<double, MC>(vn, d.B.x + c.tp * Vs, c.g, c.own);
     mdagm_cells<double, MC, NB>(vm, vt, vn, hm, ht, c.g, c.own, d.co64, c.tau == 0 ? -1.0 : 1.0,
-                                c.tau == d.lt.Nt - 1 ? -1.0 : 1.0, reinterpret_cast<cplx<double>*>(smem), d.lt.Vs, o);
+                                c.tau == d.lt.Nt - 1 ? -1.0 : 1.0, reinterpret_cast<cplx<double>*>(tl.buf), d.lt.Vs, o);
     store_cells<double, MC>(o, const_cast<cplx<double>*>(d.B.Ox) + c.tau * Vs, c.g, c.own);
 }
 
@@ -125,7 +154,9 @@ __global__ __launch_bounds__(kBS) void k_b_cg_replace(const ChainDev<R>* __restr
     if (b.chain < 0) return;
     const ChainDev<R>& d = tab[b.chain];
     if (d.frozen || !needs_update(d.scal[S_NSLOT * kpar + S_DONE])) return;
-    cg_replace_body<R, MC, NB>(d.lt, d.B, d.gauge, d.co, d.scal, kpar, b.tau, smem);
+    int tau;
+    const Tile tl = blk_tile(b, d.lt.Nt, smem, group_lds<R, NB>(d.lt), tau);
+    cg_replace_body<R, MC, NB>(d.lt, d.B, d.gauge, d.co, d.scal, kpar, tau, tl);
 }
 
 // One block per chain: the FP64 true residual decides -- converged (5),
@@ -143,7 +174,7 @@ __global__ void k_b_cg_check(ChainDev<R>* __restrict__ tab, int kpar, double* __
     int nd = done == 4.0 ? 4 : -1;
     if (needs_update(done)) {
         double pr[kNP];
-        reduce_partials(d->B.part + kNP * (size_t)d->lt.Nt * (it & 1), d->lt.Nt, red, red + kNP * 16, pr);
+        reduce_partials(d->B.part + kNP * (size_t)d->lt.Nt * (it & 1), d->lt.Nt, whole_block_tile(nullptr, red), pr);
         if (threadIdx.x == 0) {
             const double tr = pr[5];
             const int stall = (it + 1 == (int)sl[S_LASTUP]) ? (int)sl[S_STALL] + 1 : 0;
@@ -210,8 +241,9 @@ struct qedhmc_batch {
     std::vector<qedhmc_ctx*> ctx;
     std::vector<int64_t> toff;  // theta / momentum / force offsets in doubles (2N per chain), n + 1
     std::vector<int64_t> voff;  // vector offsets in complex elements (N per chain), n + 1
-    int maxL = 0, maxVs = 0, maxcell = 0, nblocks = 0;
-    qh::Blk* d_blk = nullptr;
+    int maxL = 0, maxVs = 0, maxcell = 0;
+    int nblocks[4] = {0, 0, 0, 0};                  // work-list length per tile shape
+    qh::Blk* d_blk[4] = {nullptr, nullptr, nullptr, nullptr};  // work list per tile shape
     int64_t* d_toff = nullptr;
     double* d_scal = nullptr;  // n x 2 x S_NSLOT
     double* d_res = nullptr;   // n x kNRes
@@ -242,18 +274,49 @@ static qedhmc_status with_bshape(int shape, F&& f) {
     }
 }
 
-static int shape_nt(const qedhmc_batch* b, int shape) {
-    const int mc = kShapeMC[shape];
-    int nt = (((b->maxcell + mc - 1) / mc + 63) / 64) * 64;
-    return nt < 64 ? 64 : nt;
+// threads per slice of a chain under a tile shape (0: the slice does not fit)
+static int group_threads(const Lat& lt, int shape) {
+    const int need = (lt.ncell + kShapeMC[shape] - 1) / kShapeMC[shape];
+    int G = 16;
+    while (G < need) G *= 2;
+    return G <= kBS ? G : 0;
 }
 
+// dynamic LDS of a workgroup: the exchange buffers of its kBS / G groups (the
+// largest over the chains) and the reduction scratch
 static size_t shape_lds(const qedhmc_batch* b, int shape, size_t csz) {
-    return (size_t)kShapeNB[shape] * 2 * b->maxVs * csz + (kNP * 16 + 16) * sizeof(double);
+    size_t most = 0;
+    for (const qedhmc_ctx* h : b->ctx) {
+        const int G = group_threads(h->lat, shape);
+        if (G > 0) most = std::max(most, (size_t)(kBS / G) * kShapeNB[shape] * 2 * h->lat.Vs * csz);
+    }
+    return most + (kNP * 16 + 16) * sizeof(double);
 }
 
 static bool shape_ok(const qedhmc_batch* b, int shape) {
-    return shape_nt(b, shape) <= kBS && shape_lds(b, shape, sizeof(cplx<double>)) <= b->max_lds;
+    for (const qedhmc_ctx* h : b->ctx)
+        if (group_threads(h->lat, shape) == 0) return false;
+    return shape_lds(b, shape, sizeof(cplx<double>)) <= b->max_lds;
+}
+
+// Work list of a tile shape: one entry per run of kBS / G consecutive slices
+// of a chain.  Workgroup i runs on XCD i mod 8, so the list is dealt out in 8
+// contiguous ranges and each XCD's L2 sees whole runs of neighbouring slices
+// (the tau - 1 / tau + 1 halos stay local).
+static std::vector<Blk> work_list(const qedhmc_batch* b, int shape) {
+    std::vector<Blk> work;
+    for (int c = 0; c < b->n; c++) {
+        const Lat& lt = b->ctx[c]->lat;
+        const int G = group_threads(lt, shape), T = kBS / G;
+        for (int tau0 = 0; tau0 < lt.Nt; tau0 += T) work.push_back({c, tau0, G});
+    }
+    const size_t per = (work.size() + 7) / 8;
+    std::vector<Blk> blk(per * 8, Blk{-1, 0, kBS});
+    for (size_t i = 0; i < blk.size(); i++) {
+        const size_t w = (i % 8) * per + i / 8;
+        if (w < work.size()) blk[i] = work[w];
+    }
+    return blk;
 }
 
 template <typename K>
@@ -337,8 +400,8 @@ static qedhmc_status push_tab(qedhmc_batch* b, const std::vector<const double*>&
 template <typename R>
 static qedhmc_status launch_start(qedhmc_batch* b, int shape) {
     return with_bshape(shape, [&]<int MC, int NB>() -> qedhmc_status {
-        hipLaunchKernelGGL((k_b_cg_start<R, MC, NB>), dim3(b->nblocks), dim3(shape_nt(b, shape)),
-                           shape_lds(b, shape, sizeof(cplx<R>)), b->stream, dev_tab<R>(b), b->d_blk, b->d_res);
+        hipLaunchKernelGGL((k_b_cg_start<R, MC, NB>), dim3(b->nblocks[shape]), dim3(kBS),
+                           shape_lds(b, shape, sizeof(cplx<R>)), b->stream, dev_tab<R>(b), b->d_blk[shape], b->d_res);
         QH_HIP(hipGetLastError());
         return QEDHMC_OK;
     });
@@ -347,11 +410,10 @@ static qedhmc_status launch_start(qedhmc_batch* b, int shape) {
 template <typename R>
 static qedhmc_status launch_iters(qedhmc_batch* b, int shape, int kpar, int count, double tol2) {
     return with_bshape(shape, [&]<int MC, int NB>() -> qedhmc_status {
-        const int nt = shape_nt(b, shape);
         const size_t lds = shape_lds(b, shape, sizeof(cplx<R>));
         for (int k = 0; k < count; k++)
-            hipLaunchKernelGGL((k_b_cg_iter<R, MC, NB>), dim3(b->nblocks), dim3(nt), lds, b->stream, dev_tab<R>(b),
-                               b->d_blk, kpar ^ (k & 1), k, tol2);
+            hipLaunchKernelGGL((k_b_cg_iter<R, MC, NB>), dim3(b->nblocks[shape]), dim3(kBS), lds, b->stream,
+                               dev_tab<R>(b), b->d_blk[shape], kpar ^ (k & 1), k, tol2);
         QH_HIP(hipGetLastError());
         return QEDHMC_OK;
     });
@@ -360,11 +422,10 @@ static qedhmc_status launch_iters(qedhmc_batch* b, int shape, int kpar, int coun
 template <typename R>
 static qedhmc_status launch_update(qedhmc_batch* b, int shape, int kpar) {
     QH_TRY(with_bshape(shape, [&]<int MC, int NB>() -> qedhmc_status {
-        const int nt = shape_nt(b, shape);
-        hipLaunchKernelGGL((k_b_ox<R, MC, NB>), dim3(b->nblocks), dim3(nt), shape_lds(b, shape, sizeof(cplx<double>)),
-                           b->stream, dev_tab<R>(b), b->d_blk, kpar);
-        hipLaunchKernelGGL((k_b_cg_replace<R, MC, NB>), dim3(b->nblocks), dim3(nt),
-                           shape_lds(b, shape, sizeof(cplx<R>)), b->stream, dev_tab<R>(b), b->d_blk, kpar);
+        hipLaunchKernelGGL((k_b_ox<R, MC, NB>), dim3(b->nblocks[shape]), dim3(kBS),
+                           shape_lds(b, shape, sizeof(cplx<double>)), b->stream, dev_tab<R>(b), b->d_blk[shape], kpar);
+        hipLaunchKernelGGL((k_b_cg_replace<R, MC, NB>), dim3(b->nblocks[shape]), dim3(kBS),
+                           shape_lds(b, shape, sizeof(cplx<R>)), b->stream, dev_tab<R>(b), b->d_blk[shape], kpar);
         return QEDHMC_OK;
     }));
     hipLaunchKernelGGL(k_b_cg_check<R>, dim3(b->n), dim3(64), 0, b->stream,
@@ -593,7 +654,6 @@ qedhmc_status qedhmc_batch_create(const qedhmc_params* params, int32_t n_chains,
     b->params.assign(params, params + n_chains);
     b->toff.assign(n_chains + 1, 0);
     b->voff.assign(n_chains + 1, 0);
-    std::vector<Blk> work;
     for (int c = 0; c < n_chains; c++) {
         qedhmc_ctx* h = nullptr;
         const qedhmc_status st = qedhmc_init_lattice(&params[c], b->stream, &h);
@@ -606,21 +666,16 @@ qedhmc_status qedhmc_batch_create(const qedhmc_params* params, int32_t n_chains,
         b->maxVs = std::max(b->maxVs, h->lat.Vs);
         b->maxcell = std::max(b->maxcell, h->lat.ncell);
         b->max_lds = h->max_lds;
-        for (int tau = 0; tau < h->lat.Nt; tau++) work.push_back({c, tau});
     }
-    // XCD-aware work list: workgroup i runs on XCD i mod 8, so the list is
-    // dealt out in 8 contiguous ranges and each XCD's L2 sees whole runs of
-    // neighbouring slices (the tau - 1 / tau + 1 halos stay local).
-    const int per = (int)((work.size() + 7) / 8);
-    std::vector<Blk> blk((size_t)per * 8, Blk{-1, 0});
-    for (size_t i = 0; i < blk.size(); i++) {
-        const size_t w = (i % 8) * per + i / 8;
-        if (w < work.size()) blk[i] = work[w];
-    }
-    b->nblocks = (int)blk.size();
     const size_t tot = (size_t)b->toff[n_chains];
     bool ok = true;
-    ok = ok && hipMalloc(&b->d_blk, blk.size() * sizeof(Blk)) == hipSuccess;
+    std::vector<Blk> blk[4];
+    for (int s = 0; s < 4 && ok; s++) {
+        if (!shape_ok(b, s)) continue;
+        blk[s] = work_list(b, s);
+        b->nblocks[s] = (int)blk[s].size();
+        ok = hipMalloc(&b->d_blk[s], blk[s].size() * sizeof(Blk)) == hipSuccess;
+    }
     ok = ok && hipMalloc(&b->d_toff, (n_chains + 1) * sizeof(int64_t)) == hipSuccess;
     ok = ok && hipMalloc(&b->d_scal, (size_t)n_chains * 2 * S_NSLOT * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc(&b->d_res, (size_t)n_chains * kNRes * sizeof(double)) == hipSuccess;
@@ -636,9 +691,10 @@ qedhmc_status qedhmc_batch_create(const qedhmc_params* params, int32_t n_chains,
                                  hipHostMallocDefault) == hipSuccess;
         ok = ok && hipEventCreateWithFlags(&b->ev[k], hipEventDisableTiming) == hipSuccess;
     }
-    if (ok)
-        ok = hipMemcpyAsync(b->d_blk, blk.data(), blk.size() * sizeof(Blk), hipMemcpyHostToDevice, b->stream) ==
-             hipSuccess;
+    for (int s = 0; s < 4 && ok; s++)
+        if (b->d_blk[s])
+            ok = hipMemcpyAsync(b->d_blk[s], blk[s].data(), blk[s].size() * sizeof(Blk), hipMemcpyHostToDevice,
+                                b->stream) == hipSuccess;
     if (ok)
         ok = hipMemcpyAsync(b->d_toff, b->toff.data(), (n_chains + 1) * sizeof(int64_t), hipMemcpyHostToDevice,
                             b->stream) == hipSuccess;
@@ -682,7 +738,7 @@ qedhmc_status qedhmc_batch_destroy(qedhmc_batch_t b) {
     for (int i = 0; i < 2; i++)
         for (int j = 0; j < 2; j++)
             if (b->graph[i][j]) (void)hipGraphExecDestroy(b->graph[i][j]);
-    (void)hipFree(b->d_blk);
+    for (int s = 0; s < 4; s++) (void)hipFree(b->d_blk[s]);
     (void)hipFree(b->d_toff);
     (void)hipFree(b->d_scal);
     (void)hipFree(b->d_res);
@@ -724,7 +780,7 @@ qedhmc_status qedhmc_batch_tile(qedhmc_batch_t b, qedhmc_precision prec, int32_t
     const int pi = prec == QEDHMC_FP64 ? 1 : 0;
     const int s = b->shape[pi];
     *cells_per_thread = kShapeMC[s];
-    *threads = shape_nt(b, s);
+    *threads = kBS;
     *exchange_buffers = kShapeNB[s];
     for (int k = 0; k < 4; k++) us_per_iter[k] = b->tune_us[pi][k];
     return QEDHMC_OK;

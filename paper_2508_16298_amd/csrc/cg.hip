@@ -14,7 +14,8 @@ __global__ __launch_bounds__(BS) void k_cg_start(Lat lt, CgBufs<R> B, const cplx
     extern __shared__ __align__(16) unsigned char smem[];
     const int tau = slice_of_block(blockIdx.x, lt.Nt);
     if (tau < 0) return;
-    cg_start_body<R, MC, NB>(lt, B, gauge, co, scal, tau, tau == 0, smem);
+    const Tile tl = whole_block_tile(smem, reinterpret_cast<double*>(smem + (size_t)NB * 2 * lt.Vs * sizeof(cplx<R>)));
+    cg_start_body<R, MC, NB>(lt, B, gauge, co, scal, tau, tau == 0, tl);
 }
 
 template <typename R, int MC, int NB, int BS>
@@ -24,7 +25,8 @@ __global__ __launch_bounds__(BS) void k_cg_iter(Lat lt, CgBufs<R> B, const cplx<
     extern __shared__ __align__(16) unsigned char smem[];
     const int tau = slice_of_block(blockIdx.x, lt.Nt);
     if (tau < 0) return;
-    cg_iter_body<R, MC, NB>(lt, B, gauge, co, scal, kpar, ipar, tol2, mixed, tau, tau == 0, smem);
+    const Tile tl = whole_block_tile(smem, reinterpret_cast<double*>(smem + (size_t)NB * 2 * lt.Vs * sizeof(cplx<R>)));
+    cg_iter_body<R, MC, NB>(lt, B, gauge, co, scal, kpar, ipar, tol2, mixed, tau, tau == 0, tl);
 }
 
 template <typename R, int MC, int NB, int BS>
@@ -33,7 +35,8 @@ __global__ __launch_bounds__(BS) void k_cg_replace(Lat lt, CgBufs<R> B, const cp
     extern __shared__ __align__(16) unsigned char smem[];
     const int tau = slice_of_block(blockIdx.x, lt.Nt);
     if (tau < 0) return;
-    cg_replace_body<R, MC, NB>(lt, B, gauge, co, scal, kpar, tau, smem);
+    const Tile tl = whole_block_tile(smem, reinterpret_cast<double*>(smem + (size_t)NB * 2 * lt.Vs * sizeof(cplx<R>)));
+    cg_replace_body<R, MC, NB>(lt, B, gauge, co, scal, kpar, tau, tl);
 }
 
 __global__ void k_cg_check(double* __restrict__ scal, int kpar, const double* __restrict__ part, int Nt,

@@ -53,11 +53,10 @@ namespace qh {
 template <typename R, int MC, int NB>
 __device__ __forceinline__ void cg_start_body(const Lat& lt, const CgBufs<R>& B, const cplx<R>* __restrict__ gauge,
                                               const Coef<R>& co, double* __restrict__ scal, int tau, bool lead,
-                                              unsigned char* smem) {
-    cplx<R>* buf2 = reinterpret_cast<cplx<R>*>(smem);
-    double* red = reinterpret_cast<double*>(smem + (size_t)NB * 2 * lt.Vs * sizeof(cplx<R>));
+                                              const Tile& tl) {
+    cplx<R>* buf2 = reinterpret_cast<cplx<R>*>(tl.buf);
     SliceCtx<MC> c;
-    slice_ctx<MC>(lt, c, tau);
+    slice_ctx<MC>(lt, c, tau, tl);
     const size_t Vs = lt.Vs;
     cplx<R> hm[MC][12], ht[MC][12];
     hops_of<R, MC>(gauge, lt, c.tm, c.idx, co, hm);
@@ -85,13 +84,13 @@ __device__ __forceinline__ void cg_start_body(const Lat& lt, const CgBufs<R>& B,
                            c.tau == lt.Nt - 1 ? R(-1) : R(1), buf2, lt.Vs, w);
     store_cells<R, MC>(w, B.w[0] + c.tau * Vs, c.g, c.own);
     double v[kNP] = {dot_cells<R, MC>(r0, r0, c.own), dot_cells<R, MC>(w, r0, c.own), 0.0, 0.0, 0.0, b2};
-    write_partials(B.part + kNP * (size_t)c.tau, v, red);  // parity 0
-    if (lead && threadIdx.x < S_NSLOT) {
+    write_partials(B.part + kNP * (size_t)c.tau, v, tl);  // parity 0
+    if (lead && tl.ltid < S_NSLOT) {
         double v = 0.0;
-        if (threadIdx.x == S_FIRST) v = 1.0;
-        if (threadIdx.x == S_B2) v = -1.0;
-        if (threadIdx.x == S_GPREV || threadIdx.x == S_APREV) v = 1.0;
-        scal[threadIdx.x] = v;
+        if (tl.ltid == S_FIRST) v = 1.0;
+        if (tl.ltid == S_B2) v = -1.0;
+        if (tl.ltid == S_GPREV || tl.ltid == S_APREV) v = 1.0;
+        scal[tl.ltid] = v;
     }
 }
 
@@ -101,10 +100,8 @@ __device__ __forceinline__ void cg_start_body(const Lat& lt, const CgBufs<R>& B,
 template <typename R, int MC, int NB>
 __device__ __forceinline__ void cg_iter_body(const Lat& lt, const CgBufs<R>& B, const cplx<R>* __restrict__ gauge,
                                              const Coef<R>& co, double* __restrict__ scal, int kpar, int ipar,
-                                             double tol2, int mixed, int tau, bool lead, unsigned char* smem) {
-    cplx<R>* buf2 = reinterpret_cast<cplx<R>*>(smem);
-    double* red = reinterpret_cast<double*>(smem + (size_t)NB * 2 * lt.Vs * sizeof(cplx<R>));
-    double* bc = red + kNP * 16;
+                                             double tol2, int mixed, int tau, bool lead, const Tile& tl) {
+    cplx<R>* buf2 = reinterpret_cast<cplx<R>*>(tl.buf);
     const double* sin_ = scal + S_NSLOT * kpar;
     double* sout = scal + S_NSLOT * (kpar ^ 1);
     // Every load of the launch is issued before the scalars arrive: the
@@ -117,7 +114,7 @@ __device__ __forceinline__ void cg_iter_body(const Lat& lt, const CgBufs<R>& B, 
     const int it = (int)sin_[S_ITERS];
     const int ip = ipar, nx = ip ^ 1;
     SliceCtx<MC> c;
-    slice_ctx<MC>(lt, c, tau);
+    slice_ctx<MC>(lt, c, tau, tl);
     const size_t Vs = lt.Vs;
     Cells<R, MC> wm, wt, wn, sm, st, sn, rm, rt, rn, pp;
     load_cells<R, MC>(wm, B.w[ip] + c.tm * Vs, c.g, c.own);
@@ -134,12 +131,12 @@ __device__ __forceinline__ void cg_iter_body(const Lat& lt, const CgBufs<R>& B, 
     hops_of<R, MC>(gauge, lt, c.tm, c.idx, co, hm);
     hops_of<R, MC>(gauge, lt, c.tau, c.idx, co, ht);
     if (done != 0.0) {
-        if (lead && threadIdx.x < S_NSLOT) sout[threadIdx.x] = sin_[threadIdx.x];
+        if (lead && tl.ltid < S_NSLOT) sout[tl.ltid] = sin_[tl.ltid];
         return;
     }
 
     double pr[kNP];
-    reduce_partials(B.part + kNP * (size_t)lt.Nt * ip, lt.Nt, red, bc, pr);
+    reduce_partials(B.part + kNP * (size_t)lt.Nt * ip, lt.Nt, tl, pr);
     const double gam = pr[0], del = pr[1], aux = pr[5];
     double b2 = sin_[S_B2], target = sin_[S_TARGET], rrupd = sin_[S_RRUPD];
     if (b2 < 0.0) {  // first iteration of the solve: the start kernel left |rhs|^2 partials in aux
@@ -155,14 +152,14 @@ __device__ __forceinline__ void cg_iter_body(const Lat& lt, const CgBufs<R>& B, 
     else if (mixed && (gam <= kDecade2 * rrupd || it - (int)sin_[S_ITUPD] >= kCap))
         stop = 2;
     if (stop) {
-        if (lead && threadIdx.x < S_NSLOT) {
-            double v = sin_[threadIdx.x];
-            if (threadIdx.x == S_DONE) v = (double)stop;
-            if (threadIdx.x == S_B2) v = b2;
-            if (threadIdx.x == S_TARGET) v = target;
-            if (threadIdx.x == S_RRUPD) v = rrupd;
-            if (threadIdx.x == S_GCUR) v = gam;
-            sout[threadIdx.x] = v;
+        if (lead && tl.ltid < S_NSLOT) {
+            double v = sin_[tl.ltid];
+            if (tl.ltid == S_DONE) v = (double)stop;
+            if (tl.ltid == S_B2) v = b2;
+            if (tl.ltid == S_TARGET) v = target;
+            if (tl.ltid == S_RRUPD) v = rrupd;
+            if (tl.ltid == S_GCUR) v = gam;
+            sout[tl.ltid] = v;
         }
         return;
     }
@@ -170,14 +167,14 @@ __device__ __forceinline__ void cg_iter_body(const Lat& lt, const CgBufs<R>& B, 
     const double beta = first ? 0.0 : gam / sin_[S_GPREV];
     const double den = first ? del : del + beta * (pr[2] + pr[3]) + beta * beta * pr[4];  // <p_i, s_i>
     if (!(den > 0.0)) {
-        if (lead && threadIdx.x < S_NSLOT) {
-            double v = sin_[threadIdx.x];
-            if (threadIdx.x == S_DONE) v = 3.0;
-            if (threadIdx.x == S_B2) v = b2;
-            if (threadIdx.x == S_TARGET) v = target;
-            if (threadIdx.x == S_RRUPD) v = rrupd;
-            if (threadIdx.x == S_GCUR) v = gam;
-            sout[threadIdx.x] = v;
+        if (lead && tl.ltid < S_NSLOT) {
+            double v = sin_[tl.ltid];
+            if (tl.ltid == S_DONE) v = 3.0;
+            if (tl.ltid == S_B2) v = b2;
+            if (tl.ltid == S_TARGET) v = target;
+            if (tl.ltid == S_RRUPD) v = rrupd;
+            if (tl.ltid == S_GCUR) v = gam;
+            sout[tl.ltid] = v;
         }
         return;
     }
@@ -220,18 +217,18 @@ __device__ __forceinline__ void cg_iter_body(const Lat& lt, const CgBufs<R>& B, 
     double v[kNP] = {dot_cells<R, MC>(rnew, rnew, c.own), dot_cells<R, MC>(w, rnew, c.own),
                      dot_cells<R, MC>(rnew, st, c.own), dot_cells<R, MC>(pp, w, c.own),
                      dot_cells<R, MC>(pp, st, c.own), 0.0};
-    write_partials(B.part + kNP * ((size_t)lt.Nt * nx + c.tau), v, red);
-    if (lead && threadIdx.x < S_NSLOT) {
-        double v = sin_[threadIdx.x];
-        if (threadIdx.x == S_GPREV) v = gam;
-        if (threadIdx.x == S_APREV) v = alpha;
-        if (threadIdx.x == S_ITERS) v = (double)(it + 1);
-        if (threadIdx.x == S_FIRST) v = 0.0;
-        if (threadIdx.x == S_B2) v = b2;
-        if (threadIdx.x == S_TARGET) v = target;
-        if (threadIdx.x == S_RRUPD) v = rrupd;
-        if (threadIdx.x == S_GCUR) v = gam;
-        sout[threadIdx.x] = v;
+    write_partials(B.part + kNP * ((size_t)lt.Nt * nx + c.tau), v, tl);
+    if (lead && tl.ltid < S_NSLOT) {
+        double v = sin_[tl.ltid];
+        if (tl.ltid == S_GPREV) v = gam;
+        if (tl.ltid == S_APREV) v = alpha;
+        if (tl.ltid == S_ITERS) v = (double)(it + 1);
+        if (tl.ltid == S_FIRST) v = 0.0;
+        if (tl.ltid == S_B2) v = b2;
+        if (tl.ltid == S_TARGET) v = target;
+        if (tl.ltid == S_RRUPD) v = rrupd;
+        if (tl.ltid == S_GCUR) v = gam;
+        sout[tl.ltid] = v;
     }
 }
 
@@ -243,13 +240,12 @@ __device__ __forceinline__ void cg_iter_body(const Lat& lt, const CgBufs<R>& B, 
 template <typename R, int MC, int NB>
 __device__ __forceinline__ void cg_replace_body(const Lat& lt, const CgBufs<R>& B, const cplx<R>* __restrict__ gauge,
                                                 const Coef<R>& co, const double* __restrict__ scal, int kpar,
-                                                int tau, unsigned char* smem) {
-    cplx<R>* buf2 = reinterpret_cast<cplx<R>*>(smem);
-    double* red = reinterpret_cast<double*>(smem + (size_t)NB * 2 * lt.Vs * sizeof(cplx<R>));
+                                                int tau, const Tile& tl) {
+    cplx<R>* buf2 = reinterpret_cast<cplx<R>*>(tl.buf);
     const int it = (int)scal[S_NSLOT * kpar + S_ITERS];
     const int ip = it & 1;
     SliceCtx<MC> c;
-    slice_ctx<MC>(lt, c, tau);
+    slice_ctx<MC>(lt, c, tau, tl);
     const size_t Vs = lt.Vs;
     cplx<R> hm[MC][12], ht[MC][12];
     hops_of<R, MC>(gauge, lt, c.tm, c.idx, co, hm);
@@ -275,7 +271,7 @@ __device__ __forceinline__ void cg_replace_body(const Lat& lt, const CgBufs<R>& 
     double v[kNP] = {dot_cells<R, MC>(r0, r0, c.own), dot_cells<R, MC>(w, r0, c.own),
                      dot_cells<R, MC>(r0, sp, c.own), dot_cells<R, MC>(pt_, w, c.own),
                      dot_cells<R, MC>(pt_, sp, c.own), t2};
-    write_partials(B.part + kNP * ((size_t)lt.Nt * ip + c.tau), v, red);
+    write_partials(B.part + kNP * ((size_t)lt.Nt * ip + c.tau), v, tl);
 }
 
 
@@ -287,7 +283,7 @@ __device__ __forceinline__ void cg_check_body(double* __restrict__ scal, int kpa
     double* sl = scal + S_NSLOT * kpar;
     const int ip = ((int)sl[S_ITERS]) & 1;
     double pr[kNP];
-    reduce_partials(part + kNP * (size_t)Nt * ip, Nt, red, red + kNP * 16, pr);
+    reduce_partials(part + kNP * (size_t)Nt * ip, Nt, whole_block_tile(nullptr, red), pr);
     const double a = pr[0], c = pr[5];
     if (threadIdx.x == 0) {
         sl[S_TRUE] = c;

@@ -68,8 +68,62 @@ __device__ __forceinline__ void block_sumk(double (&v)[K], double* red) {
     }
 }
 
-// Sum of the Nt partial tuples of one parity, broadcast to every thread.
-__device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int Nt, double* red, double* bc,
+// The threads of one time slice inside a workgroup.  Single-lattice kernels
+// give the whole workgroup to one slice; the batched kernels may pack several
+// slices of one chain into a workgroup, each handled by G consecutive threads
+// (G = 16, 32 or a multiple of 64) with LDS exchange buffers of its own.
+struct Tile {
+    int ltid;            // thread index within the group
+    int G;               // threads of the group
+    bool valid;          // false for a padding group past the chain's last slice
+    unsigned char* buf;  // this group's LDS exchange buffers
+    double* red;         // LDS scratch shared by the workgroup: kNP * 16 + 16 doubles
+};
+
+__device__ __forceinline__ Tile whole_block_tile(unsigned char* buf, double* red) {
+    return Tile{(int)threadIdx.x, (int)blockDim.x, true, buf, red};
+}
+
+// Sum of K doubles over the threads of a group; the total is valid in the
+// group's last thread.  Every thread of the workgroup calls it (groups of 64
+// and more meet at workgroup barriers; smaller groups reduce within their
+// 16- or 32-lane rows through DPP alone).  Fixed order.
+template <int K>
+__device__ __forceinline__ void group_sumk(double (&v)[K], const Tile& tl) {
+    if (tl.G < 64) {
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            double x = v[k];
+            x += dpp_f64<0xB1, 0xF>(x);
+            x += dpp_f64<0x4E, 0xF>(x);
+            x += dpp_f64<0x141, 0xF>(x);
+            x += dpp_f64<0x140, 0xF>(x);
+            if (tl.G == 32) x += dpp_f64<0x142, 0xA>(x);
+            v[k] = x;
+        }
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < K; k++) v[k] = wave_sum_f64(v[k]);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 63)
+#pragma unroll
+        for (int k = 0; k < K; k++) tl.red[K * wv + k] = v[k];
+    __syncthreads();
+    if (tl.ltid == tl.G - 1) {
+        const int w0 = (threadIdx.x - tl.ltid) >> 6, nw = tl.G >> 6;
+#pragma unroll
+        for (int k = 0; k < K; k++) v[k] = 0.0;
+        for (int w = 0; w < nw; w++)
+#pragma unroll
+            for (int k = 0; k < K; k++) v[k] += tl.red[K * (w0 + w) + k];
+    }
+}
+
+// Sum of the Nt partial tuples of one parity (a chain's: every group of the
+// workgroup belongs to it), broadcast to every thread of the workgroup.
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int Nt, const Tile& tl,
                                                 double (&out)[kNP]) {
     double v[kNP];
 #pragma unroll
@@ -77,7 +131,8 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ part,
     for (int t = threadIdx.x; t < Nt; t += blockDim.x)
 #pragma unroll
         for (int k = 0; k < kNP; k++) v[k] += part[kNP * t + k];
-    block_sumk<kNP>(v, red);
+    block_sumk<kNP>(v, tl.red);
+    double* bc = tl.red + kNP * 16;
     if (threadIdx.x == 0)
 #pragma unroll
         for (int k = 0; k < kNP; k++) bc[k] = v[k];
@@ -86,9 +141,10 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ part,
     for (int k = 0; k < kNP; k++) out[k] = bc[k];
 }
 
-__device__ __forceinline__ void write_partials(double* __restrict__ pt, double (&v)[kNP], double* red) {
-    block_sumk<kNP>(v, red);
-    if (threadIdx.x == 0)
+// The group's partial tuple into pt (skipped for padding groups).
+__device__ __forceinline__ void write_partials(double* __restrict__ pt, double (&v)[kNP], const Tile& tl) {
+    group_sumk<kNP>(v, tl);
+    if (tl.valid && tl.ltid == tl.G - 1)
 #pragma unroll
         for (int k = 0; k < kNP; k++) pt[k] = v[k];
 }
@@ -115,14 +171,14 @@ struct SliceCtx {
 };
 
 template <int MC>
-__device__ __forceinline__ void slice_ctx(const Lat& lt, SliceCtx<MC>& c, int tau) {
+__device__ __forceinline__ void slice_ctx(const Lat& lt, SliceCtx<MC>& c, int tau, const Tile& tl) {
     c.tau = tau;
     c.tm = c.tau == 0 ? lt.Nt - 1 : c.tau - 1;
     c.tp = c.tau == lt.Nt - 1 ? 0 : c.tau + 1;
 #pragma unroll
     for (int m = 0; m < MC; m++) {
-        const int cell = threadIdx.x + m * blockDim.x;
-        c.own[m] = cell < lt.ncell;
+        const int cell = tl.ltid + m * tl.G;
+        c.own[m] = tl.valid && cell < lt.ncell;
         c.g[m] = cell_geo(c.own[m] ? cell : 0, lt);
         phase_index(c.g[m], lt.Vs, c.idx[m]);
     }

@@ -424,7 +424,7 @@ __global__ __launch_bounds__(BS) void k_pcg_mv(Lat lt, PcgBufs<R> B, const cplx<
     const int tau = slice_of_block(blockIdx.x, lt.Nt);
     if (tau < 0) return;
     SliceCtx<MC> c;
-    slice_ctx<MC>(lt, c, tau);
+    slice_ctx<MC>(lt, c, tau, whole_block_tile(smem, red));
     const size_t Vs = lt.Vs;
     cplx<R> hm[MC][12], ht[MC][12];
     hops_of<R, MC>(gauge, lt, c.tm, c.idx, co, hm);
