@@ -81,7 +81,10 @@ typedef enum { QEDHMC_FP64 = 0, QEDHMC_FP32 = 1 } qedhmc_precision;
 typedef enum { QEDHMC_PC_NONE = 0, QEDHMC_PC_PAPER = 1 } qedhmc_precond;
 
 /* Lattice, couplings and the seed of the trajectory random streams.
- * L even, 2 <= L <= 90; Nt >= 1. */
+ * L even, 2 <= L <= 2048; Nt >= 1; L^2 Nt < 2^31.  The calls that keep a
+ * whole time slice in one workgroup (apply_B, apply_M, fermion_force,
+ * cg_solve, hmc_trajectory) take L <= 66 and return QEDHMC_EUNSUPPORTED
+ * beyond; apply_MdagM takes every L. */
 typedef struct {
     int32_t L, Nt;
     double dtau, t, J, K;
@@ -128,7 +131,11 @@ qedhmc_status qedhmc_apply_M(qedhmc_t h, const double *theta, const void *in,
                              void *out, int32_t dagger, qedhmc_precision prec);
 
 /* out = M^dag M in, fused (Methods, matrix-free M^dagger M v).  in and out
- * must not alias. */
+ * must not alias.  Slices of more than 1024 2x2 cells (L >= 66) go through
+ * spatial tiles streamed along tau (two B_tau applications per slice); the
+ * environment variables QEDHMC_MDAGM=slice|tiled, QEDHMC_TILE_TC and
+ * QEDHMC_TILE_THREADS, read on every call, override that choice and the
+ * tile plan (tuning and tests). */
 qedhmc_status qedhmc_apply_MdagM(qedhmc_t h, const double *theta,
                                  const void *in, void *out,
                                  qedhmc_precision prec);

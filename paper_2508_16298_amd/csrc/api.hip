@@ -69,7 +69,7 @@ qedhmc_status qedhmc_init_lattice(const qedhmc_params* params, void* stream, qed
     if (!params || !out) return einval("null argument");
     const qedhmc_params& p = *params;
     if (p.L < 2 || p.L % 2 != 0) return einval("L must be even and >= 2");
-    if (p.L > 90) return einval("L > 90 is not supported");
+    if (p.L > 2048) return einval("L > 2048 is not supported");
     if (p.Nt < 1) return einval("Nt must be >= 1");
     if (!(p.dtau >= 0.0) || !(p.J > 0.0) || !std::isfinite(p.t) || !std::isfinite(p.K))
         return einval("bad couplings (need dtau >= 0, J > 0, finite t and K)");

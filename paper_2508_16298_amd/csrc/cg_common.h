@@ -233,6 +233,10 @@ inline qedhmc_status with_shape(qedhmc_ctx* h, F&& f) {
     if (nt < 64) nt = 64;
     const size_t red = (kNP * 16 + 16) * sizeof(double);
     const bool two = 4 * (size_t)lt.Vs * sizeof(cplx<R>) + red <= h->max_lds;
+    if (nt > (mc == 2 ? 576 : 1024)) {
+        set_error("the one-slice-per-workgroup kernels hold at most 1152 cells (L <= 66)");
+        return QEDHMC_EUNSUPPORTED;
+    }
     auto go = [&]<int MC, int BS>() -> qedhmc_status {
         if (two) return f.template operator()<MC, 2, BS>(nt, 4 * (size_t)lt.Vs * sizeof(cplx<R>) + red);
         return f.template operator()<MC, 1, BS>(nt, 2 * (size_t)lt.Vs * sizeof(cplx<R>) + red);

@@ -5,6 +5,9 @@
 // of its 2x2 cells in registers, applies the in-cell families f0 and f2 there
 // and exchanges values through LDS only for the cross-cell families f1 and f3
 // (four exchanges per B_tau instead of seven full sweeps through memory).
+#include <cstdlib>
+#include <cstring>
+
 #include "qedhmc_internal.h"
 
 namespace qh {
@@ -424,6 +427,10 @@ const cplx<float>* gauge_of<float>(qedhmc_ctx* h) {
 // Calls f.template operator()<MC, BS>() for the shape of this lattice.
 template <typename F>
 static qedhmc_status dispatch_shape(const Shape& s, F&& f) {
+    if (s.nt > (s.mc == 2 ? 576 : 1024)) {
+        set_error("the one-slice-per-workgroup kernels hold at most 1152 cells (L <= 66)");
+        return QEDHMC_EUNSUPPORTED;
+    }
     if (s.mc == 2) return f.template operator()<2, 576>();
     if (s.bs == 256) return f.template operator()<1, 256>();
     if (s.bs == 512) return f.template operator()<1, 512>();
@@ -454,7 +461,22 @@ static qedhmc_status mdagm_t(qedhmc_ctx* h, const void* in, void* out, double* p
     });
 }
 
+// The tiled streaming kernel serves slices past the whole-slice kernels'
+// reach and every slice of more than kTiledFrom cells; QEDHMC_MDAGM=slice or
+// =tiled (read per call) forces one form where it can run.
+static constexpr int kTiledFrom = 1024;
+
+static bool use_tiled(const qedhmc_ctx* h, const double* pdot) {
+    if (pdot) return false;
+    const bool fits = h->lat.ncell <= 1152;
+    const char* e = std::getenv("QEDHMC_MDAGM");
+    if (e && std::strcmp(e, "slice") == 0 && fits) return false;
+    if (e && std::strcmp(e, "tiled") == 0) return true;
+    return !fits || h->lat.ncell > kTiledFrom;
+}
+
 qedhmc_status launch_mdagm(qedhmc_ctx* h, qedhmc_precision prec, const void* in, void* out, double* pdot) {
+    if (use_tiled(h, pdot)) return launch_mdagm_tiled(h, prec, in, out);
     return prec == QEDHMC_FP64 ? mdagm_t<double>(h, in, out, pdot) : mdagm_t<float>(h, in, out, pdot);
 }
 

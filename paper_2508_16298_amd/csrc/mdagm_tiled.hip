@@ -1,0 +1,360 @@
+// Fused M^dag M for large slices: spatial tiles streamed along tau.
+//
+// The whole-slice kernels keep one slice per workgroup; past about a thousand
+// 2x2 cells a slice no longer fits one workgroup's threads and registers.
+// Here a workgroup owns a tile of cells (with a halo, or a whole periodic
+// ring of the slice in x and/or y) and a run of consecutive slices
+// tau0 .. tau0 + Tc - 1, and walks it slice by slice with M^dag M written as
+// M^dag (M v) (the matrices of the fermion-matrix definition):
+//
+//   y_{tau+1} = v_{tau+1} - e_tau B_tau v_tau            (M v)
+//   out_tau   = y_tau     - e_tau B_tau y_{tau+1}         (M^dag y)
+//
+// with e_tau = -1 on the wrapping link tau = Nt - 1 and +1 otherwise.  Each
+// step reads v_{tau+1} and the phases of slice tau once, applies B_tau twice
+// and carries y to the next step, so a slice costs two B applications
+// (three in the whole-slice kernel) plus one more per run for y_{tau0}.
+//
+// B_tau = E3 E2 E1 E0(2h) E1 E2 E3 (Eq. 24).  Every site lies on exactly one
+// bond of each family, so each bond factor is cosh(a) times the normalised
+// factor (v_i, v_j) -> (v_i + tanh(a) e^{i theta} v_j, v_j + tanh(a)
+// e^{-i theta} v_i), and B_tau = C B'_tau with C = cosh(h)^6 cosh(2h): the
+// sweeps use tanh-scaled phases (four FMAs per site and sweep) and C is
+// folded into the e_tau scale.
+//
+// A B application moves information by at most two cells in x and in y (two
+// f1 and two f3 sweeps).  With a halo of four cells around the output tile,
+// the first application (on v_tau) is exact on the tile plus two cells and
+// the second (on y_{tau+1}) on the tile; a region that covers the whole ring
+// of a direction needs no halo in it.  Region cells past an edge read their
+// own values in place of the missing neighbour: only halo results, which
+// are never stored, are affected.
+//
+// Exchange buffers hold the four sites of every region cell as four planes
+// (site q of cell c at q * ncell + c), so the writes and each neighbour read
+// of a wavefront are contiguous; two buffer sets alternate so one barrier per
+// cross sweep suffices.
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+
+#include "qedhmc_internal.h"
+
+namespace qh {
+
+struct TiledGeo {
+    int L, hL, Nt, Vs;
+    int RW, RH;      // region cells in x and y
+    int hx, hy;      // halo cells on each side (0: the region is the whole ring)
+    int TX, TY;      // output cells of a tile in x and y
+    int ntx, nty;    // tiles per direction
+    int Tc, nchunk;  // slices per run, runs
+    int nwork;       // ntx * nty * nchunk
+};
+
+template <typename R>
+struct TCoef {
+    R t1, t2, C;  // tanh(h), tanh(2h), cosh(h)^6 cosh(2h)
+};
+
+// v + h w and v + conj(h) w
+template <typename R>
+__device__ __forceinline__ cplx<R> pl_hw(cplx<R> v, cplx<R> h, cplx<R> w) {
+    return mk<R>(v.re + h.re * w.re - h.im * w.im, v.im + h.re * w.im + h.im * w.re);
+}
+template <typename R>
+__device__ __forceinline__ cplx<R> pl_hcw(cplx<R> v, cplx<R> h, cplx<R> w) {
+    return mk<R>(v.re + h.re * w.re + h.im * w.im, v.im + h.re * w.im - h.im * w.re);
+}
+
+__device__ __forceinline__ int ring(int a, int n) {
+    a %= n;
+    return a < 0 ? a + n : a;
+}
+
+// One region cell: lattice sites, neighbour cells inside the region, whether
+// its output is stored.
+struct TCell {
+    int s0, l1, d2;        // site 0; site 1 of the -x neighbour; site 2 of the -y neighbour
+    int xp, xm, yp, ym;    // region indices of the four neighbour cells
+    int c;                 // own region index
+    bool act, store;
+};
+
+template <bool FX, bool FY>
+__device__ __forceinline__ TCell tcell(const TiledGeo& G, int tx, int ty) {
+    TCell k;
+    const int nreg = G.RW * G.RH;
+    const int t = threadIdx.x;
+    k.act = t < nreg;
+    k.c = k.act ? t : nreg - 1;
+    const int i = k.c % G.RW, j = k.c / G.RW;
+    const int cx = ring(tx * G.TX - G.hx + i, G.hL), cy = ring(ty * G.TY - G.hy + j, G.hL);
+    const int cxm = cx == 0 ? G.hL - 1 : cx - 1, cym = cy == 0 ? G.hL - 1 : cy - 1;
+    k.s0 = 2 * cy * G.L + 2 * cx;
+    k.l1 = 2 * cy * G.L + 2 * cxm + 1;
+    k.d2 = (2 * cym + 1) * G.L + 2 * cx;
+    k.xp = i + 1 < G.RW ? k.c + 1 : (FX ? k.c + 1 - G.RW : k.c);
+    k.xm = i > 0 ? k.c - 1 : (FX ? k.c - 1 + G.RW : k.c);
+    k.yp = j + 1 < G.RH ? k.c + G.RW : (FY ? k.c + G.RW - nreg : k.c);
+    k.ym = j > 0 ? k.c - G.RW : (FY ? k.c - G.RW + nreg : k.c);
+    const int ox = tx * G.TX + i - G.hx, oy = ty * G.TY + j - G.hy;  // unwrapped tile coordinates
+    k.store = k.act && i >= G.hx && i < G.hx + G.TX && j >= G.hy && j < G.hy + G.TY && ox < G.hL && oy < G.hL;
+    return k;
+}
+
+// tanh-scaled phases of the cell's twelve bonds in slice tau (same bond
+// order as the whole-slice kernels: f0 from sites 0, 2; f1 from 1, 3; f2 from
+// 0, 1; f3 from 2, 3; f1 into 0, 2; f3 into 0, 1)
+template <typename R>
+__device__ __forceinline__ void tile_hops(const cplx<R>* __restrict__ gauge, const TiledGeo& G, const TCell& k,
+                                          int tau, const TCoef<R>& co, cplx<R> (&h)[12]) {
+    const cplx<R>* g0 = gauge + (size_t)tau * G.Vs;
+    const cplx<R>* g1 = gauge + ((size_t)G.Nt + tau) * G.Vs;
+    const int s0 = k.s0, s1 = s0 + 1, s2 = s0 + G.L, s3 = s2 + 1;
+    const cplx<R> e[12] = {g0[s0], g0[s2], g0[s1], g0[s3], g1[s0], g1[s1],
+                           g1[s2], g1[s3], g0[k.l1], g0[k.l1 + G.L], g1[k.d2], g1[k.d2 + 1]};
+#pragma unroll
+    for (int q = 0; q < 12; q++) {
+        const R t = q < 2 ? co.t2 : co.t1;
+        h[q] = mk<R>(t * e[q].re, t * e[q].im);
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void tile_load(cplx<R> (&v)[4], const cplx<R>* __restrict__ slice, const TiledGeo& G,
+                                          const TCell& k) {
+    v[0] = slice[k.s0];
+    v[1] = slice[k.s0 + 1];
+    v[2] = slice[k.s0 + G.L];
+    v[3] = slice[k.s0 + G.L + 1];
+}
+
+// One cross sweep (f1 if X, else f3) of the cell through exchange buffer b.
+template <typename R, bool X>
+__device__ __forceinline__ void tile_cross(cplx<R> (&v)[4], const cplx<R> (&h)[12], cplx<R>* b, int nreg,
+                                           const TCell& k) {
+    if (k.act) {
+        b[k.c] = v[0];
+        b[nreg + k.c] = v[1];
+        b[2 * nreg + k.c] = v[2];
+        b[3 * nreg + k.c] = v[3];
+    }
+    __syncthreads();
+    if (X) {
+        const cplx<R> R0 = b[k.xp], R2 = b[2 * nreg + k.xp], L1 = b[nreg + k.xm], L3 = b[3 * nreg + k.xm];
+        v[1] = pl_hw(v[1], h[2], R0);
+        v[3] = pl_hw(v[3], h[3], R2);
+        v[0] = pl_hcw(v[0], h[8], L1);
+        v[2] = pl_hcw(v[2], h[9], L3);
+    } else {
+        const cplx<R> U0 = b[k.yp], U1 = b[nreg + k.yp], D2 = b[2 * nreg + k.ym], D3 = b[3 * nreg + k.ym];
+        v[2] = pl_hw(v[2], h[6], U0);
+        v[3] = pl_hw(v[3], h[7], U1);
+        v[0] = pl_hcw(v[0], h[10], D2);
+        v[1] = pl_hcw(v[1], h[11], D3);
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void tile_f0(cplx<R> (&v)[4], const cplx<R> (&h)[12]) {
+    const cplx<R> a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3];
+    v[0] = pl_hw(a0, h[0], a1);
+    v[1] = pl_hcw(a1, h[0], a0);
+    v[2] = pl_hw(a2, h[1], a3);
+    v[3] = pl_hcw(a3, h[1], a2);
+}
+
+template <typename R>
+__device__ __forceinline__ void tile_f2(cplx<R> (&v)[4], const cplx<R> (&h)[12]) {
+    const cplx<R> a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3];
+    v[0] = pl_hw(a0, h[4], a2);
+    v[2] = pl_hcw(a2, h[4], a0);
+    v[1] = pl_hw(a1, h[5], a3);
+    v[3] = pl_hcw(a3, h[5], a1);
+}
+
+// v <- B'_tau v (normalised factors, rightmost first: f3 f2 f1 f0 f1 f2 f3)
+template <typename R>
+__device__ __forceinline__ void tile_B(cplx<R> (&v)[4], const cplx<R> (&h)[12], cplx<R>* xb, int nreg,
+                                       const TCell& k, int& kb) {
+    tile_cross<R, false>(v, h, xb + (size_t)kb * 4 * nreg, nreg, k);
+    kb ^= 1;
+    tile_f2(v, h);
+    tile_cross<R, true>(v, h, xb + (size_t)kb * 4 * nreg, nreg, k);
+    kb ^= 1;
+    tile_f0(v, h);
+    tile_cross<R, true>(v, h, xb + (size_t)kb * 4 * nreg, nreg, k);
+    kb ^= 1;
+    tile_f2(v, h);
+    tile_cross<R, false>(v, h, xb + (size_t)kb * 4 * nreg, nreg, k);
+    kb ^= 1;
+}
+
+template <typename R, bool FX, bool FY>
+__global__ __launch_bounds__(1024) void k_mdagm_tiled(TiledGeo G, const cplx<R>* __restrict__ in,
+                                                      cplx<R>* __restrict__ out, const cplx<R>* __restrict__ gauge,
+                                                      TCoef<R> co) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cplx<R>* xb = reinterpret_cast<cplx<R>*>(smem);
+    const int nreg = G.RW * G.RH;
+    // work items dealt to the eight XCDs in contiguous ranges: the tiles of
+    // one run and neighbouring runs share an XCD's L2 (halo and tau + 1 reads)
+    const int per = (G.nwork + 7) >> 3;
+    const int w = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (w >= G.nwork) return;
+    const int ntile = G.ntx * G.nty;
+    const int tile = w % ntile, run = w / ntile;
+    const TCell k = tcell<FX, FY>(G, tile % G.ntx, tile / G.ntx);
+    const int Nt = G.Nt, Vs = G.Vs;
+    const int tau0 = run * G.Tc, tau1 = min(Nt, tau0 + G.Tc);
+    int kb = 0;
+    cplx<R> h[12], y[4], u[4];
+    // y_{tau0} = v_{tau0} - e_{tau0-1} B_{tau0-1} v_{tau0-1}
+    {
+        const int tm = tau0 == 0 ? Nt - 1 : tau0 - 1;
+        tile_hops<R>(gauge, G, k, tm, co, h);
+        tile_load<R>(u, in + (size_t)tm * Vs, G, k);
+        tile_B<R>(u, h, xb, nreg, k, kb);
+        tile_load<R>(y, in + (size_t)tau0 * Vs, G, k);
+        const R e = tm == Nt - 1 ? -co.C : co.C;
+#pragma unroll
+        for (int q = 0; q < 4; q++) y[q] = mk<R>(y[q].re - e * u[q].re, y[q].im - e * u[q].im);
+    }
+    // v_tau is read again each step (it was read as v_{tau+1} one step
+    // earlier and is still in L2) rather than kept in registers across both
+    // B applications
+    for (int tau = tau0; tau < tau1; tau++) {
+        const int tp = tau == Nt - 1 ? 0 : tau + 1;
+        cplx<R> vn[4];
+        tile_hops<R>(gauge, G, k, tau, co, h);
+        tile_load<R>(u, in + (size_t)tau * Vs, G, k);
+        tile_load<R>(vn, in + (size_t)tp * Vs, G, k);
+        const R e = tau == Nt - 1 ? -co.C : co.C;
+        tile_B<R>(u, h, xb, nreg, k, kb);  // B'_tau v_tau
+        cplx<R> yn[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            yn[q] = mk<R>(vn[q].re - e * u[q].re, vn[q].im - e * u[q].im);
+            u[q] = yn[q];
+        }
+        tile_B<R>(u, h, xb, nreg, k, kb);  // B'_tau y_{tau+1}
+        if (k.store) {
+            cplx<R>* o = out + (size_t)tau * Vs;
+            o[k.s0] = mk<R>(y[0].re - e * u[0].re, y[0].im - e * u[0].im);
+            o[k.s0 + 1] = mk<R>(y[1].re - e * u[1].re, y[1].im - e * u[1].im);
+            o[k.s0 + G.L] = mk<R>(y[2].re - e * u[2].re, y[2].im - e * u[2].im);
+            o[k.s0 + G.L + 1] = mk<R>(y[3].re - e * u[3].re, y[3].im - e * u[3].im);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++) y[q] = yn[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+struct TiledPlan {
+    TiledGeo g;
+    bool fx, fy;
+    int threads;
+};
+
+// Region shape for a slice of hL x hL cells and a cap of `cap` threads (one
+// per region cell): the whole slice when it fits; else full x rings with a y
+// halo (strips) while a strip of at least four output rows fits; else square
+// tiles with halos both ways.  The run length Tc aims at about two workgroups
+// per compute unit.
+static TiledPlan plan_tiled(const Lat& lt, int tc_override, int cap) {
+    TiledPlan p{};
+    TiledGeo& g = p.g;
+    g.L = lt.L;
+    g.hL = lt.hL;
+    g.Nt = lt.Nt;
+    g.Vs = lt.Vs;
+    const int hL = lt.hL;
+    if (hL * hL <= cap) {
+        p.fx = p.fy = true;
+        g.RW = g.RH = g.TX = g.TY = hL;
+        g.hx = g.hy = 0;
+        g.ntx = g.nty = 1;
+    } else if (cap / hL - 8 >= 4) {
+        p.fx = true;
+        p.fy = false;
+        g.RW = g.TX = hL;
+        g.hx = 0;
+        g.ntx = 1;
+        const int tymax = cap / hL - 8;
+        g.nty = (hL + tymax - 1) / tymax;
+        g.TY = (hL + g.nty - 1) / g.nty;
+        g.hy = 4;
+        g.RH = g.TY + 8;
+    } else {
+        p.fx = p.fy = false;
+        int side = 1;
+        while ((side + 1) * (side + 1) <= cap) side++;
+        const int tmax = side - 8;
+        g.ntx = g.nty = (hL + tmax - 1) / tmax;
+        g.TX = g.TY = (hL + g.ntx - 1) / g.ntx;
+        g.hx = g.hy = 4;
+        g.RW = g.RH = g.TX + 8;
+    }
+    const int ntile = g.ntx * g.nty;
+    int tc = tc_override;
+    if (tc <= 0) tc = std::max(1, std::min(16, (lt.Nt * ntile + 256) / 512));
+    g.Tc = std::min(tc, lt.Nt);
+    g.nchunk = (lt.Nt + g.Tc - 1) / g.Tc;
+    g.nwork = ntile * g.nchunk;
+    p.threads = ((g.RW * g.RH + 63) / 64) * 64;
+    return p;
+}
+
+template <typename R>
+static TCoef<R> tcoef_of(const qedhmc_params& prm) {
+    const double h = 0.5 * prm.t * prm.dtau;
+    return {(R)std::tanh(h), (R)std::tanh(2 * h), (R)(std::pow(std::cosh(h), 6) * std::cosh(2 * h))};
+}
+
+// Tuning overrides, read per call: QEDHMC_TILE_TC (slices per run, 0 =
+// automatic) and QEDHMC_TILE_THREADS (thread cap of a region, 100 .. 1024).
+static int env_int(const char* name, int dflt) {
+    const char* s = std::getenv(name);
+    return s ? std::atoi(s) : dflt;
+}
+
+template <typename R>
+static qedhmc_status mdagm_tiled_t(qedhmc_ctx* h, const void* in, void* out) {
+    const int cap = std::max(100, std::min(1024, env_int("QEDHMC_TILE_THREADS", 1024)));
+    const TiledPlan p = plan_tiled(h->lat, env_int("QEDHMC_TILE_TC", 0), cap);
+    const size_t lds = (size_t)8 * p.g.RW * p.g.RH * sizeof(cplx<R>);
+    if (lds > h->max_lds) {
+        set_error("tiled M^dag M: exchange buffers exceed the workgroup's LDS");
+        return QEDHMC_EUNSUPPORTED;
+    }
+    const cplx<R>* gauge = sizeof(R) == 8 ? reinterpret_cast<const cplx<R>*>(h->gauge64)
+                                          : reinterpret_cast<const cplx<R>*>(h->gauge32);
+    const TCoef<R> co = tcoef_of<R>(h->p);
+    const int grid = 8 * ((p.g.nwork + 7) / 8);
+    auto go = [&](auto kern) -> qedhmc_status {
+        if (lds > 65536)
+            QH_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipEvent_t e0, e1;
+        if (prof_sample(h, sizeof(R) == 4 ? QEDHMC_K_MDAGM_FP32 : QEDHMC_K_MDAGM_FP64, e0, e1))
+            hipExtLaunchKernelGGL(kern, dim3(grid), dim3(p.threads), lds, h->stream, e0, e1, 0, p.g,
+                                  (const cplx<R>*)in, (cplx<R>*)out, gauge, co);
+        else
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(p.threads), lds, h->stream, p.g, (const cplx<R>*)in,
+                               (cplx<R>*)out, gauge, co);
+        QH_HIP(hipGetLastError());
+        return QEDHMC_OK;
+    };
+    if (p.fx && p.fy) return go(k_mdagm_tiled<R, true, true>);
+    if (p.fx) return go(k_mdagm_tiled<R, true, false>);
+    return go(k_mdagm_tiled<R, false, false>);
+}
+
+qedhmc_status launch_mdagm_tiled(qedhmc_ctx* h, qedhmc_precision prec, const void* in, void* out) {
+    return prec == QEDHMC_FP64 ? mdagm_tiled_t<double>(h, in, out) : mdagm_tiled_t<float>(h, in, out);
+}
+
+}  // namespace qh

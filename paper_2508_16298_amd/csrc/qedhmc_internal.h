@@ -516,6 +516,8 @@ qedhmc_status launch_apply_B(qedhmc_ctx* h, qedhmc_precision prec, int tau, cons
 // are written to pdot[0..Nt).
 qedhmc_status launch_mdagm(qedhmc_ctx* h, qedhmc_precision prec, const void* in, void* out, double* pdot);
 qedhmc_status launch_force(qedhmc_ctx* h, qedhmc_precision prec, const double* X, double* F);
+// out = M^dag M in by spatial tiles streamed along tau (mdagm_tiled.hip)
+qedhmc_status launch_mdagm_tiled(qedhmc_ctx* h, qedhmc_precision prec, const void* in, void* out);
 qedhmc_status launch_bond_tables(qedhmc_ctx* h);
 
 // CG (cg.hip) and preconditioned CG (pcg.hip)

@@ -31,7 +31,7 @@ def test_library_is_gfx950_hip():
     assert b"gfx950" in data
 
 
-@pytest.mark.parametrize("L,Nt", [(3, 4), (0, 4), (5, 1), (4, 0), (92, 4)])
+@pytest.mark.parametrize("L,Nt", [(3, 4), (0, 4), (5, 1), (4, 0), (2050, 4), (2048, 1024)])
 def test_init_rejects_bad_lattices_without_touching_the_device(L, Nt):
     lib = Q.load()
     p = Q.Params(L, Nt, 0.1, 1.0, 1.0, 1.0, 0)

@@ -1,0 +1,108 @@
+"""The tiled, tau-streamed M^dag M (large slices) against the oracle, in
+every region form: the whole periodic slice, full-x strips with a y halo and
+square tiles with halos both ways, with ragged last tiles and ragged runs of
+slices; forced on small lattices through the tuning variables, and in its
+default use at L = 66, 128 and 172."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2508_16298_amd import inputs
+from paper_2508_16298_amd import qedhmc as Q
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    a = np.asarray(a).reshape(-1)
+    b = np.asarray(b).reshape(-1)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _dev(x, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.fixture
+def tiled_env(monkeypatch):
+    def set_(form="tiled", tc=0, cap=1024):
+        monkeypatch.setenv("QEDHMC_MDAGM", form)
+        monkeypatch.setenv("QEDHMC_TILE_TC", str(tc))
+        monkeypatch.setenv("QEDHMC_TILE_THREADS", str(cap))
+    return set_
+
+
+TOL = {"fp64": 1e-12, "fp32": 3e-6}
+CDT = {"fp64": torch.complex128, "fp32": torch.complex64}
+
+# (L, Nt, slices per run, thread cap): whole slice (tiny, ragged runs), strips
+# with a ragged last strip, squares (exact and ragged), Nt = 1
+FORMS = [(2, 3, 1, 1024), (6, 10, 3, 1024), (32, 6, 4, 224), (24, 24, 5, 100), (30, 5, 2, 100), (4, 1, 0, 1024),
+         (12, 120, 7, 1024)]
+
+
+@pytest.mark.parametrize("L,Nt,tc,cap", FORMS)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tiled_mdagm_forms(L, Nt, tc, cap, prec, tiled_env):
+    tiled_env("tiled", tc, cap)
+    th = inputs.hot_start_theta(L, Nt, seed=900 + L)
+    v = inputs.gauss_cvec(L, Nt, seed=910 + L)
+    with Q.Lattice(L, Nt) as lat:
+        out = _host(lat.apply_MdagM(_dev(th), _dev(v, CDT[prec]), prec=prec))
+    err = _rel(out, O.apply_MdagM(O.lat(L, Nt), th, v))
+    print(f"L={L} Nt={Nt} Tc={tc} cap={cap} {prec}: {err:.2e}", flush=True)
+    assert err < TOL[prec]
+
+
+@pytest.mark.parametrize("L,Nt", [(66, 6), (128, 4), (172, 2)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tiled_mdagm_default_large_slices(L, Nt, prec):
+    """Default plan at large L: strips at L = 66 and 128, squares at 172."""
+    th = inputs.noisy_pi_flux_theta(L, Nt, 0.3, seed=920 + L)
+    v = inputs.gauss_cvec(L, Nt, seed=930 + L)
+    with Q.Lattice(L, Nt) as lat:
+        out = _host(lat.apply_MdagM(_dev(th), _dev(v, CDT[prec]), prec=prec))
+    err = _rel(out, O.apply_MdagM(O.lat(L, Nt), th, v))
+    print(f"L={L} Nt={Nt} {prec}: {err:.2e}", flush=True)
+    assert err < TOL[prec]
+
+
+def test_tiled_matches_whole_slice_kernel(tiled_env):
+    """Both forms run at L = 48: the same operator to rounding."""
+    L, Nt = 48, 16
+    th = inputs.hot_start_theta(L, Nt, seed=940)
+    v = _dev(inputs.gauss_cvec(L, Nt, seed=941))
+    with Q.Lattice(L, Nt) as lat:
+        tiled_env("slice")
+        a = _host(lat.apply_MdagM(_dev(th), v))
+        tiled_env("tiled")
+        b = _host(lat.apply_MdagM(_dev(th), v))
+    assert _rel(b, a) < 1e-13
+
+
+def test_whole_slice_calls_reject_large_slices():
+    """L = 68 passes the lattice checks; M^dag M runs tiled, the calls that
+    hold a slice per workgroup report QEDHMC_EUNSUPPORTED."""
+    L, Nt = 68, 2
+    th = _dev(inputs.hot_start_theta(L, Nt, seed=950))
+    v = inputs.gauss_cvec(L, Nt, seed=951)
+    with Q.Lattice(L, Nt) as lat:
+        out = _host(lat.apply_MdagM(th, _dev(v)))
+        assert _rel(out, O.apply_MdagM(O.lat(L, Nt), _host(th), v)) < 1e-12
+        with pytest.raises(Q.QedhmcError) as e:
+            lat.apply_M(th, _dev(v))
+        assert e.value.status == Q.EUNSUPPORTED
+        with pytest.raises(Q.QedhmcError) as e:
+            lat.cg_solve(th, _dev(v), tol=1e-8)
+        assert e.value.status == Q.EUNSUPPORTED
