@@ -58,9 +58,55 @@ def parse():
     ap.add_argument("--solve-only", type=int, default=0, metavar="MAXIT",
                     help="counter runs: one solve of MAXIT iterations plus 200 standalone M^dag M "
                          "launches on the workload instead of trajectories (same kernels and launch shapes)")
+    ap.add_argument("--matvec-only", type=int, default=0, metavar="L",
+                    help="only the standalone M^dag M at the large size with this L (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="counter calibration: 5 device copies of 256 MiB (torch copy kernel)")
     return ap.parse_args()
+
+
+# Standalone M^dag M past the single-launch latency floor of L=24: the
+# learned-preconditioner size and one size whose FP32 vectors (168 MB) exceed
+# the 256 MB last-level cache together with input, output and phases.
+MATVEC_LARGE = [(66, 660, 1005), (128, 1280, 1006)]
+
+
+def matvec_large(n_calls=100, only_L=0):
+    """Per-dispatch event timing of M^dag M (above 1024 cells per slice the
+    tiled, tau-streamed kernel) at the large sizes, FP32 and FP64; GB/s
+    against the algorithmic 24 / 48 B per site."""
+    import torch
+    from paper_2508_16298_amd import inputs
+    from paper_2508_16298_amd import qedhmc as Q
+    rows = []
+    for L, Nt, seed in MATVEC_LARGE:
+        if only_L and L != only_L:
+            continue
+        theta = torch.from_numpy(inputs.noisy_pi_flux_theta(L, Nt, 0.3, seed)).cuda()
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(seed)
+        N = L * L * Nt
+        with Q.Lattice(L, Nt) as lat:
+            for prec, cdt, bps, cls, tname in (("fp32", torch.complex64, 24, Q.K_MDAGM_FP32, "float"),
+                                               ("fp64", torch.complex128, 48, Q.K_MDAGM_FP64, "double")):
+                vin = torch.randn(Nt, L, L, dtype=cdt, device="cuda", generator=gen)
+                vout = torch.empty_like(vin)
+                lat.apply_MdagM(theta, vin, prec=prec, out=vout)
+                lat.profile(1)
+                for _ in range(n_calls):
+                    lat.apply_MdagM(theta, vin, prec=prec, out=vout)
+                n, ms = lat.profile_read(cls)
+                lat.profile(0)
+                us = 1e3 * ms / max(n, 1)
+                gbs = bps * N / (us * 1e-6) / 1e9
+                rows.append({"L": L, "Nt": Nt, "sites": N, "prec": prec,
+                             "kernel": f"k_mdagm_tiled<{tname}>" if L * L // 4 > 1024 else f"k_mdagm<{tname}>",
+                             "avg_launch_us": us, "alg_bytes_per_launch": bps * N, "gbs": gbs,
+                             "frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "launches": n})
+                del vin, vout
+        del theta
+        torch.cuda.empty_cache()
+    return rows
 
 
 def run_copy_calibration():
@@ -373,6 +419,9 @@ def main():
         return run_learned(a)
     if a.solve_only:
         return run_solve_only(a)
+    if a.matvec_only:
+        print(json.dumps({"matvec_large": matvec_large(only_L=a.matvec_only)}), flush=True)
+        return
     import torch
     from paper_2508_16298_amd import inputs
     from paper_2508_16298_amd import qedhmc as Q
@@ -487,6 +536,7 @@ def main():
         },
     }
     lat.close()
+    out["matvec_large"] = matvec_large()
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, cg_total, n_solves, a.cpu_iters)
     print(json.dumps(out), flush=True)

@@ -105,21 +105,90 @@ __device__ __forceinline__ TCell tcell(const TiledGeo& G, int tx, int ty) {
 
 // tanh-scaled phases of the cell's twelve bonds in slice tau (same bond
 // order as the whole-slice kernels: f0 from sites 0, 2; f1 from 1, 3; f2 from
-// 0, 1; f3 from 2, 3; f1 into 0, 2; f3 into 0, 1)
+// 0, 1; f3 from 2, 3; f1 into 0, 2; f3 into 0, 1).  HopSet<R, false> loads all
+// twelve at the start of a slice and keeps them in registers; HopSet<R, true>
+// (FP64, where twelve complex doubles would not fit beside the rest at 1024
+// threads) fetches each sweep's phases just before that sweep's exchange.
+template <typename R, bool LAZY>
+struct HopSet;
+
 template <typename R>
-__device__ __forceinline__ void tile_hops(const cplx<R>* __restrict__ gauge, const TiledGeo& G, const TCell& k,
-                                          int tau, const TCoef<R>& co, cplx<R> (&h)[12]) {
-    const cplx<R>* g0 = gauge + (size_t)tau * G.Vs;
-    const cplx<R>* g1 = gauge + ((size_t)G.Nt + tau) * G.Vs;
-    const int s0 = k.s0, s1 = s0 + 1, s2 = s0 + G.L, s3 = s2 + 1;
-    const cplx<R> e[12] = {g0[s0], g0[s2], g0[s1], g0[s3], g1[s0], g1[s1],
-                           g1[s2], g1[s3], g0[k.l1], g0[k.l1 + G.L], g1[k.d2], g1[k.d2 + 1]};
-#pragma unroll
-    for (int q = 0; q < 12; q++) {
-        const R t = q < 2 ? co.t2 : co.t1;
-        h[q] = mk<R>(t * e[q].re, t * e[q].im);
+struct HopRef {
+    const cplx<R>* g0;
+    const cplx<R>* g1;
+    int s0, l1, d2, L;
+    R t1, t2;
+    __device__ __forceinline__ void set(const cplx<R>* __restrict__ gauge, const TiledGeo& G, const TCell& k, int tau,
+                                        const TCoef<R>& co) {
+        g0 = gauge + (size_t)tau * G.Vs;
+        g1 = gauge + ((size_t)G.Nt + tau) * G.Vs;
+        s0 = k.s0;
+        l1 = k.l1;
+        d2 = k.d2;
+        L = G.L;
+        t1 = co.t1;
+        t2 = co.t2;
     }
-}
+    template <int Q>
+    __device__ __forceinline__ cplx<R> fetch() const {
+        cplx<R> e;
+        if constexpr (Q == 0) e = g0[s0];
+        if constexpr (Q == 1) e = g0[s0 + L];
+        if constexpr (Q == 2) e = g0[s0 + 1];
+        if constexpr (Q == 3) e = g0[s0 + L + 1];
+        if constexpr (Q == 4) e = g1[s0];
+        if constexpr (Q == 5) e = g1[s0 + 1];
+        if constexpr (Q == 6) e = g1[s0 + L];
+        if constexpr (Q == 7) e = g1[s0 + L + 1];
+        if constexpr (Q == 8) e = g0[l1];
+        if constexpr (Q == 9) e = g0[l1 + L];
+        if constexpr (Q == 10) e = g1[d2];
+        if constexpr (Q == 11) e = g1[d2 + 1];
+        const R t = Q < 2 ? t2 : t1;
+        return mk<R>(t * e.re, t * e.im);
+    }
+};
+
+template <typename R>
+struct HopSet<R, false> {
+    static constexpr bool lazy = false;
+    cplx<R> h[12];
+    __device__ __forceinline__ void set(const cplx<R>* __restrict__ gauge, const TiledGeo& G, const TCell& k, int tau,
+                                        const TCoef<R>& co) {
+        HopRef<R> r;
+        r.set(gauge, G, k, tau, co);
+        h[0] = r.template fetch<0>();
+        h[1] = r.template fetch<1>();
+        h[2] = r.template fetch<2>();
+        h[3] = r.template fetch<3>();
+        h[4] = r.template fetch<4>();
+        h[5] = r.template fetch<5>();
+        h[6] = r.template fetch<6>();
+        h[7] = r.template fetch<7>();
+        h[8] = r.template fetch<8>();
+        h[9] = r.template fetch<9>();
+        h[10] = r.template fetch<10>();
+        h[11] = r.template fetch<11>();
+    }
+    template <int Q>
+    __device__ __forceinline__ cplx<R> get() const {
+        return h[Q];
+    }
+};
+
+template <typename R>
+struct HopSet<R, true> {
+    static constexpr bool lazy = true;
+    HopRef<R> r;
+    __device__ __forceinline__ void set(const cplx<R>* __restrict__ gauge, const TiledGeo& G, const TCell& k, int tau,
+                                        const TCoef<R>& co) {
+        r.set(gauge, G, k, tau, co);
+    }
+    template <int Q>
+    __device__ __forceinline__ cplx<R> get() const {
+        return r.template fetch<Q>();
+    }
+};
 
 template <typename R>
 __device__ __forceinline__ void tile_load(cplx<R> (&v)[4], const cplx<R>* __restrict__ slice, const TiledGeo& G,
@@ -130,10 +199,25 @@ __device__ __forceinline__ void tile_load(cplx<R> (&v)[4], const cplx<R>* __rest
     v[3] = slice[k.s0 + G.L + 1];
 }
 
-// One cross sweep (f1 if X, else f3) of the cell through exchange buffer b.
-template <typename R, bool X>
-__device__ __forceinline__ void tile_cross(cplx<R> (&v)[4], const cplx<R> (&h)[12], cplx<R>* b, int nreg,
-                                           const TCell& k) {
+// One cross sweep (f1 if X, else f3) of the cell through exchange buffer b,
+// then the in-cell sweep IN (0: none, 1: f0, 2: f2).  The phases of both are
+// read first, so lazily fetched ones are in flight across the barrier.
+template <typename R, bool X, int IN, typename HS>
+__device__ __forceinline__ void tile_phase(cplx<R> (&v)[4], const HS& hs, cplx<R>* b, int nreg, const TCell& k) {
+    // keep lazily fetched phases at their sweep (no hoisting of every fetch
+    // of the slice to its start, which would undo the register saving)
+    if constexpr (HS::lazy) asm volatile("" ::: "memory");
+    const cplx<R> ha = hs.template get<X ? 2 : 6>(), hb = hs.template get<X ? 3 : 7>();
+    const cplx<R> hc = hs.template get<X ? 8 : 10>(), hd = hs.template get<X ? 9 : 11>();
+    cplx<R> he = mk<R>(0, 0), hf = mk<R>(0, 0);
+    if constexpr (IN == 1) {
+        he = hs.template get<0>();
+        hf = hs.template get<1>();
+    }
+    if constexpr (IN == 2) {
+        he = hs.template get<4>();
+        hf = hs.template get<5>();
+    }
     if (k.act) {
         b[k.c] = v[0];
         b[nreg + k.c] = v[1];
@@ -143,56 +227,53 @@ __device__ __forceinline__ void tile_cross(cplx<R> (&v)[4], const cplx<R> (&h)[1
     __syncthreads();
     if (X) {
         const cplx<R> R0 = b[k.xp], R2 = b[2 * nreg + k.xp], L1 = b[nreg + k.xm], L3 = b[3 * nreg + k.xm];
-        v[1] = pl_hw(v[1], h[2], R0);
-        v[3] = pl_hw(v[3], h[3], R2);
-        v[0] = pl_hcw(v[0], h[8], L1);
-        v[2] = pl_hcw(v[2], h[9], L3);
+        v[1] = pl_hw(v[1], ha, R0);
+        v[3] = pl_hw(v[3], hb, R2);
+        v[0] = pl_hcw(v[0], hc, L1);
+        v[2] = pl_hcw(v[2], hd, L3);
     } else {
         const cplx<R> U0 = b[k.yp], U1 = b[nreg + k.yp], D2 = b[2 * nreg + k.ym], D3 = b[3 * nreg + k.ym];
-        v[2] = pl_hw(v[2], h[6], U0);
-        v[3] = pl_hw(v[3], h[7], U1);
-        v[0] = pl_hcw(v[0], h[10], D2);
-        v[1] = pl_hcw(v[1], h[11], D3);
+        v[2] = pl_hw(v[2], ha, U0);
+        v[3] = pl_hw(v[3], hb, U1);
+        v[0] = pl_hcw(v[0], hc, D2);
+        v[1] = pl_hcw(v[1], hd, D3);
+    }
+    const cplx<R> a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3];
+    if constexpr (IN == 1) {  // f0: pairs (0, 1) and (2, 3)
+        v[0] = pl_hw(a0, he, a1);
+        v[1] = pl_hcw(a1, he, a0);
+        v[2] = pl_hw(a2, hf, a3);
+        v[3] = pl_hcw(a3, hf, a2);
+    }
+    if constexpr (IN == 2) {  // f2: pairs (0, 2) and (1, 3)
+        v[0] = pl_hw(a0, he, a2);
+        v[2] = pl_hcw(a2, he, a0);
+        v[1] = pl_hw(a1, hf, a3);
+        v[3] = pl_hcw(a3, hf, a1);
     }
 }
 
-template <typename R>
-__device__ __forceinline__ void tile_f0(cplx<R> (&v)[4], const cplx<R> (&h)[12]) {
-    const cplx<R> a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3];
-    v[0] = pl_hw(a0, h[0], a1);
-    v[1] = pl_hcw(a1, h[0], a0);
-    v[2] = pl_hw(a2, h[1], a3);
-    v[3] = pl_hcw(a3, h[1], a2);
-}
-
-template <typename R>
-__device__ __forceinline__ void tile_f2(cplx<R> (&v)[4], const cplx<R> (&h)[12]) {
-    const cplx<R> a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3];
-    v[0] = pl_hw(a0, h[4], a2);
-    v[2] = pl_hcw(a2, h[4], a0);
-    v[1] = pl_hw(a1, h[5], a3);
-    v[3] = pl_hcw(a3, h[5], a1);
-}
-
 // v <- B'_tau v (normalised factors, rightmost first: f3 f2 f1 f0 f1 f2 f3)
-template <typename R>
-__device__ __forceinline__ void tile_B(cplx<R> (&v)[4], const cplx<R> (&h)[12], cplx<R>* xb, int nreg,
-                                       const TCell& k, int& kb) {
-    tile_cross<R, false>(v, h, xb + (size_t)kb * 4 * nreg, nreg, k);
+template <typename R, typename HS>
+__device__ __forceinline__ void tile_B(cplx<R> (&v)[4], const HS& hs, cplx<R>* xb, int nreg, const TCell& k,
+                                       int& kb) {
+    tile_phase<R, false, 2>(v, hs, xb + (size_t)kb * 4 * nreg, nreg, k);
     kb ^= 1;
-    tile_f2(v, h);
-    tile_cross<R, true>(v, h, xb + (size_t)kb * 4 * nreg, nreg, k);
+    tile_phase<R, true, 1>(v, hs, xb + (size_t)kb * 4 * nreg, nreg, k);
     kb ^= 1;
-    tile_f0(v, h);
-    tile_cross<R, true>(v, h, xb + (size_t)kb * 4 * nreg, nreg, k);
+    tile_phase<R, true, 2>(v, hs, xb + (size_t)kb * 4 * nreg, nreg, k);
     kb ^= 1;
-    tile_f2(v, h);
-    tile_cross<R, false>(v, h, xb + (size_t)kb * 4 * nreg, nreg, k);
+    tile_phase<R, false, 0>(v, hs, xb + (size_t)kb * 4 * nreg, nreg, k);
     kb ^= 1;
 }
+
+// Threads per workgroup at most: 1024 in FP32 (108 registers); 512 in FP64,
+// whose 162 registers a 1024-thread workgroup cannot hold without spilling.
+template <typename R>
+static constexpr int kTileMaxThreads = sizeof(R) == 8 ? 512 : 1024;
 
 template <typename R, bool FX, bool FY>
-__global__ __launch_bounds__(1024) void k_mdagm_tiled(TiledGeo G, const cplx<R>* __restrict__ in,
+__global__ __launch_bounds__(kTileMaxThreads<R>) void k_mdagm_tiled(TiledGeo G, const cplx<R>* __restrict__ in,
                                                       cplx<R>* __restrict__ out, const cplx<R>* __restrict__ gauge,
                                                       TCoef<R> co) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -209,13 +290,14 @@ __global__ __launch_bounds__(1024) void k_mdagm_tiled(TiledGeo G, const cplx<R>*
     const int Nt = G.Nt, Vs = G.Vs;
     const int tau0 = run * G.Tc, tau1 = min(Nt, tau0 + G.Tc);
     int kb = 0;
-    cplx<R> h[12], y[4], u[4];
+    HopSet<R, sizeof(R) == 8> hs;
+    cplx<R> y[4], u[4];
     // y_{tau0} = v_{tau0} - e_{tau0-1} B_{tau0-1} v_{tau0-1}
     {
         const int tm = tau0 == 0 ? Nt - 1 : tau0 - 1;
-        tile_hops<R>(gauge, G, k, tm, co, h);
+        hs.set(gauge, G, k, tm, co);
         tile_load<R>(u, in + (size_t)tm * Vs, G, k);
-        tile_B<R>(u, h, xb, nreg, k, kb);
+        tile_B<R>(u, hs, xb, nreg, k, kb);
         tile_load<R>(y, in + (size_t)tau0 * Vs, G, k);
         const R e = tm == Nt - 1 ? -co.C : co.C;
 #pragma unroll
@@ -227,18 +309,21 @@ __global__ __launch_bounds__(1024) void k_mdagm_tiled(TiledGeo G, const cplx<R>*
     for (int tau = tau0; tau < tau1; tau++) {
         const int tp = tau == Nt - 1 ? 0 : tau + 1;
         cplx<R> vn[4];
-        tile_hops<R>(gauge, G, k, tau, co, h);
+        hs.set(gauge, G, k, tau, co);
         tile_load<R>(u, in + (size_t)tau * Vs, G, k);
-        tile_load<R>(vn, in + (size_t)tp * Vs, G, k);
+        // FP32 issues the read of v_{tau+1} before the first B application;
+        // FP64 after it, where its registers are free
+        if constexpr (sizeof(R) == 4) tile_load<R>(vn, in + (size_t)tp * Vs, G, k);
         const R e = tau == Nt - 1 ? -co.C : co.C;
-        tile_B<R>(u, h, xb, nreg, k, kb);  // B'_tau v_tau
+        tile_B<R>(u, hs, xb, nreg, k, kb);  // B'_tau v_tau
+        if constexpr (sizeof(R) == 8) tile_load<R>(vn, in + (size_t)tp * Vs, G, k);
         cplx<R> yn[4];
 #pragma unroll
         for (int q = 0; q < 4; q++) {
             yn[q] = mk<R>(vn[q].re - e * u[q].re, vn[q].im - e * u[q].im);
             u[q] = yn[q];
         }
-        tile_B<R>(u, h, xb, nreg, k, kb);  // B'_tau y_{tau+1}
+        tile_B<R>(u, hs, xb, nreg, k, kb);  // B'_tau y_{tau+1}
         if (k.store) {
             cplx<R>* o = out + (size_t)tau * Vs;
             o[k.s0] = mk<R>(y[0].re - e * u[0].re, y[0].im - e * u[0].im);
@@ -316,7 +401,8 @@ static TCoef<R> tcoef_of(const qedhmc_params& prm) {
 }
 
 // Tuning overrides, read per call: QEDHMC_TILE_TC (slices per run, 0 =
-// automatic) and QEDHMC_TILE_THREADS (thread cap of a region, 100 .. 1024).
+// automatic) and QEDHMC_TILE_THREADS (thread cap of a region, 100 .. 1024,
+// at most 512 in FP64).
 static int env_int(const char* name, int dflt) {
     const char* s = std::getenv(name);
     return s ? std::atoi(s) : dflt;
@@ -324,8 +410,12 @@ static int env_int(const char* name, int dflt) {
 
 template <typename R>
 static qedhmc_status mdagm_tiled_t(qedhmc_ctx* h, const void* in, void* out) {
-    const int cap = std::max(100, std::min(1024, env_int("QEDHMC_TILE_THREADS", 1024)));
-    const TiledPlan p = plan_tiled(h->lat, env_int("QEDHMC_TILE_TC", 0), cap);
+    const int cap = std::max(100, std::min(kTileMaxThreads<R>, env_int("QEDHMC_TILE_THREADS", 1024)));
+    // FP64 runs 16 slices per workgroup by default (fastest at L = 66 and
+    // 128 in a sweep of run lengths); FP32 takes the plan's default
+    int tc = env_int("QEDHMC_TILE_TC", 0);
+    if (tc <= 0 && sizeof(R) == 8) tc = 16;
+    const TiledPlan p = plan_tiled(h->lat, tc, cap);
     const size_t lds = (size_t)8 * p.g.RW * p.g.RH * sizeof(cplx<R>);
     if (lds > h->max_lds) {
         set_error("tiled M^dag M: exchange buffers exceed the workgroup's LDS");

@@ -38,9 +38,17 @@ static constexpr int kCapTau = 6;
 static constexpr double kThresh = 1e-3;
 static constexpr int kNP7 = 7;  // PCG partials: <r,r>, <r,u>, <w,u>, <u,s>, <p,w>, <p,s>, unused
 
+static constexpr int kPcSlots = 8;  // tau offsets per stencil pass at most (0 <= dt <= 6, plus one)
+
+// One stencil tap of a parity's list, q = parity + c - cmin: aidx = a - amin
+// (its slice in the window ring), off = b * half + (q >> 1) and plane = q & 1
+// (row, column pair and column parity of the source relative to the output).
 template <typename R>
 struct PTap {
-    int dt, dx, dy, pad;
+    int aidx;
+    int off;
+    int plane;
+    int pad;
     cplx<R> g;
 };
 
@@ -164,19 +172,62 @@ static qedhmc_status build_paper_precond(qedhmc_ctx* h) {
         });
     }
     h->pc_shift = shift;
-    // device copies in both precisions: [parity 0 taps][parity 1 taps]
-    const size_t nt = h->pc_taps[0].size() + h->pc_taps[1].size();
+    // The two passes as gathers out(tau, y, x) = sum h in(tau + a, y + b, x + c)
+    // over the tap list of the output's x parity (sign -1 where tau + a leaves
+    // [0, Nt)): G takes (a, b, c, h) = (-dt, dy, dx, g) from its own parity's
+    // taps; G^dag takes (dt, -dy, -dx, conj g) from every tap whose source
+    // x - dx has the parity of the list it came from.
+    std::vector<HostTap> pass[2][2];
+    for (int par = 0; par < 2; par++) {
+        for (const auto& t : h->pc_taps[par]) pass[0][par].push_back({-t.dt, t.dx, t.dy, t.gre, t.gim});
+        for (int pp = 0; pp < 2; pp++)
+            for (const auto& t : h->pc_taps[pp])
+                if ((((par - t.dx) % 2) + 2) % 2 == pp) pass[1][par].push_back({t.dt, -t.dx, -t.dy, t.gre, -t.gim});
+    }
     std::vector<PTap<double>> t64;
     std::vector<PTap<float>> t32;
-    for (int par = 0; par < 2; par++)
-        for (const auto& t : h->pc_taps[par]) {
-            t64.push_back({t.dt, t.dx, t.dy, 0, mk<double>(t.gre, t.gim)});
-            t32.push_back({t.dt, t.dx, t.dy, 0, mk<float>((float)t.gre, (float)t.gim)});
+    for (int ps = 0; ps < 2; ps++) {
+        PcPass& g = h->pc_pass[ps];
+        g.amin = g.bmin = g.cmin = 1 << 20;
+        g.amax = g.bmax = g.cmax = -(1 << 20);
+        for (int par = 0; par < 2; par++)
+            for (const auto& t : pass[ps][par]) {
+                g.amin = std::min(g.amin, t.dt);
+                g.amax = std::max(g.amax, t.dt);
+                g.bmin = std::min(g.bmin, t.dy);
+                g.bmax = std::max(g.bmax, t.dy);
+                g.cmin = std::min(g.cmin, t.dx);
+                g.cmax = std::max(g.cmax, t.dx);
+            }
+        if (g.amin > g.amax) g.amin = g.amax = g.bmin = g.bmax = g.cmin = g.cmax = 0;
+        const int half = (h->lat.L + g.cmax - g.cmin + 1) / 2;
+        for (int par = 0; par < 2; par++) {
+            auto& lst = pass[ps][par];
+            std::stable_sort(lst.begin(), lst.end(), [](const HostTap& a, const HostTap& b) { return a.dt < b.dt; });
+            g.first[par] = (int)t64.size();
+            g.count[par] = (int)lst.size();
+            // start of each tau-offset group (a = amin + k) within the list
+            for (int k = 0; k <= kPcSlots; k++) {
+                int n = 0;
+                for (const auto& t : lst)
+                    if (t.dt - g.amin < k) n++;
+                g.gstart[par][k] = n;
+            }
+            for (const auto& t : lst) {
+                const int aidx = t.dt - g.amin, q = par + t.dx - g.cmin;
+                const int off = t.dy * half + (q >> 1), plane = q & 1;
+                t64.push_back({aidx, off, plane, 0, mk<double>(t.gre, t.gim)});
+                t32.push_back({aidx, off, plane, 0, mk<float>((float)t.gre, (float)t.gim)});
+            }
         }
-    QH_HIP(hipMalloc(&h->pc_dev64, nt * sizeof(PTap<double>)));
-    QH_HIP(hipMalloc(&h->pc_dev32, nt * sizeof(PTap<float>)));
-    QH_HIP(hipMemcpyAsync(h->pc_dev64, t64.data(), nt * sizeof(PTap<double>), hipMemcpyHostToDevice, h->stream));
-    QH_HIP(hipMemcpyAsync(h->pc_dev32, t32.data(), nt * sizeof(PTap<float>), hipMemcpyHostToDevice, h->stream));
+    }
+    const size_t nt = t64.size();
+    QH_HIP(hipMalloc(&h->pc_dev64, std::max<size_t>(nt, 1) * sizeof(PTap<double>)));
+    QH_HIP(hipMalloc(&h->pc_dev32, std::max<size_t>(nt, 1) * sizeof(PTap<float>)));
+    if (nt) {
+        QH_HIP(hipMemcpyAsync(h->pc_dev64, t64.data(), nt * sizeof(PTap<double>), hipMemcpyHostToDevice, h->stream));
+        QH_HIP(hipMemcpyAsync(h->pc_dev32, t32.data(), nt * sizeof(PTap<float>), hipMemcpyHostToDevice, h->stream));
+    }
     QH_HIP(hipStreamSynchronize(h->stream));
     h->pc_ready = true;
     return QEDHMC_OK;
@@ -188,60 +239,153 @@ qedhmc_status ensure_paper_precond(qedhmc_ctx* h) {
 }
 
 // ---------------------------------------------------------------------------
-// Stencil application.  Grid (Nt, 2 parities, chunks); a block handles sites
-// of one x parity of one slice, so every thread walks the same tap list.
-//   G:     out(tau,y,x) = sum_{taps[x%2]} g in(tau-dt, y+dy, x+dx) [-1 if tau-dt < 0]
-//   G^dag: out(tau,y,x) = sum_{p'} sum_{taps[p'], (x-dx)%2 == p'} conj(g)
-//                         in(tau+dt, y-dy, x-dx) [-1 if tau+dt >= Nt]
+// Stencil application, streamed along tau.  A workgroup owns one x parity of
+// a band of TY rows (all x) and a run of Tc slices.  Its LDS holds a ring of
+// nslot = amax - amin + 1 input slices over the band plus the rows and columns
+// the taps reach (periodic in y and x, sign-flipped where the slice index
+// leaves [0, Nt)), each slice stored as two planes of even and odd window
+// columns, and a copy of the parity's taps.  Each step reads one new slice
+// into the ring (prefetched into registers during the previous step); each
+// output site is formed by a quad of lanes that split its taps (tap j to lane
+// j mod 4 within each tau-offset group: an LDS read of the tap, an LDS read of
+// the input at a fixed offset and four FMAs) and add their partial sums by
+// DPP.  Four lanes per site give the workgroup four times the wavefronts to
+// hide LDS latency with.
 // stop (nullable): a scalar slot's stop flag; non-zero makes the launch a no-op.
 // ---------------------------------------------------------------------------
-template <typename R, bool DAG>
-__global__ __launch_bounds__(256) void k_pc_apply(Lat lt, const PTap<R>* __restrict__ taps, int n0, int n1,
-                                                  const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
-                                                  const double* __restrict__ stop) {
-    if (stop && *stop != 0.0) return;
-    const int tau = blockIdx.x, par = blockIdx.y;
-    const int half = lt.Vs / 2;
-    const int k = blockIdx.z * blockDim.x + threadIdx.x;
-    if (k >= half) return;
-    const int L = lt.L, Nt = lt.Nt;
-    const int y = k / lt.hL, x = 2 * (k - y * lt.hL) + par;
-    R ar = 0, ai = 0;
-    if (!DAG) {
-        const PTap<R>* tp = taps + (par ? n0 : 0);
-        const int nt = par ? n1 : n0;
-        for (int j = 0; j < nt; j++) {
-            const PTap<R> t = tp[j];
-            int ts = tau - t.dt;
-            const R sg = ts < 0 ? R(-1) : R(1);
-            if (ts < 0) ts += Nt;
-            int ys = y + t.dy, xs = x + t.dx;
-            ys = ys < 0 ? ys + L : (ys >= L ? ys - L : ys);
-            xs = xs < 0 ? xs + L : (xs >= L ? xs - L : xs);
-            const cplx<R> v = in[(size_t)ts * lt.Vs + ys * L + xs];
-            ar += sg * (t.g.re * v.re - t.g.im * v.im);
-            ai += sg * (t.g.re * v.im + t.g.im * v.re);
-        }
+struct PcGeo {
+    int L, Nt, Vs;
+    int TY, nband, Tc, nrun;
+    int rows, cols, half, bmin, cmin, amin, nslot;
+    int first[2], count[2];
+    int gstart[2][kPcSlots + 1];  // per parity: start of each tau-offset group in the parity's list
+};
+
+// window elements per thread at most (the plan keeps rows x cols within
+// kPcElems x threads)
+static constexpr int kPcElems = 4;
+
+template <typename R>
+struct STap {
+    R re, im;
+    int toff;  // plane * plane size + off
+    int pad;
+};
+
+__device__ __forceinline__ float dpp_f32_quad(float v, int sel) {
+    const int i = __float_as_int(v);
+    const int r = sel == 0 ? __builtin_amdgcn_update_dpp(0, i, 0xB1, 0xF, 0xF, false)
+                           : __builtin_amdgcn_update_dpp(0, i, 0x4E, 0xF, 0xF, false);
+    return __int_as_float(r);
+}
+
+template <typename R>
+__device__ __forceinline__ R quad_sum(R v) {
+    if constexpr (sizeof(R) == 8) {
+        v += dpp_f64<0xB1, 0xF>(v);  // quad_perm [1,0,3,2]
+        v += dpp_f64<0x4E, 0xF>(v);  // quad_perm [2,3,0,1]
     } else {
-        for (int pp = 0; pp < 2; pp++) {
-            const PTap<R>* tp = taps + (pp ? n0 : 0);
-            const int nt = pp ? n1 : n0;
-            for (int j = 0; j < nt; j++) {
-                const PTap<R> t = tp[j];
-                if (((par - t.dx) & 1) != pp) continue;
-                int ts = tau + t.dt;
-                const R sg = ts >= Nt ? R(-1) : R(1);
-                if (ts >= Nt) ts -= Nt;
-                int ys = y - t.dy, xs = x - t.dx;
-                ys = ys < 0 ? ys + L : (ys >= L ? ys - L : ys);
-                xs = xs < 0 ? xs + L : (xs >= L ? xs - L : xs);
-                const cplx<R> v = in[(size_t)ts * lt.Vs + ys * L + xs];
-                ar += sg * (t.g.re * v.re + t.g.im * v.im);
-                ai += sg * (t.g.re * v.im - t.g.im * v.re);
+        v += dpp_f32_quad(v, 0);
+        v += dpp_f32_quad(v, 1);
+    }
+    return v;
+}
+
+template <typename R>
+__global__ __launch_bounds__(1024, 2) void k_pc_stream(PcGeo g, const PTap<R>* __restrict__ taps,
+                                                       const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
+                                                       const double* __restrict__ stop) {
+    if (stop && *stop != 0.0) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    cplx<R>* win = reinterpret_cast<cplx<R>*>(smem);
+    const int plane = g.rows * g.half;  // one column-parity plane of a slice
+    const int slice_elems = 2 * plane;
+    STap<R>* st = reinterpret_cast<STap<R>*>(win + (size_t)g.nslot * slice_elems);
+    const int nwork = g.nband * g.nrun * 2;
+    const int per = (nwork + 7) >> 3;
+    const int w = (blockIdx.x & 7) * per + (blockIdx.x >> 3);  // runs of one XCD are contiguous
+    if (w >= nwork) return;
+    const int par = w & 1, band = (w >> 1) % g.nband, run = (w >> 1) / g.nband;
+    const int y0 = band * g.TY;
+    const int tau0 = run * g.Tc, tau1 = min(g.Nt, tau0 + g.Tc);
+    const int hx = g.L / 2;
+    const int q = threadIdx.x & 3, o = threadIdx.x >> 2;
+    const int iy = o / hx, jx = o - iy * hx;
+    const bool act = iy < g.TY && y0 + iy < g.L;
+    const int base = act ? (iy - g.bmin) * g.half + jx : -g.bmin * g.half;  // idle lanes read the first site's window
+    const int ntap = g.count[par];
+    {
+        const PTap<R>* tp = taps + g.first[par];
+        for (int j = threadIdx.x; j < ntap; j += blockDim.x) {
+            const PTap<R> t = tp[j];
+            st[j] = STap<R>{t.g.re, t.g.im, t.plane * plane + t.off, 0};
+        }
+    }
+    // this thread's window elements (the same for every slice): source site
+    // inside a slice and LDS position inside a slot (-1: none)
+    int soff[kPcElems], doff[kPcElems];
+    {
+        const int total = g.rows * g.cols;
+#pragma unroll
+        for (int k = 0; k < kPcElems; k++) {
+            const int e = (int)threadIdx.x + k * (int)blockDim.x;
+            doff[k] = -1;
+            soff[k] = 0;
+            if (e < total) {
+                const int r = e / g.cols, c = e - r * g.cols;
+                const int yy = (y0 + g.bmin + r + 8 * g.L) % g.L, xx = (g.cmin + c + 8 * g.L) % g.L;
+                soff[k] = yy * g.L + xx;
+                doff[k] = (c & 1) * plane + r * g.half + (c >> 1);
             }
         }
     }
-    out[(size_t)tau * lt.Vs + y * L + x] = mk<R>(ar, ai);
+    auto fetch = [&](int s, cplx<R> (&v)[kPcElems]) {
+        const cplx<R>* src = in + (size_t)(((s % g.Nt) + g.Nt) % g.Nt) * g.Vs;
+#pragma unroll
+        for (int k = 0; k < kPcElems; k++) v[k] = src[soff[k]];  // unused entries read site 0
+    };
+    auto store = [&](int s, const cplx<R> (&v)[kPcElems]) {
+        const R sg = (s < 0 || s >= g.Nt) ? R(-1) : R(1);
+        cplx<R>* dst = win + (size_t)(((s % g.nslot) + g.nslot) % g.nslot) * slice_elems;
+#pragma unroll
+        for (int k = 0; k < kPcElems; k++)
+            if (doff[k] >= 0) dst[doff[k]] = mk<R>(sg * v[k].re, sg * v[k].im);
+    };
+    cplx<R> nxt[kPcElems];
+    for (int s = tau0 + g.amin; s < tau0 + g.amin + g.nslot - 1; s++) {
+        fetch(s, nxt);
+        store(s, nxt);
+    }
+    fetch(tau0 + g.amin + g.nslot - 1, nxt);
+    const int* gs = g.gstart[par];
+    for (int tau = tau0; tau < tau1; tau++) {
+        store(tau + g.amin + g.nslot - 1, nxt);
+        __syncthreads();
+        if (tau + 1 < tau1) fetch(tau + g.amin + g.nslot, nxt);  // in flight during the taps
+        const int r0 = (((tau + g.amin) % g.nslot) + g.nslot) % g.nslot;
+        R ar = 0, ai = 0;
+        for (int gg = 0; gg < g.nslot; gg++) {
+            int sl = r0 + gg;
+            sl = sl >= g.nslot ? sl - g.nslot : sl;
+            const cplx<R>* ws = win + (size_t)sl * slice_elems + base;
+            const int j1 = gs[gg + 1];
+#pragma unroll 4
+            for (int j = gs[gg] + q; j < j1; j += 4) {
+                const STap<R> t = st[j];
+                const cplx<R> v = ws[t.toff];
+                // four FMAs into the running sums (a product formed first and
+                // then added would cost two more instructions per tap)
+                ar = fma(t.re, v.re, ar);
+                ar = fma(-t.im, v.im, ar);
+                ai = fma(t.re, v.im, ai);
+                ai = fma(t.im, v.re, ai);
+            }
+        }
+        ar = quad_sum(ar);
+        ai = quad_sum(ai);
+        if (act && q == 3) out[(size_t)tau * g.Vs + (y0 + iy) * g.L + 2 * jx + par] = mk<R>(ar, ai);
+        __syncthreads();  // the next step overwrites the oldest slot
+    }
 }
 
 template <typename R>
@@ -252,12 +396,68 @@ static const PTap<R>* taps_for(qedhmc_ctx* h) {
         return (const PTap<float>*)h->pc_dev32;
 }
 
-template <typename R, bool DAG>
-static qedhmc_status launch_pc(qedhmc_ctx* h, const cplx<R>* in, cplx<R>* out, const double* stop) {
-    const int half = h->lat.Vs / 2;
-    const dim3 grid(h->lat.Nt, 2, (half + 255) / 256);
-    hipLaunchKernelGGL((k_pc_apply<R, DAG>), grid, dim3(256), 0, h->stream, h->lat, taps_for<R>(h),
-                       (int)h->pc_taps[0].size(), (int)h->pc_taps[1].size(), in, out, stop);
+// Band height TY: at most 512 output sites of one parity per step and an LDS
+// window within 64 KB (FP32) or 128 KB (FP64); runs of 2 .. 16 slices aiming
+// at about 512 workgroups.
+// Band height TY: four lanes per output site, at most 1024 lanes, and an LDS
+// window within 64 KB (FP32) or 128 KB (FP64); runs of 2 .. 16 slices aiming
+// at about 512 workgroups.
+template <typename R>
+static qedhmc_status launch_pc(qedhmc_ctx* h, int ps, const cplx<R>* in, cplx<R>* out, const double* stop) {
+    const PcPass& pp = h->pc_pass[ps];
+    const Lat& lt = h->lat;
+    PcGeo g{};
+    g.L = lt.L;
+    g.Nt = lt.Nt;
+    g.Vs = lt.Vs;
+    g.bmin = pp.bmin;
+    g.cmin = pp.cmin;
+    g.amin = pp.amin;
+    g.nslot = pp.amax - pp.amin + 1;
+    if (g.nslot > kPcSlots) {
+        set_error("paper preconditioner: stencil reaches too many slices");
+        return QEDHMC_EUNSUPPORTED;
+    }
+    g.cols = lt.L + pp.cmax - pp.cmin;
+    g.half = (g.cols + 1) / 2;
+    for (int par = 0; par < 2; par++) {
+        g.first[par] = pp.first[par];
+        g.count[par] = pp.count[par];
+        for (int k = 0; k <= kPcSlots; k++) g.gstart[par][k] = pp.gstart[par][std::min(k, g.nslot)];
+    }
+    const int hx = lt.L / 2;
+    const int maxtap = std::max(pp.count[0], pp.count[1]);
+    const size_t tap_bytes = (size_t)maxtap * sizeof(STap<R>);
+    const size_t budget = std::min<size_t>(sizeof(R) == 8 ? 131072 : 65536, h->max_lds);
+    auto lds_of = [&](int ty) {
+        return (size_t)g.nslot * (ty + pp.bmax - pp.bmin) * 2 * g.half * sizeof(cplx<R>) + tap_bytes;
+    };
+    int TY = std::max(1, std::min(lt.L, 1024 / (4 * hx)));
+    while (TY > 1 && lds_of(TY) > budget) TY--;
+    if (4 * hx > 1024 || lds_of(TY) > h->max_lds) {
+        set_error("paper preconditioner: the stencil window exceeds one workgroup at this L");
+        return QEDHMC_EUNSUPPORTED;
+    }
+    g.nband = (lt.L + TY - 1) / TY;
+    g.TY = (lt.L + g.nband - 1) / g.nband;
+    g.rows = g.TY + pp.bmax - pp.bmin;
+    g.Tc = std::max(2, std::min(16, lt.Nt * g.nband * 2 / 512));
+    g.Tc = std::min(g.Tc, lt.Nt);
+    g.nrun = (lt.Nt + g.Tc - 1) / g.Tc;
+    const size_t lds = lds_of(g.TY);
+    int threads = ((4 * g.TY * hx + 63) / 64) * 64;
+    // every window element of a slice has a thread (kPcElems each at most)
+    const int need = (g.rows * g.cols + kPcElems - 1) / kPcElems;
+    threads = std::max(threads, ((need + 63) / 64) * 64);
+    if (threads > 1024) {
+        set_error("paper preconditioner: stencil window too large for one workgroup at this L");
+        return QEDHMC_EUNSUPPORTED;
+    }
+    const int nwork = g.nband * g.nrun * 2;
+    if (lds > 65536)
+        QH_HIP(hipFuncSetAttribute((const void*)k_pc_stream<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_pc_stream<R>, dim3(8 * ((nwork + 7) / 8)), dim3(threads), lds, h->stream, g, taps_for<R>(h),
+                       in, out, stop);
     QH_HIP(hipGetLastError());
     return QEDHMC_OK;
 }
@@ -265,8 +465,8 @@ static qedhmc_status launch_pc(qedhmc_ctx* h, const cplx<R>* in, cplx<R>* out, c
 // z = G^dag (G r); tmp: scratch vector of the same precision
 template <typename R>
 static qedhmc_status apply_P_t(qedhmc_ctx* h, const cplx<R>* r, cplx<R>* z, cplx<R>* tmp, const double* stop) {
-    QH_TRY((launch_pc<R, false>(h, r, tmp, stop)));
-    return launch_pc<R, true>(h, tmp, z, stop);
+    QH_TRY(launch_pc<R>(h, 0, r, tmp, stop));
+    return launch_pc<R>(h, 1, tmp, z, stop);
 }
 
 qedhmc_status launch_apply_precond(qedhmc_ctx* h, qedhmc_precision prec, const void* in, void* out) {

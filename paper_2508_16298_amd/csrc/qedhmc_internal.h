@@ -428,6 +428,14 @@ struct HostTap {
     double gre, gim;
 };
 
+// One pass of the preconditioner (G, then G^dag) as a gather: reach of its
+// taps and where each parity's list starts in the device arrays.
+struct PcPass {
+    int amin, amax, bmin, bmax, cmin, cmax;
+    int first[2], count[2];
+    int gstart[2][9];  // per parity: start of the taps of tau offset amin + k, k = 0 .. 8
+};
+
 struct qedhmc_ctx {
     qedhmc_params p;
     qh::Lat lat;
@@ -476,6 +484,7 @@ struct qedhmc_ctx {
     bool pc_ready;
     double pc_shift;
     std::vector<HostTap> pc_taps[2];  // per x parity
+    PcPass pc_pass[2];                // G and G^dag
     void* pc_dev64;                   // device taps, FP64 and FP32
     void* pc_dev32;
 };
