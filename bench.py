@@ -40,7 +40,7 @@ HBM_PEAK_GBS = 8000.0
 # (profiles/k_cg_iter_mixed_l24_hbm_counters.md): FETCH_SIZE and WRITE_SIZE in
 # KiB, scaled by the copy-kernel calibration (x2.0 and x1.0).  Valid for the
 # kernel as measured there; set to None whenever k_cg_iter changes.
-CG_ITER_COUNTER_BYTES = {"fp32": (4637.5 * 2.0 + 6491.4 * 1.0) * 1024, "fp64": None}
+CG_ITER_COUNTER_BYTES = {"fp32": (4643.5 * 2.0 + 6491.4 * 1.0) * 1024, "fp64": None}
 
 
 def parse():
@@ -60,6 +60,8 @@ def parse():
                          "launches on the workload instead of trajectories (same kernels and launch shapes)")
     ap.add_argument("--matvec-only", type=int, default=0, metavar="L",
                     help="only the standalone M^dag M at the large size with this L (for profiler runs)")
+    ap.add_argument("--precond-only", type=int, default=0, metavar="L",
+                    help="only the paper preconditioner z = G^dag G r at L, Nt = 10 L, FP32 (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="counter calibration: 5 device copies of 256 MiB (torch copy kernel)")
     return ap.parse_args()
@@ -107,6 +109,31 @@ def matvec_large(n_calls=100, only_L=0):
         del theta
         torch.cuda.empty_cache()
     return rows
+
+
+def run_precond_only(L, n_calls=6):
+    """The paper preconditioner applied n_calls times (after its build and one
+    untimed call) to a seeded Gaussian vector at L, Nt = 10 L, FP32; the time
+    per application from one event pair on the handle's stream."""
+    import torch
+    from paper_2508_16298_amd import qedhmc as Q
+    Nt = 10 * L
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1005)
+    with Q.Lattice(L, Nt) as lat:
+        v = torch.randn(Nt, L, L, dtype=torch.complex64, device="cuda", generator=gen)
+        z = torch.empty_like(v)
+        lat.apply_precond(v, prec="fp32", out=z)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n_calls):
+            lat.apply_precond(v, prec="fp32", out=z)
+        e1.record()
+        torch.cuda.synchronize()
+        us = 1e3 * e0.elapsed_time(e1) / n_calls
+    print(json.dumps({"precond_only": {"L": L, "Nt": Nt, "prec": "fp32", "us_per_apply": us,
+                                       "passes_per_apply": 2, "calls": n_calls}}), flush=True)
 
 
 def run_copy_calibration():
@@ -419,6 +446,8 @@ def main():
         return run_learned(a)
     if a.solve_only:
         return run_solve_only(a)
+    if a.precond_only:
+        return run_precond_only(a.precond_only)
     if a.matvec_only:
         print(json.dumps({"matvec_large": matvec_large(only_L=a.matvec_only)}), flush=True)
         return
