@@ -321,6 +321,8 @@ qedhmc_status qedhmc_net_train_step(qedhmc_net_t n, const double *theta,
  * over the last 10 iterations the solve continues with the fallback
  * preconditioner (QEDHMC_PC_PAPER or QEDHMC_PC_NONE) and *switched_at
  * (host, nullable) receives that iteration (-1 if the network kept it).
+ * The paper's preconditioner as fallback runs its stencil passes in FP32
+ * (flexible CG tolerates the inexact preconditioner).
  * All vectors FP64 complex on the device.  ENOCONV as for qedhmc_cg_solve. */
 qedhmc_status qedhmc_fcg_solve(qedhmc_net_t n, const double *theta,
                                const double *rhs, double *x, double tol,

@@ -796,7 +796,7 @@ qedhmc_status qedhmc_fcg_solve(qedhmc_net_t n, const double* theta, const double
             QH_HIP(hipGetLastError());
             return QEDHMC_OK;
         }
-        if (fallback == QEDHMC_PC_PAPER) return launch_apply_precond(h, QEDHMC_FP64, n->fr, out);
+        if (fallback == QEDHMC_PC_PAPER) return launch_apply_precond_fp32(h, (const double*)n->fr, (double*)out);
         QH_HIP(hipMemcpyAsync(out, n->fr, (size_t)N * sizeof(cplx<double>), hipMemcpyDeviceToDevice, st));
         return QEDHMC_OK;
     };

@@ -469,6 +469,32 @@ static qedhmc_status apply_P_t(qedhmc_ctx* h, const cplx<R>* r, cplx<R>* z, cplx
     return launch_pc<R>(h, 1, tmp, z, stop);
 }
 
+template <typename A, typename B>
+__global__ void k_pc_convert(const cplx<A>* __restrict__ a, cplx<B>* __restrict__ b, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        b[i] = mk<B>((B)a[i].re, (B)a[i].im);
+}
+
+// out = P in on FP64 vectors with the stencil passes in FP32 (the input
+// rounded once, the result widened): for flexible CG, which tolerates an
+// inexact preconditioner.  Scratch: ws[8] and ws[9].
+qedhmc_status launch_apply_precond_fp32(qedhmc_ctx* h, const double* in, double* out) {
+    QH_TRY(ensure_paper_precond(h));
+    const size_t N = (size_t)h->lat.Nt * h->lat.Vs;
+    cplx<float>* r32 = reinterpret_cast<cplx<float>*>(h->ws[9]);
+    cplx<float>* t32 = r32 + N;
+    cplx<float>* z32 = reinterpret_cast<cplx<float>*>(h->ws[8]);
+    const int grid = (int)std::min<size_t>((N + 255) / 256, 4096);
+    hipLaunchKernelGGL((k_pc_convert<double, float>), dim3(grid), dim3(256), 0, h->stream,
+                       reinterpret_cast<const cplx<double>*>(in), r32, N);
+    QH_HIP(hipGetLastError());
+    QH_TRY(apply_P_t<float>(h, r32, z32, t32, nullptr));
+    hipLaunchKernelGGL((k_pc_convert<float, double>), dim3(grid), dim3(256), 0, h->stream, (const cplx<float>*)z32,
+                       reinterpret_cast<cplx<double>*>(out), N);
+    QH_HIP(hipGetLastError());
+    return QEDHMC_OK;
+}
+
 qedhmc_status launch_apply_precond(qedhmc_ctx* h, qedhmc_precision prec, const void* in, void* out) {
     QH_TRY(ensure_paper_precond(h));
     if (prec == QEDHMC_FP64)

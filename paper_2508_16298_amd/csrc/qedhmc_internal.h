@@ -540,6 +540,8 @@ qedhmc_status cg2_solve_impl(qedhmc_ctx* h, const double* rhs, double* x, double
                              qedhmc_precision prec, int* iters, double* true_rel, int* n_reliable);
 qedhmc_status ensure_paper_precond(qedhmc_ctx* h);
 qedhmc_status launch_apply_precond(qedhmc_ctx* h, qedhmc_precision prec, const void* in, void* out);
+// FP64 in and out, stencil passes in FP32 (scratch ws[8], ws[9])
+qedhmc_status launch_apply_precond_fp32(qedhmc_ctx* h, const double* in, double* out);
 
 // Gauge-field and trajectory kernels (boson.hip)
 qedhmc_status launch_bosonic(qedhmc_ctx* h, const double* theta, double* F_B, double* S_dev);
