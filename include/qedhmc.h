@@ -83,8 +83,9 @@ typedef enum { QEDHMC_PC_NONE = 0, QEDHMC_PC_PAPER = 1 } qedhmc_precond;
 /* Lattice, couplings and the seed of the trajectory random streams.
  * L even, 2 <= L <= 2048; Nt >= 1; L^2 Nt < 2^31.  The calls that keep a
  * whole time slice in one workgroup (apply_B, apply_M, fermion_force,
- * cg_solve, hmc_trajectory) take L <= 66 and return QEDHMC_EUNSUPPORTED
- * beyond; apply_MdagM takes every L. */
+ * hmc_trajectory) take L <= 66 and return QEDHMC_EUNSUPPORTED beyond;
+ * apply_MdagM and cg_solve (tiled M^dag M) take every L, the paper's
+ * preconditioner as long as its stencil window fits a workgroup's LDS. */
 typedef struct {
     int32_t L, Nt;
     double dtau, t, J, K;

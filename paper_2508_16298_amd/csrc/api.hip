@@ -105,6 +105,10 @@ qedhmc_status qedhmc_init_lattice(const qedhmc_params* params, void* stream, qed
     ok = ok && hipMalloc(&h->force, 2 * N * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc(&h->force_b, 2 * N * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc(&h->partial, ((size_t)12 * p.Nt + 4096) * sizeof(double)) == hipSuccess;
+    if (ok && h->lat.ncell > 1024) {
+        h->tpart_tiles = std::max(mdagm_tiled_tiles(h->lat, false), mdagm_tiled_tiles(h->lat, true));
+        ok = hipMalloc(&h->tpart, ((size_t)7 * p.Nt * h->tpart_tiles + p.Nt + 64) * sizeof(double)) == hipSuccess;
+    }
     ok = ok && hipMalloc(&h->scal, 128 * sizeof(double)) == hipSuccess;
     ok = ok && hipHostMalloc(&h->h_pinned, 64 * sizeof(double), hipHostMallocDefault) == hipSuccess;
     if (!ok) {
@@ -141,6 +145,7 @@ qedhmc_status qedhmc_destroy(qedhmc_t h) {
     (void)hipFree(h->force);
     (void)hipFree(h->force_b);
     (void)hipFree(h->partial);
+    if (h->tpart) (void)hipFree(h->tpart);
     (void)hipFree(h->scal);
     if (h->h_pinned) (void)hipHostFree(h->h_pinned);
     if (h->prof_ready)

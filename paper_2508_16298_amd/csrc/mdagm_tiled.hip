@@ -272,13 +272,38 @@ __device__ __forceinline__ void tile_B(cplx<R> (&v)[4], const HS& hs, cplx<R>* x
 template <typename R>
 static constexpr int kTileMaxThreads = sizeof(R) == 8 ? 512 : 1024;
 
-template <typename R, bool FX, bool FY>
+// Extra operands of the CG form (PART): with w = out = O u, the partial sums
+// <r,r>, <r,u>, <w,u>, <u,s>, <p,w>, <p,s> of every (slice, tile) over the
+// tile's output cells go to part[kTileParts * (tau * ntile + tile)]; a
+// non-zero *stop makes the launch a no-op.
+static constexpr int kTileParts = 7;
+
+template <typename R>
+struct TPart {
+    const cplx<R>* r;
+    const cplx<R>* p;
+    const cplx<R>* s;
+    double* part;
+    const double* stop;
+};
+
+template <typename R>
+__device__ __forceinline__ double tdot(const cplx<R> (&a)[4], const cplx<R> (&b)[4]) {
+    double d = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) d += (double)a[q].re * (double)b[q].re + (double)a[q].im * (double)b[q].im;
+    return d;
+}
+
+template <typename R, bool FX, bool FY, bool PART>
 __global__ __launch_bounds__(kTileMaxThreads<R>) void k_mdagm_tiled(TiledGeo G, const cplx<R>* __restrict__ in,
                                                       cplx<R>* __restrict__ out, const cplx<R>* __restrict__ gauge,
-                                                      TCoef<R> co) {
+                                                      TCoef<R> co, TPart<R> ops) {
+    if (PART && ops.stop && *ops.stop != 0.0) return;
     extern __shared__ __align__(16) unsigned char smem[];
     cplx<R>* xb = reinterpret_cast<cplx<R>*>(smem);
     const int nreg = G.RW * G.RH;
+    double* red = reinterpret_cast<double*>(xb + (size_t)8 * nreg);  // PART: per-wavefront sums
     // work items dealt to the eight XCDs in contiguous ranges: the tiles of
     // one run and neighbouring runs share an XCD's L2 (halo and tau + 1 reads)
     const int per = (G.nwork + 7) >> 3;
@@ -324,12 +349,51 @@ __global__ __launch_bounds__(kTileMaxThreads<R>) void k_mdagm_tiled(TiledGeo G, 
             u[q] = yn[q];
         }
         tile_B<R>(u, hs, xb, nreg, k, kb);  // B'_tau y_{tau+1}
+        cplx<R> w[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) w[q] = mk<R>(y[q].re - e * u[q].re, y[q].im - e * u[q].im);
         if (k.store) {
             cplx<R>* o = out + (size_t)tau * Vs;
-            o[k.s0] = mk<R>(y[0].re - e * u[0].re, y[0].im - e * u[0].im);
-            o[k.s0 + 1] = mk<R>(y[1].re - e * u[1].re, y[1].im - e * u[1].im);
-            o[k.s0 + G.L] = mk<R>(y[2].re - e * u[2].re, y[2].im - e * u[2].im);
-            o[k.s0 + G.L + 1] = mk<R>(y[3].re - e * u[3].re, y[3].im - e * u[3].im);
+            o[k.s0] = w[0];
+            o[k.s0 + 1] = w[1];
+            o[k.s0 + G.L] = w[2];
+            o[k.s0 + G.L + 1] = w[3];
+        }
+        if constexpr (PART) {
+            double v[kTileParts] = {0, 0, 0, 0, 0, 0, 0};
+            if (k.store) {
+                cplx<R> rt[4], ut[4], pt[4], st[4];
+                tile_load<R>(rt, ops.r + (size_t)tau * Vs, G, k);
+                tile_load<R>(ut, in + (size_t)tau * Vs, G, k);
+                tile_load<R>(pt, ops.p + (size_t)tau * Vs, G, k);
+                tile_load<R>(st, ops.s + (size_t)tau * Vs, G, k);
+                v[0] = tdot(rt, rt);
+                v[1] = tdot(rt, ut);
+                v[2] = tdot(w, ut);
+                v[3] = tdot(ut, st);
+                v[4] = tdot(pt, w);
+                v[5] = tdot(pt, st);
+            }
+            // fixed-order workgroup sum: DPP within each wavefront, then the
+            // wavefronts' sums in order (the exchange barriers separate the
+            // reuse of red from one slice to the next)
+            const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+            for (int q = 0; q < kTileParts - 1; q++) v[q] = wave_sum_f64(v[q]);
+            if (lane == 63)
+#pragma unroll
+                for (int q = 0; q < kTileParts - 1; q++) red[(kTileParts - 1) * wv + q] = v[q];
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double t[kTileParts] = {0, 0, 0, 0, 0, 0, 0};
+                const int nw = (int)(blockDim.x + 63) >> 6;
+                for (int i = 0; i < nw; i++)
+#pragma unroll
+                    for (int q = 0; q < kTileParts - 1; q++) t[q] += red[(kTileParts - 1) * i + q];
+                double* dst = ops.part + (size_t)kTileParts * ((size_t)tau * ntile + tile);
+#pragma unroll
+                for (int q = 0; q < kTileParts; q++) dst[q] = t[q];
+            }
         }
 #pragma unroll
         for (int q = 0; q < 4; q++) y[q] = yn[q];
@@ -408,15 +472,30 @@ static int env_int(const char* name, int dflt) {
     return s ? std::atoi(s) : dflt;
 }
 
+// The plan of precision R: the tuning variables apply to the plain operator
+// only; the CG form always takes the default plan (its partial buffer is
+// sized for it).  FP64 runs 16 slices per workgroup by default (fastest at
+// L = 66 and 128 in a sweep of run lengths); FP32 takes the plan's default.
 template <typename R>
-static qedhmc_status mdagm_tiled_t(qedhmc_ctx* h, const void* in, void* out) {
-    const int cap = std::max(100, std::min(kTileMaxThreads<R>, env_int("QEDHMC_TILE_THREADS", 1024)));
-    // FP64 runs 16 slices per workgroup by default (fastest at L = 66 and
-    // 128 in a sweep of run lengths); FP32 takes the plan's default
-    int tc = env_int("QEDHMC_TILE_TC", 0);
+static TiledPlan plan_for(const Lat& lt, bool tunable) {
+    int cap = kTileMaxThreads<R>, tc = 0;
+    if (tunable) {
+        cap = std::max(100, std::min(kTileMaxThreads<R>, env_int("QEDHMC_TILE_THREADS", 1024)));
+        tc = env_int("QEDHMC_TILE_TC", 0);
+    }
     if (tc <= 0 && sizeof(R) == 8) tc = 16;
-    const TiledPlan p = plan_tiled(h->lat, tc, cap);
-    const size_t lds = (size_t)8 * p.g.RW * p.g.RH * sizeof(cplx<R>);
+    return plan_tiled(lt, tc, cap);
+}
+
+int mdagm_tiled_tiles(const Lat& lt, bool fp64) {
+    const TiledPlan p = fp64 ? plan_for<double>(lt, false) : plan_for<float>(lt, false);
+    return p.g.ntx * p.g.nty;
+}
+
+template <typename R, bool PART>
+static qedhmc_status mdagm_tiled_t(qedhmc_ctx* h, const void* in, void* out, const TPart<R>& tpart) {
+    const TiledPlan p = plan_for<R>(h->lat, !PART);
+    const size_t lds = (size_t)8 * p.g.RW * p.g.RH * sizeof(cplx<R>) + (PART ? 16 * kTileParts * sizeof(double) : 0);
     if (lds > h->max_lds) {
         set_error("tiled M^dag M: exchange buffers exceed the workgroup's LDS");
         return QEDHMC_EUNSUPPORTED;
@@ -429,22 +508,37 @@ static qedhmc_status mdagm_tiled_t(qedhmc_ctx* h, const void* in, void* out) {
         if (lds > 65536)
             QH_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         hipEvent_t e0, e1;
-        if (prof_sample(h, sizeof(R) == 4 ? QEDHMC_K_MDAGM_FP32 : QEDHMC_K_MDAGM_FP64, e0, e1))
+        const int cls = PART ? (sizeof(R) == 4 ? QEDHMC_K_PCG_MV_FP32 : QEDHMC_K_PCG_MV_FP64)
+                             : (sizeof(R) == 4 ? QEDHMC_K_MDAGM_FP32 : QEDHMC_K_MDAGM_FP64);
+        if (prof_sample(h, cls, e0, e1))
             hipExtLaunchKernelGGL(kern, dim3(grid), dim3(p.threads), lds, h->stream, e0, e1, 0, p.g,
-                                  (const cplx<R>*)in, (cplx<R>*)out, gauge, co);
+                                  (const cplx<R>*)in, (cplx<R>*)out, gauge, co, tpart);
         else
             hipLaunchKernelGGL(kern, dim3(grid), dim3(p.threads), lds, h->stream, p.g, (const cplx<R>*)in,
-                               (cplx<R>*)out, gauge, co);
+                               (cplx<R>*)out, gauge, co, tpart);
         QH_HIP(hipGetLastError());
         return QEDHMC_OK;
     };
-    if (p.fx && p.fy) return go(k_mdagm_tiled<R, true, true>);
-    if (p.fx) return go(k_mdagm_tiled<R, true, false>);
-    return go(k_mdagm_tiled<R, false, false>);
+    if (p.fx && p.fy) return go(k_mdagm_tiled<R, true, true, PART>);
+    if (p.fx) return go(k_mdagm_tiled<R, true, false, PART>);
+    return go(k_mdagm_tiled<R, false, false, PART>);
 }
 
 qedhmc_status launch_mdagm_tiled(qedhmc_ctx* h, qedhmc_precision prec, const void* in, void* out) {
-    return prec == QEDHMC_FP64 ? mdagm_tiled_t<double>(h, in, out) : mdagm_tiled_t<float>(h, in, out);
+    return prec == QEDHMC_FP64 ? mdagm_tiled_t<double, false>(h, in, out, TPart<double>{})
+                               : mdagm_tiled_t<float, false>(h, in, out, TPart<float>{});
 }
+
+template <typename R>
+qedhmc_status launch_mdagm_tiled_parts(qedhmc_ctx* h, const cplx<R>* u, cplx<R>* w, const cplx<R>* r,
+                                       const cplx<R>* p, const cplx<R>* s, double* part, const double* stop) {
+    return mdagm_tiled_t<R, true>(h, u, w, TPart<R>{r, p, s, part, stop});
+}
+template qedhmc_status launch_mdagm_tiled_parts<float>(qedhmc_ctx*, const cplx<float>*, cplx<float>*,
+                                                       const cplx<float>*, const cplx<float>*, const cplx<float>*,
+                                                       double*, const double*);
+template qedhmc_status launch_mdagm_tiled_parts<double>(qedhmc_ctx*, const cplx<double>*, cplx<double>*,
+                                                        const cplx<double>*, const cplx<double>*,
+                                                        const cplx<double>*, double*, const double*);
 
 }  // namespace qh

@@ -516,8 +516,9 @@ struct PcgBufs {
     cplx<double>* x;
     const cplx<double>* rhs;
     const cplx<double>* Ox;
-    double* part;   // [Nt][kNP7]
+    double* part;   // [nparts][kNP7]: per slice, or per (slice, tile) for the tiled matvec
     double* partb;  // [Nt]: |rhs|^2 or the FP64 true |r|^2
+    int nparts;
 };
 
 // r = rhs, x = p = s = 0; partb = |rhs|^2 per slice
@@ -588,7 +589,7 @@ __global__ __launch_bounds__(256) void k_pcg_upd(Lat lt, PcgBufs<R> B, double* _
         return;
     }
     double pr[kNP7];
-    reduce_k<kNP7>(B.part, lt.Nt, red, red + kNP7 * 16, pr);
+    reduce_k<kNP7>(B.part, B.nparts, red, red + kNP7 * 16, pr);
     const double rr = pr[0], gam = pr[1], del = pr[2];
     const int it = (int)sin_[S_ITERS];
     int stop = 0;
@@ -697,14 +698,12 @@ __global__ __launch_bounds__(256) void k_pcg_rep(Lat lt, PcgBufs<R> B) {
 
 // After a replacement and a fresh u, w and partials: converged -> stop 1;
 // otherwise resume (restart sets beta = 0 on the next iteration).
-__global__ void k_pcg_check(double* __restrict__ scal, int kpar, const double* __restrict__ part,
+__global__ void k_pcg_check(double* __restrict__ scal, int kpar, const double* __restrict__ part, int nparts,
                             const double* __restrict__ partb, int Nt, int restart) {
     __shared__ double red[64];
     double v[2] = {0.0, 0.0};
-    for (int t = threadIdx.x; t < Nt; t += blockDim.x) {
-        v[0] += partb[t];
-        v[1] += part[kNP7 * t];
-    }
+    for (int t = threadIdx.x; t < Nt; t += blockDim.x) v[0] += partb[t];
+    for (int t = threadIdx.x; t < nparts; t += blockDim.x) v[1] += part[kNP7 * t];
     block_sumk<2>(v, red);
     if (threadIdx.x == 0) {
         double* sl = scal + S_NSLOT * kpar;
@@ -737,13 +736,22 @@ static PcgBufs<R> pbufs_of(qedhmc_ctx* h, const double* rhs, double* x) {
     B.x = reinterpret_cast<cplx<double>*>(x);
     B.rhs = reinterpret_cast<const cplx<double>*>(rhs);
     B.Ox = reinterpret_cast<const cplx<double>*>(h->ws[3]);
-    B.part = h->partial;
-    B.partb = h->partial + kNP7 * (size_t)h->lat.Nt;
+    if (h->lat.ncell > 1024) {
+        // the tiled matvec writes one partial tuple per (slice, tile)
+        B.nparts = h->lat.Nt * mdagm_tiled_tiles(h->lat, sizeof(R) == 8);
+        B.part = h->tpart;
+        B.partb = h->tpart + kNP7 * (size_t)h->lat.Nt * h->tpart_tiles;
+    } else {
+        B.nparts = h->lat.Nt;
+        B.part = h->partial;
+        B.partb = h->partial + kNP7 * (size_t)h->lat.Nt;
+    }
     return B;
 }
 
 template <typename R>
 static qedhmc_status launch_mv(qedhmc_ctx* h, const PcgBufs<R>& B, const double* stop, bool timed) {
+    if (h->lat.ncell > 1024) return launch_mdagm_tiled_parts<R>(h, B.u, B.w, B.r, B.p, B.s, B.part, stop);
     return with_shape<R>(h, [&]<int MC, int NB, int BS>(int nt, size_t lds) -> qedhmc_status {
         QH_TRY(lds_attr(h, k_pcg_mv<R, MC, NB, BS>, lds));
         hipEvent_t e0, e1;
@@ -820,7 +828,7 @@ static qedhmc_status pcg_t(qedhmc_ctx* h, const double* rhs, double* x, double t
         QH_TRY(launch_mdagm(h, prec == QEDHMC_FP64 ? QEDHMC_FP64 : QEDHMC_FP32, B.p, B.s, nullptr));
         QH_TRY(pcg_tail<R>(h, B, nullptr, identity));
         hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(256), 0, h->stream, h->scal, kpar, (const double*)B.part,
-                           (const double*)B.partb, Nt, (!mixed || flag == 3.0) ? 1 : 0);
+                           B.nparts, (const double*)B.partb, Nt, (!mixed || flag == 3.0) ? 1 : 0);
         QH_HIP(hipGetLastError());
         nrel++;
         QH_TRY(read_slot(h, kpar));

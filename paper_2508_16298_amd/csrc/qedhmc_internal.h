@@ -456,6 +456,8 @@ struct qedhmc_ctx {
     double* force;              // total force
     double* force_b;            // bosonic force
     double* partial;            // per-block partial sums: [2][Nt][6] for CG, then 4096 more
+    double* tpart;              // slices of more than 1024 cells: CG partials per (slice, tile), then Nt more
+    int tpart_tiles;            // tiles per slice the buffer holds
     double* scal;               // device scalars: [0,32) CG slots, [64,80) trajectory, [100] action
     double* h_pinned;           // pinned host mirror of a few scalars
     // sampled kernel timing (qedhmc_profile)
@@ -527,6 +529,14 @@ qedhmc_status launch_mdagm(qedhmc_ctx* h, qedhmc_precision prec, const void* in,
 qedhmc_status launch_force(qedhmc_ctx* h, qedhmc_precision prec, const double* X, double* F);
 // out = M^dag M in by spatial tiles streamed along tau (mdagm_tiled.hip)
 qedhmc_status launch_mdagm_tiled(qedhmc_ctx* h, qedhmc_precision prec, const void* in, void* out);
+// the same as the matvec of the two-launch CG: w = O u and the partial sums
+// <r,r>, <r,u>, <w,u>, <u,s>, <p,w>, <p,s> (and a zero) of every (slice,
+// tile) into part[7 * (tau * tiles + tile)]; stop: nullable slot flag
+template <typename R>
+qedhmc_status launch_mdagm_tiled_parts(qedhmc_ctx* h, const cplx<R>* u, cplx<R>* w, const cplx<R>* r,
+                                       const cplx<R>* p, const cplx<R>* s, double* part, const double* stop);
+// tiles per slice of the default plan (the CG form's) in FP32 or FP64
+int mdagm_tiled_tiles(const Lat& lt, bool fp64);
 qedhmc_status launch_bond_tables(qedhmc_ctx* h);
 
 // CG (cg.hip) and preconditioned CG (pcg.hip)

@@ -104,5 +104,28 @@ def test_whole_slice_calls_reject_large_slices():
             lat.apply_M(th, _dev(v))
         assert e.value.status == Q.EUNSUPPORTED
         with pytest.raises(Q.QedhmcError) as e:
-            lat.cg_solve(th, _dev(v), tol=1e-8)
+            lat.fermion_force(th, _dev(v))
         assert e.value.status == Q.EUNSUPPORTED
+
+
+@pytest.mark.parametrize("L,Nt,prec,tol,precond", [(68, 6, "fp64", 1e-10, None), (68, 6, "fp32", 1e-8, None),
+                                                   (128, 4, "fp32", 1e-8, None), (66, 12, "fp32", 1e-8, "paper"),
+                                                   (70, 10, "fp64", 1e-10, "paper")])
+def test_cg_past_whole_slice_limit(L, Nt, prec, tol, precond):
+    """CG and PCG on slices of more than 1024 cells run in the two-launch form
+    with the tiled M^dag M writing one partial tuple per (slice, tile); past
+    L = 66 this is the only form.  True residual recomputed by the oracle;
+    the FP64 CG iteration count matches the oracle's."""
+    p = O.lat(L, Nt)
+    th = inputs.noisy_pi_flux_theta(L, Nt, 0.3, 960 + L)
+    R = inputs.gauss_cvec(L, Nt, 961 + L)
+    eta = O.apply_M(p, th, R, dagger=True).reshape(Nt, L, L)
+    with Q.Lattice(L, Nt) as lat:
+        x, st, it, rel = lat.cg_solve(_dev(th), _dev(eta), tol=tol, prec=prec, precond=precond)
+        xg = _host(x)
+    true = np.linalg.norm(eta.reshape(-1) - O.apply_MdagM(p, th, xg).reshape(-1)) / np.linalg.norm(eta)
+    print(f"L={L} Nt={Nt} {prec} precond={precond}: {it} iterations, true residual {true:.2e}", flush=True)
+    assert st == Q.OK and rel <= tol and true <= 1.05 * tol
+    if prec == "fp64" and precond is None:
+        _, _, ito, _ = O.cg_solve(p, th, eta, tol=tol)
+        assert abs(it - ito) <= max(2, ito // 50), (it, ito)
