@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <vector>
 
+#include <cstdlib>
 #include "cg_common.h"
 
 namespace qh {
@@ -399,9 +400,9 @@ static const PTap<R>* taps_for(qedhmc_ctx* h) {
 // Band height TY: at most 512 output sites of one parity per step and an LDS
 // window within 64 KB (FP32) or 128 KB (FP64); runs of 2 .. 16 slices aiming
 // at about 512 workgroups.
-// Band height TY: four lanes per output site, at most 1024 lanes, and an LDS
+// Band height TY: four lanes per output site, about 448 lanes, and an LDS
 // window within 64 KB (FP32) or 128 KB (FP64); runs of 2 .. 16 slices aiming
-// at about 512 workgroups.
+// at about 4096 workgroups.
 template <typename R>
 static qedhmc_status launch_pc(qedhmc_ctx* h, int ps, const cplx<R>* in, cplx<R>* out, const double* stop) {
     const PcPass& pp = h->pc_pass[ps];
@@ -432,8 +433,16 @@ static qedhmc_status launch_pc(qedhmc_ctx* h, int ps, const cplx<R>* in, cplx<R>
     auto lds_of = [&](int ty) {
         return (size_t)g.nslot * (ty + pp.bmax - pp.bmin) * 2 * g.half * sizeof(cplx<R>) + tap_bytes;
     };
-    int TY = std::max(1, std::min(lt.L, 1024 / (4 * hx)));
+    // tuning overrides, read per call: QEDHMC_PC_TY (rows per band, at most
+    // the plan's) and QEDHMC_PC_TC (slices per run); 0 or unset: automatic
+    const char* ety = std::getenv("QEDHMC_PC_TY");
+    const char* etc = std::getenv("QEDHMC_PC_TC");
+    // about 448 lanes per workgroup: several small workgroups per compute
+    // unit beat one large one (less barrier coupling; measured at L = 24,
+    // 48, 66)
+    int TY = std::max(1, std::min(lt.L, 448 / (4 * hx)));
     while (TY > 1 && lds_of(TY) > budget) TY--;
+    if (ety && std::atoi(ety) > 0) TY = std::min(TY, std::atoi(ety));
     if (4 * hx > 1024 || lds_of(TY) > h->max_lds) {
         set_error("paper preconditioner: the stencil window exceeds one workgroup at this L");
         return QEDHMC_EUNSUPPORTED;
@@ -441,7 +450,8 @@ static qedhmc_status launch_pc(qedhmc_ctx* h, int ps, const cplx<R>* in, cplx<R>
     g.nband = (lt.L + TY - 1) / TY;
     g.TY = (lt.L + g.nband - 1) / g.nband;
     g.rows = g.TY + pp.bmax - pp.bmin;
-    g.Tc = std::max(2, std::min(16, lt.Nt * g.nband * 2 / 512));
+    g.Tc = std::max(2, std::min(16, lt.Nt * g.nband * 2 / 4096));
+    if (etc && std::atoi(etc) > 0) g.Tc = std::atoi(etc);
     g.Tc = std::min(g.Tc, lt.Nt);
     g.nrun = (lt.Nt + g.Tc - 1) / g.Tc;
     const size_t lds = lds_of(g.TY);
