@@ -62,6 +62,22 @@ def test_apply_precond_matches_oracle(L, Nt, prec, tol):
     assert _rel(out, PC.apply_P(taps, v)) < tol
 
 
+@pytest.mark.parametrize("L,Nt,ty,tc", [(24, 30, 5, 3), (12, 7, 1, 4), (16, 9, 3, 1), (6, 11, 2, 16), (66, 8, 0, 0)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 5e-6)])
+def test_apply_precond_forced_plans(L, Nt, ty, tc, prec, tol, monkeypatch):
+    """The streamed stencil under plans forced through its tuning variables:
+    ragged last bands (24 = 5 + 5 + 5 + 5 + 4), one-row bands, one-slice
+    runs, runs longer than N_tau, and the default plan at L = 66."""
+    monkeypatch.setenv("QEDHMC_PC_TY", str(ty))
+    monkeypatch.setenv("QEDHMC_PC_TC", str(tc))
+    taps = _oracle_taps()
+    v = inputs.gauss_cvec(L, Nt, 41 + L)
+    cdt = torch.complex128 if prec == "fp64" else torch.complex64
+    with Q.Lattice(L, Nt) as lat:
+        out = _host(lat.apply_precond(_dev(v, cdt), prec=prec))
+    assert _rel(out, PC.apply_P(taps, v)) < tol
+
+
 @pytest.mark.parametrize("which", ["pi", "noisy", "hot"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_pcg_small_vs_oracle(which, prec):
