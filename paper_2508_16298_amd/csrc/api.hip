@@ -158,6 +158,8 @@ qedhmc_status qedhmc_destroy(qedhmc_t h) {
             for (auto& g : b)
                 if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    for (auto& e : h->cg_ev)
+        if (e) (void)hipEventDestroy(e);
     delete h;
     return QEDHMC_OK;
 }

@@ -47,6 +47,7 @@ struct ChainDev {
     int maxit;   // host: iteration budget of the solve
     int mixed;   // host: 1 for the mixed-precision recursion
     int it0;     // device: iterations done at the start of the current chunk
+    int rel0;    // device: parity of the iterations since the last update at the start of the chunk
     int frozen;  // device: 1 once the solve of this chain is final
 };
 
@@ -76,9 +77,6 @@ __device__ __forceinline__ size_t group_lds(const Lat& lt) {
     return (size_t)NB * 2 * lt.Vs * sizeof(cplx<R>);
 }
 
-__device__ __forceinline__ bool needs_update(double done) {
-    return done == 1.0 || done == 2.0 || done == 3.0 || done == 6.0;
-}
 
 // ---------------------------------------------------------------------------
 // Batched slice kernels: block -> (chain, tau) from the work list
@@ -116,8 +114,8 @@ __global__ __launch_bounds__(kBS) void k_b_cg_iter(const ChainDev<R>* __restrict
     }
     int tau;
     const Tile tl = blk_tile(b, d.lt.Nt, smem, group_lds<R, NB>(d.lt), tau);
-    cg_iter_body<R, MC, NB>(d.lt, d.B, d.gauge, d.co, d.scal, kpar, it & 1, tol2, d.mixed, tau, tl.valid && tau == 0,
-                            tl);
+    cg_iter_body<R, MC, NB>(d.lt, d.B, d.gauge, d.co, d.scal, kpar, (d.rel0 + k) & 1, tol2, d.mixed, d.maxit, tau,
+                            tl.valid && tau == 0, tl);
 }
 
 // FP64 O x of the chains that stopped or paused
@@ -128,7 +126,7 @@ __global__ __launch_bounds__(kBS) void k_b_ox(const ChainDev<R>* __restrict__ ta
     const Blk b = blk[blockIdx.x];
     if (b.chain < 0) return;
     const ChainDev<R>& d = tab[b.chain];
-    if (d.frozen || !needs_update(d.scal[S_NSLOT * kpar + S_DONE])) return;
+    if (d.frozen || !gate_open(d.scal[S_NSLOT * kpar + S_DONE])) return;
     int tau;
     const Tile tl = blk_tile(b, d.lt.Nt, smem, group_lds<double, NB>(d.lt), tau);
     SliceCtx<MC> c;
@@ -153,7 +151,7 @@ __global__ __launch_bounds__(kBS) void k_b_cg_replace(const ChainDev<R>* __restr
     const Blk b = blk[blockIdx.x];
     if (b.chain < 0) return;
     const ChainDev<R>& d = tab[b.chain];
-    if (d.frozen || !needs_update(d.scal[S_NSLOT * kpar + S_DONE])) return;
+    if (d.frozen || !gate_open(d.scal[S_NSLOT * kpar + S_DONE])) return;
     int tau;
     const Tile tl = blk_tile(b, d.lt.Nt, smem, group_lds<R, NB>(d.lt), tau);
     cg_replace_body<R, MC, NB>(d.lt, d.B, d.gauge, d.co, d.scal, kpar, tau, tl);
@@ -172,9 +170,9 @@ __global__ void k_b_cg_check(ChainDev<R>* __restrict__ tab, int kpar, double* __
     const double done = sl[S_DONE];
     const int it = (int)sl[S_ITERS];
     int nd = done == 4.0 ? 4 : -1;
-    if (needs_update(done)) {
+    if (gate_open(done)) {
         double pr[kNP];
-        reduce_partials(d->B.part + kNP * (size_t)d->lt.Nt * (it & 1), d->lt.Nt, whole_block_tile(nullptr, red), pr);
+        reduce_partials(d->B.part, d->lt.Nt, whole_block_tile(nullptr, red), pr);  // the replacement's (parity 0)
         if (threadIdx.x == 0) {
             const double tr = pr[5];
             const int stall = (it + 1 == (int)sl[S_LASTUP]) ? (int)sl[S_STALL] + 1 : 0;
@@ -199,6 +197,7 @@ __global__ void k_b_cg_check(ChainDev<R>* __restrict__ tab, int kpar, double* __
     }
     if (threadIdx.x == 0) {
         d->it0 = it;
+        d->rel0 = (it - (int)sl[S_ITUPD]) & 1;
         if (nd == 4 || nd == 5) {
             d->frozen = 1;
             double* r = res + kNRes * blockIdx.x;
@@ -391,6 +390,7 @@ static qedhmc_status push_tab(qedhmc_batch* b, const std::vector<const double*>&
         tab[c].maxit = maxit;
         tab[c].mixed = mixed ? 1 : 0;
         tab[c].it0 = 0;
+        tab[c].rel0 = 0;
         tab[c].frozen = 0;
     }
     QH_HIP(hipMemcpyAsync(b->d_tab[pidx<R>()], tab, b->n * sizeof(ChainDev<R>), hipMemcpyHostToDevice, b->stream));

@@ -100,16 +100,19 @@ __device__ __forceinline__ void cg_start_body(const Lat& lt, const CgBufs<R>& B,
 template <typename R, int MC, int NB>
 __device__ __forceinline__ void cg_iter_body(const Lat& lt, const CgBufs<R>& B, const cplx<R>* __restrict__ gauge,
                                              const Coef<R>& co, double* __restrict__ scal, int kpar, int ipar,
-                                             double tol2, int mixed, int tau, bool lead, const Tile& tl) {
+                                             double tol2, int mixed, int maxit, int tau, bool lead,
+                                             const Tile& tl) {
     cplx<R>* buf2 = reinterpret_cast<cplx<R>*>(tl.buf);
     const double* sin_ = scal + S_NSLOT * kpar;
     double* sout = scal + S_NSLOT * (kpar ^ 1);
     // Every load of the launch is issued before the scalars arrive: the
-    // buffer parity ipar comes from the host (the iteration count at the
-    // start of its chunk plus the launch index; after a stop or pause inside
-    // a chunk the remaining launches are no-ops, so the guess is never used
-    // wrongly), and the stop flag is looked at only after the loads.  All
-    // loads are in bounds whatever the flag says.
+    // buffer parity ipar comes from the host -- the parity of the number of
+    // iterations since the last reliable update (the ping-pong of r, s, w
+    // restarts at buffer 0 after every update, so a chunk that starts right
+    // after one has ipar = launch index & 1 whatever the iteration count; after
+    // a stop or pause inside a chunk the remaining launches are no-ops, so the
+    // guess is never used wrongly) -- and the stop flag is looked at only
+    // after the loads.  All loads are in bounds whatever the flag says.
     const double done = sin_[S_DONE];
     const int it = (int)sin_[S_ITERS];
     const int ip = ipar, nx = ip ^ 1;
@@ -130,8 +133,14 @@ __device__ __forceinline__ void cg_iter_body(const Lat& lt, const CgBufs<R>& B, 
     cplx<R> hm[MC][12], ht[MC][12];
     hops_of<R, MC>(gauge, lt, c.tm, c.idx, co, hm);
     hops_of<R, MC>(gauge, lt, c.tau, c.idx, co, ht);
-    if (done != 0.0) {
-        if (lead && tl.ltid < S_NSLOT) sout[tl.ltid] = sin_[tl.ltid];
+    if (done != 0.0 || it >= maxit) {
+        // stopped or paused: carry the state over; a running solve that used
+        // its iteration budget is marked for its final true residual (6)
+        if (lead && tl.ltid < S_NSLOT) {
+            double v = sin_[tl.ltid];
+            if (tl.ltid == S_DONE && v == 0.0) v = 6.0;
+            sout[tl.ltid] = v;
+        }
         return;
     }
 
@@ -145,7 +154,7 @@ __device__ __forceinline__ void cg_iter_body(const Lat& lt, const CgBufs<R>& B, 
         rrupd = gam;
     }
     int stop = 0;
-    if (!isfinite(gam) || !isfinite(del) || (it & 1) != ipar)
+    if (!isfinite(gam) || !isfinite(del) || ((it - (int)sin_[S_ITUPD]) & 1) != ipar)
         stop = 4;  // breakdown: non-finite recursion (or a host/device parity mismatch)
     else if (gam <= target)
         stop = 1;
@@ -242,8 +251,7 @@ __device__ __forceinline__ void cg_replace_body(const Lat& lt, const CgBufs<R>& 
                                                 const Coef<R>& co, const double* __restrict__ scal, int kpar,
                                                 int tau, const Tile& tl) {
     cplx<R>* buf2 = reinterpret_cast<cplx<R>*>(tl.buf);
-    const int it = (int)scal[S_NSLOT * kpar + S_ITERS];
-    const int ip = it & 1;
+    const int ip = 0;  // the resumed recursion restarts its ping-pong at buffer 0
     SliceCtx<MC> c;
     slice_ctx<MC>(lt, c, tau, tl);
     const size_t Vs = lt.Vs;
@@ -281,7 +289,7 @@ __device__ __forceinline__ void cg_replace_body(const Lat& lt, const CgBufs<R>& 
 __device__ __forceinline__ void cg_check_body(double* __restrict__ scal, int kpar, const double* __restrict__ part,
                                               int Nt, int restart, double* red) {
     double* sl = scal + S_NSLOT * kpar;
-    const int ip = ((int)sl[S_ITERS]) & 1;
+    const int ip = 0;  // the replacement's partials
     double pr[kNP];
     reduce_partials(part + kNP * (size_t)Nt * ip, Nt, whole_block_tile(nullptr, red), pr);
     const double a = pr[0], c = pr[5];

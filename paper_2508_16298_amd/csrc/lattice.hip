@@ -175,16 +175,16 @@ __global__ __launch_bounds__(BS) void k_apply_M(Lat lt, int dagger, const cplx<R
 
 // ---------------------------------------------------------------------------
 // Fused out = M^dag M in, slice by slice (mdagm_cells: three B applications,
-// the first two together).  Optionally writes the slice partial of
-// Re <in, out>.
+// the first two together).  gate (nullable): a CG slot's stop flag; the
+// launch runs only when it asks for a reliable update.
 // ---------------------------------------------------------------------------
 template <typename R, int MC, int NB, int BS>
 __global__ __launch_bounds__(BS) void k_mdagm(Lat lt, const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
                                               const cplx<R>* __restrict__ gauge, Coef<R> co,
-                                              double* __restrict__ pdot) {
+                                              const double* __restrict__ gate) {
+    if (gate && !gate_open(*gate)) return;
     extern __shared__ __align__(16) unsigned char smem[];
     cplx<R>* buf2 = reinterpret_cast<cplx<R>*>(smem);
-    double* red = reinterpret_cast<double*>(smem + (size_t)NB * 2 * lt.Vs * sizeof(cplx<R>));
     const int tau = slice_of_block(blockIdx.x, lt.Nt), Nt = lt.Nt;
     if (tau < 0) return;
     const int tm = tau == 0 ? Nt - 1 : tau - 1, tp = tau == Nt - 1 ? 0 : tau + 1;
@@ -204,17 +204,6 @@ __global__ __launch_bounds__(BS) void k_mdagm(Lat lt, const cplx<R>* __restrict_
     load_cells<R, MC>(vn, in + (size_t)tp * lt.Vs, g, own);
     mdagm_cells<R, MC, NB>(vm, vt, vn, hm, ht, g, own, co, eps_m, eps_t, buf2, lt.Vs, o);
     store_cells<R, MC>(o, out + (size_t)tau * lt.Vs, g, own);
-    if (pdot) {
-        double dot = 0.0;
-#pragma unroll
-        for (int m = 0; m < MC; m++)
-            if (own[m])
-#pragma unroll
-                for (int q = 0; q < 4; q++)
-                    dot += (double)vt.v[m][q].re * (double)o.v[m][q].re + (double)vt.v[m][q].im * (double)o.v[m][q].im;
-        const double sum = block_sum(dot, red);
-        if (threadIdx.x == 0) pdot[tau] = sum;
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -438,7 +427,7 @@ static qedhmc_status dispatch_shape(const Shape& s, F&& f) {
 }
 
 template <typename R>
-static qedhmc_status mdagm_t(qedhmc_ctx* h, const void* in, void* out, double* pdot) {
+static qedhmc_status mdagm_t(qedhmc_ctx* h, const void* in, void* out, const double* gate) {
     const Shape s = shape_of(h->lat);
     const size_t red = 32 * sizeof(double);
     const bool two = 4 * h->lat.Vs * sizeof(cplx<R>) + red <= h->max_lds;
@@ -450,10 +439,10 @@ static qedhmc_status mdagm_t(qedhmc_ctx* h, const void* in, void* out, double* p
             if (prof_sample(h, sizeof(R) == 4 ? QEDHMC_K_MDAGM_FP32 : QEDHMC_K_MDAGM_FP64, e0, e1))
                 hipExtLaunchKernelGGL((k_mdagm<R, MC, NB, BS>), dim3(slice_grid(h->lat.Nt)), dim3(s.nt), lds, h->stream, e0, e1,
                                       0, h->lat, (const cplx<R>*)in, (cplx<R>*)out, gauge_of<R>(h),
-                                      coef_of<R>(h->p), pdot);
+                                      coef_of<R>(h->p), gate);
             else
                 hipLaunchKernelGGL((k_mdagm<R, MC, NB, BS>), dim3(slice_grid(h->lat.Nt)), dim3(s.nt), lds, h->stream, h->lat,
-                                   (const cplx<R>*)in, (cplx<R>*)out, gauge_of<R>(h), coef_of<R>(h->p), pdot);
+                                   (const cplx<R>*)in, (cplx<R>*)out, gauge_of<R>(h), coef_of<R>(h->p), gate);
             QH_HIP(hipGetLastError());
             return QEDHMC_OK;
         };
@@ -466,8 +455,8 @@ static qedhmc_status mdagm_t(qedhmc_ctx* h, const void* in, void* out, double* p
 // =tiled (read per call) forces one form where it can run.
 static constexpr int kTiledFrom = 1024;
 
-static bool use_tiled(const qedhmc_ctx* h, const double* pdot) {
-    if (pdot) return false;
+static bool use_tiled(const qedhmc_ctx* h, const double* gate) {
+    if (gate) return false;
     const bool fits = h->lat.ncell <= 1152;
     const char* e = std::getenv("QEDHMC_MDAGM");
     if (e && std::strcmp(e, "slice") == 0 && fits) return false;
@@ -475,9 +464,9 @@ static bool use_tiled(const qedhmc_ctx* h, const double* pdot) {
     return !fits || h->lat.ncell > kTiledFrom;
 }
 
-qedhmc_status launch_mdagm(qedhmc_ctx* h, qedhmc_precision prec, const void* in, void* out, double* pdot) {
-    if (use_tiled(h, pdot)) return launch_mdagm_tiled(h, prec, in, out);
-    return prec == QEDHMC_FP64 ? mdagm_t<double>(h, in, out, pdot) : mdagm_t<float>(h, in, out, pdot);
+qedhmc_status launch_mdagm(qedhmc_ctx* h, qedhmc_precision prec, const void* in, void* out, const double* gate) {
+    if (use_tiled(h, gate)) return launch_mdagm_tiled(h, prec, in, out);
+    return prec == QEDHMC_FP64 ? mdagm_t<double>(h, in, out, gate) : mdagm_t<float>(h, in, out, gate);
 }
 
 template <typename R>

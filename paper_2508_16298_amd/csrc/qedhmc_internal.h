@@ -401,6 +401,12 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
     return v;
 }
 
+// A CG slot's stop flag asks for a reliable update: stop (1), pause (2),
+// pause with restart (3) or iteration budget used (6).
+__host__ __device__ __forceinline__ bool gate_open(double flag) {
+    return flag == 1.0 || flag == 2.0 || flag == 3.0 || flag == 6.0;
+}
+
 // Fixed-order block reduction of one double per thread (deterministic for a
 // fixed block size).  red: LDS scratch of at least blockDim/64 doubles.
 __device__ __forceinline__ double block_sum(double x, double* red) {
@@ -479,9 +485,10 @@ struct qedhmc_ctx {
         const void* x;
         const void* rhs;
         double tol2;
-        int mixed, count;
+        int mixed, count, maxit;
     } cg_graph[2][2][2];
     hipStream_t cap_stream;
+    hipEvent_t cg_ev[2];  // the pipelined mixed CG: one per round in flight
     // the paper's preconditioner (built on first use)
     bool pc_ready;
     double pc_shift;
@@ -523,9 +530,10 @@ qedhmc_status prof_drain(qedhmc_ctx* h);
 qedhmc_status ensure_gauge(qedhmc_ctx* h, const double* theta, qedhmc_precision prec);
 qedhmc_status launch_apply_M(qedhmc_ctx* h, qedhmc_precision prec, const void* in, void* out, int dagger);
 qedhmc_status launch_apply_B(qedhmc_ctx* h, qedhmc_precision prec, int tau, const void* in, void* out);
-// out = M^dag M in; if pdot != nullptr the per-slice partials of Re<in, out>
-// are written to pdot[0..Nt).
-qedhmc_status launch_mdagm(qedhmc_ctx* h, qedhmc_precision prec, const void* in, void* out, double* pdot);
+// out = M^dag M in; gate (nullable): a CG slot's stop flag, the launch runs
+// only when the flag asks for a reliable update (1, 2 or 3; see gate_open)
+qedhmc_status launch_mdagm(qedhmc_ctx* h, qedhmc_precision prec, const void* in, void* out,
+                           const double* gate = nullptr);
 qedhmc_status launch_force(qedhmc_ctx* h, qedhmc_precision prec, const double* X, double* F);
 // out = M^dag M in by spatial tiles streamed along tau (mdagm_tiled.hip)
 qedhmc_status launch_mdagm_tiled(qedhmc_ctx* h, qedhmc_precision prec, const void* in, void* out);
