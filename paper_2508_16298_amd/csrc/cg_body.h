@@ -133,6 +133,10 @@ __device__ __forceinline__ void cg_iter_body(const Lat& lt, const CgBufs<R>& B, 
     cplx<R> hm[MC][12], ht[MC][12];
     hops_of<R, MC>(gauge, lt, c.tm, c.idx, co, hm);
     hops_of<R, MC>(gauge, lt, c.tau, c.idx, co, ht);
+    // x is read here with the rest (its update comes after stores that the
+    // compiler cannot tell apart from x, which would hold the read back)
+    Cells<double, MC> xo;
+    load_cells<double, MC>(xo, B.x + c.tau * Vs, c.g, c.own);
     if (done != 0.0 || it >= maxit) {
         // stopped or paused: carry the state over; a running solve that used
         // its iteration budget is marked for its final true residual (6)
@@ -209,15 +213,12 @@ __device__ __forceinline__ void cg_iter_body(const Lat& lt, const CgBufs<R>& B, 
     // x_{i+1} = x_i + alpha p_i in FP64
 #pragma unroll
     for (int m = 0; m < MC; m++)
-        if (c.own[m])
 #pragma unroll
-            for (int q = 0; q < 4; q++) {
-                cplx<double>* xp = B.x + c.tau * Vs + c.g[m].s[q];
-                cplx<double> xv = *xp;
-                xv.re += alpha * (double)pp.v[m][q].re;
-                xv.im += alpha * (double)pp.v[m][q].im;
-                *xp = xv;
-            }
+        for (int q = 0; q < 4; q++) {
+            xo.v[m][q].re += alpha * (double)pp.v[m][q].re;
+            xo.v[m][q].im += alpha * (double)pp.v[m][q].im;
+        }
+    store_cells<double, MC>(xo, B.x + c.tau * Vs, c.g, c.own);
     const Cells<R, MC> rnew = rt;
     Cells<R, MC> w;
     mdagm_cells<R, MC, NB>(rm, rt, rn, hm, ht, c.g, c.own, co, c.tau == 0 ? R(-1) : R(1),

@@ -128,9 +128,23 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ part,
     double v[kNP];
 #pragma unroll
     for (int k = 0; k < kNP; k++) v[k] = 0.0;
-    for (int t = threadIdx.x; t < Nt; t += blockDim.x)
+    // tuples t, t + blockDim, ... in that order; up to four of them are
+    // loaded before any is added, so a workgroup smaller than Nt waits for
+    // memory once rather than once per tuple
+    constexpr int U = 4;
+    for (int t0 = threadIdx.x; t0 < Nt; t0 += U * blockDim.x) {
+        double a[U][kNP];
 #pragma unroll
-        for (int k = 0; k < kNP; k++) v[k] += part[kNP * t + k];
+        for (int u = 0; u < U; u++) {
+            const int t = t0 + u * (int)blockDim.x;
+#pragma unroll
+            for (int k = 0; k < kNP; k++) a[u][k] = t < Nt ? part[kNP * t + k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int k = 0; k < kNP; k++) v[k] += a[u][k];
+    }
     block_sumk<kNP>(v, tl.red);
     double* bc = tl.red + kNP * 16;
     if (threadIdx.x == 0)
