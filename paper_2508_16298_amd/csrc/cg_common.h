@@ -198,11 +198,12 @@ __device__ __forceinline__ void slice_ctx(const Lat& lt, SliceCtx<MC>& c, int ta
     }
 }
 
+// normalised (tanh-scaled) hops of slice tau, as mdagm_cells takes them
 template <typename R, int MC>
 __device__ __forceinline__ void hops_of(const cplx<R>* __restrict__ gauge, const Lat& lt, int tau,
                                         const int (&idx)[MC][12], const Coef<R>& co, cplx<R> (&h)[MC][12]) {
 #pragma unroll
-    for (int m = 0; m < MC; m++) load_hops(gauge, lt, tau, idx[m], co, h[m]);
+    for (int m = 0; m < MC; m++) load_hops<R, true>(gauge, lt, tau, idx[m], co, h[m]);
 }
 
 // c = (R)(a - b) (b may be null); sq += |a - b|^2 in FP64 over owned cells

@@ -12,15 +12,21 @@
 
 namespace qh {
 
+// computed in FP64, rounded once to the working precision
+template <typename R>
+static Coef<R> coef_rounded(const qedhmc_params& p) {
+    const double h = 0.5 * p.t * p.dtau, c1 = std::cosh(h);
+    const double C = c1 * c1 * c1 * c1 * c1 * c1 * std::cosh(2 * h);
+    return {(R)c1, (R)std::sinh(h), (R)std::cosh(2 * h), (R)std::sinh(2 * h),
+            (R)std::tanh(h), (R)std::tanh(2 * h), (R)C};
+}
 template <>
 Coef<double> coef_of<double>(const qedhmc_params& p) {
-    const double h = 0.5 * p.t * p.dtau;
-    return {std::cosh(h), std::sinh(h), std::cosh(2 * h), std::sinh(2 * h)};
+    return coef_rounded<double>(p);
 }
 template <>
 Coef<float> coef_of<float>(const qedhmc_params& p) {
-    const double h = 0.5 * p.t * p.dtau;
-    return {(float)std::cosh(h), (float)std::sinh(h), (float)std::cosh(2 * h), (float)std::sinh(2 * h)};
+    return coef_rounded<float>(p);
 }
 
 // ---------------------------------------------------------------------------
@@ -103,11 +109,11 @@ __device__ __forceinline__ void my_cells(const Lat& lt, CellGeo (&g)[MC], bool (
     }
 }
 
-template <typename R, int MC>
+template <typename R, int MC, bool TN = false>
 __device__ __forceinline__ void load_hops_all(const cplx<R>* __restrict__ gauge, const Lat& lt, int tau,
                                               const int (&idx)[MC][12], const Coef<R>& co, cplx<R> (&h)[MC][12]) {
 #pragma unroll
-    for (int m = 0; m < MC; m++) load_hops(gauge, lt, tau, idx[m], co, h[m]);
+    for (int m = 0; m < MC; m++) load_hops<R, TN>(gauge, lt, tau, idx[m], co, h[m]);
 }
 
 // ---------------------------------------------------------------------------
@@ -197,8 +203,8 @@ __global__ __launch_bounds__(BS) void k_mdagm(Lat lt, const cplx<R>* __restrict_
     my_cells<MC>(lt, g, own, idx);
     cplx<R> hm[MC][12], ht[MC][12];
     Cells<R, MC> vm, vt, vn, o;
-    load_hops_all<R, MC>(gauge, lt, tm, idx, co, hm);
-    load_hops_all<R, MC>(gauge, lt, tau, idx, co, ht);
+    load_hops_all<R, MC, true>(gauge, lt, tm, idx, co, hm);
+    load_hops_all<R, MC, true>(gauge, lt, tau, idx, co, ht);
     load_cells<R, MC>(vm, in + (size_t)tm * lt.Vs, g, own);
     load_cells<R, MC>(vt, in + (size_t)tau * lt.Vs, g, own);
     load_cells<R, MC>(vn, in + (size_t)tp * lt.Vs, g, own);

@@ -77,10 +77,15 @@ __device__ __forceinline__ int slice_of_block(int b, int Nt) {
 }
 
 // Hopping coefficients of one bond factor: cosh/sinh of the half step h and
-// of the merged central step 2h (Eq. 24).
+// of the merged central step 2h (Eq. 24); and the normalised form used by the
+// fused M^dag M: every site lies on exactly one bond of each family, so each
+// factor is cosh(a) times (v_i, v_j) -> (v_i + tanh(a) e^{i theta} v_j,
+// v_j + tanh(a) e^{-i theta} v_i), and B_tau = C B'_tau with
+// C = cosh(h)^6 cosh(2h).
 template <typename R>
 struct Coef {
     R c1, s1, c2, s2;
+    R t1, t2, C;  // tanh(h), tanh(2h), cosh(h)^6 cosh(2h)
 };
 
 // Static geometry of one 2x2 cell (site indices inside a slice).
@@ -90,6 +95,8 @@ struct CellGeo {
     int l1, l3;              // -x neighbour's sites 1 and 3
     int u0, u1;              // +y neighbour's sites 0 and 1
     int d2, d3;              // -y neighbour's sites 2 and 3
+    int c;                   // own cell index (cy * L/2 + cx)
+    int xp, xm, yp, ym;      // cell indices of the four neighbour cells
 };
 
 __device__ __forceinline__ int wrap(int x, int L) { return x < 0 ? x + L : (x >= L ? x - L : x); }
@@ -112,6 +119,12 @@ __device__ __forceinline__ CellGeo cell_geo(int cell, const Lat& lt) {
     g.u1 = yu * L + x0 + 1;
     g.d2 = yd * L + x0;
     g.d3 = yd * L + x0 + 1;
+    const int h = lt.hL;
+    g.c = cell;
+    g.xp = b * h + (a + 1 == h ? 0 : a + 1);
+    g.xm = b * h + (a == 0 ? h - 1 : a - 1);
+    g.yp = (b + 1 == h ? 0 : b + 1) * h + a;
+    g.ym = (b == 0 ? h - 1 : b - 1) * h + a;
     return g;
 }
 
@@ -137,9 +150,10 @@ __device__ __forceinline__ void phase_index(const CellGeo& g, int Vs, int (&idx)
     idx[11] = Vs + g.d3;
 }
 
-// Load the scaled hopping terms h_k = sinh(a_k) e^{i theta_k} of one slice:
-// gauge is [2][Nt][Vs]; idx (from phase_index) packs d*Vs + s.
-template <typename R>
+// Load the scaled hopping terms h_k = sinh(a_k) e^{i theta_k} of one slice
+// (TN: tanh(a_k) e^{i theta_k}, the normalised factors): gauge is
+// [2][Nt][Vs]; idx (from phase_index) packs d*Vs + s.
+template <typename R, bool TN = false>
 __device__ __forceinline__ void load_hops(const cplx<R>* __restrict__ gauge, const Lat& lt, int tau,
                                           const int (&idx)[12], const Coef<R>& co, cplx<R> (&h)[12]) {
 #pragma unroll
@@ -148,7 +162,7 @@ __device__ __forceinline__ void load_hops(const cplx<R>* __restrict__ gauge, con
         const int d = id >= lt.Vs ? 1 : 0;
         const int s = id - d * lt.Vs;
         const cplx<R> e = gauge[((size_t)d * lt.Nt + tau) * lt.Vs + s];
-        const R sc = (k < 2) ? co.s2 : co.s1;
+        const R sc = TN ? ((k < 2) ? co.t2 : co.t1) : ((k < 2) ? co.s2 : co.s1);
         h[k] = mk<R>(sc * e.re, sc * e.im);
     }
 }
@@ -259,99 +273,147 @@ __device__ __forceinline__ void apply_B_cells(Cells<R, MC>& c, const cplx<R> (&h
     cross_sweep<R, MC, NB, false>(c, h, g, own, co.c1, xb);
 }
 
-// Two independent cross sweeps (vector a with hops ha, vector b with hops
-// hb) sharing one LDS round trip: a uses the first Vs entries of the buffer
-// and b the next Vs.  Buffers of 2 Vs values alternate as in Xchg (NB = 2) or
-// are closed by a second barrier (NB = 1).
-template <typename R, int MC, int NB, bool X>
-__device__ __forceinline__ void cross_sweep2(Cells<R, MC>& a, const cplx<R> (&ha)[MC][12], Cells<R, MC>& b,
-                                             const cplx<R> (&hb)[MC][12], const CellGeo (&g)[MC],
-                                             const bool (&own)[MC], R cc, cplx<R>* buf2, int Vs, int& k) {
-    cplx<R>* ba = buf2 + (size_t)(NB == 2 ? k : 0) * 2 * Vs;
-    cplx<R>* bb = ba + Vs;
+// ---------------------------------------------------------------------------
+// The fused M^dag M in normalised factors (tanh-scaled hops from
+// load_hops<R, true>): four FMAs per site and sweep, C folded into the
+// combinations.  Exchange buffers hold the four sites of every cell as four
+// planes (site q of cell c at q * ncell + c), so a wavefront's writes and each
+// of its neighbour reads are contiguous.
+// ---------------------------------------------------------------------------
+// v + h w and v + conj(h) w
+template <typename R>
+__device__ __forceinline__ cplx<R> add_hw(cplx<R> v, cplx<R> h, cplx<R> w) {
+    return mk<R>(v.re + h.re * w.re - h.im * w.im, v.im + h.re * w.im + h.im * w.re);
+}
+template <typename R>
+__device__ __forceinline__ cplx<R> add_hcw(cplx<R> v, cplx<R> h, cplx<R> w) {
+    return mk<R>(v.re + h.re * w.re + h.im * w.im, v.im + h.re * w.im - h.im * w.re);
+}
+
+// In-cell normalised factor: f0 (F = 0, pairs (0,1), (2,3)) or f2 (F = 2,
+// pairs (0,2), (1,3)).
+template <typename R, int F>
+__device__ __forceinline__ void sweep_in_n(cplx<R> (&v)[4], const cplx<R> (&h)[12]) {
+    const cplx<R> a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3];
+    if constexpr (F == 0) {
+        v[0] = add_hw(a0, h[0], a1);
+        v[1] = add_hcw(a1, h[0], a0);
+        v[2] = add_hw(a2, h[1], a3);
+        v[3] = add_hcw(a3, h[1], a2);
+    } else {
+        v[0] = add_hw(a0, h[4], a2);
+        v[2] = add_hcw(a2, h[4], a0);
+        v[1] = add_hw(a1, h[5], a3);
+        v[3] = add_hcw(a3, h[5], a1);
+    }
+}
+
+// Cross-cell normalised factor f1 (X) or f3 of one cell, the neighbours'
+// pre-sweep values read from the plane buffer b.
+template <typename R, bool X>
+__device__ __forceinline__ void sweep_cross_n(cplx<R> (&v)[4], const cplx<R> (&h)[12], const cplx<R>* b, int nc,
+                                              const CellGeo& g) {
+    const cplx<R> a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3];
+    if constexpr (X) {
+        const cplx<R> R0 = b[g.xp], R2 = b[2 * nc + g.xp], L1 = b[nc + g.xm], L3 = b[3 * nc + g.xm];
+        v[1] = add_hw(a1, h[2], R0);
+        v[3] = add_hw(a3, h[3], R2);
+        v[0] = add_hcw(a0, h[8], L1);
+        v[2] = add_hcw(a2, h[9], L3);
+    } else {
+        const cplx<R> U0 = b[g.yp], U1 = b[nc + g.yp], D2 = b[2 * nc + g.ym], D3 = b[3 * nc + g.ym];
+        v[2] = add_hw(a2, h[6], U0);
+        v[3] = add_hw(a3, h[7], U1);
+        v[0] = add_hcw(a0, h[10], D2);
+        v[1] = add_hcw(a1, h[11], D3);
+    }
+}
+
+// One cross family on NV vectors (1 or 2) sharing one LDS round trip.
+// Buffers of 8 * nc values (2 * Vs) alternate with k (NB = 2, one barrier per
+// sweep) or are closed by a second barrier (NB = 1).
+template <typename R, int MC, int NB, bool X, int NV>
+__device__ __forceinline__ void cross_n(Cells<R, MC>* const (&v)[NV], const cplx<R> (*const (&h)[NV])[MC][12],
+                                        const CellGeo (&g)[MC], const bool (&own)[MC], int nc, cplx<R>* buf,
+                                        int& k) {
+    cplx<R>* b = buf + (size_t)(NB == 2 ? k : 0) * 8 * nc;
     k ^= 1;
 #pragma unroll
-    for (int m = 0; m < MC; m++)
-        if (own[m]) {
+    for (int j = 0; j < NV; j++)
 #pragma unroll
-            for (int q = 0; q < 4; q++) {
-                ba[g[m].s[q]] = a.v[m][q];
-                bb[g[m].s[q]] = b.v[m][q];
-            }
-        }
+        for (int m = 0; m < MC; m++)
+            if (own[m])
+#pragma unroll
+                for (int q = 0; q < 4; q++) b[(4 * j + q) * nc + g[m].c] = v[j]->v[m][q];
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < MC; m++)
-        if (own[m]) {
-            if (X) {
-                sweep_f1(a.v[m], ha[m], cc, ba[g[m].r0], ba[g[m].r2], ba[g[m].l1], ba[g[m].l3]);
-                sweep_f1(b.v[m], hb[m], cc, bb[g[m].r0], bb[g[m].r2], bb[g[m].l1], bb[g[m].l3]);
-            } else {
-                sweep_f3(a.v[m], ha[m], cc, ba[g[m].u0], ba[g[m].u1], ba[g[m].d2], ba[g[m].d3]);
-                sweep_f3(b.v[m], hb[m], cc, bb[g[m].u0], bb[g[m].u1], bb[g[m].d2], bb[g[m].d3]);
-            }
-        }
+    for (int j = 0; j < NV; j++)
+#pragma unroll
+        for (int m = 0; m < MC; m++)
+            if (own[m]) sweep_cross_n<R, X>(v[j]->v[m], (*h[j])[m], b + 4 * j * nc, nc, g[m]);
     if (NB == 1) __syncthreads();
 }
 
-// B_{tau-1} a and B_tau b applied together (Eq. 24 factor order on both).
-template <typename R, int MC, int NB>
-__device__ __forceinline__ void apply_B2_cells(Cells<R, MC>& a, const cplx<R> (&ha)[MC][12], Cells<R, MC>& b,
-                                               const cplx<R> (&hb)[MC][12], const CellGeo (&g)[MC],
-                                               const bool (&own)[MC], const Coef<R>& co, cplx<R>* buf2, int Vs,
-                                               int& k) {
-    cross_sweep2<R, MC, NB, false>(a, ha, b, hb, g, own, co.c1, buf2, Vs, k);
+// B'_tau on NV vectors at once (factor order of Eq. 24: E3 E2 E1 E0(2h) E1 E2 E3).
+template <typename R, int MC, int NB, int NV>
+__device__ __forceinline__ void apply_Bn(Cells<R, MC>* const (&v)[NV], const cplx<R> (*const (&h)[NV])[MC][12],
+                                         const CellGeo (&g)[MC], const bool (&own)[MC], int nc, cplx<R>* buf,
+                                         int& k) {
+    cross_n<R, MC, NB, false, NV>(v, h, g, own, nc, buf, k);
 #pragma unroll
-    for (int m = 0; m < MC; m++) {
-        sweep_f2(a.v[m], ha[m], co.c1);
-        sweep_f2(b.v[m], hb[m], co.c1);
-    }
-    cross_sweep2<R, MC, NB, true>(a, ha, b, hb, g, own, co.c1, buf2, Vs, k);
+    for (int j = 0; j < NV; j++)
 #pragma unroll
-    for (int m = 0; m < MC; m++) {
-        sweep_f0(a.v[m], ha[m], co.c2);
-        sweep_f0(b.v[m], hb[m], co.c2);
-    }
-    cross_sweep2<R, MC, NB, true>(a, ha, b, hb, g, own, co.c1, buf2, Vs, k);
+        for (int m = 0; m < MC; m++) sweep_in_n<R, 2>(v[j]->v[m], (*h[j])[m]);
+    cross_n<R, MC, NB, true, NV>(v, h, g, own, nc, buf, k);
 #pragma unroll
-    for (int m = 0; m < MC; m++) {
-        sweep_f2(a.v[m], ha[m], co.c1);
-        sweep_f2(b.v[m], hb[m], co.c1);
-    }
-    cross_sweep2<R, MC, NB, false>(a, ha, b, hb, g, own, co.c1, buf2, Vs, k);
+    for (int j = 0; j < NV; j++)
+#pragma unroll
+        for (int m = 0; m < MC; m++) sweep_in_n<R, 0>(v[j]->v[m], (*h[j])[m]);
+    cross_n<R, MC, NB, true, NV>(v, h, g, own, nc, buf, k);
+#pragma unroll
+    for (int j = 0; j < NV; j++)
+#pragma unroll
+        for (int m = 0; m < MC; m++) sweep_in_n<R, 2>(v[j]->v[m], (*h[j])[m]);
+    cross_n<R, MC, NB, false, NV>(v, h, g, own, nc, buf, k);
 }
 
 // Fused M^dag M on the cells of slice tau given the cells of the input at
-// tau-1 (vm), tau (vt), tau+1 (vn) and the hops of slices tau-1 (hm) and tau
-// (ht):
-//   out = vt - eps_{tau-1} B_{tau-1} vm + B_tau (B_tau vt - eps_tau vn),
+// tau-1 (vm), tau (vt), tau+1 (vn) and the normalised hops of slices tau-1
+// (hm) and tau (ht):
+//   out = vt - eps_{tau-1} C B'_{tau-1} vm + C B'_tau (C B'_tau vt - eps_tau vn),
 // the definition M^dag (M v) expanded with eps^2 = 1 (eps_{Nt-1} = -1 at the
-// antiperiodic corner, +1 elsewhere).  B_{tau-1} vm and B_tau vt run together.
-// vm is consumed.  buf2: LDS of NB * 2 * Vs values.
+// antiperiodic corner, +1 elsewhere).  B'_{tau-1} vm and B'_tau vt run
+// together.  vm is consumed.  buf2: LDS of NB * 2 * Vs values.
 template <typename R, int MC, int NB>
 __device__ __forceinline__ void mdagm_cells(Cells<R, MC>& vm, const Cells<R, MC>& vt, const Cells<R, MC>& vn,
                                             const cplx<R> (&hm)[MC][12], const cplx<R> (&ht)[MC][12],
                                             const CellGeo (&g)[MC], const bool (&own)[MC], const Coef<R>& co,
                                             R eps_m, R eps_t, cplx<R>* buf2, int Vs, Cells<R, MC>& out) {
+    const int nc = Vs >> 2;
+    const R C = co.C;
     int k = 0;
     Cells<R, MC> t = vt;
-    apply_B2_cells<R, MC, NB>(vm, hm, t, ht, g, own, co, buf2, Vs, k);
+    {
+        Cells<R, MC>* const v[2] = {&vm, &t};
+        const cplx<R>(*const h[2])[MC][12] = {&hm, &ht};
+        apply_Bn<R, MC, NB, 2>(v, h, g, own, nc, buf2, k);
+    }
 #pragma unroll
     for (int m = 0; m < MC; m++)
 #pragma unroll
         for (int q = 0; q < 4; q++) {
-            out.v[m][q] = cfma(-eps_m, vm.v[m][q], vt.v[m][q]);
-            t.v[m][q] = cfma(-eps_t, vn.v[m][q], t.v[m][q]);
+            out.v[m][q] = cfma(-eps_m * C, vm.v[m][q], vt.v[m][q]);
+            t.v[m][q] = mk<R>(C * t.v[m][q].re - eps_t * vn.v[m][q].re, C * t.v[m][q].im - eps_t * vn.v[m][q].im);
         }
-    // third B_tau on t: reuse the pair sweep with a dummy second vector
-    // would double the LDS traffic, so use the single-vector form on the
-    // first half of the pair buffers.
-    Xchg<R, NB> xb{buf2, 2 * Vs, k};
-    apply_B_cells<R, MC, NB>(t, ht, g, own, co, xb);
+    {
+        Cells<R, MC>* const v[1] = {&t};
+        const cplx<R>(*const h[1])[MC][12] = {&ht};
+        apply_Bn<R, MC, NB, 1>(v, h, g, own, nc, buf2, k);
+    }
 #pragma unroll
     for (int m = 0; m < MC; m++)
 #pragma unroll
-        for (int q = 0; q < 4; q++) out.v[m][q] = cadd(out.v[m][q], t.v[m][q]);
+        for (int q = 0; q < 4; q++) out.v[m][q] = cfma(C, t.v[m][q], out.v[m][q]);
 }
 
 template <typename R, int MC>
