@@ -87,6 +87,7 @@ qedhmc_status qedhmc_init_lattice(const qedhmc_params* params, void* stream, qed
     hipError_t e = hipGetDevice(&h->device);
     int lds = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, h->device);
     if (e != hipSuccess) {
         delete h;
         return hip_fail(e, "hipGetDevice / attribute");

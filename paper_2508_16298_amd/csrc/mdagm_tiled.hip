@@ -409,12 +409,36 @@ struct TiledPlan {
     int threads;
 };
 
+// Run length: each workgroup walks Tc slices (plus one B application for
+// y_{tau0}), and the workgroups run in rounds of `slots` (the workgroups the
+// device holds at once), so a pass costs about rounds x (Tc + 1/2) slice
+// steps; the smallest such Tc is taken.  Counting rounds matters: a last
+// round that is only partly filled costs as much as a full one.
+static void set_run_length(TiledGeo& g, int tc, int slots) {
+    const int ntile = g.ntx * g.nty;
+    if (tc <= 0) {
+        double best = 0.0;
+        tc = 1;
+        for (int c = 1; c <= std::min(g.Nt, 64); c++) {
+            const long nwork = (long)ntile * ((g.Nt + c - 1) / c);
+            const long rounds = (nwork + slots - 1) / slots;
+            const double cost = (double)rounds * (c + 0.5);
+            if (c == 1 || cost < best) {
+                best = cost;
+                tc = c;
+            }
+        }
+    }
+    g.Tc = std::min(tc, g.Nt);
+    g.nchunk = (g.Nt + g.Tc - 1) / g.Tc;
+    g.nwork = ntile * g.nchunk;
+}
+
 // Region shape for a slice of hL x hL cells and a cap of `cap` threads (one
 // per region cell): the whole slice when it fits; else full x rings with a y
 // halo (strips) while a strip of at least four output rows fits; else square
-// tiles with halos both ways.  The run length Tc aims at about two workgroups
-// per compute unit.
-static TiledPlan plan_tiled(const Lat& lt, int tc_override, int cap) {
+// tiles with halos both ways.  The run length is set later (set_run_length).
+static TiledPlan plan_tiled(const Lat& lt, int cap) {
     TiledPlan p{};
     TiledGeo& g = p.g;
     g.L = lt.L;
@@ -448,12 +472,6 @@ static TiledPlan plan_tiled(const Lat& lt, int tc_override, int cap) {
         g.hx = g.hy = 4;
         g.RW = g.RH = g.TX + 8;
     }
-    const int ntile = g.ntx * g.nty;
-    int tc = tc_override;
-    if (tc <= 0) tc = std::max(1, std::min(16, (lt.Nt * ntile + 256) / 512));
-    g.Tc = std::min(tc, lt.Nt);
-    g.nchunk = (lt.Nt + g.Tc - 1) / g.Tc;
-    g.nwork = ntile * g.nchunk;
     p.threads = ((g.RW * g.RH + 63) / 64) * 64;
     return p;
 }
@@ -472,29 +490,30 @@ static int env_int(const char* name, int dflt) {
     return s ? std::atoi(s) : dflt;
 }
 
-// The plan of precision R: the tuning variables apply to the plain operator
-// only; the CG form always takes the default plan (its partial buffer is
-// sized for it).  FP64 runs 16 slices per workgroup by default (fastest at
-// L = 66 and 128 in a sweep of run lengths); FP32 takes the plan's default.
+// The region plan of precision R (the run length is set at launch): the
+// tuning variables apply to the plain operator only; the CG form always takes
+// the default plan (its partial buffer is sized for it).
 template <typename R>
-static TiledPlan plan_for(const Lat& lt, bool tunable) {
-    int cap = kTileMaxThreads<R>, tc = 0;
+static TiledPlan plan_for(const Lat& lt, bool tunable, int* tc) {
+    int cap = kTileMaxThreads<R>;
+    *tc = 0;
     if (tunable) {
         cap = std::max(100, std::min(kTileMaxThreads<R>, env_int("QEDHMC_TILE_THREADS", 1024)));
-        tc = env_int("QEDHMC_TILE_TC", 0);
+        *tc = env_int("QEDHMC_TILE_TC", 0);
     }
-    if (tc <= 0 && sizeof(R) == 8) tc = 16;
-    return plan_tiled(lt, tc, cap);
+    return plan_tiled(lt, cap);
 }
 
 int mdagm_tiled_tiles(const Lat& lt, bool fp64) {
-    const TiledPlan p = fp64 ? plan_for<double>(lt, false) : plan_for<float>(lt, false);
+    int tc;
+    const TiledPlan p = fp64 ? plan_for<double>(lt, false, &tc) : plan_for<float>(lt, false, &tc);
     return p.g.ntx * p.g.nty;
 }
 
 template <typename R, bool PART>
 static qedhmc_status mdagm_tiled_t(qedhmc_ctx* h, const void* in, void* out, const TPart<R>& tpart) {
-    const TiledPlan p = plan_for<R>(h->lat, !PART);
+    int tc;
+    TiledPlan p = plan_for<R>(h->lat, !PART, &tc);
     const size_t lds = (size_t)8 * p.g.RW * p.g.RH * sizeof(cplx<R>) + (PART ? 16 * kTileParts * sizeof(double) : 0);
     if (lds > h->max_lds) {
         set_error("tiled M^dag M: exchange buffers exceed the workgroup's LDS");
@@ -503,10 +522,13 @@ static qedhmc_status mdagm_tiled_t(qedhmc_ctx* h, const void* in, void* out, con
     const cplx<R>* gauge = sizeof(R) == 8 ? reinterpret_cast<const cplx<R>*>(h->gauge64)
                                           : reinterpret_cast<const cplx<R>*>(h->gauge32);
     const TCoef<R> co = tcoef_of<R>(h->p);
-    const int grid = 8 * ((p.g.nwork + 7) / 8);
     auto go = [&](auto kern) -> qedhmc_status {
         if (lds > 65536)
             QH_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        int per_cu = 0;
+        QH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, p.threads, lds));
+        set_run_length(p.g, tc, std::max(1, per_cu) * std::max(1, h->n_cu));
+        const int grid = 8 * ((p.g.nwork + 7) / 8);
         hipEvent_t e0, e1;
         const int cls = PART ? (sizeof(R) == 4 ? QEDHMC_K_PCG_MV_FP32 : QEDHMC_K_PCG_MV_FP64)
                              : (sizeof(R) == 4 ? QEDHMC_K_MDAGM_FP32 : QEDHMC_K_MDAGM_FP64);

@@ -510,6 +510,7 @@ struct qedhmc_ctx {
     hipStream_t stream;
     int device;
     size_t max_lds;
+    int n_cu;  // compute units of the device
     int32_t* d_tables;          // [4][Vs/2][3]
     // working-precision gauge caches e^{i theta}
     qh::cplx<double>* gauge64;
