@@ -40,7 +40,7 @@ HBM_PEAK_GBS = 8000.0
 # (profiles/k_cg_iter_mixed_l24_hbm_counters.md): FETCH_SIZE and WRITE_SIZE in
 # KiB, scaled by the copy-kernel calibration (x2.0 and x1.0).  Valid for the
 # kernel as measured there; set to None whenever k_cg_iter changes.
-CG_ITER_COUNTER_BYTES = {"fp32": (4643.5 * 2.0 + 6491.4 * 1.0) * 1024, "fp64": None}
+CG_ITER_COUNTER_BYTES = {"fp32": (4652.0 * 2.0 + 6491.4 * 1.0) * 1024, "fp64": None}
 
 
 def parse():
