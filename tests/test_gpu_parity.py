@@ -174,6 +174,43 @@ def test_cg_edge_cases():
             lat.cg_solve(_dev(th), _dev(eta), tol=-1.0)
 
 
+def test_cg_mixed_device_decided_edge_cases():
+    """The mixed solve whose reliable updates are decided on the device
+    (rounds of 51 launches, the next one queued behind the running one) gives
+    bitwise what the host-driven loop gives: a zero right-hand side (no
+    iteration), an iteration budget inside the first round and across rounds
+    (ENOCONV with exactly maxit iterations), and a loose tolerance met after a
+    few iterations."""
+    import os
+    L, Nt = 6, 10
+    th = inputs.hot_start_theta(L, Nt, 7)
+    eta = inputs.gauss_cvec(L, Nt, 8)
+    zero = np.zeros((Nt, L, L), complex)
+    cases = [(zero, 1e-8, 1000), (eta, 1e-14, 3), (eta, 1e-14, 75), (eta, 1e-14, 102), (eta, 1e-2, 1000)]
+    out = {}
+    with Q.Lattice(L, Nt) as lat:
+        for mode in ("device", "host"):
+            if mode == "host":
+                os.environ["QEDHMC_NO_GRAPH"] = "1"
+            try:
+                for i, (rhs, tol, maxit) in enumerate(cases):
+                    x, st, it, rel = lat.cg_solve(_dev(th), _dev(rhs), tol=tol, maxit=maxit, prec="fp32")
+                    out[mode, i] = (_host(x), st, it, rel)
+            finally:
+                os.environ.pop("QEDHMC_NO_GRAPH", None)
+    for i, (rhs, tol, maxit) in enumerate(cases):
+        xd, sd, itd, reld = out["device", i]
+        xh, sh, ith, relh = out["host", i]
+        print(f"case {i}: tol {tol:g} maxit {maxit}: {sd} {itd} {reld:.3e} | host {sh} {ith} {relh:.3e}", flush=True)
+        assert (sd, itd, reld) == (sh, ith, relh)
+        assert np.array_equal(xd, xh)
+    assert out["device", 0][1] == Q.OK and out["device", 0][2] == 0 and np.abs(out["device", 0][0]).max() == 0
+    for i in (1, 2, 3):
+        assert out["device", i][1] == Q.ENOCONV and out["device", i][2] == cases[i][2]
+    xd, sd, itd, reld = out["device", 4]
+    assert sd == Q.OK and itd > 0 and reld <= 1e-2
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-8)])
 def test_cg_solve_at_full_sizes(prec, tol):
     """L=12, Nt=120 and L=24, Nt=240 from a hot start (the hardest first
