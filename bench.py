@@ -21,9 +21,11 @@ bandwidth is measured after the timed region on the standalone fused
 M^dag M kernel at 24 B per site (v in, out written, two FP32 angles; 48 B in
 FP64): the start/end events of each of 200 dispatches (the events' own
 cost included; rocprofv3's kernel-only duration is in profiles/).
-The CPU baseline is the plain FP64 oracle on a bounded sample (a fixed
-number of CG iterations plus one force at the same lattice), scaled to the
-trajectory's measured CG iteration count.
+`fp64_path` times the plain FP64 GPU path on the same workload (one
+trajectory, same initial angles and draws as the first timed mixed one) for
+comparison.  The CPU baseline is the plain FP64 oracle on a bounded sample (a
+fixed number of CG iterations plus one force at the same lattice), scaled to
+the trajectory's measured CG iteration count.
 """
 import argparse
 import json
@@ -321,31 +323,38 @@ def run_learned(a):
 
     wl = inputs.WORKLOADS["learned_l66"]
     n_train_theta = int(os.environ.get("QEDHMC_NET_TRIPLES", "8"))
-    n_steps = int(os.environ.get("QEDHMC_NET_STEPS", "400"))
+    n_steps = int(os.environ.get("QEDHMC_NET_STEPS", "1000"))
     Lt, Ntt = 24, 240
     out = {}
     t0 = time.perf_counter()
     with Q.Lattice(Lt, Ntt, dtau=wl.dtau, t=wl.t, J=wl.J, K=wl.K, seed=5000) as lt, Q.Net(lt) as net:
-        triples = []
+        # residuals r_k = eta - O x_k of the method's own (mixed) solves,
+        # stopped after k = 0, 50, ..., 1250 iterations
+        pool = []
         for k in range(n_train_theta):
             th = torch.from_numpy(inputs.noisy_pi_flux_theta(Lt, Ntt, 0.3, 5000 + k)).cuda()
             R = torch.from_numpy(inputs.gauss_cvec(Lt, Ntt, 5100 + k)).cuda()
             eta = lt.apply_M(th, R, dagger=True)
-            X, st, it, rel = lt.cg_solve(th, eta, tol=1e-8, prec="fp32")
-            triples.append((th, eta, X))
+            pool.append((th, eta))
+            for its in range(50, 1300, 50):
+                x, st, it, rel = lt.cg_solve(th, eta, tol=1e-12, maxit=its, prec="fp32")
+                pool.append((th, eta - lt.apply_MdagM(th, x, prec="fp64")))
+        torch.cuda.synchronize()
         t_data = time.perf_counter() - t0
         net.set_params(inputs.net_init_weights(wl.seed))
         losses = []
+        rng = np.random.default_rng(wl.seed)
         t1 = time.perf_counter()
         for s in range(n_steps):
-            th, eta, X = triples[s % len(triples)]
-            loss, _ = net.train_step(th, eta, X, lr=1e-3)
+            th, r = pool[int(rng.integers(len(pool)))]
+            loss, _ = net.train_step_residual(th, r, lr=1e-3)
             losses.append(loss)
         torch.cuda.synchronize()
         t_train = time.perf_counter() - t1
         params = net.get_params()
-    out["training"] = {"lattice": f"L={Lt} Nt={Ntt}", "triples": n_train_theta, "steps": n_steps,
-                       "loss_first": losses[0], "loss_last_avg": float(np.mean(losses[-len(triples):])),
+    out["training"] = {"lattice": f"L={Lt} Nt={Ntt}", "form": "residual |O z - r|^2 / |r|^2",
+                       "residuals": len(pool), "thetas": n_train_theta, "steps": n_steps,
+                       "loss_first": losses[0], "loss_last_avg": float(np.mean(losses[-50:])),
                        "data_s": t_data, "train_s": t_train, "ms_per_step": 1e3 * t_train / max(n_steps, 1)}
     L, Nt = wl.L, wl.Nt
     th_np = inputs.noisy_pi_flux_theta(L, Nt, 0.3, wl.seed)
@@ -430,6 +439,24 @@ def cpu_baseline_learned(iters, switched, flat_params, L, Nt):
             "sample": (f"oracle FP64 network forward ({t1 - t0:.2f} s), M^dag M ({t2 - t1:.3f} s) and paper "
                        f"preconditioner ({t4 - t3:.2f} s) on L={Ls} Nt={Nts}, scaled per site to L={L} Nt={Nt} and "
                        f"to {iters} iterations ({n_net} with the network) (extrapolation)")}
+
+
+def fp64_path(lat, wl, th0, mixed_first, s_mixed, pc):
+    """The plain FP64 GPU path on the same workload, for comparison with the
+    mixed one: from the same initial angles, trajectory 0 untimed (kernels
+    and graphs of the FP64 path loaded), then trajectory 1 timed -- the same
+    momenta and pseudofermion draws as the first timed mixed trajectory."""
+    import torch
+    theta = torch.from_numpy(th0).cuda()
+    lat.hmc_trajectory(theta, 0, wl.n_steps, wl.traj_len, wl.tol, prec="fp64", precond=pc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = lat.hmc_trajectory(theta, 1, wl.n_steps, wl.traj_len, wl.tol, prec="fp64", precond=pc)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    return {"s_per_traj": t, "cg_iters_total": r["cg_iters_total"], "dH": r["dH"], "accepted": r["accepted"],
+            "mixed_dH_same_traj": mixed_first["dH"], "mixed_speedup": t / s_mixed, "trajectories": 1,
+            "tol": wl.tol}
 
 
 def main():
@@ -564,6 +591,8 @@ def main():
             "timed_launches": n_k,
         },
     }
+    if prec != "fp64":
+        out["fp64_path"] = fp64_path(lat, wl, th0, results[0], s_per_traj, pc)
     lat.close()
     out["matvec_large"] = matvec_large()
     if not a.no_cpu_baseline:

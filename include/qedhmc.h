@@ -315,10 +315,26 @@ qedhmc_status qedhmc_net_train_step(qedhmc_net_t n, const double *theta,
                                     double lr, qedhmc_net_arith arith,
                                     double *loss, float *grad_host);
 
+/* One training step in residual form on the pair (theta, r): loss =
+ * |O z - r|^2 / |r|^2 with z = N(theta, r) and O = M^dag M (the FP64 fused
+ * operator of the handle) -- the error z - e of the triple (theta, r, e),
+ * O e = r, measured as |O (z - e)| / |O e|, which needs no e.  It weighs the
+ * error along each eigenvector of O by the eigenvalue instead of letting the
+ * lowest modes dominate.  Gradient (2 s O (O z - r) / |r|^2 at the outputs,
+ * s the output scale) into grad_host (nullable), then one Adam step as
+ * above.  r: device complex FP64 [Nt][L][L], e.g. a residual r_k of one of
+ * the method's own solves.  FP32 arithmetic only. */
+qedhmc_status qedhmc_net_train_step_residual(qedhmc_net_t n,
+                                             const double *theta,
+                                             const double *r, double lr,
+                                             qedhmc_net_arith arith,
+                                             double *loss,
+                                             float *grad_host);
+
 /* Flexible CG on M^dag M x = rhs preconditioned by the network (Notay's
  * flexible CG: alpha = <p, r> / <p, O p>, beta = -<O p, z'> / <p, O p>),
  * from x = 0, stopping on the FP64 true residual |rhs - O x| / |rhs| <= tol.
- * The residual judges the network: when |r| has fallen by less than 10 %
+ * The residual judges the network: when |r| has not at least halved
  * over the last 10 iterations the solve continues with the fallback
  * preconditioner (QEDHMC_PC_PAPER or QEDHMC_PC_NONE) and *switched_at
  * (host, nullable) receives that iteration (-1 if the network kept it).

@@ -18,7 +18,9 @@ Layer l: out[co, n] = b[co] + sum_{ci, k} W[co, ci, k] in~[ci, n + d_k],
 k = (dt + 1) * 9 + (dy + 1) * 3 + (dx + 1) over dt, dy, dx in {-1, 0, 1}.
 
 Training loss for one triple (theta, r, e) with e the solution of
-O e = r (O = M^dag M): |z - e|^2 / |e|^2; Adam (Kingma and Ba 2015).
+O e = r (O = M^dag M): |z - e|^2 / |e|^2; or in residual form
+|O z - r|^2 / |r|^2 = |O (z - e)|^2 / |O e|^2, which needs no e; Adam
+(Kingma and Ba 2015).
 
 Flexible CG (Golub and Ye 1999; Notay 2000) with a nonlinear preconditioner:
   r0 = rhs, z0 = N(r0), p0 = z0
@@ -33,8 +35,9 @@ iteration is preconditioned CG.  It stops on the recursion's residual and
 confirms with the true residual |rhs - O x| / |rhs| <= tol (restarting from
 the true residual if it is not met).
 
-The residual judges the network: when |r| has fallen by less than a factor
-0.9 over the last 10 iterations, or the network's direction is not one of
+The residual judges the network: when |r| has not at least halved over the
+last 10 iterations (a decade per about 33 iterations: a network slower than
+that loses to the paper's preconditioner as fallback), or the network's direction is not one of
 descent (<p, O p> <= 0), the solve continues with the fallback preconditioner
 (the paper's, or none), restarting its directions from the current residual.
 """
@@ -173,6 +176,32 @@ def loss_and_grads(params, theta, r, e):
     return loss, grads
 
 
+def loss_and_grads_residual(params, theta, r, apply_O):
+    """Residual form: loss |O z - r|^2 / |r|^2 (O = M^dag M, apply_O on arrays
+    of r's shape) and its gradients; d loss / d z = 2 O (O z - r) / |r|^2
+    since O is Hermitian."""
+    z, (acts, pres, s) = forward(params, theta, r, keep=True)
+    nr2 = np.vdot(r, r).real
+    d = apply_O(z) - r
+    loss = np.vdot(d, d).real / nr2
+    dz = 2.0 * apply_O(d) / nr2
+    return loss, _backward(params, acts, pres, s * np.stack([dz.real, dz.imag]))
+
+
+def _backward(params, acts, pres, g):
+    """Gradients w.r.t. every (W, b) given d loss / d (last layer's outputs)."""
+    grads = [None] * len(params)
+    n = len(params)
+    for l in range(n - 1, -1, -1):
+        W, _ = params[l]
+        if l < n - 1:
+            g = g * dsilu(pres[l])
+        dX, dW, db = conv_backward(acts[l], W, g, ANTI0 if l == 0 else None, need_dx=l > 0)
+        grads[l] = (dW, db)
+        g = dX
+    return grads
+
+
 def adam_step(params, grads, state, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     """One Adam step (in place on new lists); state = (t, m, v)."""
     t, m, v = state
@@ -198,7 +227,7 @@ def adam_init(params):
 
 
 JUDGE_WINDOW = 10
-JUDGE_FACTOR = 0.9
+JUDGE_FACTOR = 0.5
 
 
 def fcg_solve(apply_O, precond, rhs, tol=1e-10, maxit=10000, fallback=None):

@@ -41,10 +41,12 @@ __global__ __launch_bounds__(BS) void k_cg_replace(Lat lt, CgBufs<R> B, const cp
     cg_replace_body<R, MC, NB>(lt, B, gauge, co, scal, kpar, tau, tl);
 }
 
-// Record of the latest decision taken on the device (pipelined driver):
-// iterations, FP64 true |r|^2, |rhs|^2, reliable updates so far, state (0
+// Record of the solve kept on the device (pipelined driver): iterations,
+// |rhs|^2 and the latest |r|^2 estimate (the FP64 true residual after an
+// update, else the recursion's gamma) after every round; from the latest
+// decision the FP64 true |r|^2, the reliable updates so far, the state (0
 // resumed, 4 failed, 5 converged) and, for a failure, its cause.
-enum { CR_ITERS = 0, CR_TRUE = 1, CR_B2 = 2, CR_NREL = 3, CR_DONE = 4, CR_WHY = 5, CR_N = 8 };
+enum { CR_ITERS = 0, CR_TRUE = 1, CR_B2 = 2, CR_NREL = 3, CR_DONE = 4, CR_WHY = 5, CR_EST = 6, CR_N = 8 };
 enum { WHY_BREAKDOWN = 1, WHY_NONFINITE = 2, WHY_BUDGET = 3, WHY_STALL = 4 };
 
 // The reliable-update decision on the device, after the gated FP64 O x and
@@ -52,14 +54,16 @@ enum { WHY_BREAKDOWN = 1, WHY_NONFINITE = 2, WHY_BUDGET = 3, WHY_STALL = 4 };
 // failed (4) on a non-finite residual, the iteration budget used or no
 // progress across three updates, or a breakdown flagged by the recursion;
 // otherwise resume (0; restart with beta = 0 after a non-positive
-// denominator).  A solve already final is left as it is.
+// denominator, and after every update with restart_all: the FP64 path's
+// p = r).  A solve already final is left as it is.
 __global__ void k_cg_check_dev(double* __restrict__ scal, int kpar, const double* __restrict__ part, int Nt,
-                               int maxit, double* __restrict__ rec) {
+                               int maxit, int restart_all, double* __restrict__ rec) {
     __shared__ double red[kNP * 16 + 16];
     double* sl = scal + S_NSLOT * kpar;
     const double done = sl[S_DONE];
     const int it = (int)sl[S_ITERS];
     int nd = -1, why = 0;
+    double est = sl[S_GCUR];
     if (done == 4.0 && rec[CR_DONE] != 4.0) {
         nd = 4;
         why = WHY_BREAKDOWN;
@@ -74,6 +78,7 @@ __global__ void k_cg_check_dev(double* __restrict__ scal, int kpar, const double
             sl[S_LASTUP] = it + 1;
             sl[S_NREL] += 1.0;
             sl[S_TRUE] = tr;
+            est = tr;
             if (!isfinite(tr)) {
                 nd = 4;
                 why = WHY_NONFINITE;
@@ -84,20 +89,23 @@ __global__ void k_cg_check_dev(double* __restrict__ scal, int kpar, const double
                 why = it >= maxit ? WHY_BUDGET : WHY_STALL;
             } else {
                 nd = 0;
-                if (done == 3.0) sl[S_FIRST] = 1.0;
+                if (restart_all || done == 3.0) sl[S_FIRST] = 1.0;
                 sl[S_ITUPD] = it;
                 sl[S_RRUPD] = pr[0];
             }
         }
     }
-    if (threadIdx.x == 0 && nd >= 0) {
-        sl[S_DONE] = nd;
+    if (threadIdx.x == 0) {
         rec[CR_ITERS] = it;
-        rec[CR_TRUE] = sl[S_TRUE];
         rec[CR_B2] = sl[S_B2];
-        rec[CR_NREL] = sl[S_NREL];
-        rec[CR_DONE] = nd;
-        rec[CR_WHY] = why;
+        rec[CR_EST] = est;
+        if (nd >= 0) {
+            sl[S_DONE] = nd;
+            rec[CR_TRUE] = sl[S_TRUE];
+            rec[CR_NREL] = sl[S_NREL];
+            rec[CR_DONE] = nd;
+            rec[CR_WHY] = why;
+        }
     }
 }
 
@@ -245,33 +253,36 @@ static qedhmc_status launch_true(qedhmc_ctx* h, const CgBufs<R>& B, const double
     return QEDHMC_OK;
 }
 
-// The mixed-precision solve with every decision taken on the device.  A
-// round is a graph replay of kCap + 1 iteration launches followed by the
-// gated FP64 O x, replacement and decision; the recursion pauses itself
-// within those launches, so every round ends in a reliable update and the
-// next one starts at buffer parity 0, on the other launch parity (the count
-// is odd).  The host keeps the next round queued behind the running one and
-// reads each round's decision record from pinned memory through an event,
-// so the GPU does not wait for the host between rounds.  The round after
-// the last is skipped when the true residuals of the last two rounds,
-// extrapolated geometrically, say the running round converges; a wrong
-// guess costs one host round trip.
+// The solve with every decision taken on the device.  A round is a graph
+// replay of a chunk of iteration launches followed by the FP64 O x, the
+// replacement and the decision, all gated on the slot's stop flag.  Mixed:
+// kCap + 1 launches, within which the recursion pauses itself, so every round
+// ends in a reliable update and the next one starts at buffer parity 0 on the
+// other launch parity (the count is odd).  FP64: 64 launches and no pauses;
+// a round either stops (then updates, resuming at buffer parity 0) or runs
+// all 64 iterations (an even count: parities unchanged), so every round
+// starts at launch and buffer parity 0.  The host keeps the next round
+// queued behind the running one and reads each round's record from pinned
+// memory through an event, so the GPU does not wait for the host between
+// rounds.  The round after the last is skipped when the residual estimates of
+// the last two rounds, extrapolated geometrically, say the running round
+// converges; a wrong guess costs one host round trip.
 template <typename R>
-static qedhmc_status cg_pipelined(qedhmc_ctx* h, const CgBufs<R>& B, double* x, double tol, int maxit, int* iters,
-                                  double* true_rel, int* n_reliable) {
-    constexpr int chunk = kCap + 1;
-    static_assert(chunk & 1, "rounds alternate the launch parity");
+static qedhmc_status cg_pipelined(qedhmc_ctx* h, const CgBufs<R>& B, double* x, double tol, int maxit, bool mixed,
+                                  int* iters, double* true_rel, int* n_reliable) {
+    const int chunk = mixed ? kCap + 1 : 64;
+    static_assert((kCap + 1) & 1, "mixed rounds alternate the launch parity");
     double* rec = h->scal + 40;
     for (auto& e : h->cg_ev)
         if (!e) QH_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     QH_TRY(launch_start<R>(h, B));
     QH_HIP(hipMemsetAsync(rec, 0, CR_N * sizeof(double), h->stream));
     auto round = [&](long n) -> qedhmc_status {
-        const int kp = (int)(n & 1), ke = kp ^ 1;
-        QH_TRY(launch_iters_graph<R>(h, B, kp, 0, chunk, tol * tol, 1, maxit));
+        const int kp = (chunk & 1) ? (int)(n & 1) : 0, ke = kp ^ (chunk & 1);
+        QH_TRY(launch_iters_graph<R>(h, B, kp, 0, chunk, tol * tol, mixed ? 1 : 0, maxit));
         QH_TRY(launch_replace<R>(h, B, x, ke, true));
         hipLaunchKernelGGL(k_cg_check_dev, dim3(1), dim3(256), 0, h->stream, h->scal, ke, (const double*)h->partial,
-                           h->lat.Nt, maxit, rec);
+                           h->lat.Nt, maxit, mixed ? 0 : 1, rec);
         QH_HIP(hipGetLastError());
         QH_HIP(hipMemcpyAsync(h->h_pinned + 32 + 16 * (n & 1), rec, CR_N * sizeof(double), hipMemcpyDeviceToHost,
                               h->stream));
@@ -297,7 +308,7 @@ static qedhmc_status cg_pipelined(qedhmc_ctx* h, const CgBufs<R>& B, double* x, 
             return QEDHMC_ENOCONV;
         }
         if (queued < n + 2) QH_TRY(round(queued++));  // round n + 1 was held back wrongly
-        const double tr = r[CR_TRUE], target = tol * tol * r[CR_B2];
+        const double tr = r[CR_EST], target = tol * tol * r[CR_B2];
         const bool last = prev > 0.0 && tr > 0.0 && tr * (tr / prev) <= target;
         prev = tr;
         if (!last && queued < n + 3) QH_TRY(round(queued++));
@@ -333,7 +344,7 @@ static qedhmc_status cg_t(qedhmc_ctx* h, const double* rhs, double* x, double to
     // QEDHMC_NO_GRAPH (read per solve) launches every chunk directly from a
     // host-driven loop
     const bool no_graph = std::getenv("QEDHMC_NO_GRAPH") != nullptr;
-    if (mixed && !no_graph) return cg_pipelined<R>(h, B, x, tol, maxit, iters, true_rel, n_reliable);
+    if (!no_graph) return cg_pipelined<R>(h, B, x, tol, maxit, mixed, iters, true_rel, n_reliable);
     // chunk of launches between host checks; the mixed path pauses itself at
     // most every kCap + 1 launches
     const int chunk = mixed ? kCap + 1 : 64;

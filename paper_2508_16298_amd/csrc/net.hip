@@ -270,6 +270,36 @@ __global__ __launch_bounds__(256) void k_net_loss(int N, const float* __restrict
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
+// Residual form of the loss, |O z - r|^2 / |r|^2: the error z - e measured by
+// |O (z - e)| relative to |O e| (O e = r).  It weighs the error's components
+// along the eigenvectors of O by the eigenvalue, where |z - e|^2 lets the
+// lowest modes of O (which a local network cannot represent) dominate.
+// d = O z - r in place of O z, and per-block partials of |d|^2.
+__global__ __launch_bounds__(256) void k_net_resid(int N, cplx<double>* __restrict__ d,
+                                                   const cplx<double>* __restrict__ r, double* __restrict__ part) {
+    __shared__ double red[16];
+    double acc = 0.0;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < N; n += gridDim.x * blockDim.x) {
+        const cplx<double> v = mk<double>(d[n].re - r[n].re, d[n].im - r[n].im);
+        acc += v.re * v.re + v.im * v.im;
+        d[n] = v;
+    }
+    const double t = block_sum(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// Its gradient at the last layer's outputs o (z = s o, O Hermitian):
+// g = 2 s (O d) / |r|^2.
+__global__ void k_net_resgrad(int N, const cplx<double>* __restrict__ Od, const double* __restrict__ rr,
+                              float* __restrict__ gout) {
+    const double s = sqrt(*rr / (double)N);
+    const double c = 2.0 * s / *rr;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < N; n += gridDim.x * blockDim.x) {
+        gout[2 * n] = (float)(c * Od[n].re);
+        gout[2 * n + 1] = (float)(c * Od[n].im);
+    }
+}
+
 // Adam (Kingma and Ba 2015): m = b1 m + (1 - b1) g; v = b2 v + (1 - b2) g^2;
 // p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
 __global__ void k_adam(int n, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
@@ -536,6 +566,8 @@ static qedhmc_status launch_dgrad(qedhmc_net* n, int l, const float* gout, float
     return QEDHMC_OK;
 }
 
+qedhmc_status net_backward_adam(qedhmc_net* n, const double* r, double lr, float* grad_host);
+
 }  // namespace qh
 
 // ---------------------------------------------------------------------------
@@ -728,6 +760,56 @@ qedhmc_status qedhmc_net_train_step(qedhmc_net_t n, const double* theta, const d
                        n->dpart);
     hipLaunchKernelGGL(k_sum1, dim3(1), dim3(64), 0, st, (const double*)n->dpart, kRedBlocks, n->dscal + 2);
     QH_HIP(hipGetLastError());
+    QH_TRY(net_backward_adam(n, r, lr, grad_host));
+    QH_HIP(hipMemcpyAsync(n->hpin, n->dscal, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+    QH_HIP(hipStreamSynchronize(st));
+    *loss = n->hpin[1] > 0.0 ? n->hpin[2] / n->hpin[1] : 0.0;
+    return QEDHMC_OK;
+}
+
+qedhmc_status qedhmc_net_train_step_residual(qedhmc_net_t n, const double* theta, const double* r, double lr,
+                                             qedhmc_net_arith a, double* loss, float* grad_host) {
+    QH_TRY(net_args(n, theta, r, a));
+    if (!loss || !(lr >= 0.0)) {
+        set_error("net: bad training arguments");
+        return QEDHMC_EINVAL;
+    }
+    if (a != QEDHMC_NET_FP32) {
+        set_error("net: training runs in FP32 arithmetic");
+        return QEDHMC_EUNSUPPORTED;
+    }
+    QH_TRY(net_alloc_train(n));
+    const NetGeo& g = n->g;
+    hipStream_t st = n->h->stream;
+    QH_TRY(ensure_gauge(n->h, theta, QEDHMC_FP64));
+    QH_TRY(net_forward(n, theta, r, a, true));
+    // z = s o (FP64), O z, d = O z - r, |d|^2, O d: the FP64 fused M^dag M
+    hipLaunchKernelGGL(k_net_out, dim3(blocks_for(g.N, 256)), dim3(256), 0, st, g.N,
+                       (const float*)n->act[kNetLayers], (const double*)n->dscal, n->fz);
+    QH_HIP(hipGetLastError());
+    QH_TRY(launch_mdagm(n->h, QEDHMC_FP64, n->fz, n->fs));
+    hipLaunchKernelGGL(k_net_resid, dim3(kRedBlocks), dim3(256), 0, st, g.N, n->fs,
+                       reinterpret_cast<const cplx<double>*>(r), n->dpart);
+    hipLaunchKernelGGL(k_sum1, dim3(1), dim3(64), 0, st, (const double*)n->dpart, kRedBlocks, n->dscal + 2);
+    QH_HIP(hipGetLastError());
+    QH_TRY(launch_mdagm(n->h, QEDHMC_FP64, n->fs, n->fp));
+    hipLaunchKernelGGL(k_net_resgrad, dim3(blocks_for(g.N, 256)), dim3(256), 0, st, g.N,
+                       (const cplx<double>*)n->fp, (const double*)n->dscal, n->gbuf[0]);
+    QH_HIP(hipGetLastError());
+    QH_TRY(net_backward_adam(n, r, lr, grad_host));
+    QH_HIP(hipMemcpyAsync(n->hpin, n->dscal, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+    QH_HIP(hipStreamSynchronize(st));
+    *loss = n->hpin[0] > 0.0 ? n->hpin[2] / n->hpin[0] : 0.0;
+    return QEDHMC_OK;
+}
+
+}  // extern "C"
+
+namespace qh {
+
+// Backward pass from d(loss)/d(outputs) in gbuf[0], then one Adam step.
+qedhmc_status net_backward_adam(qedhmc_net* n, const double* r, double lr, float* grad_host) {
+    hipStream_t st = n->h->stream;
     // backward through the layers: gbuf alternates between d(loss)/d(pre) of
     // consecutive layers
     int cur = 0;
@@ -748,16 +830,17 @@ qedhmc_status qedhmc_net_train_step(qedhmc_net_t n, const double* theta, const d
                        (const float*)n->grads, n->adam_m, n->adam_v, (float)lr, (float)b1, (float)b2, 1e-8f, c1, c2);
     QH_HIP(hipGetLastError());
     n->wbf_ready = false;
-    QH_HIP(hipMemcpyAsync(n->hpin, n->dscal, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
-    QH_HIP(hipStreamSynchronize(st));
-    *loss = n->hpin[1] > 0.0 ? n->hpin[2] / n->hpin[1] : 0.0;
     return QEDHMC_OK;
 }
+
+}  // namespace qh
+
+extern "C" {
 
 // Flexible CG with the network as preconditioner (see net.hip's header and
 // the FCG description): alpha = <p, r> / <p, O p>, beta = -<O p, z'> / <p, O p>;
 // the residual judges the network and hands over to the fallback when |r|
-// fell by less than 10% over the last 10 iterations.
+// has not at least halved over the last 10 iterations.
 qedhmc_status qedhmc_fcg_solve(qedhmc_net_t n, const double* theta, const double* rhs, double* x, double tol,
                                int32_t maxit, qedhmc_net_arith a, qedhmc_precond fallback, int32_t* iters,
                                double* true_rel, int32_t* switched_at) {

@@ -13,7 +13,7 @@ static constexpr int kNetLayers = 6;
 static constexpr int kNetCh[kNetLayers + 1] = {6, 32, 32, 32, 32, 32, 2};
 static constexpr int kWChunk = 1024;     // output sites per weight-gradient partial
 static constexpr int kJudgeWindow = 10;  // flexible CG: iterations the residual judge looks back
-static constexpr double kJudgeFactor = 0.9;
+static constexpr double kJudgeFactor = 0.5;
 
 struct NetGeo {
     int L, Nt, Vs, N;

@@ -89,6 +89,7 @@ def load():
         "qedhmc_net_reset_optimizer": [_P],
         "qedhmc_net_apply": [_P, _P, _P, _P, C.c_int],
         "qedhmc_net_train_step": [_P, _P, _P, _P, C.c_double, C.c_int, C.POINTER(C.c_double), _P],
+        "qedhmc_net_train_step_residual": [_P, _P, _P, C.c_double, C.c_int, C.POINTER(C.c_double), _P],
         "qedhmc_fcg_solve": [_P, _P, _P, _P, C.c_double, C.c_int32, C.c_int, C.c_int, C.POINTER(C.c_int32),
                              C.POINTER(C.c_double), C.POINTER(C.c_int32)],
         "qedhmc_batch_create": [C.POINTER(Params), C.c_int32, _P, C.POINTER(_P)],
@@ -476,6 +477,19 @@ class Net:
         _check(load().qedhmc_net_train_step(self.h, _ptr(theta), _ptr(r), _ptr(e), float(lr), _ARITH[arith],
                                             C.byref(loss),
                                             grad.ctypes.data_as(C.c_void_p) if want_grad else None))
+        return loss.value, grad
+
+    def train_step_residual(self, theta, r, lr=1e-3, arith="fp32", want_grad=False):
+        """Residual-form step (loss |O N(r) - r|^2 / |r|^2).  Returns (loss, grad)."""
+        import numpy as np
+        self.lat._check_theta(theta)
+        self.lat._check_vec(r, "fp64")
+        loss = C.c_double(0.0)
+        grad = np.zeros(self.count, dtype=np.float32) if want_grad else None
+        self.lat._sync_stream()
+        _check(load().qedhmc_net_train_step_residual(self.h, _ptr(theta), _ptr(r), float(lr), _ARITH[arith],
+                                                     C.byref(loss),
+                                                     grad.ctypes.data_as(C.c_void_p) if want_grad else None))
         return loss.value, grad
 
     def fcg_solve(self, theta, rhs, tol=1e-10, maxit=100_000, arith="bf16", fallback="paper", x=None):

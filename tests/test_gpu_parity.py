@@ -174,10 +174,11 @@ def test_cg_edge_cases():
             lat.cg_solve(_dev(th), _dev(eta), tol=-1.0)
 
 
-def test_cg_mixed_device_decided_edge_cases():
-    """The mixed solve whose reliable updates are decided on the device
-    (rounds of 51 launches, the next one queued behind the running one) gives
-    bitwise what the host-driven loop gives: a zero right-hand side (no
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_cg_device_decided_edge_cases(prec):
+    """The solve whose reliable updates are decided on the device (rounds of
+    51 launches mixed, 64 in FP64, the next one queued behind the running
+    one) gives bitwise what the host-driven loop gives: a zero right-hand side (no
     iteration), an iteration budget inside the first round and across rounds
     (ENOCONV with exactly maxit iterations), and a loose tolerance met after a
     few iterations."""
@@ -194,7 +195,7 @@ def test_cg_mixed_device_decided_edge_cases():
                 os.environ["QEDHMC_NO_GRAPH"] = "1"
             try:
                 for i, (rhs, tol, maxit) in enumerate(cases):
-                    x, st, it, rel = lat.cg_solve(_dev(th), _dev(rhs), tol=tol, maxit=maxit, prec="fp32")
+                    x, st, it, rel = lat.cg_solve(_dev(th), _dev(rhs), tol=tol, maxit=maxit, prec=prec)
                     out[mode, i] = (_host(x), st, it, rel)
             finally:
                 os.environ.pop("QEDHMC_NO_GRAPH", None)

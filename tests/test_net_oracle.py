@@ -103,6 +103,47 @@ def test_loss_gradients_match_finite_differences():
         assert abs(fd - grads[l][1][j]) <= 1e-6 * max(1.0, abs(fd))
 
 
+def test_residual_loss_gradients_match_finite_differences():
+    """The residual-form loss |O z - r|^2 / |r|^2 (O = M^dag M from the
+    plain C oracle) against central finite differences of the same loss, and
+    its value against the triple form's error measured through O: for e with
+    O e = r it is |O (z - e)|^2 / |O e|^2."""
+    L, Nt = 4, 4
+    p = O.lat(L, Nt)
+    th = inputs.hot_start_theta(L, Nt, 21)
+    r = inputs.gauss_cvec(L, Nt, 22)
+    apply_O = lambda v: O.apply_MdagM(p, th, v).reshape(Nt, L, L)
+    params = _small_net(24)
+    params = [(W, _rand(W.shape[0], 25 + l) * 0.1) for l, (W, _) in enumerate(params)]
+    loss, grads = NN.loss_and_grads_residual(params, th, r, apply_O)
+    e = np.linalg.solve(O.dense_MdagM(p, th), r.reshape(-1)).reshape(Nt, L, L)
+    z = NN.forward(params, th, r)
+    Oe = apply_O(e)
+    assert abs(loss - np.linalg.norm(apply_O(z - e)) ** 2 / np.linalg.norm(Oe) ** 2) <= 1e-10 * loss
+    f = lambda q: NN.loss_and_grads_residual(q, th, r, apply_O)[0]
+    rng = np.random.default_rng(26)
+    h = 1e-6
+    for l in range(len(params)):
+        W, b = params[l]
+        for _ in range(3):
+            idx = tuple(rng.integers(0, n) for n in W.shape)
+            Wp, Wm = W.copy(), W.copy()
+            Wp[idx] += h
+            Wm[idx] -= h
+            pp = list(params); pp[l] = (Wp, b)
+            pm = list(params); pm[l] = (Wm, b)
+            fd = (f(pp) - f(pm)) / (2 * h)
+            assert abs(fd - grads[l][0][idx]) <= 1e-6 * max(1.0, abs(fd)), (l, idx, fd, grads[l][0][idx])
+        j = rng.integers(0, b.size)
+        bp, bm = b.copy(), b.copy()
+        bp[j] += h
+        bm[j] -= h
+        pp = list(params); pp[l] = (W, bp)
+        pm = list(params); pm[l] = (W, bm)
+        fd = (f(pp) - f(pm)) / (2 * h)
+        assert abs(fd - grads[l][1][j]) <= 1e-6 * max(1.0, abs(fd))
+
+
 def test_network_translation_covariance():
     """Spatial translations commute with the network.  A shift by one slice
     in tau (theta periodic, r antiperiodic) shifts the output exactly on the
