@@ -55,9 +55,11 @@ enum { WHY_BREAKDOWN = 1, WHY_NONFINITE = 2, WHY_BUDGET = 3, WHY_STALL = 4 };
 // progress across three updates, or a breakdown flagged by the recursion;
 // otherwise resume (0; restart with beta = 0 after a non-positive
 // denominator, and after every update with restart_all: the FP64 path's
-// p = r).  A solve already final is left as it is.
+// p = r).  A solve already final is left as it is.  The record (kept in
+// device memory across rounds) is also stored to out, a slot of pinned host
+// memory, so the host needs no copy.
 __global__ void k_cg_check_dev(double* __restrict__ scal, int kpar, const double* __restrict__ part, int Nt,
-                               int maxit, int restart_all, double* __restrict__ rec) {
+                               int maxit, int restart_all, double* __restrict__ rec, double* __restrict__ out) {
     __shared__ double red[kNP * 16 + 16];
     double* sl = scal + S_NSLOT * kpar;
     const double done = sl[S_DONE];
@@ -106,6 +108,8 @@ __global__ void k_cg_check_dev(double* __restrict__ scal, int kpar, const double
             rec[CR_DONE] = nd;
             rec[CR_WHY] = why;
         }
+#pragma unroll
+        for (int k = 0; k < CR_N; k++) out[k] = rec[k];
     }
 }
 
@@ -282,10 +286,8 @@ static qedhmc_status cg_pipelined(qedhmc_ctx* h, const CgBufs<R>& B, double* x, 
         QH_TRY(launch_iters_graph<R>(h, B, kp, 0, chunk, tol * tol, mixed ? 1 : 0, maxit));
         QH_TRY(launch_replace<R>(h, B, x, ke, true));
         hipLaunchKernelGGL(k_cg_check_dev, dim3(1), dim3(256), 0, h->stream, h->scal, ke, (const double*)h->partial,
-                           h->lat.Nt, maxit, mixed ? 0 : 1, rec);
+                           h->lat.Nt, maxit, mixed ? 0 : 1, rec, h->h_pinned + 32 + 16 * (n & 1));
         QH_HIP(hipGetLastError());
-        QH_HIP(hipMemcpyAsync(h->h_pinned + 32 + 16 * (n & 1), rec, CR_N * sizeof(double), hipMemcpyDeviceToHost,
-                              h->stream));
         QH_HIP(hipEventRecord(h->cg_ev[n & 1], h->stream));
         return QEDHMC_OK;
     };
