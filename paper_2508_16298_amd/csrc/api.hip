@@ -2,10 +2,39 @@
 // orchestration of the trajectory (Methods, HQMC steps (i)-(iv)).
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <unordered_set>
 
 #include "qedhmc_internal.h"
 
 namespace qh {
+
+qedhmc_status allow_lds(const void* k, size_t max_lds) {
+    static std::mutex m;
+    static std::unordered_set<const void*> done;
+    std::lock_guard<std::mutex> g(m);
+    if (done.count(k)) return QEDHMC_OK;
+    QH_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds));
+    done.insert(k);
+    return QEDHMC_OK;
+}
+
+qedhmc_status blocks_per_cu(const void* k, int threads, size_t lds, int* out) {
+    static std::mutex m;
+    static std::map<std::tuple<const void*, int, size_t>, int> cache;
+    std::lock_guard<std::mutex> g(m);
+    const auto key = std::make_tuple(k, threads, lds);
+    auto it = cache.find(key);
+    if (it == cache.end()) {
+        int n = 0;
+        QH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, threads, lds));
+        it = cache.emplace(key, n).first;
+    }
+    *out = it->second;
+    return QEDHMC_OK;
+}
 
 static thread_local std::string g_err;
 
@@ -161,6 +190,10 @@ qedhmc_status qedhmc_destroy(qedhmc_t h) {
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     for (auto& e : h->cg_ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto& a : h->pcg_graph)
+        for (auto& b : a)
+            for (auto& g : b)
+                if (g.exec) (void)hipGraphExecDestroy(g.exec);
     delete h;
     return QEDHMC_OK;
 }

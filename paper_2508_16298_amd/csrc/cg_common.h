@@ -268,8 +268,7 @@ inline qedhmc_status lds_attr(qedhmc_ctx* h, K kern, size_t bytes) {
         set_error("lattice too large for LDS on this device");
         return QEDHMC_EUNSUPPORTED;
     }
-    if (bytes > 65536)
-        QH_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    if (bytes > 65536) return allow_lds((const void*)kern, h->max_lds);
     return QEDHMC_OK;
 }
 

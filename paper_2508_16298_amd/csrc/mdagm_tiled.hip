@@ -523,10 +523,9 @@ static qedhmc_status mdagm_tiled_t(qedhmc_ctx* h, const void* in, void* out, con
                                           : reinterpret_cast<const cplx<R>*>(h->gauge32);
     const TCoef<R> co = tcoef_of<R>(h->p);
     auto go = [&](auto kern) -> qedhmc_status {
-        if (lds > 65536)
-            QH_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        if (lds > 65536) QH_TRY(allow_lds((const void*)kern, h->max_lds));
         int per_cu = 0;
-        QH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, p.threads, lds));
+        QH_TRY(blocks_per_cu((const void*)kern, p.threads, lds, &per_cu));
         set_run_length(p.g, tc, std::max(1, per_cu) * std::max(1, h->n_cu));
         const int grid = 8 * ((p.g.nwork + 7) / 8);
         hipEvent_t e0, e1;

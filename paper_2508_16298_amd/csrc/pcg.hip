@@ -464,8 +464,7 @@ static qedhmc_status launch_pc(qedhmc_ctx* h, int ps, const cplx<R>* in, cplx<R>
         return QEDHMC_EUNSUPPORTED;
     }
     const int nwork = g.nband * g.nrun * 2;
-    if (lds > 65536)
-        QH_HIP(hipFuncSetAttribute((const void*)k_pc_stream<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    if (lds > 65536) QH_TRY(allow_lds((const void*)k_pc_stream<R>, h->max_lds));
     hipLaunchKernelGGL(k_pc_stream<R>, dim3(8 * ((nwork + 7) / 8)), dim3(threads), lds, h->stream, g, taps_for<R>(h),
                        in, out, stop);
     QH_HIP(hipGetLastError());
@@ -785,6 +784,63 @@ static qedhmc_status pcg_tail(qedhmc_ctx* h, const PcgBufs<R>& B, const double* 
     return launch_mv<R>(h, B, stop, stop != nullptr);
 }
 
+// n iterations from launch parity kpar: update, then preconditioner and
+// matvec, each gated on the slot's stop flag
+template <typename R>
+static qedhmc_status pcg_chunk(qedhmc_ctx* h, const PcgBufs<R>& B, int kpar, int n, bool mixed, bool identity) {
+    for (int k = 0; k < n; k++) {
+        hipLaunchKernelGGL(k_pcg_upd<R>, dim3(h->lat.Nt), dim3(256), 0, h->stream, h->lat, B, h->scal, kpar,
+                           mixed ? 1 : 0);
+        kpar ^= 1;
+        QH_TRY(pcg_tail<R>(h, B, h->scal + S_NSLOT * kpar + S_DONE, identity));
+    }
+    QH_HIP(hipGetLastError());
+    return QEDHMC_OK;
+}
+
+// The same chunk replayed from a graph captured the first time this
+// (buffers, mode, chunk) combination is seen on the handle; the launch
+// shapes (and kernel attributes) are those of the solve's first matvec,
+// made before any capture.
+template <typename R>
+static qedhmc_status pcg_chunk_graph(qedhmc_ctx* h, const PcgBufs<R>& B, int kpar, int n, bool mixed, bool identity) {
+    qedhmc_ctx::PcgGraph& gr = h->pcg_graph[sizeof(R) == 8 ? 1 : 0][identity ? 1 : 0][kpar];
+    if (gr.exec && (gr.x != B.x || gr.rhs != B.rhs || gr.mixed != (int)mixed || gr.count != n)) {
+        QH_HIP(hipGraphExecDestroy(gr.exec));
+        gr.exec = nullptr;
+    }
+    if (!gr.exec) {
+        if (!h->cap_stream) QH_HIP(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+        hipStream_t user = h->stream;
+        const int prof = h->prof_every;
+        h->stream = h->cap_stream;
+        h->prof_every = 0;  // no event launches inside a graph
+        hipGraph_t g = nullptr;
+        qedhmc_status st = QEDHMC_OK;
+        hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            st = pcg_chunk<R>(h, B, kpar, n, mixed, identity);
+            e = hipStreamEndCapture(h->cap_stream, &g);
+        }
+        h->stream = user;
+        h->prof_every = prof;
+        if (st != QEDHMC_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        QH_HIP(e);
+        e = hipGraphInstantiate(&gr.exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        QH_HIP(e);
+        gr.x = B.x;
+        gr.rhs = B.rhs;
+        gr.mixed = mixed ? 1 : 0;
+        gr.count = n;
+    }
+    QH_HIP(hipGraphLaunch(gr.exec, h->stream));
+    return QEDHMC_OK;
+}
+
 // identity = true: plain CG in the same two-launch form (update, then
 // M^dag M with the partials), the form used for lattices whose slices hold
 // more than 1024 cells: there the fused one-launch iteration would need two
@@ -798,6 +854,8 @@ static qedhmc_status pcg_t(qedhmc_ctx* h, const double* rhs, double* x, double t
     if (identity) B.u = B.r;
     const int Nt = h->lat.Nt;
     const int chunk = mixed ? kCap + 1 : 64;
+    // QEDHMC_NO_GRAPH (read per solve) launches every chunk directly
+    const bool no_graph = std::getenv("QEDHMC_NO_GRAPH") != nullptr;
     int kpar = 0, nrel = 0, it = 0, stalled = 0, last_it = -1;
     double rel = 1.0;
     bool converged = false, broken = false;
@@ -809,13 +867,11 @@ static qedhmc_status pcg_t(qedhmc_ctx* h, const double* rhs, double* x, double t
     while (true) {
         const int left = maxit - it;
         const int n = left < chunk ? left : chunk;
-        for (int k = 0; k < n; k++) {
-            hipLaunchKernelGGL(k_pcg_upd<R>, dim3(Nt), dim3(256), 0, h->stream, h->lat, B, h->scal, kpar,
-                               mixed ? 1 : 0);
-            kpar ^= 1;
-            QH_TRY(pcg_tail<R>(h, B, h->scal + S_NSLOT * kpar + S_DONE, identity));
-        }
-        QH_HIP(hipGetLastError());
+        if (n == chunk && !no_graph)
+            QH_TRY(pcg_chunk_graph<R>(h, B, kpar, n, mixed, identity));
+        else
+            QH_TRY(pcg_chunk<R>(h, B, kpar, n, mixed, identity));
+        if (n & 1) kpar ^= 1;
         QH_TRY(read_slot(h, kpar));
         it = (int)h->h_pinned[S_ITERS];
         const double flag = h->h_pinned[S_DONE];

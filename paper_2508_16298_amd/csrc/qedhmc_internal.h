@@ -552,6 +552,14 @@ struct qedhmc_ctx {
     } cg_graph[2][2][2];
     hipStream_t cap_stream;
     hipEvent_t cg_ev[2];  // the pipelined mixed CG: one per round in flight
+    // chunks of the two-launch (P)CG captured the same way: [R is
+    // double][identity preconditioner][launch parity]
+    struct PcgGraph {
+        hipGraphExec_t exec;
+        const void* x;
+        const void* rhs;
+        int mixed, count;
+    } pcg_graph[2][2][2];
     // the paper's preconditioner (built on first use)
     bool pc_ready;
     double pc_shift;
@@ -598,6 +606,12 @@ qedhmc_status launch_apply_B(qedhmc_ctx* h, qedhmc_precision prec, int tau, cons
 qedhmc_status launch_mdagm(qedhmc_ctx* h, qedhmc_precision prec, const void* in, void* out,
                            const double* gate = nullptr);
 qedhmc_status launch_force(qedhmc_ctx* h, qedhmc_precision prec, const double* X, double* F);
+// Per-launch host work done once per kernel (api.hip): allow_lds lets kernel
+// k take up to max_lds bytes of dynamic LDS (every caller sets the same
+// value); blocks_per_cu returns the workgroups of `threads` threads and
+// `lds` bytes one compute unit holds, cached per (kernel, shape).
+qedhmc_status allow_lds(const void* k, size_t max_lds);
+qedhmc_status blocks_per_cu(const void* k, int threads, size_t lds, int* out);
 // out = M^dag M in by spatial tiles streamed along tau (mdagm_tiled.hip)
 qedhmc_status launch_mdagm_tiled(qedhmc_ctx* h, qedhmc_precision prec, const void* in, void* out);
 // the same as the matvec of the two-launch CG: w = O u and the partial sums

@@ -129,3 +129,36 @@ def test_cg_past_whole_slice_limit(L, Nt, prec, tol, precond):
     if prec == "fp64" and precond is None:
         _, _, ito, _ = O.cg_solve(p, th, eta, tol=tol)
         assert abs(it - ito) <= max(2, ito // 50), (it, ito)
+
+
+@pytest.mark.parametrize("L,Nt,prec,precond", [(68, 6, "fp32", None), (68, 6, "fp64", None),
+                                               (12, 40, "fp32", "paper"), (66, 12, "fp32", "paper")])
+def test_two_launch_graph_replays_match_direct_launches(L, Nt, prec, precond):
+    """Two-launch CG (slices of more than 1024 cells) and PCG replay their full
+    chunks from captured graphs; over several solves on one handle (graphs
+    replayed many times, reliable updates and host reads in between) they give
+    bitwise the solution, iteration count and residual of the same solves
+    launched directly."""
+    p = O.lat(L, Nt)
+    tol = 1e-10 if prec == "fp64" else 1e-8
+    out = {}
+    with Q.Lattice(L, Nt) as lat:
+        for mode in ("graph", "direct", "graph"):
+            if mode == "direct":
+                os.environ["QEDHMC_NO_GRAPH"] = "1"
+            try:
+                res = []
+                for seed in (31, 32):
+                    th = inputs.noisy_pi_flux_theta(L, Nt, 0.3, seed)
+                    eta = O.apply_M(p, th, inputs.gauss_cvec(L, Nt, seed + 50), dagger=True).reshape(Nt, L, L)
+                    x, st, it, rel = lat.cg_solve(_dev(th), _dev(eta), tol=tol, prec=prec, precond=precond)
+                    res.append((_host(x), st, it, rel))
+            finally:
+                os.environ.pop("QEDHMC_NO_GRAPH", None)
+            out.setdefault(mode, []).append(res)
+    ref = out["direct"][0]
+    for run in out["graph"]:
+        for (xg, sg, ig, rg), (xd, sd, id_, rd) in zip(run, ref):
+            print(f"L={L} {prec} {precond}: graph {sg} {ig} {rg:.3e} direct {sd} {id_} {rd:.3e}", flush=True)
+            assert sg == sd == Q.OK and ig == id_ and rg == rd
+            assert np.array_equal(xg, xd)
