@@ -146,7 +146,15 @@ qedhmc_status qedhmc_apply_MdagM(qedhmc_t h, const double *theta,
  * at exit).  rhs, x: device complex FP64 [Nt][L][L].  iters and
  * true_rel_resid (host pointers, nullable) receive the iteration count and
  * the final true relative residual.  prec = QEDHMC_FP32 runs the mixed path.
- * Returns QEDHMC_ENOCONV (x still written) when maxit is reached. */
+ * Returns QEDHMC_ENOCONV (x still written) when maxit is reached, on a
+ * breakdown (non-finite inner products or residual) or when three reliable
+ * updates in a row make no progress; qedhmc_last_error says which.  The call
+ * synchronises the handle's stream before it returns.  Iterations run as
+ * graph-captured chunks; without a preconditioner on slices of at most 1024
+ * cells the stop, pause and reliable-update decisions are also taken on the
+ * device (otherwise by the host between chunks).  The environment variable
+ * QEDHMC_NO_GRAPH (read on every call) makes the host launch every iteration
+ * and take every decision itself (same results bit for bit; tests). */
 qedhmc_status qedhmc_cg_solve(qedhmc_t h, const double *theta,
                               const double *rhs, double *x, double tol,
                               int32_t maxit, qedhmc_precision prec,
