@@ -463,7 +463,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {a.gpus} is not supported (this path has no "
-              "multi-GPU sharding; see DESIGN.md for how it would shard along tau)", file=sys.stderr)
+              "multi-GPU sharding: it would shard along tau, with halo slices exchanged between neighbours)", file=sys.stderr)
         sys.exit(2)
     if a.copy_calibration:
         return run_copy_calibration()

@@ -59,8 +59,7 @@ def load():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
-                           "or python -m paper_2508_16298_amd.build")
+        raise RuntimeError(f"{LIB_PATH} is not built: run python -m paper_2508_16298_amd.build")
     L = C.CDLL(LIB_PATH)
     st = C.c_int
     sig = {
