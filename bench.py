@@ -4,28 +4,37 @@ fused M^dag M kernel, on one MI355X.
 Workload (default): L=24, Nt=240, dtau=0.1, t=1, J=K=1, theta = pi flux plus
 Gaussian noise (sigma 0.3, seed 1013; the stand-in for a thermalised
 configuration -- a hot start at this size sits next to det M = 0 and its
-molecular dynamics diverges), 20 leapfrog steps of total length 1, CG to true
-relative residual 1e-8, mixed precision (complex-FP32 matvecs and force, FP64
-solution, reliable updates and reductions).  One step = one trajectory of the
-chain: heat bath, 21 solves, 21 forces, leapfrog, Metropolis.
+molecular dynamics diverges within one step), 20 leapfrog steps of total
+length 1, CG to true relative residual 1e-8, mixed precision (complex-FP32
+matvecs and force, FP64 solution, reliable updates and reductions).  One
+step = one trajectory: heat bath, 21 solves, 21 forces, leapfrog, Metropolis.
 
-Prints one JSON line.  The roofline block is for the dominant kernel, the
-fused CG iteration k_cg_iter (one launch per iteration: recurrences, x update,
-M^dag M, inner products).  Its algorithmic bytes per site are, in the mixed
-path, r, w, s, p read (4 x 8 B), two FP32 angles (8 B), x read and written
-(2 x 16 B, FP64) and r, s, p, w written (4 x 8 B): 104 B per site (176 B in
-FP64).  Its duration comes from event pairs around every 8th graph replay of
-51 back-to-back iteration launches (a replay holds nothing else) over the
-timed region; `traffic` is the counter-measured HBM bytes per launch.  The metric's M^dag M
-bandwidth is measured after the timed region on the standalone fused
-M^dag M kernel at 24 B per site (v in, out written, two FP32 angles; 48 B in
-FP64): the start/end events of each of 200 dispatches (the events' own
-cost included; rocprofv3's kernel-only duration is in profiles/).
-`fp64_path` times the plain FP64 GPU path on the same workload (one
-trajectory, same initial angles and draws as the first timed mixed one) for
-comparison.  The CPU baseline is the plain FP64 oracle on a bounded sample (a
-fixed number of CG iterations plus one force at the same lattice), scaled to
-the trajectory's measured CG iteration count.
+The timed set is stationary and does not depend on --warmup: a fixed number
+of chained equilibration trajectories (--equilibrate, untimed) moves the
+angles off the relaxing start, and every warm-up and timed trajectory then
+starts from that same point with its own trajectory index (its own momenta,
+source and Metropolis draw).  The first --compare timed trajectories, plus the
+one with the largest |dH|, are rerun on the other paths from the same start
+with the same indices: the plain FP64 GPU path and the mixed path with the
+learned preconditioner (network trained at setup, untimed, on residuals of
+the method's own solves); dH, decisions, iterations and seconds side by side.
+
+Prints one JSON line.  The roofline block is for the dominant kernel of the
+timed path, by default the fused CG iteration k_cg_iter (one launch per
+iteration: recurrences, x update, M^dag M, inner products).  Its algorithmic
+bytes per site are, in the mixed path, r, w, s, p read (4 x 8 B), two FP32
+angles (8 B), x read and written (2 x 16 B, FP64) and r, s, p, w written
+(4 x 8 B): 104 B per site (176 B in FP64).  Its duration comes from event
+pairs around every 8th graph replay of 51 back-to-back iteration launches (a
+replay holds nothing else) over the timed region; `traffic` is the
+counter-measured HBM bytes per launch.  The metric's M^dag M bandwidth is
+measured after the timed region on the standalone fused M^dag M kernel at
+24 B per site (v in, out written, two FP32 angles; 48 B in FP64): the
+start/end events of each of 200 dispatches (the events' own cost included;
+rocprofv3's kernel-only duration is in profiles/).  The CPU baseline is the
+plain FP64 oracle on a bounded sample (a fixed number of CG iterations plus
+one force at the same lattice and angles), scaled to the trajectory's
+measured CG iteration count.
 """
 import argparse
 import json
@@ -52,10 +61,17 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="mixed_l24")
     ap.add_argument("--prec", default=None, help="override: fp64 or mixed")
-    ap.add_argument("--precond", default="none", choices=["none", "paper"],
-                    help="CG preconditioner: none, or the paper's G^dag G stencil")
+    ap.add_argument("--precond", default="none", choices=["none", "paper", "learned"],
+                    help="preconditioner of the timed path: none, the paper's G^dag G stencil, or the "
+                         "learned network (trained at setup on the method's own residuals)")
+    ap.add_argument("--equilibrate", type=int, default=10,
+                    help="chained trajectories from the workload's angles before the timed set (untimed)")
+    ap.add_argument("--compare", type=int, default=3,
+                    help="timed trajectories rerun on the other paths for the side-by-side comparison")
+    ap.add_argument("--no-compare-learned", dest="compare_learned", action="store_false",
+                    help="skip the learned-preconditioner path in the comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=200, help="oracle CG iterations in the CPU sample")
+    ap.add_argument("--cpu-iters", type=int, default=800, help="oracle CG iterations in the CPU sample")
     ap.add_argument("--profile-every", type=int, default=8)
     ap.add_argument("--solve-only", type=int, default=0, metavar="MAXIT",
                     help="counter runs: one solve of MAXIT iterations plus 200 standalone M^dag M "
@@ -177,15 +193,16 @@ def run_solve_only(a):
                                      "matvec_launches": 200}}), flush=True)
 
 
-def cpu_baseline(wl, total_cg_iters, n_solves, n_iter):
+def cpu_baseline(wl, th, total_cg_iters, n_solves, n_iter):
     """Oracle (plain FP64 C, single thread) on a bounded sample of the same
     workload: n_iter CG iterations and one fermion force at the same lattice
-    and theta, scaled to the trajectory's CG iteration and solve counts."""
-    import numpy as np
+    and angles (the timed trajectories' start), scaled to the trajectory's
+    CG iteration and solve counts.  The oracle is single-threaded: a
+    trajectory is a sequence of dependent solves and the oracle's CG runs on
+    one core."""
     import oracle as O
     from paper_2508_16298_amd import inputs
     p = O.lat(wl.L, wl.Nt, wl.dtau, wl.t, wl.J, wl.K)
-    th = wl.initial_theta()
     R = inputs.gauss_cvec(wl.L, wl.Nt, wl.seed + 1)
     eta = O.apply_M(p, th, R, dagger=True)
     t0 = time.perf_counter()
@@ -197,12 +214,14 @@ def cpu_baseline(wl, total_cg_iters, n_solves, n_iter):
     t_force = time.perf_counter() - t0
     per_iter = t_cg / max(it, 1)
     est = per_iter * total_cg_iters + t_force * n_solves
+    hi = host_info()
     return {
-        "value": est, "unit": "s/trajectory", "cores": 1, "kind": "oracle",
+        "value": est, "unit": "s/trajectory", "cores": 1, "kind": "oracle", "host": hi,
+        "s_per_cg_iter": per_iter,
         "sample": (f"oracle FP64 CG, {it} iterations ({t_cg:.1f} s) + one fermion and gauge force "
-                   f"({t_force:.2f} s) at L={wl.L} Nt={wl.Nt}, same theta; scaled to the GPU "
-                   f"trajectory's {total_cg_iters} CG iterations and {n_solves} forces "
-                   f"(extrapolation, single thread)"),
+                   f"({t_force:.2f} s) at L={wl.L} Nt={wl.Nt}, the timed trajectories' start angles; scaled to "
+                   f"the GPU trajectory's {total_cg_iters:.0f} CG iterations and {n_solves} forces "
+                   f"(extrapolation, single thread; host {hi['nproc']} cores, {hi['cpu_model']})"),
     }
 
 
@@ -441,22 +460,67 @@ def cpu_baseline_learned(iters, switched, flat_params, L, Nt):
                        f"to {iters} iterations ({n_net} with the network) (extrapolation)")}
 
 
-def fp64_path(lat, wl, th0, mixed_first, s_mixed, pc):
-    """The plain FP64 GPU path on the same workload, for comparison with the
-    mixed one: from the same initial angles, trajectory 0 untimed (kernels
-    and graphs of the FP64 path loaded), then trajectory 1 timed -- the same
-    momenta and pseudofermion draws as the first timed mixed trajectory."""
+def host_info():
+    """Core count and CPU model of the host the CPU baseline ran on."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def train_learned(lat, net, theta, n_eta=4, steps=600, seed=1003):
+    """Setup of the learned path (untimed): the network (initial weights
+    seed `seed`) trained with Adam (lr 1e-3, FP32) in residual form on
+    residuals r_k = eta - O x_k of the method's own mixed CG solves at the
+    starting angles, stopped after k = 0, 50, ..., 1000 iterations, for
+    n_eta sources eta = M^dag R; then bound as the handle's learned
+    preconditioner (BF16 MFMA inference, the paper's preconditioner as
+    fallback)."""
+    import numpy as np
     import torch
-    theta = torch.from_numpy(th0).cuda()
-    lat.hmc_trajectory(theta, 0, wl.n_steps, wl.traj_len, wl.tol, prec="fp64", precond=pc)
-    torch.cuda.synchronize()
+    from paper_2508_16298_amd import inputs
     t0 = time.perf_counter()
-    r = lat.hmc_trajectory(theta, 1, wl.n_steps, wl.traj_len, wl.tol, prec="fp64", precond=pc)
+    pool = []
+    for k in range(n_eta):
+        R = torch.from_numpy(inputs.gauss_cvec(lat.L, lat.Nt, seed + 100 + k)).cuda()
+        eta = lat.apply_M(theta, R, dagger=True)
+        pool.append(eta)
+        for its in range(50, 1050, 50):
+            x, _, _, _ = lat.cg_solve(theta, eta, tol=1e-12, maxit=its, prec="fp32")
+            pool.append(eta - lat.apply_MdagM(theta, x, prec="fp64"))
+    net.set_params(inputs.net_init_weights(seed))
+    rng = np.random.default_rng(seed)
+    losses = []
+    for _ in range(steps):
+        loss, _ = net.train_step_residual(theta, pool[int(rng.integers(len(pool)))], lr=1e-3)
+        losses.append(loss)
+    net.bind("bf16", "paper")
     torch.cuda.synchronize()
-    t = time.perf_counter() - t0
-    return {"s_per_traj": t, "cg_iters_total": r["cg_iters_total"], "dH": r["dH"], "accepted": r["accepted"],
-            "mixed_dH_same_traj": mixed_first["dH"], "mixed_speedup": t / s_mixed, "trajectories": 1,
-            "tol": wl.tol}
+    return {"form": "residual |O z - r|^2 / |r|^2 on the method's own CG residuals at the starting angles",
+            "residuals": len(pool), "steps": steps, "loss_first": losses[0],
+            "loss_last_avg": float(np.mean(losses[-50:])), "setup_s": time.perf_counter() - t0,
+            "inference": "bf16 (MFMA)", "fallback": "paper"}
+
+
+def run_set(lat, theta, th_start, indices, wl, prec, pc):
+    """Trajectories with the given indices, each from th_start (restored
+    before every one), timed one by one; returns (results, seconds)."""
+    import torch
+    out, secs = [], []
+    for k in indices:
+        theta.copy_(th_start)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = lat.hmc_trajectory(theta, k, wl.n_steps, wl.traj_len, wl.tol, prec=prec, precond=pc)
+        torch.cuda.synchronize()
+        secs.append(time.perf_counter() - t0)
+        out.append(r)
+    return out, secs
 
 
 def main():
@@ -478,6 +542,7 @@ def main():
     if a.matvec_only:
         print(json.dumps({"matvec_large": matvec_large(only_L=a.matvec_only)}), flush=True)
         return
+    import numpy as np
     import torch
     from paper_2508_16298_amd import inputs
     from paper_2508_16298_amd import qedhmc as Q
@@ -487,34 +552,81 @@ def main():
     th0 = wl.initial_theta()
     theta = torch.from_numpy(th0).cuda()
     lat = Q.Lattice(wl.L, wl.Nt, dtau=wl.dtau, t=wl.t, J=wl.J, K=wl.K, seed=wl.seed)
+    pc = None if a.precond == "none" else a.precond
 
     # load every kernel once (code objects, LDS attributes) before timing
     v = torch.zeros((wl.Nt, wl.L, wl.L), dtype=torch.complex128, device="cuda")
     v[0, 0, 0] = 1.0
-    pc = None if a.precond == "none" else a.precond
-    lat.cg_solve(theta, v, tol=1e-3, maxit=50, prec=prec, precond=pc)
+    lat.cg_solve(theta, v, tol=1e-3, maxit=50, prec=prec, precond="paper" if pc == "paper" else None)
     lat.fermion_force(theta, v, prec=prec)
     lat.bosonic_action_force(theta)
     torch.cuda.synchronize()
 
-    traj = 0
-    for _ in range(a.warmup):
-        lat.hmc_trajectory(theta, traj, wl.n_steps, wl.traj_len, wl.tol, prec=prec, precond=pc)
-        traj += 1
-    torch.cuda.synchronize()
+    # (1) equilibration: a fixed number of chained trajectories (indices
+    # 0 .. E-1) from the workload's angles, untimed and independent of
+    # --warmup; their end point is the start of every later trajectory
+    t_eq = time.perf_counter()
+    eq = [lat.hmc_trajectory(theta, k, wl.n_steps, wl.traj_len, wl.tol, prec=prec) for k in range(a.equilibrate)]
+    th_start = theta.clone()
+    t_eq = time.perf_counter() - t_eq
+    net, training = None, None
+    if pc == "learned":
+        net = Q.Net(lat)
+        training = train_learned(lat, net, th_start)
 
+    # (2) warm-up and (3) timed trajectories: each from th_start with its
+    # own trajectory index (its own momenta, source and Metropolis draw), so
+    # the timed set is a fixed sample whatever --warmup is
+    run_set(lat, theta, th_start, [1000 + k for k in range(a.warmup)], wl, prec, pc)
+    timed_idx = [2000 + k for k in range(a.steps)]
     lat.profile(a.profile_every)
-    results = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(a.steps):
-        results.append(lat.hmc_trajectory(theta, traj, wl.n_steps, wl.traj_len, wl.tol, prec=prec, precond=pc))
-        traj += 1
+    results, secs = run_set(lat, theta, th_start, timed_idx, wl, prec, pc)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    kcls = Q.K_CG_FP32 if prec != "fp64" else Q.K_CG_FP64
-    n_k, ms_k = lat.profile_read(kcls)
+    prof = {c: lat.profile_read(c) for c in (Q.K_CG_FP32, Q.K_CG_FP64, Q.K_NET_MFMA, Q.K_MDAGM_FP32,
+                                             Q.K_MDAGM_FP64, Q.K_PCG_MV_FP32, Q.K_PCG_MV_FP64)}
     lat.profile(0)
+
+    # (4) the same trajectories (same start, same indices) on the other
+    # paths: the plain FP64 GPU path, and the mixed path with and without the
+    # learned preconditioner; the timed trajectory with the largest |dH| is
+    # always among the ones rerun in FP64
+    m = min(a.steps, a.compare)
+    worst = int(np.argmax([abs(r["dH"]) for r in results]))
+    cmp_pos = list(range(m)) + ([worst] if worst >= m else [])
+    cmp_idx = [timed_idx[i] for i in cmp_pos]
+
+    def side_by_side(name, p_prec, p_pc):
+        rs, ss = run_set(lat, theta, th_start, cmp_idx, wl, p_prec, p_pc)
+        rows = []
+        for i, r, s_ in zip(cmp_pos, rs, ss):
+            rows.append({"traj": timed_idx[i], "dH": r["dH"], "dH_timed_path": results[i]["dH"],
+                         "accepted": r["accepted"], "accepted_timed_path": results[i]["accepted"],
+                         "cg_iters_total": r["cg_iters_total"], "s": s_, "s_timed_path": secs[i],
+                         "status": r["status"], "max_true_resid": r["max_true_resid"],
+                         "pc_fallbacks": r.get("pc_fallbacks", 0)})
+        t_path = sum(ss[:m]) / m
+        t_here = sum(secs[:m]) / m
+        return {"path": name, "trajectories": rows, "s_per_traj_first": t_path, "timed_path_s_per_traj_first": t_here,
+                "time_ratio_vs_timed_path": t_path / t_here, "first": m}
+
+    paths = {}
+    if not (prec == "fp64" and pc is None):
+        paths["fp64"] = side_by_side("plain FP64 GPU path (FP64 CG at the same tolerance)", "fp64", None)
+    if a.compare_learned and pc != "learned" and prec != "fp64":
+        try:
+            with Q.Net(lat) as cnet:
+                tr = train_learned(lat, cnet, th_start)
+                paths["learned"] = side_by_side("mixed precision + learned preconditioner (flexible CG)", prec,
+                                                "learned")
+                paths["learned"]["training"] = tr
+                cnet.unbind()
+        except Q.QedhmcError as e:
+            paths["learned"] = {"error": str(e)}
+    if pc is not None and prec != "fp64":
+        paths["mixed_plain"] = side_by_side("mixed precision, no preconditioner", prec, None)
 
     # standalone fused M^dag M on the same lattice (the metric's matvec)
     cdt = torch.complex64 if prec != "fp64" else torch.complex128
@@ -525,7 +637,7 @@ def main():
     lat.profile(1)
     for _ in range(200):
         lat.apply_MdagM(theta, vin, prec=mv_prec, out=vout)
-    n_ev, ms_ev = lat.profile_read(Q.K_MDAGM_FP32 if prec != "fp64" else Q.K_MDAGM_FP64)
+    n_mv, ms_mv = lat.profile_read(Q.K_MDAGM_FP32 if prec != "fp64" else Q.K_MDAGM_FP64)
     lat.profile(0)
     # the same 200 calls between one event pair on the handle's stream
     # (torch's current stream): includes the host's per-call cost and gaps
@@ -536,18 +648,31 @@ def main():
     ev1.record()
     torch.cuda.synchronize()
     b2b_us = 1e3 * ev0.elapsed_time(ev1) / 200
-    n_mv, ms_mv = n_ev, ms_ev
 
     N = wl.L * wl.L * wl.Nt
     mv_bytes = (24 if prec != "fp64" else 48) * N
     mv_us = 1e3 * ms_mv / max(n_mv, 1)
     mv_gbs = mv_bytes / (mv_us * 1e-6) / 1e9 if n_mv else None
-    it_bytes = (104 if prec != "fp64" else 176) * N
+    # the dominant kernel of the timed path and its algorithmic work per launch
+    if pc == "learned":
+        kcls, work, unit, bound, peak, kname = (Q.K_NET_MFMA, 2.0 * 27 * 32 * 32 * N, "TFLOP/s", "mfma", 2500.0,
+                                                "k_conv_mfma<true> (one 32->32 3x3x3 layer, BF16 MFMA)")
+    elif pc == "paper":
+        kcls = Q.K_PCG_MV_FP32 if prec != "fp64" else Q.K_PCG_MV_FP64
+        work, unit, bound, peak = (24 if prec != "fp64" else 48) * N, "GB/s", "hbm", HBM_PEAK_GBS
+        kname = "k_mdagm (M^dag M of the preconditioned CG, 24 / 48 B per site counted)"
+    else:
+        kcls = Q.K_CG_FP32 if prec != "fp64" else Q.K_CG_FP64
+        work, unit, bound, peak = (104 if prec != "fp64" else 176) * N, "GB/s", "hbm", HBM_PEAK_GBS
+        kname = f"k_cg_iter<{'float' if prec != 'fp64' else 'double'}> (one fused CG iteration)"
+    n_k, ms_k = prof[kcls]
     avg_ms = ms_k / max(n_k, 1)
-    achieved = it_bytes / (avg_ms * 1e-3) / 1e9 if n_k else None
+    scale = 1e12 if unit == "TFLOP/s" else 1e9
+    achieved = work / (avg_ms * 1e-3) / scale if n_k else None
     s_per_traj = elapsed / a.steps
-    cg_total = sum(r["cg_iters_total"] for r in results) // a.steps
+    cg_all = sum(r["cg_iters_total"] for r in results)
     n_solves = results[-1]["n_solves"]
+    traffic = CG_ITER_COUNTER_BYTES["fp32" if prec != "fp64" else "fp64"] if pc is None else None
 
     out = {
         "metric": "s per HMC trajectory + M†M matvec HBM GB/s at L=24 Nτ=240, CG resid 1e-8",
@@ -564,39 +689,53 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": (f"{wl.name}: L={wl.L} Nt={wl.Nt} dtau={wl.dtau} t={wl.t} J={wl.J} K={wl.K}, "
-                         f"theta {wl.theta}{' sigma %g' % wl.sigma if wl.sigma else ''}, {wl.n_steps} leapfrog steps, length {wl.traj_len}, "
-                         f"CG true residual {wl.tol}, {'mixed FP32/FP64' if prec != 'fp64' else 'FP64'}"),
+                         f"theta {wl.theta}{' sigma %g' % wl.sigma if wl.sigma else ''} then {a.equilibrate} "
+                         f"chained equilibration trajectories; every timed trajectory starts there with its own "
+                         f"index; {wl.n_steps} leapfrog steps, length {wl.traj_len}, CG true residual {wl.tol}, "
+                         f"{'mixed FP32/FP64' if prec != 'fp64' else 'FP64'}"),
             "L": wl.L, "Nt": wl.Nt, "sites": N, "n_steps": wl.n_steps, "tol": wl.tol,
-            "precision": prec, "preconditioner": a.precond,
+            "precision": prec, "preconditioner": a.precond, "equilibration_trajectories": a.equilibrate,
+            "timed_traj_indices": [timed_idx[0], timed_idx[-1]],
         },
+        "s_per_traj_each": secs,
+        "cg_iters_per_traj": cg_all / a.steps,
+        "s_per_cg_iter": elapsed / max(cg_all, 1),
+        "equilibration": {"trajectories": a.equilibrate, "s": t_eq,
+                          "dH": [r["dH"] for r in eq], "accepted": [r["accepted"] for r in eq],
+                          "cg_iters_total": [r["cg_iters_total"] for r in eq]},
         "matvec_gbs": mv_gbs,
         "matvec": {"kernel": f"k_mdagm<{'float' if prec != 'fp64' else 'double'}> (standalone fused M^dag M)",
                    "avg_launch_us": mv_us, "alg_bytes_per_launch": mv_bytes, "gbs": mv_gbs,
                    "frac_of_hbm_peak": (mv_gbs / HBM_PEAK_GBS) if mv_gbs else None, "launches": n_mv,
                    "timing": "start/end events of each dispatch (hipExtLaunchKernelGGL)",
                    "host_driven_back_to_back_us": b2b_us},
-        "cg_iters_per_traj": cg_total,
-        "traj": [{k: r[k] for k in ("dH", "accepted", "cg_iters_total", "cg_iters_max",
-                                    "reliable_updates", "max_true_resid", "status")} for r in results],
+        "traj": [{"traj": timed_idx[i], **{k: r[k] for k in ("dH", "accepted", "cg_iters_total", "cg_iters_max",
+                                                             "reliable_updates", "max_true_resid", "status",
+                                                             "pc_fallbacks")}}
+                 for i, r in enumerate(results)],
+        "worst_dH_traj": timed_idx[worst],
+        "paths": paths,
         "roofline": {
-            "bound": "hbm",
-            "kernel": f"k_cg_iter<{'float' if prec != 'fp64' else 'double'}> (one fused CG iteration)",
+            "bound": bound,
+            "kernel": kname,
             "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": CG_ITER_COUNTER_BYTES["fp32" if prec != "fp64" else "fp64"],
-            "alg_bytes_per_launch": it_bytes,
+            "peak": peak,
+            "unit": unit,
+            "frac": (achieved / peak) if achieved else None,
+            "traffic": traffic,
+            "alg_work_per_launch": work,
             "avg_launch_us": avg_ms * 1e3,
             "timed_launches": n_k,
         },
     }
-    if prec != "fp64":
-        out["fp64_path"] = fp64_path(lat, wl, th0, results[0], s_per_traj, pc)
+    if training:
+        out["training"] = training
+    if net is not None:
+        net.close()
     lat.close()
     out["matvec_large"] = matvec_large()
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, cg_total, n_solves, a.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(wl, th_start.cpu().numpy(), cg_all / a.steps, n_solves, a.cpu_iters)
     print(json.dumps(out), flush=True)
 
 

@@ -77,19 +77,34 @@ typedef enum { QEDHMC_FP64 = 0, QEDHMC_FP32 = 1 } qedhmc_precision;
  * preconditioner P = G^dag G (Methods, "CG method and preconditioner";
  * Fig. 3): G the truncated inverse of the forward IC(0) factor of M^dag M at
  * pi flux on an 8 x 8 x 24 build lattice (0 <= dtau <= 6, |g| >= 1e-3),
- * tiled over the lattice per x parity; built on first use. */
-typedef enum { QEDHMC_PC_NONE = 0, QEDHMC_PC_PAPER = 1 } qedhmc_precond;
+ * tiled over the lattice per x parity; built on first use.
+ * QEDHMC_PC_LEARNED (not in the paper): the network bound to the handle by
+ * qedhmc_set_learned_precond, in flexible CG, with its residual judge and
+ * fallback (QEDHMC_PC_PAPER or none); QEDHMC_FP32 runs that solve in mixed
+ * precision (complex-FP32 residual, direction and M^dag M, FP64 solution,
+ * inner products and reliable-update residuals), QEDHMC_FP64 in FP64
+ * vectors (the flexible CG of qedhmc_fcg_solve). */
+typedef enum { QEDHMC_PC_NONE = 0, QEDHMC_PC_PAPER = 1, QEDHMC_PC_LEARNED = 2 } qedhmc_precond;
 
-/* Lattice, couplings and the seed of the trajectory random streams.
- * L even, 2 <= L <= 2048; Nt >= 1; L^2 Nt < 2^31.  The calls that keep a
- * whole time slice in one workgroup (apply_B, apply_M, fermion_force,
+/* Gauge action S_B = dtau sum_tau L_B: the compact Lagrangian L_B^c or the
+ * non-compact L_B^nc of Results, Eq. (3) (time-link term (dtheta)^2 instead
+ * of 1 - cos(dtheta), same prefactor 1/(J dtau^2)); the plaquette term
+ * K cos(curl theta) is the same in both. */
+typedef enum { QEDHMC_COMPACT = 0, QEDHMC_NONCOMPACT = 1 } qedhmc_action;
+
+/* Lattice, couplings, gauge action and the seed of the trajectory random
+ * streams.  L even, 2 <= L <= 2048; Nt >= 1; L^2 Nt < 2^31.  The calls that
+ * keep a whole time slice in one workgroup (apply_B, apply_M, fermion_force,
  * hmc_trajectory) take L <= 66 and return QEDHMC_EUNSUPPORTED beyond;
  * apply_MdagM and cg_solve (tiled M^dag M) take every L, the paper's
- * preconditioner as long as its stencil window fits a workgroup's LDS. */
+ * preconditioner as long as its stencil window fits a workgroup's LDS.
+ * action: a qedhmc_action; reserved must be 0. */
 typedef struct {
     int32_t L, Nt;
     double dtau, t, J, K;
     uint64_t seed;
+    int32_t action;
+    int32_t reserved;
 } qedhmc_params;
 
 /* Result of one trajectory (all energies FP64). */
@@ -105,6 +120,9 @@ typedef struct {
     int32_t status;        /* worst solve status (0 ok, 2 no convergence) */
     int32_t reliable_updates;
     double max_true_resid; /* largest final true relative residual        */
+    int32_t pc_fallbacks;  /* QEDHMC_PC_LEARNED: solves whose residual judge
+                              handed over to the fallback                 */
+    int32_t reserved;
 } qedhmc_traj_result;
 
 /* Create a handle: validates params, builds the bond tables on the device
@@ -182,9 +200,13 @@ qedhmc_status qedhmc_fermion_force(qedhmc_t h, const double *theta,
                                    const double *X, double *F,
                                    qedhmc_precision prec);
 
-/* Compact gauge action
- *   S_B = 1/(J dtau) sum [1 - cos(theta_{tau+1} - theta_tau)]
- *         + K dtau sum_plaquettes cos(curl theta)
+/* Gauge action of the handle (params.action)
+ *   compact      S_B = 1/(J dtau) sum [1 - cos(theta_{tau+1} - theta_tau)]
+ *                      + K dtau sum_plaquettes cos(curl theta)
+ *                (Results, L_B^c)
+ *   non-compact  S_B = 1/(J dtau) sum (theta_{tau+1} - theta_tau)^2
+ *                      + K dtau sum_plaquettes cos(curl theta)
+ *                (Results, Eq. 3)
  * (tau periodic) into *S_B_host (nullable) and, if F_B is not NULL, its force
  * -dS_B/dtheta into device double[2][Nt][L][L]. */
 qedhmc_status qedhmc_bosonic_action_force(qedhmc_t h, const double *theta,
@@ -206,6 +228,29 @@ qedhmc_status qedhmc_hmc_trajectory(qedhmc_t h, double *theta_inout,
                                     double traj_len, double tol, int32_t maxit,
                                     qedhmc_precision prec, qedhmc_precond pc,
                                     qedhmc_traj_result *out);
+
+/* Checkpoint and resume of one chain.  The trajectory random streams are
+ * counter-based (Philox keyed by the seed, the trajectory index in the
+ * counter; Methods, HQMC steps (i) and (iii)), so the lattice parameters,
+ * theta and the index of the next trajectory fix the rest of the chain: a
+ * chain resumed from a checkpoint runs bit for bit the trajectories it would
+ * have run without the stop.
+ * File (little endian): magic "QEDHMCK1", then uint64 version (1), int64 L,
+ * int64 Nt, double dtau, t, J, K, uint64 seed, int64 action, uint64
+ * next_traj, uint64 n = 2 Nt L^2, double theta[n] in the device layout, and
+ * a uint64 FNV-1a-64 hash of every byte before it.  qedhmc_checkpoint_save writes "<path>.tmp"
+ * and renames it over path (theta: device, the handle's lattice; synchronises
+ * the stream).  qedhmc_checkpoint_info reads the header of a verified file
+ * (no device work).  qedhmc_checkpoint_load checks the file (magic, version,
+ * sizes, hash) and that its parameters equal the handle's bit for bit, then
+ * copies theta to the device buffer and returns next_traj (synchronises).
+ * A bad or mismatched file is QEDHMC_EINVAL with nothing written. */
+qedhmc_status qedhmc_checkpoint_save(qedhmc_t h, const double *theta,
+                                     uint64_t next_traj, const char *path);
+qedhmc_status qedhmc_checkpoint_info(const char *path, qedhmc_params *params,
+                                     uint64_t *next_traj);
+qedhmc_status qedhmc_checkpoint_load(qedhmc_t h, const char *path,
+                                     double *theta, uint64_t *next_traj);
 
 /* ------------------------------------------------------------------------
  * Batched chains: many independent Markov chains, each on its own lattice
@@ -354,6 +399,20 @@ qedhmc_status qedhmc_fcg_solve(qedhmc_net_t n, const double *theta,
                                int32_t maxit, qedhmc_net_arith arith,
                                qedhmc_precond fallback, int32_t *iters,
                                double *true_rel_resid, int32_t *switched_at);
+
+/* Bind network n (created on this handle) as the handle's learned
+ * preconditioner: QEDHMC_PC_LEARNED in qedhmc_cg_solve and
+ * qedhmc_hmc_trajectory then runs flexible CG with z = N(theta, r) in
+ * arithmetic arith, judged by the residual as in qedhmc_fcg_solve, with
+ * fallback QEDHMC_PC_PAPER or QEDHMC_PC_NONE.  n = NULL unbinds.  The handle
+ * keeps a reference only: destroying the network unbinds it; the network
+ * must not outlive the handle.  EINVAL when n belongs to another handle or an
+ * enum is out of range.  (North-star extension; the paper's fixed
+ * preconditioner of Methods, "CG method and preconditioner", is the
+ * fallback.) */
+qedhmc_status qedhmc_set_learned_precond(qedhmc_t h, qedhmc_net_t n,
+                                         qedhmc_net_arith arith,
+                                         qedhmc_precond fallback);
 
 /* Kernel timing for measurement (not part of the method).  qedhmc_profile
  * with every > 0 times every every-th launch of the timed kernel classes

@@ -23,7 +23,8 @@ _LIB = None
 class Lat(C.Structure):
     """Lattice and couplings (Methods, Model and partition function)."""
     _fields_ = [("L", C.c_int32), ("Nt", C.c_int32), ("dtau", C.c_double),
-                ("t", C.c_double), ("J", C.c_double), ("K", C.c_double)]
+                ("t", C.c_double), ("J", C.c_double), ("K", C.c_double),
+                ("noncompact", C.c_int32)]
 
     @property
     def Vs(self):
@@ -90,8 +91,10 @@ def lib():
     return _LIB
 
 
-def lat(L, Nt, dtau=0.1, t=1.0, J=1.0, K=1.0):
-    return Lat(L, Nt, dtau, t, J, K)
+def lat(L, Nt, dtau=0.1, t=1.0, J=1.0, K=1.0, noncompact=False):
+    """Lattice and couplings; noncompact selects the gauge action L_B^nc of
+    Results, Eq. (3) instead of the compact L_B^c."""
+    return Lat(L, Nt, dtau, t, J, K, 1 if noncompact else 0)
 
 
 def _ptr(a):

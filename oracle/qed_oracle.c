@@ -31,10 +31,12 @@
 typedef double complex cplx;
 
 /* Lattice and couplings.  dtau: Trotter step; t: hopping amplitude;
- * J, K: couplings of the compact gauge action. */
+ * J, K: couplings of the gauge action; noncompact: 0 for the compact
+ * Lagrangian L_B^c, 1 for the non-compact L_B^nc of Results, Eq. (3). */
 typedef struct {
     int32_t L, Nt;
     double dtau, t, J, K;
+    int32_t noncompact;
 } oracle_lat;
 
 /* ------------------------------------------------------------------------ */
@@ -355,7 +357,9 @@ double oracle_bosonic_action(const oracle_lat *p, const double *theta)
             for (int s = 0; s < Vs; s++) {
                 const double a = theta[((size_t)d * Nt + (tau + 1) % Nt) * Vs + s];
                 const double b = theta[((size_t)d * Nt + tau) * Vs + s];
-                kin += 1.0 - cos(a - b);
+                /* compact: 1 - cos of the time difference (L_B^c);
+                 * non-compact: its square, same prefactor (Eq. 3) */
+                kin += p->noncompact ? (a - b) * (a - b) : 1.0 - cos(a - b);
             }
     for (int tau = 0; tau < Nt; tau++)
         for (int s = 0; s < Vs; s++) pot += cos(plaq(p, theta, tau, s));
@@ -374,10 +378,11 @@ void oracle_bosonic_force(const oracle_lat *p, const double *theta, double *F)
             for (int s = 0; s < Vs; s++) {
                 const size_t ia = ((size_t)d * Nt + (tau + 1) % Nt) * Vs + s;
                 const size_t ib = ((size_t)d * Nt + tau) * Vs + s;
-                /* term 1 - cos(a - b): d/da = sin(a-b), d/db = -sin(a-b) */
-                const double sn = sin(theta[ia] - theta[ib]);
-                F[ia] -= cj * sn;
-                F[ib] += cj * sn;
+                /* term 1 - cos(a - b): d/da = sin(a-b), d/db = -sin(a-b);
+                 * term (a - b)^2:      d/da = 2(a-b),   d/db = -2(a-b) */
+                const double g = p->noncompact ? 2.0 * (theta[ia] - theta[ib]) : sin(theta[ia] - theta[ib]);
+                F[ia] -= cj * g;
+                F[ib] += cj * g;
             }
     for (int tau = 0; tau < Nt; tau++)
         for (int s = 0; s < Vs; s++) {

@@ -7,6 +7,7 @@
 #include <tuple>
 #include <unordered_set>
 
+#include "net_internal.h"
 #include "qedhmc_internal.h"
 
 namespace qh {
@@ -103,6 +104,8 @@ qedhmc_status qedhmc_init_lattice(const qedhmc_params* params, void* stream, qed
     if (!(p.dtau >= 0.0) || !(p.J > 0.0) || !std::isfinite(p.t) || !std::isfinite(p.K))
         return einval("bad couplings (need dtau >= 0, J > 0, finite t and K)");
     if ((size_t)p.L * p.L * p.Nt >= ((size_t)1 << 31)) return einval("lattice too large");
+    if ((p.action != QEDHMC_COMPACT && p.action != QEDHMC_NONCOMPACT) || p.reserved != 0)
+        return einval("bad gauge action (QEDHMC_COMPACT or QEDHMC_NONCOMPACT; reserved 0)");
     *out = nullptr;
     qedhmc_ctx* h = new (std::nothrow) qedhmc_ctx{};
     if (!h) return QEDHMC_ENOMEM;
@@ -273,21 +276,45 @@ qedhmc_status qedhmc_apply_MdagM(qedhmc_t h, const double* theta, const void* in
     return launch_mdagm(h, prec, in, out, nullptr);
 }
 
+// switched (nullable): with the learned preconditioner, the iteration at
+// which its judge handed the solve to the fallback (-1: kept it)
 static qedhmc_status solve_at(qedhmc_ctx* h, const double* theta, const double* rhs, double* x, double tol,
                               int32_t maxit, qedhmc_precision prec, qedhmc_precond pc, int32_t* iters, double* rel,
-                              int* nrel) {
+                              int* nrel, int* switched = nullptr) {
     QH_TRY(ensure_gauge(h, theta, QEDHMC_FP64));
-    if (prec != QEDHMC_FP64) QH_TRY(ensure_gauge(h, theta, prec));
-    int it = 0, nr = 0;
+    if (prec != QEDHMC_FP64 || pc == QEDHMC_PC_LEARNED) QH_TRY(ensure_gauge(h, theta, QEDHMC_FP32));
+    int it = 0, nr = 0, sw = -1;
     double r = 0.0;
-    const qedhmc_status st = pc == QEDHMC_PC_PAPER ? pcg_solve_impl(h, rhs, x, tol, maxit, prec, &it, &r, &nr)
-                                                   : cg_solve_impl(h, rhs, x, tol, maxit, prec, &it, &r, &nr);
+    qedhmc_status st;
+    if (pc == QEDHMC_PC_LEARNED) {
+        if (!h->pc_net) return einval("QEDHMC_PC_LEARNED: no network bound to the handle");
+        if (prec == QEDHMC_FP64) {
+            int32_t it32 = 0, sw32 = -1;
+            st = qedhmc_fcg_solve(h->pc_net, theta, rhs, x, tol, maxit, h->pc_arith, h->pc_fallback, &it32, &r,
+                                  &sw32);
+            it = it32;
+            sw = sw32;
+        } else {
+            st = mfcg_solve_impl(h->pc_net, rhs, x, tol, maxit, h->pc_arith, h->pc_fallback, &it, &r, &nr, &sw);
+        }
+    } else if (pc == QEDHMC_PC_PAPER) {
+        st = pcg_solve_impl(h, rhs, x, tol, maxit, prec, &it, &r, &nr);
+    } else {
+        st = cg_solve_impl(h, rhs, x, tol, maxit, prec, &it, &r, &nr);
+    }
     if (iters) *iters = it;
     if (rel) *rel = r;
     if (nrel) *nrel = nr;
-    if (st == QEDHMC_ENOCONV)
+    if (switched) *switched = sw;
+    if (st == QEDHMC_ENOCONV && pc != QEDHMC_PC_LEARNED)
         set_error("CG reached maxit=" + std::to_string(maxit) + " with true residual " + std::to_string(r));
     return st;
+}
+
+static qedhmc_status check_pc(qedhmc_precond pc) {
+    if (pc != QEDHMC_PC_NONE && pc != QEDHMC_PC_PAPER && pc != QEDHMC_PC_LEARNED)
+        return einval("unknown preconditioner");
+    return QEDHMC_OK;
 }
 
 qedhmc_status qedhmc_cg_solve(qedhmc_t h, const double* theta, const double* rhs, double* x, double tol,
@@ -297,9 +324,27 @@ qedhmc_status qedhmc_cg_solve(qedhmc_t h, const double* theta, const double* rhs
     if (!theta || !rhs || !x) return einval("null pointer");
     if (rhs == x) return einval("rhs and x alias");
     if (!(tol > 0.0) || maxit < 1) return einval("need tol > 0 and maxit >= 1");
-    if (pc != QEDHMC_PC_NONE && pc != QEDHMC_PC_PAPER) return einval("unknown preconditioner");
+    QH_TRY(check_pc(pc));
     QH_TRY(check_prec(prec));
+    if (pc == QEDHMC_PC_LEARNED && !h->pc_net) return einval("QEDHMC_PC_LEARNED: no network bound to the handle");
     return solve_at(h, theta, rhs, x, tol, maxit, prec, pc, iters, true_rel_resid, nullptr);
+}
+
+qedhmc_status qedhmc_set_learned_precond(qedhmc_t h, qedhmc_net_t n, qedhmc_net_arith arith,
+                                         qedhmc_precond fallback) {
+    CHECK_H(h);
+    if (!n) {
+        h->pc_net = nullptr;
+        return QEDHMC_OK;
+    }
+    if (n->h != h) return einval("the network belongs to another lattice handle");
+    if (arith != QEDHMC_NET_FP32 && arith != QEDHMC_NET_BF16) return einval("bad network arithmetic");
+    if (fallback != QEDHMC_PC_NONE && fallback != QEDHMC_PC_PAPER)
+        return einval("the fallback is QEDHMC_PC_NONE or QEDHMC_PC_PAPER");
+    h->pc_net = n;
+    h->pc_arith = arith;
+    h->pc_fallback = fallback;
+    return QEDHMC_OK;
 }
 
 qedhmc_status qedhmc_precond_taps(qedhmc_t h, int32_t parity, int32_t* count, double* out, int32_t capacity) {
@@ -360,8 +405,9 @@ qedhmc_status qedhmc_hmc_trajectory(qedhmc_t h, double* theta, uint64_t traj, in
     CHECK_H(h);
     if (!theta || !out) return einval("null pointer");
     if (n_steps < 1 || !(traj_len > 0.0) || !(tol > 0.0) || maxit < 1) return einval("bad trajectory parameters");
-    if (pc != QEDHMC_PC_NONE && pc != QEDHMC_PC_PAPER) return einval("unknown preconditioner");
+    QH_TRY(check_pc(pc));
     QH_TRY(check_prec(prec));
+    if (pc == QEDHMC_PC_LEARNED && !h->pc_net) return einval("QEDHMC_PC_LEARNED: no network bound to the handle");
     std::memset(out, 0, sizeof(*out));
     const size_t N = nsites(h), nb = 2 * N;
     const double dt = traj_len / n_steps;
@@ -374,10 +420,11 @@ qedhmc_status qedhmc_hmc_trajectory(qedhmc_t h, double* theta, uint64_t traj, in
     auto solve = [&](const double* th) -> qedhmc_status {
         int32_t it = 0;
         double rel = 0.0;
-        int nr = 0;
-        const qedhmc_status st = solve_at(h, th, eta, X, tol, maxit, prec, pc, &it, &rel, &nr);
+        int nr = 0, sw = -1;
+        const qedhmc_status st = solve_at(h, th, eta, X, tol, maxit, prec, pc, &it, &rel, &nr, &sw);
         if (st != QEDHMC_OK && st != QEDHMC_ENOCONV) return st;
         if (st == QEDHMC_ENOCONV) worst = 2;
+        if (sw >= 0) out->pc_fallbacks++;
         out->n_solves++;
         it_total += it;
         if (it > it_max) it_max = it;
@@ -411,7 +458,9 @@ qedhmc_status qedhmc_hmc_trajectory(qedhmc_t h, double* theta, uint64_t traj, in
     // H at the end, (iii) Metropolis, restore on rejection
     QH_TRY(launch_dot_re(h, eta, X, 2 * N, sc + 5));
     QH_TRY(launch_sumsq(h, h->mom, nb, sc + 4));
-    QH_TRY(launch_metropolis(h, traj, sc));
+    // a solve that missed its tolerance leaves a dH that is not the leapfrog's
+    // (reversibility fails), so such a trajectory is always rejected
+    QH_TRY(launch_metropolis(h, traj, worst != 0, sc));
     QH_TRY(launch_restore(h, theta, h->theta0, sc, nb));
     QH_HIP(hipMemcpyAsync(h->h_pinned, sc, 9 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     QH_HIP(hipStreamSynchronize(h->stream));
@@ -432,6 +481,11 @@ qedhmc_status qedhmc_hmc_trajectory(qedhmc_t h, double* theta, uint64_t traj, in
     out->status = worst;
     out->reliable_updates = nrel_total;
     out->max_true_resid = max_rel;
+    if (worst != 0) {
+        set_error("a solve of the trajectory did not converge (largest true residual " + std::to_string(max_rel) +
+                  "); the proposal was rejected");
+        return QEDHMC_ENOCONV;
+    }
     return QEDHMC_OK;
 }
 

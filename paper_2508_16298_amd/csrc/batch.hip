@@ -910,7 +910,8 @@ qedhmc_status qedhmc_batch_trajectory(qedhmc_batch_t b, double* theta_all, uint6
         double* sc = h->scal + 64;
         QH_TRY(launch_dot_re(h, eta[c], X[c], 2 * N, sc + 5));
         QH_TRY(launch_sumsq(h, sl(b->mom, c), 2 * N, sc + 4));
-        QH_TRY(launch_metropolis(h, traj, sc));
+        // a chain with an unconverged solve rejects its proposal
+        QH_TRY(launch_metropolis(h, traj, out[c].status != 0, sc));
         QH_TRY(launch_restore(h, theta_all + b->toff[c], b->theta0 + b->toff[c], sc, 2 * N));
         QH_HIP(hipMemcpyAsync(h->h_pinned, sc, 9 * sizeof(double), hipMemcpyDeviceToHost, b->stream));
     }
@@ -929,6 +930,12 @@ qedhmc_status qedhmc_batch_trajectory(qedhmc_batch_t b, double* theta_all, uint6
         out[c].u = v[7];
         out[c].accepted = v[8] != 0.0 ? 1 : 0;
     }
+    for (int c = 0; c < n; c++)
+        if (out[c].status != 0) {
+            set_error("batch: a solve of chain " + std::to_string(c) +
+                      " did not converge; its proposal was rejected");
+            return QEDHMC_ENOCONV;
+        }
     return QEDHMC_OK;
 }
 

@@ -16,9 +16,10 @@ __global__ void k_sum_partials(const double* __restrict__ part, int n, double* _
 }
 
 // ---------------------------------------------------------------------------
-// Compact gauge action (Results, L_B^c, integrated as dtau sum_tau):
-//   S_B = 1/(J dtau) sum_{d,tau,s} [1 - cos(theta_{d,tau+1,s} - theta_{d,tau,s})]
+// Gauge action (Results, L_B^c and Eq. 3 for L_B^nc, integrated as dtau sum_tau):
+//   S_B = 1/(J dtau) sum_{d,tau,s} k(theta_{d,tau+1,s} - theta_{d,tau,s})
 //       + K dtau sum_{tau,s} cos Phi_{tau,s},
+//   k(u) = 1 - cos u (compact) or u^2 (non-compact),
 //   Phi_{tau,s} = th_x(s) + th_y(s+x) - th_x(s+y) - th_y(s).
 // One thread per space-time site; the force on the two bonds leaving the
 // site is assembled from the two time-link terms and the two plaquettes each
@@ -32,7 +33,7 @@ __device__ __forceinline__ double plaq(const double* __restrict__ th, const Lat&
     return tx[y * L + x] + ty[y * L + xp] - tx[yp * L + x] - ty[y * L + x];
 }
 
-__global__ void k_bosonic(Lat lt, double J, double K, double dtau, const double* __restrict__ th,
+__global__ void k_bosonic(Lat lt, double J, double K, double dtau, int noncompact, const double* __restrict__ th,
                           double* __restrict__ F, double* __restrict__ part) {
     __shared__ double red[16];
     const double cj = 1.0 / (J * dtau), kd = K * dtau;
@@ -51,8 +52,13 @@ __global__ void k_bosonic(Lat lt, double J, double K, double dtau, const double*
             const double a = td[(size_t)tau * lt.Vs + s];
             const double an = td[(size_t)tp * lt.Vs + s];
             const double ap = td[(size_t)tm * lt.Vs + s];
-            s_act += cj * (1.0 - cos(an - a));
-            f[d] = cj * (sin(an - a) - sin(a - ap));
+            if (noncompact) {
+                s_act += cj * (an - a) * (an - a);
+                f[d] = cj * (2.0 * (an - a) - 2.0 * (a - ap));
+            } else {
+                s_act += cj * (1.0 - cos(an - a));
+                f[d] = cj * (sin(an - a) - sin(a - ap));
+            }
         }
         if (F) {
             const double g0 = kd * sin(P);
@@ -68,8 +74,8 @@ __global__ void k_bosonic(Lat lt, double J, double K, double dtau, const double*
 
 qedhmc_status launch_bosonic(qedhmc_ctx* h, const double* theta, double* F_B, double* S_dev) {
     double* part = (h->partial + 12 * (size_t)h->lat.Nt);
-    hipLaunchKernelGGL(k_bosonic, dim3(kGridR), dim3(kBlockR), 0, h->stream, h->lat, h->p.J, h->p.K, h->p.dtau, theta,
-                       F_B, part);
+    hipLaunchKernelGGL(k_bosonic, dim3(kGridR), dim3(kBlockR), 0, h->stream, h->lat, h->p.J, h->p.K, h->p.dtau,
+                       h->p.action == QEDHMC_NONCOMPACT ? 1 : 0, theta, F_B, part);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, h->stream, (const double*)part, kGridR, S_dev);
     QH_HIP(hipGetLastError());
     return QEDHMC_OK;
@@ -200,7 +206,10 @@ qedhmc_status launch_drift(qedhmc_ctx* h, double* theta, const double* mom, doub
 // Metropolis (step iii): scalar slots sc[0..5] = SB0, K0, SF0, SB1, K1, SF1;
 // writes sc[6] = dH, sc[7] = u, sc[8] = accepted (1/0).
 // ---------------------------------------------------------------------------
-__global__ void k_metropolis(uint64_t seed, uint64_t traj, double* __restrict__ sc) {
+// reject: a solve of the trajectory did not converge, so the energy change
+// is not that of the reversible leapfrog and the proposal is refused whatever
+// dH and u say.
+__global__ void k_metropolis(uint64_t seed, uint64_t traj, int reject, double* __restrict__ sc) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const double H0 = sc[0] + sc[1] + sc[2];
     const double H1 = sc[3] + sc[4] + sc[5];
@@ -208,14 +217,14 @@ __global__ void k_metropolis(uint64_t seed, uint64_t traj, double* __restrict__ 
     uint32_t x[4];
     draw_block(seed, traj, 3u, 0u, x);
     const double u = uniform53(x[0], x[1]);
-    const bool acc = (dH <= 0.0) || (u < exp(-dH));
+    const bool acc = !reject && ((dH <= 0.0) || (u < exp(-dH)));
     sc[6] = dH;
     sc[7] = u;
     sc[8] = acc ? 1.0 : 0.0;
 }
 
-qedhmc_status launch_metropolis(qedhmc_ctx* h, uint64_t traj, double* scal_dev) {
-    hipLaunchKernelGGL(k_metropolis, dim3(1), dim3(64), 0, h->stream, h->p.seed, traj, scal_dev);
+qedhmc_status launch_metropolis(qedhmc_ctx* h, uint64_t traj, bool reject, double* scal_dev) {
+    hipLaunchKernelGGL(k_metropolis, dim3(1), dim3(64), 0, h->stream, h->p.seed, traj, reject ? 1 : 0, scal_dev);
     QH_HIP(hipGetLastError());
     return QEDHMC_OK;
 }

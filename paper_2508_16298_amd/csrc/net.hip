@@ -34,19 +34,21 @@ __device__ __forceinline__ double inv_scale(const double* rr, int N) {
     return s > 0.0 ? 1.0 / s : 0.0;
 }
 
-// the six input channels at site m; sg multiplies the residual channels
+// the six input channels at site m; sg multiplies the residual channels.
+// The residual is complex FP64 or, inside the mixed-precision solver, FP32.
+template <typename TR>
 __device__ __forceinline__ void features(const NetGeo& g, const cplx<float>* __restrict__ g32,
-                                         const cplx<double>* __restrict__ r, int m, float sg, double inv_s,
+                                         const cplx<TR>* __restrict__ r, int m, float sg, double inv_s,
                                          float (&f)[6]) {
     const cplx<float> gx = g32[m];
     const cplx<float> gy = g32[(size_t)g.N + m];
-    const cplx<double> rv = r[m];
+    const cplx<TR> rv = r[m];
     f[0] = gx.re;
     f[1] = gx.im;
     f[2] = gy.re;
     f[3] = gy.im;
-    f[4] = sg * (float)(rv.re * inv_s);
-    f[5] = sg * (float)(rv.im * inv_s);
+    f[4] = sg * (float)((double)rv.re * inv_s);
+    f[5] = sg * (float)((double)rv.im * inv_s);
 }
 
 // ---------------------------------------------------------------------------
@@ -54,10 +56,10 @@ __device__ __forceinline__ void features(const NetGeo& g, const cplx<float>* __r
 // W device layout [27][CIN][COUT]; pre = W * in + b; act = SiLU(pre) or pre.
 // FIRST: the input is the feature map of (theta, r).
 // ---------------------------------------------------------------------------
-template <int CIN, int COUT, bool FIRST, bool SILU, typename TIN, typename TOUT>
+template <int CIN, int COUT, bool FIRST, bool SILU, typename TIN, typename TOUT, typename TR = double>
 __global__ __launch_bounds__(256) void k_conv_fwd(NetGeo g, const TIN* __restrict__ in,
                                                   const cplx<float>* __restrict__ g32,
-                                                  const cplx<double>* __restrict__ r, const double* __restrict__ rr,
+                                                  const cplx<TR>* __restrict__ r, const double* __restrict__ rr,
                                                   const float* __restrict__ W, const float* __restrict__ b,
                                                   float* __restrict__ pre, TOUT* __restrict__ act) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
@@ -420,11 +422,16 @@ qedhmc_status net_alloc_train(qedhmc_net* n);
 
 // first layer (FP32 arithmetic) writing BF16 activations, last layer
 // reading BF16 activations: the ends of the BF16 forward
-qedhmc_status launch_first_bf16(const NetGeo& g, hipStream_t st, const cplx<float>* g32, const double* r,
+qedhmc_status launch_first_bf16(const NetGeo& g, hipStream_t st, const cplx<float>* g32, const void* r, bool r32,
                                 const double* rr, const float* W, const float* b, uint16_t* out) {
-    hipLaunchKernelGGL((k_conv_fwd<6, 32, true, true, float, uint16_t>), dim3(blocks_for(g.N, 256)), dim3(256), 0,
-                       st, g, (const float*)nullptr, g32, reinterpret_cast<const cplx<double>*>(r), rr, W, b,
-                       (float*)nullptr, out);
+    if (r32)
+        hipLaunchKernelGGL((k_conv_fwd<6, 32, true, true, float, uint16_t, float>), dim3(blocks_for(g.N, 256)),
+                           dim3(256), 0, st, g, (const float*)nullptr, g32, static_cast<const cplx<float>*>(r), rr,
+                           W, b, (float*)nullptr, out);
+    else
+        hipLaunchKernelGGL((k_conv_fwd<6, 32, true, true, float, uint16_t>), dim3(blocks_for(g.N, 256)), dim3(256),
+                           0, st, g, (const float*)nullptr, g32, static_cast<const cplx<double>*>(r), rr, W, b,
+                           (float*)nullptr, out);
     QH_HIP(hipGetLastError());
     return QEDHMC_OK;
 }
@@ -476,17 +483,21 @@ static qedhmc_status sumsq_to(qedhmc_net* n, const double* v, size_t count, doub
     return launch_sumsq(n->h, v, count, dst);
 }
 
-// layer l forward in FP32: input act[l] (or the features for l = 0)
-static qedhmc_status fwd_layer_f32(qedhmc_net* n, int l, const double* r, const float* in, float* pre, float* act) {
+// layer l forward in FP32: input act[l] (or the features for l = 0, from
+// the residual r: complex FP64, or FP32 when r32; rr: device |r|^2)
+static qedhmc_status fwd_layer_f32(qedhmc_net* n, int l, const void* r, bool r32, const double* rr, const float* in,
+                                   float* pre, float* act) {
     const NetGeo& g = n->g;
     const float* W = n->params + n->woff[l];
     const float* b = n->params + n->boff[l];
     const dim3 grid(blocks_for(g.N, 256)), blk(256);
     hipStream_t st = n->h->stream;
     const cplx<float>* g32 = n->h->gauge32;
-    const cplx<double>* rc = reinterpret_cast<const cplx<double>*>(r);
-    const double* rr = n->dscal;
-    if (l == 0)
+    const cplx<double>* rc = static_cast<const cplx<double>*>(r);
+    if (l == 0 && r32)
+        hipLaunchKernelGGL((k_conv_fwd<6, 32, true, true, float, float, float>), grid, blk, 0, st, g, in, g32,
+                           static_cast<const cplx<float>*>(r), rr, W, b, pre, act);
+    else if (l == 0)
         hipLaunchKernelGGL((k_conv_fwd<6, 32, true, true, float, float>), grid, blk, 0, st, g, in, g32, rc, rr, W, b, pre, act);
     else if (l < kNetLayers - 1) {
         hipEvent_t e0, e1;
@@ -510,7 +521,7 @@ static qedhmc_status net_forward(qedhmc_net* n, const double* theta, const doubl
                                  bool build_gauge = true) {
     if (build_gauge) QH_TRY(ensure_gauge(n->h, theta, QEDHMC_FP32));
     QH_TRY(sumsq_to(n, r, 2 * (size_t)n->g.N, n->dscal + 0));
-    if (a == QEDHMC_NET_BF16 && !keep) return net_forward_bf16(n, r);
+    if (a == QEDHMC_NET_BF16 && !keep) return net_forward_bf16(n, r, false, n->dscal);
     const float* in = nullptr;
     for (int l = 0; l < kNetLayers; l++) {
         float* out;
@@ -521,7 +532,25 @@ static qedhmc_status net_forward(qedhmc_net* n, const double* theta, const doubl
         } else {
             out = (l == kNetLayers - 1) ? n->act[kNetLayers] : n->gbuf[l & 1];
         }
-        QH_TRY(fwd_layer_f32(n, l, r, in, pre, out));
+        QH_TRY(fwd_layer_f32(n, l, r, false, n->dscal, in, pre, out));
+        in = out;
+    }
+    return QEDHMC_OK;
+}
+
+}  // namespace qh
+
+namespace qh {
+
+// Inference on a residual already in device memory, FP64 or (r32) FP32, with
+// |r|^2 at rr (device) and the FP32 e^{i theta} cache of the handle already
+// built; output channels in n->act[kNetLayers].
+qedhmc_status net_infer(qedhmc_net* n, const void* r, bool r32, const double* rr, qedhmc_net_arith a) {
+    if (a == QEDHMC_NET_BF16) return net_forward_bf16(n, r, r32, rr);
+    const float* in = nullptr;
+    for (int l = 0; l < kNetLayers; l++) {
+        float* out = (l == kNetLayers - 1) ? n->act[kNetLayers] : n->gbuf[l & 1];
+        QH_TRY(fwd_layer_f32(n, l, r, r32, rr, in, nullptr, out));
         in = out;
     }
     return QEDHMC_OK;
@@ -601,7 +630,7 @@ qedhmc_status qedhmc_net_create(qedhmc_t h, qedhmc_net_t* out) {
     for (int k = 0; k < 2; k++) ok = ok && hipMalloc(&n->gbuf[k], N * 32 * sizeof(float)) == hipSuccess;
     ok = ok && hipMalloc(&n->act[kNetLayers], N * 2 * sizeof(float)) == hipSuccess;
     for (int k = 0; k < 2; k++) ok = ok && hipMalloc(&n->actb[k], N * 32 * sizeof(uint16_t)) == hipSuccess;
-    ok = ok && hipMalloc(&n->dscal, 16 * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc(&n->dscal, 32 * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc(&n->dpart, (size_t)4 * kRedBlocks * sizeof(double)) == hipSuccess;
     ok = ok && hipHostMalloc(&n->hpin, 16 * sizeof(double), hipHostMallocDefault) == hipSuccess;
     ok = ok && hipMalloc(&n->fr, N * sizeof(cplx<double>)) == hipSuccess;
@@ -625,6 +654,7 @@ qedhmc_status qedhmc_net_create(qedhmc_t h, qedhmc_net_t* out) {
 qedhmc_status qedhmc_net_destroy(qedhmc_net_t n) {
     if (!n) return QEDHMC_OK;
     if (n->h) (void)hipStreamSynchronize(n->h->stream);
+    if (n->h && n->h->pc_net == n) n->h->pc_net = nullptr;  // no longer the handle's learned preconditioner
     (void)hipFree(n->params);
     (void)hipFree(n->grads);
     (void)hipFree(n->adam_m);

@@ -66,16 +66,27 @@ __device__ __forceinline__ uint16_t from_f32<uint16_t>(float v) {
     return f32_to_bf16(v);
 }
 
-qedhmc_status launch_first_bf16(const NetGeo& g, hipStream_t st, const cplx<float>* g32, const double* r,
+// r: complex FP64, or FP32 when r32; rr: device |r|^2
+qedhmc_status launch_first_bf16(const NetGeo& g, hipStream_t st, const cplx<float>* g32, const void* r, bool r32,
                                 const double* rr, const float* W, const float* b, uint16_t* out);
 qedhmc_status launch_last_bf16(const NetGeo& g, hipStream_t st, const uint16_t* in, const float* W, const float* b,
                                float* out);
 
-// BF16 forward of the network (MFMA for the 32 -> 32 layers); leaves the
-// two output channels in FP32 where the FP32 forward leaves them
-qedhmc_status net_forward_bf16(qedhmc_net* n, const double* r);
+// BF16 forward of the network (MFMA for the 32 -> 32 layers) on the
+// residual r (complex FP64, or FP32 when r32) with |r|^2 at rr (device);
+// leaves the two output channels in FP32 where the FP32 forward leaves them
+qedhmc_status net_forward_bf16(qedhmc_net* n, const void* r, bool r32, const double* rr);
+// inference in either arithmetic on a residual already on the device (the
+// FP32 e^{i theta} cache of the handle built); output in n->act[kNetLayers]
+qedhmc_status net_infer(qedhmc_net* n, const void* r, bool r32, const double* rr, qedhmc_net_arith a);
 // number of BF16 weight elements the MFMA layers keep (fragment order)
 size_t net_bf16_weight_elems();
+// mixed-precision flexible CG with the network as preconditioner (mfcg.hip):
+// FP32 residual, direction and matvec, FP64 solution, reductions and
+// reliable updates; the handle's FP64 and FP32 e^{i theta} caches built
+qedhmc_status mfcg_solve_impl(qedhmc_net* n, const double* rhs, double* x, double tol, int maxit,
+                              qedhmc_net_arith arith, qedhmc_precond fallback, int* iters, double* true_rel,
+                              int* n_reliable, int* switched_at);
 
 }  // namespace qh
 

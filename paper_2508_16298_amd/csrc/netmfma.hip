@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_mfma(NetGeo g, const uint16_t* 
         }
 }
 
-qedhmc_status net_forward_bf16(qedhmc_net* n, const double* r) {
+qedhmc_status net_forward_bf16(qedhmc_net* n, const void* r, bool r32, const double* rr) {
     const NetGeo& g = n->g;
     hipStream_t st = n->h->stream;
     if (!n->wbf_ready) {
@@ -116,7 +116,7 @@ qedhmc_status net_forward_bf16(qedhmc_net* n, const double* r) {
         QH_HIP(hipGetLastError());
         n->wbf_ready = true;
     }
-    QH_TRY(launch_first_bf16(g, st, n->h->gauge32, r, n->dscal, n->params + n->woff[0], n->params + n->boff[0],
+    QH_TRY(launch_first_bf16(g, st, n->h->gauge32, r, r32, rr, n->params + n->woff[0], n->params + n->boff[0],
                              n->actb[0]));
     int cur = 0;
     const int blocks = (g.N + kSitesPerBlock - 1) / kSitesPerBlock;

@@ -504,6 +504,8 @@ struct PcPass {
     int gstart[2][9];  // per parity: start of the taps of tau offset amin + k, k = 0 .. 8
 };
 
+struct qedhmc_net;
+
 struct qedhmc_ctx {
     qedhmc_params p;
     qh::Lat lat;
@@ -567,6 +569,11 @@ struct qedhmc_ctx {
     PcPass pc_pass[2];                // G and G^dag
     void* pc_dev64;                   // device taps, FP64 and FP32
     void* pc_dev32;
+    // the learned preconditioner (QEDHMC_PC_LEARNED): a network bound to this
+    // handle, its arithmetic and the fallback its residual judge hands over to
+    qedhmc_net* pc_net;
+    qedhmc_net_arith pc_arith;
+    qedhmc_precond pc_fallback;
 };
 
 namespace qh {
@@ -645,7 +652,9 @@ qedhmc_status launch_dot_re(qedhmc_ctx* h, const double* a, const double* b, siz
 qedhmc_status launch_sumsq(qedhmc_ctx* h, const double* a, size_t n, double* out_dev);
 qedhmc_status launch_kick(qedhmc_ctx* h, double* mom, const double* F, const double* Fb, double c, size_t n);
 qedhmc_status launch_drift(qedhmc_ctx* h, double* theta, const double* mom, double c, size_t n);
-qedhmc_status launch_metropolis(qedhmc_ctx* h, uint64_t traj, double* scal_dev);
+// Metropolis test of the trajectory (dH, u, decision into scal_dev[6..8]);
+// reject = true refuses the proposal whatever dH is (an unconverged solve)
+qedhmc_status launch_metropolis(qedhmc_ctx* h, uint64_t traj, bool reject, double* scal_dev);
 qedhmc_status launch_restore(qedhmc_ctx* h, double* theta, const double* theta0, const double* scal_dev, size_t n);
 
 }  // namespace qh

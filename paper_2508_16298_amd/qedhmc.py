@@ -20,8 +20,10 @@ OK, EINVAL, ENOCONV, EHIP, ENOMEM, EUNSUPPORTED = range(6)
 (K_MDAGM_FP32, K_MDAGM_FP64, K_FORCE, K_CG_FP32, K_CG_FP64, K_PCG_MV_FP32, K_PCG_MV_FP64, K_NET_MFMA,
  K_NET_FP32) = range(9)
 FP64, FP32 = 0, 1
-PC_NONE, PC_PAPER = 0, 1
-_PC = {None: PC_NONE, "none": PC_NONE, "paper": PC_PAPER, PC_NONE: PC_NONE, PC_PAPER: PC_PAPER}
+COMPACT, NONCOMPACT = 0, 1
+PC_NONE, PC_PAPER, PC_LEARNED = 0, 1, 2
+_PC = {None: PC_NONE, "none": PC_NONE, "paper": PC_PAPER, "learned": PC_LEARNED, PC_NONE: PC_NONE,
+       PC_PAPER: PC_PAPER, PC_LEARNED: PC_LEARNED}
 
 _PREC = {"fp64": FP64, "fp32": FP32, "mixed": FP32, FP64: FP64, FP32: FP32}
 
@@ -34,7 +36,8 @@ class QedhmcError(RuntimeError):
 
 class Params(C.Structure):
     _fields_ = [("L", C.c_int32), ("Nt", C.c_int32), ("dtau", C.c_double), ("t", C.c_double),
-                ("J", C.c_double), ("K", C.c_double), ("seed", C.c_uint64)]
+                ("J", C.c_double), ("K", C.c_double), ("seed", C.c_uint64), ("action", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class TrajResult(C.Structure):
@@ -43,7 +46,8 @@ class TrajResult(C.Structure):
                 ("K1", C.c_double), ("u", C.c_double), ("accepted", C.c_int32),
                 ("n_solves", C.c_int32), ("cg_iters_total", C.c_int32),
                 ("cg_iters_max", C.c_int32), ("status", C.c_int32),
-                ("reliable_updates", C.c_int32), ("max_true_resid", C.c_double)]
+                ("reliable_updates", C.c_int32), ("max_true_resid", C.c_double),
+                ("pc_fallbacks", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -89,6 +93,10 @@ def load():
         "qedhmc_net_apply": [_P, _P, _P, _P, C.c_int],
         "qedhmc_net_train_step": [_P, _P, _P, _P, C.c_double, C.c_int, C.POINTER(C.c_double), _P],
         "qedhmc_net_train_step_residual": [_P, _P, _P, C.c_double, C.c_int, C.POINTER(C.c_double), _P],
+        "qedhmc_set_learned_precond": [_P, _P, C.c_int, C.c_int],
+        "qedhmc_checkpoint_save": [_P, _P, C.c_uint64, C.c_char_p],
+        "qedhmc_checkpoint_info": [C.c_char_p, C.POINTER(Params), C.POINTER(C.c_uint64)],
+        "qedhmc_checkpoint_load": [_P, C.c_char_p, _P, C.POINTER(C.c_uint64)],
         "qedhmc_fcg_solve": [_P, _P, _P, _P, C.c_double, C.c_int32, C.c_int, C.c_int, C.POINTER(C.c_int32),
                              C.POINTER(C.c_double), C.POINTER(C.c_int32)],
         "qedhmc_batch_create": [C.POINTER(Params), C.c_int32, _P, C.POINTER(_P)],
@@ -131,13 +139,21 @@ def _stream_handle():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def checkpoint_info(path):
+    """(params dict, next_traj) from a checkpoint file's verified header (no device work)."""
+    p = Params()
+    nxt = C.c_uint64(0)
+    _check(load().qedhmc_checkpoint_info(os.fsencode(path), C.byref(p), C.byref(nxt)))
+    return {k: getattr(p, k) for k, _ in p._fields_}, nxt.value
+
+
 class Lattice:
     """A qedhmc handle (qedhmc_init_lattice) bound to torch's current stream."""
 
-    def __init__(self, L, Nt, dtau=0.1, t=1.0, J=1.0, K=1.0, seed=0):
+    def __init__(self, L, Nt, dtau=0.1, t=1.0, J=1.0, K=1.0, seed=0, noncompact=False):
         import torch
         self.L, self.Nt = int(L), int(Nt)
-        self.params = Params(self.L, self.Nt, dtau, t, J, K, seed)
+        self.params = Params(self.L, self.Nt, dtau, t, J, K, seed, NONCOMPACT if noncompact else COMPACT, 0)
         self._torch = torch
         h = _P()
         _check(load().qedhmc_init_lattice(C.byref(self.params), _stream_handle(), C.byref(h)))
@@ -273,15 +289,35 @@ class Lattice:
 
     def hmc_trajectory(self, theta, traj, n_steps, traj_len=1.0, tol=1e-10, maxit=1_000_000,
                        prec="fp64", precond=None):
-        """theta is updated in place (proposal on acceptance); returns the result dict."""
+        """theta is updated in place (proposal on acceptance); returns the result dict.
+        A trajectory with an unconverged solve (ENOCONV) is rejected and returns
+        its dict with status 2."""
         self._check_theta(theta)
         res = TrajResult()
         self._sync_stream()
         _check(load().qedhmc_hmc_trajectory(self.h, _ptr(theta), int(traj), int(n_steps),
                                             float(traj_len), float(tol), int(maxit), _PREC[prec],
-                                            _PC[precond], C.byref(res)))
+                                            _PC[precond], C.byref(res)), allow=(OK, ENOCONV))
         return res.as_dict()
 
+
+    def checkpoint_save(self, theta, next_traj, path):
+        """Write the chain state (parameters, theta, next trajectory index) to path."""
+        self._check_theta(theta)
+        self._sync_stream()
+        _check(load().qedhmc_checkpoint_save(self.h, _ptr(theta), int(next_traj), os.fsencode(path)))
+
+    def checkpoint_load(self, path, theta=None):
+        """Read a checkpoint of this lattice into theta (allocated if None);
+        returns (theta, next_traj)."""
+        import torch
+        if theta is None:
+            theta = torch.empty((2, self.Nt, self.L, self.L), dtype=torch.float64, device="cuda")
+        self._check_theta(theta)
+        nxt = C.c_uint64(0)
+        self._sync_stream()
+        _check(load().qedhmc_checkpoint_load(self.h, os.fsencode(path), _ptr(theta), C.byref(nxt)))
+        return theta, nxt.value
 
     def profile(self, every):
         """Time every every-th launch of the timed kernels with HIP events (0: off)."""
@@ -304,14 +340,15 @@ class Batch:
     theta_off[c] in (2, Nt_c, L_c, L_c) order; vectors complex128
     (vec_off[-1],) with chain c at vec_off[c]."""
 
-    def __init__(self, sizes, dtau=0.1, t=1.0, J=1.0, K=1.0, seeds=None):
+    def __init__(self, sizes, dtau=0.1, t=1.0, J=1.0, K=1.0, seeds=None, noncompact=False):
         import numpy as np
         import torch
         self._torch = torch
         self.sizes = [(int(L), int(Nt)) for L, Nt in sizes]
         n = len(self.sizes)
         seeds = list(range(n)) if seeds is None else [int(s) for s in seeds]
-        arr = (Params * n)(*[Params(L, Nt, dtau, t, J, K, sd) for (L, Nt), sd in zip(self.sizes, seeds)])
+        act = NONCOMPACT if noncompact else COMPACT
+        arr = (Params * n)(*[Params(L, Nt, dtau, t, J, K, sd, act, 0) for (L, Nt), sd in zip(self.sizes, seeds)])
         self.params = arr
         h = _P()
         _check(load().qedhmc_batch_create(arr, n, _stream_handle(), C.byref(h)))
@@ -379,11 +416,13 @@ class Batch:
         return x_all, st, it, rel
 
     def trajectory(self, theta_all, traj, n_steps, traj_len=1.0, tol=1e-10, maxit=1_000_000, prec="fp64"):
-        """theta_all updated per chain in place; returns a list of result dicts."""
+        """theta_all updated per chain in place; returns a list of result dicts.
+        A chain with an unconverged solve rejects its proposal (status 2)."""
         self._check_all(theta_all, int(self.theta_off[-1]), self._torch.float64)
         res = (TrajResult * self.n)()
         _check(load().qedhmc_batch_trajectory(self.h, _ptr(theta_all), int(traj), int(n_steps),
-                                              float(traj_len), float(tol), int(maxit), _PREC[prec], res))
+                                              float(traj_len), float(tol), int(maxit), _PREC[prec], res),
+               allow=(OK, ENOCONV))
         return [r.as_dict() for r in res]
 
 
@@ -490,6 +529,15 @@ class Net:
                                                      C.byref(loss),
                                                      grad.ctypes.data_as(C.c_void_p) if want_grad else None))
         return loss.value, grad
+
+    def bind(self, arith="bf16", fallback="paper"):
+        """Make this network the lattice's learned preconditioner
+        (precond="learned" in cg_solve and hmc_trajectory)."""
+        _check(load().qedhmc_set_learned_precond(self.lat.h, self.h, _ARITH[arith], _PC[fallback]))
+        return self
+
+    def unbind(self):
+        _check(load().qedhmc_set_learned_precond(self.lat.h, None, 0, 0))
 
     def fcg_solve(self, theta, rhs, tol=1e-10, maxit=100_000, arith="bf16", fallback="paper", x=None):
         """Returns (x, status, iters, true_rel, switched_at)."""

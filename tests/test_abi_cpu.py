@@ -31,6 +31,15 @@ def test_library_is_gfx950_hip():
     assert b"gfx950" in data
 
 
+def test_init_rejects_bad_gauge_action_without_touching_the_device():
+    lib = Q.load()
+    h = C.c_void_p(1234)
+    for act, res in ((2, 0), (-1, 0), (0, 1)):
+        p = Q.Params(4, 4, 0.1, 1.0, 1.0, 1.0, 0, act, res)
+        assert lib.qedhmc_init_lattice(C.byref(p), None, C.byref(h)) == Q.EINVAL
+        assert "gauge action" in Q.last_error()
+
+
 @pytest.mark.parametrize("L,Nt", [(3, 4), (0, 4), (5, 1), (4, 0), (2050, 4), (2048, 1024)])
 def test_init_rejects_bad_lattices_without_touching_the_device(L, Nt):
     lib = Q.load()
@@ -50,3 +59,50 @@ def test_null_arguments_are_rejected():
     p = Q.Params(4, 4, 0.1, 1.0, -1.0, 1.0, 0)  # J <= 0
     h = C.c_void_p()
     assert lib.qedhmc_init_lattice(C.byref(p), None, C.byref(h)) == Q.EINVAL
+
+
+def _fnv1a(b):
+    h = 1469598103934665603
+    for x in b:
+        h ^= x
+        h = (h * 1099511628211) % (1 << 64)
+    return h
+
+
+def _write_checkpoint(path, L, Nt, next_traj, theta, dtau=0.1, t=1.0, J=1.0, K=1.0, seed=7, action=0):
+    import struct
+    body = b"QEDHMCK1" + struct.pack("<Qqqdddd", 1, L, Nt, dtau, t, J, K)
+    body += struct.pack("<QqQQ", seed, action, next_traj, theta.size) + theta.astype("<f8").tobytes()
+    open(path, "wb").write(body + struct.pack("<Q", _fnv1a(body)))
+
+
+def test_checkpoint_info_reads_the_documented_format(tmp_path):
+    """A checkpoint written here byte by byte from the layout qedhmc.h states
+    is read back by qedhmc_checkpoint_info; a flipped byte, a wrong magic, a
+    wrong length or an odd L are refused (EINVAL)."""
+    import numpy as np
+    L, Nt = 4, 3
+    th = np.random.default_rng(1).uniform(0, 6.28, size=(2, Nt, L, L))
+    path = str(tmp_path / "chain.ckpt")
+    _write_checkpoint(path, L, Nt, 12345, th, dtau=0.05, J=1.25, seed=99, action=1)
+    prm, nxt = Q.checkpoint_info(path)
+    assert (prm["L"], prm["Nt"], prm["seed"], prm["action"], nxt) == (L, Nt, 99, Q.NONCOMPACT, 12345)
+    assert (prm["dtau"], prm["t"], prm["J"], prm["K"]) == (0.05, 1.0, 1.25, 1.0)
+    raw = bytearray(open(path, "rb").read())
+    for mutate in (lambda b: b.__setitem__(200, b[200] ^ 1),       # a theta byte
+                   lambda b: b.__setitem__(0, ord("X")),           # magic
+                   lambda b: b.__delitem__(slice(100, 108))):      # length
+        bad = bytearray(raw)
+        mutate(bad)
+        open(path, "wb").write(bytes(bad))
+        with pytest.raises(Q.QedhmcError) as e:
+            Q.checkpoint_info(path)
+        assert e.value.status == Q.EINVAL
+    _write_checkpoint(path, 5, Nt, 0, np.zeros((2, Nt, 5, 5)))
+    with pytest.raises(Q.QedhmcError):
+        Q.checkpoint_info(path)
+    _write_checkpoint(path, L, Nt, 0, th, action=2)  # not a gauge action
+    with pytest.raises(Q.QedhmcError):
+        Q.checkpoint_info(path)
+    with pytest.raises(Q.QedhmcError):
+        Q.checkpoint_info(str(tmp_path / "missing.ckpt"))

@@ -197,3 +197,20 @@ def test_batch_trajectory_matches_single_lattice_at_workload_size():
         assert rb["u"] == r1["u"]
         if abs(r1["dH"] + np.log(r1["u"])) > 1e-5 * abs(r1["H0"]):
             assert rb["accepted"] == r1["accepted"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_trajectory_unconverged_chains_reject(prec):
+    """Chains whose solves stop at maxit reject their proposals (theta
+    unchanged bitwise, status 2), whatever dH says."""
+    sizes = [(6, 10), (4, 6)]
+    seeds = [1001, 77]
+    ths = [inputs.hot_start_theta(L, Nt, s) for (L, Nt), s in zip(sizes, seeds)]
+    with Q.Batch(sizes, seeds=seeds) as b:
+        for traj in range(3):
+            thd = _cat(ths)
+            rs = b.trajectory(thd, traj=traj, n_steps=4, traj_len=0.2, tol=1e-12, maxit=3, prec=prec)
+            for c in range(b.n):
+                print(traj, c, rs[c]["dH"], rs[c]["accepted"], rs[c]["status"], flush=True)
+                assert rs[c]["status"] == 2 and rs[c]["accepted"] == 0
+                assert np.array_equal(_host(b.theta_view(thd, c)), ths[c])

@@ -12,8 +12,10 @@ from paper_2508_16298_amd import qedhmc as Q
 
 pytestmark = pytest.mark.gpu
 
-# lattices spanning a ragged last tile of the MFMA kernel (N not a multiple of 256)
-SIZES = [(4, 6), (6, 10), (8, 5), (2, 3)]
+# lattices spanning a ragged last tile of the MFMA kernel (N not a multiple of
+# 256), and lattices of many MFMA workgroups (512 sites each): 5760 sites is
+# 11 full workgroups and a ragged twelfth, 6144 exactly 12
+SIZES = [(4, 6), (6, 10), (8, 5), (2, 3), (12, 40), (16, 24)]
 
 
 def _dev(x):
@@ -73,7 +75,7 @@ def test_net_forward_zero_residual():
     assert np.abs(z).max() == 0.0  # s = 0 scales the output to zero
 
 
-@pytest.mark.parametrize("L,Nt", [(4, 6), (6, 10)])
+@pytest.mark.parametrize("L,Nt", [(4, 6), (6, 10), (12, 40)])
 def test_net_train_step_gradients_and_adam(L, Nt):
     th, r = _case(L, Nt, 400 + L)
     e = inputs.gauss_cvec(L, Nt, 401 + L)
@@ -97,7 +99,7 @@ def test_net_train_step_gradients_and_adam(L, Nt):
     assert _rel(newp, Q.Net.pack(ref)) <= 1e-6
 
 
-@pytest.mark.parametrize("L,Nt", [(4, 6), (6, 10)])
+@pytest.mark.parametrize("L,Nt", [(4, 6), (6, 10), (12, 40)])
 def test_net_train_step_residual_gradients_and_adam(L, Nt):
     """The residual-form step (two FP64 M^dag M inside) against the oracle's
     loss and gradients; Adam's first step from the GPU's gradient."""
@@ -164,6 +166,27 @@ def test_fcg_untrained_network_falls_back(fallback):
         assert ok and sw == swo and abs(it - ito) <= 3, (it, ito, sw, swo)
 
 
+@pytest.mark.parametrize("arith", ["fp32", "bf16"])
+def test_fcg_multi_workgroup_lattice_true_residual(arith):
+    """Flexible CG with the network (fallback: the paper's preconditioner) at
+    L=12, Nt=40 -- 5760 sites, twelve MFMA workgroups -- from the noisy
+    pi-flux ensemble: the oracle recomputes the true residual of the GPU's
+    solution and its distance to the oracle's own CG solution."""
+    L, Nt = 12, 40
+    th, _ = _case(L, Nt, 801)
+    p = O.lat(L, Nt)
+    eta = O.apply_M(p, th, inputs.gauss_cvec(L, Nt, 802), dagger=True).reshape(Nt, L, L)
+    with Q.Lattice(L, Nt) as lat, Q.Net(lat) as net:
+        net.set_params(_params(13))
+        x, st, it, rel, sw = net.fcg_solve(_dev(th), _dev(eta), tol=1e-10, arith=arith, fallback="paper")
+        xg = _host(x)
+    true = np.linalg.norm(eta.reshape(-1) - O.apply_MdagM(p, th, xg).reshape(-1)) / np.linalg.norm(eta)
+    xo, sto, ito, relo = O.cg_solve(p, th, eta, tol=1e-12)
+    print(f"{arith}: {it} iterations (switched at {sw}), true residual {true:.2e}; oracle CG {ito}", flush=True)
+    assert st == Q.OK and rel <= 1e-10 and true <= 1.05e-10
+    assert _rel(xg, xo) <= 1e-5  # both residuals <= 1e-10; the gap is bounded by cond(O) times that
+
+
 def test_fcg_zero_network_falls_back_at_once():
     """All parameters zero: z = 0 gives no descent direction, the solve
     falls back at iteration 0, and with the fallback 'none' it is plain CG."""
@@ -223,9 +246,113 @@ def test_trained_network_gain_over_none():
         x, st, it, rel, sw = net.fcg_solve(thd_h, etad_h, tol=1e-10, arith="fp32", fallback="none")
         xg = _host(x)
         _, st0, it0, rel0 = lat.cg_solve(thd_h, etad_h, tol=1e-10)
+        # the same network through QEDHMC_PC_LEARNED in mixed precision,
+        # against the mixed CG without it
+        net.bind("fp32", "none")
+        xm, stm, itm, relm = lat.cg_solve(thd_h, etad_h, tol=1e-8, prec="fp32", precond="learned")
+        _, stm0, itm0, _ = lat.cg_solve(thd_h, etad_h, tol=1e-8, prec="fp32")
+        xm = _host(xm)
     print(f"held-out residual-form loss: untrained {loss0:.3f} -> trained {loss1:.3f}; "
           f"FCG with the trained net {it} iterations (judge switched at {sw}) vs CG {it0}", flush=True)
+    print(f"mixed precision: learned flexible CG {itm} iterations vs mixed CG {itm0}", flush=True)
     assert loss1 < loss0
     assert st == Q.OK and rel <= 1e-10 and st0 == Q.OK
     assert it < it0
     assert np.linalg.norm(xg.reshape(-1) - X_h.reshape(-1)) <= 1e-7 * np.linalg.norm(X_h)
+    assert stm == Q.OK and stm0 == Q.OK and relm <= 1e-8 and itm < itm0
+    true = np.linalg.norm(eta_h.reshape(-1) - O.apply_MdagM(p, th_h, xm).reshape(-1)) / np.linalg.norm(eta_h)
+    assert true <= 1.05e-8
+
+
+def test_learned_precond_needs_a_bound_network():
+    L, Nt = 4, 6
+    th, r = _case(L, Nt, 901)
+    with Q.Lattice(L, Nt) as lat:
+        with pytest.raises(Q.QedhmcError) as e:
+            lat.cg_solve(_dev(th), _dev(r), tol=1e-8, prec="fp32", precond="learned")
+        assert e.value.status == Q.EINVAL
+        with Q.Lattice(L, Nt) as other, Q.Net(other) as net:
+            # a network of another handle is refused
+            assert Q.load().qedhmc_set_learned_precond(lat.h, net.h, 0, 0) == Q.EINVAL
+        with Q.Net(lat) as net:
+            net.bind("bf16", "paper")
+        # destroying the network unbinds it
+        with pytest.raises(Q.QedhmcError):
+            lat.cg_solve(_dev(th), _dev(r), tol=1e-8, prec="fp32", precond="learned")
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-8)])
+@pytest.mark.parametrize("arith", ["fp32", "bf16"])
+def test_cg_solve_learned_precond_true_residual(prec, tol, arith):
+    """cg_solve with QEDHMC_PC_LEARNED (untrained network, the paper's
+    preconditioner as fallback) at L=12, Nt=40: FP64 flexible CG or the
+    mixed-precision flexible CG; the oracle recomputes the true residual."""
+    L, Nt = 12, 40
+    th, _ = _case(L, Nt, 811)
+    p = O.lat(L, Nt)
+    eta = O.apply_M(p, th, inputs.gauss_cvec(L, Nt, 812), dagger=True).reshape(Nt, L, L)
+    with Q.Lattice(L, Nt) as lat, Q.Net(lat) as net:
+        net.set_params(_params(14))
+        net.bind(arith, "paper")
+        x, st, it, rel = lat.cg_solve(_dev(th), _dev(eta), tol=tol, prec=prec, precond="learned")
+        xg = _host(x)
+    true = np.linalg.norm(eta.reshape(-1) - O.apply_MdagM(p, th, xg).reshape(-1)) / np.linalg.norm(eta)
+    print(f"{prec} {arith}: {it} iterations, reported {rel:.2e}, oracle true residual {true:.2e}", flush=True)
+    assert st == Q.OK and rel <= tol and true <= 1.05 * tol
+
+
+def _train_on_own_residuals(lat, net, thd, etas, steps, lr, seed):
+    """Residual-form training on r_k = eta - O x_k of the method's own CG
+    solves stopped after k = 0, 10, ..., 140 iterations."""
+    pool = []
+    for etad in etas:
+        for its in range(0, 150, 10):
+            if its == 0:
+                pool.append(etad.clone())
+            else:
+                x, _, _, _ = lat.cg_solve(thd, etad, tol=1e-14, maxit=its)
+                pool.append(etad - lat.apply_MdagM(thd, x, prec="fp64"))
+    rng = np.random.default_rng(seed)
+    for _ in range(steps):
+        net.train_step_residual(thd, pool[int(rng.integers(len(pool)))], lr=lr)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-8), ("fp64", 1e-10)])
+def test_learned_trajectory_matches_oracle_golden(prec, tol):
+    """The spec path: an HMC trajectory whose every solve is flexible
+    CG with the learned preconditioner (QEDHMC_PC_LEARNED; network trained
+    here in residual form on residuals of the method's own CG solves at the
+    chain's start, BF16 MFMA inference, the paper's preconditioner as
+    fallback), mixed precision at residual 1e-8 or FP64 at 1e-10, against the
+    oracle's first trajectory of the L=12, Nt=120 golden chain (plain FP64 CG
+    at 1e-10): dH within 1e-6 |H0|, the same u and decision, then the FP32
+    force on the oracle's solution within 1e-6."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "fp64_l12_trajectories.json")))
+    ref = gold["trajectories"][0]
+    wl = inputs.WORKLOADS["fp64_l12"]
+    th0 = wl.initial_theta()
+    p = O.lat(wl.L, wl.Nt)
+    with Q.Lattice(wl.L, wl.Nt, seed=wl.seed) as lat, Q.Net(lat) as net:
+        thd = _dev(th0)
+        etas = [_dev(O.apply_M(p, th0, inputs.gauss_cvec(wl.L, wl.Nt, 3000 + k), dagger=True)
+                     .reshape(wl.Nt, wl.L, wl.L)) for k in range(3)]
+        net.set_params(_params(15, bias=0.0))
+        _train_on_own_residuals(lat, net, thd, etas, steps=300, lr=1e-3, seed=16)
+        net.bind("bf16", "paper")
+        th = _dev(th0)
+        r = lat.hmc_trajectory(th, traj=0, n_steps=wl.n_steps, traj_len=wl.traj_len, tol=tol, prec=prec,
+                               precond="learned")
+        th = _dev(th0)
+        r0 = lat.hmc_trajectory(th, traj=0, n_steps=wl.n_steps, traj_len=wl.traj_len, tol=tol, prec=prec)
+    gap = 1e-6 * abs(ref["H0"])
+    print(f"{prec}: dH learned {r['dH']:.6f} plain {r0['dH']:.6f} oracle {ref['dH']:.6f} (gap {gap:.2e}); "
+          f"iterations learned {r['cg_iters_total']} (fallbacks in {r['pc_fallbacks']} of {r['n_solves']} solves) "
+          f"plain {r0['cg_iters_total']}", flush=True)
+    assert r["status"] == 0 and r["max_true_resid"] <= tol and r["n_solves"] == wl.n_steps + 1
+    assert abs(r["H0"] - ref["H0"]) <= gap
+    assert abs(r["dH"] - ref["dH"]) <= gap
+    assert r["u"] == pytest.approx(ref["u"], abs=1e-15)
+    if abs(ref["dH"] + np.log(ref["u"])) > gap:
+        assert r["accepted"] == ref["accepted"]

@@ -123,6 +123,46 @@ def test_bosonic_action_and_force(L, Nt):
         assert _rel(_host(F), O.bosonic_force(p, th)) < 1e-12
 
 
+@pytest.mark.parametrize("L,Nt", [(2, 3), (4, 1), (6, 10), (24, 240)])
+def test_bosonic_action_and_force_noncompact(L, Nt):
+    """The non-compact action (Results, Eq. 3) and its force against the
+    oracle, on a hot start and on angles far outside [0, 2 pi) (the action
+    is not periodic in them)."""
+    p = O.lat(L, Nt, J=1.25, K=0.7, noncompact=True)
+    with Q.Lattice(L, Nt, J=1.25, K=0.7, noncompact=True) as lat:
+        for th in (inputs.hot_start_theta(L, Nt, seed=950 + L),
+                   7.0 * inputs.hot_start_theta(L, Nt, seed=960 + L) - 20.0):
+            S, F = lat.bosonic_action_force(_dev(th))
+            So = O.bosonic_action(p, th)
+            assert abs(S - So) < 1e-12 * abs(So)
+            assert _rel(_host(F), O.bosonic_force(p, th)) < 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_trajectory_small_noncompact_vs_oracle(prec):
+    """One 10-step trajectory of length 1 at L=6, Nt=10 with the
+    non-compact gauge action (J = 1.25, K = 1, the paper's production
+    couplings) against the oracle's."""
+    L, Nt, seed = 6, 10, 1001
+    p = O.lat(L, Nt, J=1.25, noncompact=True)
+    th = inputs.noisy_pi_flux_theta(L, Nt, 0.3, seed)
+    tol = 1e-10
+    th_o, ro, *_ = O.hmc_trajectory(p, th, seed=seed, traj=0, n_steps=10, traj_len=1.0, tol=tol)
+    with Q.Lattice(L, Nt, J=1.25, seed=seed, noncompact=True) as lat:
+        thd = _dev(th)
+        rg = lat.hmc_trajectory(thd, traj=0, n_steps=10, traj_len=1.0, tol=tol, prec=prec)
+        th_g = _host(thd)
+    print({k: (rg[k], ro[k]) for k in ("dH", "H0", "SB0", "accepted")}, flush=True)
+    assert rg["status"] == 0
+    assert abs(rg["SB0"] - ro["SB0"]) <= 1e-12 * abs(ro["SB0"])
+    gap = 1e-7 if prec == "fp64" else 1e-5
+    assert abs(rg["dH"] - ro["dH"]) <= gap * max(1.0, abs(ro["H0"])) * 1e-2 + gap
+    if abs(ro["dH"] + np.log(ro["u"])) > 10 * gap:
+        assert rg["accepted"] == ro["accepted"]
+        if ro["accepted"]:
+            assert np.abs(th_g - th_o).max() < 1e3 * gap
+
+
 @pytest.mark.parametrize("L,Nt", [(2, 3), (6, 10), (12, 40)])
 def test_heatbath_matches_oracle_streams(L, Nt):
     p = O.lat(L, Nt)
@@ -377,3 +417,103 @@ def test_cg_graph_replays_match_direct_launches(prec):
         for (xg, sg, ig, rg), (xd, sd, id_, rd) in zip(run, ref):
             assert sg == sd == Q.OK and ig == id_ and rg == rd
             assert np.array_equal(xg, xd)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_trajectory_with_unconverged_solve_is_rejected(prec):
+    """A solve that stops at maxit leaves a dH that is not the reversible
+    leapfrog's, so the trajectory must reject whatever dH and u say: theta
+    unchanged bitwise, accepted 0, status 2 (ENOCONV).  Several trajectory
+    indices, so some of them would have been accepted on dH alone."""
+    L, Nt, seed = 6, 10, 1001
+    th = inputs.hot_start_theta(L, Nt, seed)
+    with Q.Lattice(L, Nt, seed=seed) as lat:
+        for traj in range(4):
+            thd = _dev(th)
+            r = lat.hmc_trajectory(thd, traj=traj, n_steps=4, traj_len=0.2, tol=1e-10, maxit=3, prec=prec)
+            print(traj, r["dH"], r["u"], r["accepted"], r["status"], flush=True)
+            assert r["status"] == 2 and r["accepted"] == 0
+            assert np.array_equal(_host(thd), th)
+        # the same handle still runs converged trajectories afterwards
+        thd = _dev(th)
+        r = lat.hmc_trajectory(thd, traj=0, n_steps=4, traj_len=0.2, tol=1e-10, prec=prec)
+        assert r["status"] == 0
+
+
+def test_mixed_chain_matches_oracle_golden():
+    """The mixed path (complex-FP32 matvecs and force, FP64 reliable updates
+    and reductions, CG residual 1e-8) on the oracle's 20-trajectory FP64 chain
+    at L=12, Nt=120 (tests/golden/fp64_l12_trajectories.json, written from the
+    oracle alone): dH per trajectory within 1e-6 |H0| of the oracle's, the same
+    accept decision wherever |dH + ln u| exceeds that gap, and the chain
+    carried on from the GPU's own theta.  Then the FP32 force kernel on the
+    oracle's own solution X at the chain's start within 1e-6 of the oracle's
+    force."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "fp64_l12_trajectories.json")))
+    wl = inputs.WORKLOADS["fp64_l12"]
+    th0 = wl.initial_theta()
+    th = _dev(th0)
+    worst = 0.0
+    diverged = False
+    with Q.Lattice(wl.L, wl.Nt, seed=wl.seed) as lat:
+        for k, ref in enumerate(gold["trajectories"]):
+            r = lat.hmc_trajectory(th, traj=k, n_steps=wl.n_steps, traj_len=wl.traj_len, tol=1e-8, prec="fp32")
+            gap = 1e-6 * abs(ref["H0"])
+            d = abs(r["dH"] - ref["dH"])
+            worst = max(worst, d / abs(ref["H0"]))
+            print(k, f"dH mixed {r['dH']:.6f} oracle {ref['dH']:.6f} |diff| {d:.2e} (gap {gap:.2e}) acc "
+                  f"{r['accepted']} {ref['accepted']} iters {r['cg_iters_total']} {ref['cg_iters_total']}",
+                  flush=True)
+            assert r["status"] == 0 and r["max_true_resid"] <= 1e-8
+            assert r["u"] == pytest.approx(ref["u"], abs=1e-15)
+            assert d <= gap, (k, r["dH"], ref["dH"])
+            if abs(ref["dH"] + np.log(ref["u"])) > gap:
+                assert r["accepted"] == ref["accepted"], k
+            elif r["accepted"] != ref["accepted"]:
+                diverged = True  # a tie within the gap: the chains legitimately part here
+                break
+        # the FP32 force kernel on the oracle's solution at the chain's start
+        p = O.lat(wl.L, wl.Nt)
+        _, R = O.heatbath(p, wl.seed, 0)
+        eta = O.apply_M(p, th0, R, dagger=True).reshape(wl.Nt, wl.L, wl.L)
+        X, sto, _, _ = O.cg_solve(p, th0, eta, tol=1e-10)
+        F32 = _host(lat.fermion_force(_dev(th0), _dev(X), prec="fp32"))
+    assert _rel(F32, O.fermion_force(p, th0, X)) < 1e-6
+    print("worst |dH mixed - dH oracle| / |H0| =", worst, "(chains parted at a tie)" if diverged else "", flush=True)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_checkpoint_resume_is_bitwise(prec, tmp_path):
+    """Two trajectories, a checkpoint, a fresh handle that loads it and two
+    more trajectories give bit for bit the chain of four trajectories run
+    straight through (same theta, same dH and decisions), since the heat bath
+    and the Metropolis draws are counter-based.  A checkpoint of another
+    lattice is refused."""
+    L, Nt, seed = 12, 40, 1002
+    th0 = inputs.noisy_pi_flux_theta(L, Nt, 0.3, 2024)
+    kw = dict(n_steps=10, traj_len=0.5, tol=1e-10 if prec == "fp64" else 1e-8, prec=prec)
+    with Q.Lattice(L, Nt, seed=seed) as lat:
+        th = _dev(th0)
+        straight = [lat.hmc_trajectory(th, traj=k, **kw) for k in range(4)]
+        th_straight = _host(th)
+    path = str(tmp_path / "chain.ckpt")
+    with Q.Lattice(L, Nt, seed=seed) as lat:
+        th = _dev(th0)
+        first = [lat.hmc_trajectory(th, traj=k, **kw) for k in range(2)]
+        lat.checkpoint_save(th, 2, path)
+    prm, nxt = Q.checkpoint_info(path)
+    assert (prm["L"], prm["Nt"], prm["seed"], nxt) == (L, Nt, seed, 2)
+    with Q.Lattice(L, Nt, seed=seed) as lat:
+        th, nxt = lat.checkpoint_load(path)
+        second = [lat.hmc_trajectory(th, traj=k, **kw) for k in range(nxt, nxt + 2)]
+        th_resumed = _host(th)
+    print([(r["dH"], r["accepted"]) for r in straight], flush=True)
+    assert np.array_equal(th_resumed, th_straight)
+    for a, b in zip(first + second, straight):
+        assert a["dH"] == b["dH"] and a["accepted"] == b["accepted"] and a["cg_iters_total"] == b["cg_iters_total"]
+    with Q.Lattice(L, Nt, seed=seed + 1) as other:
+        with pytest.raises(Q.QedhmcError) as e:
+            other.checkpoint_load(path)
+        assert e.value.status == Q.EINVAL

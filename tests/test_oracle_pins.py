@@ -323,6 +323,84 @@ def test_bosonic_action_gauge_invariant_and_force_fd():
 
 
 # ---------------------------------------------------------------------------
+# Non-compact gauge action (Results, Eq. 3): the time-link term is the square
+# of the time difference, with the compact term's prefactor 1/(J dtau^2),
+# integrated as dtau sum_tau; the plaquette term is the compact one.
+# ---------------------------------------------------------------------------
+def test_noncompact_action_closed_forms():
+    L, Nt, J, K, dtau = 4, 5, 1.25, 0.7, 0.1
+    p = _lat(L, Nt, J=J, K=K, dtau=dtau, noncompact=True)
+    n = L * L * Nt
+    cj = 1.0 / (J * dtau)
+    assert abs(O.bosonic_action(p, np.zeros((2, Nt, L, L))) - K * dtau * n) < 1e-12
+    # every bond ramped by c per slice: Nt - 1 differences c and the periodic
+    # wrap -c (Nt - 1), on each of the 2 L^2 bonds; all plaquettes stay zero
+    # (the ramp is the same on every bond of a slice)
+    c = 0.03
+    th = np.broadcast_to(c * np.arange(Nt)[None, :, None, None], (2, Nt, L, L)).copy()
+    expect = cj * 2 * L * L * ((Nt - 1) * c ** 2 + (c * (Nt - 1)) ** 2) + K * dtau * n
+    assert abs(O.bosonic_action(p, th) - expect) < 1e-10
+    # one bond displaced by a: two time links of a^2, two plaquettes +-a
+    a = 0.37
+    th = np.zeros((2, Nt, L, L))
+    th[1, 2, 1, 3] = a
+    expect = 2 * a * a * cj + K * dtau * (n - 2 + 2 * np.cos(a))
+    assert abs(O.bosonic_action(p, th) - expect) < 1e-12
+
+
+def test_noncompact_small_angle_limit_and_lost_periodicity():
+    """For small time differences 1 - cos d = d^2/2 - d^4/24 + ..., so with
+    K = 0 the non-compact action is twice the compact one up to O(eps^4);
+    a 2 pi shift of one angle leaves the compact action unchanged but not
+    the non-compact one."""
+    L, Nt = 4, 6
+    X = inputs.hot_start_theta(L, Nt, 91)
+    pc = _lat(L, Nt, K=0.0)
+    pn = _lat(L, Nt, K=0.0, noncompact=True)
+    for eps in (1e-2, 1e-3):
+        r = O.bosonic_action(pn, eps * X) / O.bosonic_action(pc, eps * X)
+        assert abs(r - 2.0) < 2 * eps * eps * np.abs(X).max() ** 2
+    th = inputs.hot_start_theta(L, Nt, 92)
+    sh = th.copy()
+    sh[0, 3, 2, 1] += 2 * np.pi
+    pc1, pn1 = _lat(L, Nt), _lat(L, Nt, noncompact=True)
+    assert abs(O.bosonic_action(pc1, sh) - O.bosonic_action(pc1, th)) < 1e-9
+    assert abs(O.bosonic_action(pn1, sh) - O.bosonic_action(pn1, th)) > 1.0
+
+
+def test_noncompact_gauge_invariant_and_force_fd():
+    L, Nt = 4, 4
+    p = _lat(L, Nt, J=1.25, K=1.0, noncompact=True)
+    th = inputs.noisy_pi_flux_theta(L, Nt, 0.5, 93)
+    al = inputs.gauge_angles(L, seed=94)
+    assert abs(O.bosonic_action(p, _gauge_transform(th, al)) - O.bosonic_action(p, th)) < 1e-9
+    F = O.bosonic_force(p, th)
+    h = 1e-6
+    flat = th.reshape(-1)
+    Ffd = np.zeros_like(flat)
+    for b in range(flat.size):
+        tp, tm = flat.copy(), flat.copy()
+        tp[b] += h
+        tm[b] -= h
+        Ffd[b] = -(O.bosonic_action(p, tp.reshape(th.shape))
+                   - O.bosonic_action(p, tm.reshape(th.shape))) / (2 * h)
+    assert np.abs(F.reshape(-1) - Ffd).max() < 1e-6 * np.abs(Ffd).max()
+
+
+def test_noncompact_leapfrog_energy_error_is_second_order():
+    p = _lat(4, 4, J=1.25, noncompact=True)
+    th = inputs.noisy_pi_flux_theta(4, 4, 0.3, 95)
+    mom = inputs.gauss_real((2, 4, 4, 4), 96, np.sqrt(0.5))
+    eta = O.apply_M(p, th, inputs.gauss_cvec(4, 4, 97), dagger=True)
+    dH = []
+    for n in (8, 16, 32, 64):
+        _, _, hb, ha = O.leapfrog(p, th, mom, eta, n, traj_len=0.5, tol=1e-13)
+        dH.append(abs(ha - hb))
+    slope = np.polyfit(np.log([0.5 / 8, 0.5 / 16, 0.5 / 32, 0.5 / 64]), np.log(dH), 1)[0]
+    assert 1.8 < slope < 2.2, (slope, dH)
+
+
+# ---------------------------------------------------------------------------
 # Leapfrog and trajectory (Eq. leapfrog, Eq. H_hmc, steps (i)-(iv))
 # ---------------------------------------------------------------------------
 def _md_inputs(L, Nt, seed):
