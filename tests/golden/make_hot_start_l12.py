@@ -82,34 +82,59 @@ def _first(args):
     return what, out
 
 
+def _write(out):
+    tmp = OUT + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(out, f, indent=1)
+    os.replace(tmp, OUT)
+
+
 def main(workers=6, n_traj=20):
     wl = _wl()
     th0 = wl.initial_theta()
     t0 = time.time()
-    with mp.get_context("fork").Pool(workers) as pool:
-        firsts = pool.map_async(_first, [("solve0", 0), ("steps", 1), ("steps", 2), ("steps", 3)], chunksize=1)
-        trajs = pool.map(_traj, [(k, th0) for k in range(n_traj)], chunksize=1)
-        firsts = firsts.get()
-    rows = [r for r, _ in trajs]
-    # the parallel runs assumed every trajectory rejected; redo in order after an acceptance
-    notes = []
-    for k in range(n_traj):
-        if rows[k]["accepted"]:
-            notes.append(f"trajectory {k} accepted: trajectories after it rerun in order")
-            th = trajs[k][1]
-            for j in range(k + 1, n_traj):
-                rows[j], th = _traj((j, th))
-            break
     out = {"workload": "fp64_l12_hot", "source": "oracle/qed_oracle.c via oracle (cg_solve, fermion_force, "
            "bosonic_force, leapfrog, hmc_trajectory)", "L": wl.L, "Nt": wl.Nt, "seed": wl.seed,
            "theta": "hot", "theta_seed": wl.theta_seed or wl.seed, "n_steps": wl.n_steps,
-           "traj_len": wl.traj_len, "tol": wl.tol, "notes": notes,
-           "solve0": [o for w, o in firsts if w == "solve0"][0],
-           "first_steps": [o for w, o in firsts if w == "steps"],
-           "trajectories": rows, "wall_seconds": time.time() - t0}
-    with open(OUT, "w") as f:
-        json.dump(out, f, indent=1)
+           "traj_len": wl.traj_len, "tol": wl.tol, "notes": [], "solve0": None, "first_steps": [],
+           "trajectories": [], "complete": False}
+    # the record is rewritten after every finished piece, so an interrupted run keeps what it has
+    with mp.get_context("fork").Pool(workers) as pool:
+        jobs = [("first", a) for a in (("solve0", 0), ("steps", 1), ("steps", 2), ("steps", 3))]
+        jobs += [("traj", (k, th0)) for k in range(n_traj)]
+        thetas = {}
+        for kind, res in pool.imap_unordered(_job, jobs):
+            if kind == "first":
+                what, o = res
+                if what == "solve0":
+                    out["solve0"] = o
+                else:
+                    out["first_steps"] = sorted(out["first_steps"] + [o], key=lambda r: r["steps"])
+            else:
+                row, th1 = res
+                thetas[row["traj"]] = th1
+                out["trajectories"] = sorted(out["trajectories"] + [row], key=lambda r: r["traj"])
+            out["wall_seconds"] = time.time() - t0
+            _write(out)
+    rows = out["trajectories"]
+    # the parallel runs assumed every trajectory rejected; redo in order after an acceptance
+    for k in range(n_traj):
+        if rows[k]["accepted"]:
+            out["notes"].append(f"trajectory {k} accepted: trajectories after it rerun in order")
+            th = thetas[k]
+            for j in range(k + 1, n_traj):
+                rows[j], th = _traj((j, th))
+                _write(out)
+            break
+    out["complete"] = True
+    out["wall_seconds"] = time.time() - t0
+    _write(out)
     print("wrote", OUT, flush=True)
+
+
+def _job(job):
+    kind, args = job
+    return kind, (_first(args) if kind == "first" else _traj(args))
 
 
 if __name__ == "__main__":

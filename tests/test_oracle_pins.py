@@ -54,6 +54,49 @@ def test_heatbath_distribution():
     assert 0.0 <= min(u) and max(u) < 1.0 and abs(np.mean(u) - 0.5) < 5 * np.sqrt(1 / 12 / 2000)
 
 
+def test_heatbath_box_muller_pairs_independent():
+    """Step (i): the two normals of one Box-Muller pair (bonds 2k and 2k+1;
+    Re and Im of R at site k) form an isotropic pair of independent normals:
+    their squared radius is exponential with mean 2 * 1/2 and their angle is
+    uniform, and neither member predicts the other or its square.  A pair
+    built from one member twice, or from the same trig function, fails."""
+    from scipy import stats
+    p = _lat(12, 60)
+    mom, R = O.heatbath(p, seed=11, traj=5)
+    m = mom.reshape(-1)
+    for a, b in ((m[0::2], m[1::2]), (R.real.reshape(-1), R.imag.reshape(-1))):
+        n = a.size
+        assert abs(np.corrcoef(a, b)[0, 1]) < 5 / np.sqrt(n)
+        assert abs(np.corrcoef(a * a, b * b)[0, 1]) < 5 / np.sqrt(n)
+        assert stats.kstest(a * a + b * b, "expon", args=(0, 1.0)).pvalue > 1e-4
+        assert stats.kstest(np.arctan2(b, a), "uniform", args=(-np.pi, 2 * np.pi)).pvalue > 1e-4
+    # consecutive pairs come from different counters: no correlation across them
+    assert abs(np.corrcoef(m[1:-1:2], m[2::2])[0, 1]) < 5 / np.sqrt(m.size // 2)
+
+
+@pytest.mark.slow
+def test_creutz_equality_at_cpu_workload():
+    """Methods, HQMC algorithm (Eq. Z_aug, Eq. H_hmc): in equilibrium the
+    area-preserving, reversible leapfrog gives <exp(-dH)> = 1.  Lattice and
+    couplings of the CPU workload (L=6, N_tau=10), hot start, 100 trajectories
+    to thermalise, then 1000 trajectories of 10 steps of length 0.5."""
+    L, Nt, seed = 6, 10, 1001
+    p = _lat(L, Nt)
+    th = inputs.hot_start_theta(L, Nt, seed)
+    dH = []
+    for k in range(1100):
+        th, res, *_ = O.hmc_trajectory(p, th, seed=seed, traj=k, n_steps=10, traj_len=0.5, tol=1e-10)
+        assert res["status"] == 0
+        if k >= 100:
+            dH.append(res["dH"])
+    e = np.exp(-np.array(dH))
+    err = e.std() / np.sqrt(e.size)
+    assert err < 0.05, err
+    assert abs(e.mean() - 1.0) < 4 * err, (e.mean(), err)
+    # <dH> = var(dH)/2 + O(dH^3) follows from the same identity
+    assert 0 < np.mean(dH) < 1.0
+
+
 # ---------------------------------------------------------------------------
 # Bond families (Fig. 1, Eq. 24)
 # ---------------------------------------------------------------------------
