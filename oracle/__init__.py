@@ -78,6 +78,7 @@ def lib():
         L.oracle_philox4x32_10.argtypes = [_P, _P, _P]
         L.oracle_heatbath.argtypes = [LP, C.c_uint64, C.c_uint64, _P, _P]
         L.oracle_metropolis_uniform.argtypes = [C.c_uint64, C.c_uint64]
+        L.oracle_probes.argtypes = [LP, C.c_uint64, C.c_uint64, C.c_int32, _P]
         L.oracle_metropolis_uniform.restype = C.c_double
         L.oracle_hmc_trajectory.argtypes = [LP, _P, C.c_uint64, C.c_uint64, C.c_int32,
                                             C.c_double, C.c_double, C.c_int32,
@@ -207,6 +208,14 @@ def heatbath(p, seed, traj):
     R = np.zeros((p.Nt, p.L, p.L), dtype=np.complex128)
     lib().oracle_heatbath(C.byref(p), seed, traj, _ptr(mom), _ptr(R))
     return mom, R
+
+
+def probes(p, seed, meas, n_rv):
+    """Probe vectors of the stochastic estimation: complex128 (n_rv, Nt, L, L)."""
+    assert n_rv * p.N < 2 ** 32
+    xi = np.zeros((n_rv, p.Nt, p.L, p.L), dtype=np.complex128)
+    lib().oracle_probes(C.byref(p), seed, meas, n_rv, _ptr(xi))
+    return xi
 
 
 def metropolis_uniform(seed, traj):

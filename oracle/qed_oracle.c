@@ -421,8 +421,10 @@ void oracle_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2],
 
 /* Random-number streams of one trajectory.  Counter = (element, trajectory
  * low word, purpose, trajectory high word), key = (seed low, seed high).
- * Purposes: 1 momenta, 2 pseudofermion source R, 3 Metropolis uniform. */
-enum { PURPOSE_MOMENTUM = 1, PURPOSE_SOURCE = 2, PURPOSE_METROPOLIS = 3 };
+ * Purposes: 1 momenta, 2 pseudofermion source R, 3 Metropolis uniform,
+ * 4 probe vectors of the stochastic estimation (the "trajectory" words then
+ * hold the measurement index). */
+enum { PURPOSE_MOMENTUM = 1, PURPOSE_SOURCE = 2, PURPOSE_METROPOLIS = 3, PURPOSE_PROBE = 4 };
 
 static void draw(uint64_t seed, uint64_t traj, uint32_t purpose, uint32_t elem,
                  uint32_t out[4])
@@ -468,6 +470,24 @@ void oracle_heatbath(const oracle_lat *p, uint64_t seed, uint64_t traj,
         draw(seed, traj, PURPOSE_SOURCE, (uint32_t)k, x);
         gauss2(x, &g1, &g2);
         R[k] = r2 * g1 + I * (r2 * g2);
+    }
+}
+
+/* Probe vectors of the stochastic estimation (Methods, "Stochastic
+ * estimation of fermionic observables"): entries i.i.d. complex Gaussian with
+ * E[xi_i^* xi_j] = delta_ij (Re, Im ~ N(0, 1/2)).  Probe k, site n takes the
+ * block of element k * N + n (n_rv * N < 2^32). */
+void oracle_probes(const oracle_lat *p, uint64_t seed, uint64_t meas, int32_t n_rv,
+                   cplx *xi /* [n_rv][N] */)
+{
+    const size_t N = (size_t)p->L * p->L * p->Nt;
+    const double r2 = 1.0 / sqrt(2.0);
+    uint32_t x[4];
+    double g1, g2;
+    for (size_t e = 0; e < (size_t)n_rv * N; e++) {
+        draw(seed, meas, PURPOSE_PROBE, (uint32_t)e, x);
+        gauss2(x, &g1, &g2);
+        xi[e] = r2 * g1 + I * (r2 * g2);
     }
 }
 
