@@ -1,6 +1,7 @@
 // Gauge-field side of the trajectory: compact action and force, Philox heat
 // bath, leapfrog kicks and drifts, FP64 reductions, Metropolis test.
 #include "qedhmc_internal.h"
+#include "rng.h"
 
 namespace qh {
 
@@ -79,49 +80,6 @@ qedhmc_status launch_bosonic(qedhmc_ctx* h, const double* theta, double* F_B, do
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, h->stream, (const double*)part, kGridR, S_dev);
     QH_HIP(hipGetLastError());
     return QEDHMC_OK;
-}
-
-// ---------------------------------------------------------------------------
-// Philox4x32-10 (Salmon et al., SC'11) and Box-Muller
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void philox10(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int r = 0; r < 10; r++) {
-        if (r > 0) {
-            k0 += 0x9E3779B9u;
-            k1 += 0xBB67AE85u;
-        }
-        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
-        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
-        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = lo1;
-        c[2] = n2;
-        c[3] = lo0;
-    }
-}
-
-__device__ __forceinline__ double uniform53(uint32_t a, uint32_t b) {
-    return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * (1.0 / 9007199254740992.0);
-}
-
-// Counter (element, traj low, purpose, traj high), key (seed low, seed high).
-__device__ __forceinline__ void draw_block(uint64_t seed, uint64_t traj, uint32_t purpose, uint32_t elem,
-                                           uint32_t (&x)[4]) {
-    x[0] = elem;
-    x[1] = (uint32_t)traj;
-    x[2] = purpose;
-    x[3] = (uint32_t)(traj >> 32);
-    philox10(x, (uint32_t)seed, (uint32_t)(seed >> 32));
-}
-
-__device__ __forceinline__ void gauss_pair(const uint32_t (&x)[4], double& g1, double& g2) {
-    const double u1 = uniform53(x[0], x[1]), u2 = uniform53(x[2], x[3]);
-    const double rad = sqrt(-2.0 * log(1.0 - u1));
-    double s, c;
-    sincos(2.0 * M_PI * u2, &s, &c);
-    g1 = rad * c;
-    g2 = rad * s;
 }
 
 // p ~ N(0, 1/2) per bond (pair 2k, 2k+1 from block k of purpose 1) and

@@ -7,6 +7,8 @@ Solves are compared through what is unique: the true residual (recomputed by
 the oracle) and the distance to the oracle's solution, bounded by the
 residuals and the smallest eigenvalue of M^dag M where that is computable.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -517,3 +519,77 @@ def test_checkpoint_resume_is_bitwise(prec, tmp_path):
         with pytest.raises(Q.QedhmcError) as e:
             other.checkpoint_load(path)
         assert e.value.status == Q.EINVAL
+
+
+def _hot_start_record():
+    import json
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "hot_start_l12_record.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+def test_hot_start_l12_first_solve_matches_oracle_record():
+    """The plain FP64 workload at L=12, Nt=120 from the hot start it is
+    specified with (angles uniform on [0, 2 pi), seed 1002): the first solve
+    and forces against the oracle-only record in tests/golden (Methods, HQMC
+    step (ii); Supplemental Material SI).  The solve's true residual is
+    recomputed by the oracle on the GPU's X; the forces of the two solves
+    agree as far as two different CG round-off histories at 1.4e4 iterations
+    allow (1e-3 relative); the gauge force involves no solve (1e-12)."""
+    rec = _hot_start_record()
+    wl = inputs.WORKLOADS["fp64_l12_hot"]
+    L, Nt = wl.L, wl.Nt
+    p = O.lat(L, Nt)
+    th = wl.initial_theta()
+    s0 = rec["solve0"]
+    with Q.Lattice(L, Nt, seed=wl.seed) as lat:
+        thd = _dev(th)
+        _, R = lat.heatbath(0)
+        eta = lat.apply_M(thd, R, dagger=True)
+        print(f"hot start L={L} Nt={Nt}: FP64 solve", flush=True)
+        x, st, it, rel = lat.cg_solve(thd, eta, tol=wl.tol, prec="fp64")
+        F = _host(lat.fermion_force(thd, x))
+        _, Fb = lat.bosonic_action_force(thd)
+        Fb = _host(Fb)
+        xg, etag = _host(x), _host(eta)
+    print(f"GPU {it} iterations (oracle {s0['cg_iters']}), residual {rel:.3e}; max|F_F| {np.abs(F).max():.6e} "
+          f"(oracle {s0['max_abs_F_F']:.6e})", flush=True)
+    assert st == Q.OK and rel <= wl.tol
+    true = np.linalg.norm(etag.reshape(-1) - O.apply_MdagM(p, th, xg).reshape(-1)) / np.linalg.norm(etag)
+    assert true <= 1.05 * wl.tol, true
+    assert abs(it - s0["cg_iters"]) <= 0.1 * s0["cg_iters"]
+    assert abs(np.abs(F).max() / s0["max_abs_F_F"] - 1) < 1e-3
+    assert abs(np.sqrt((F ** 2).mean()) / s0["rms_F_F"] - 1) < 1e-3
+    assert abs(np.abs(Fb).max() / s0["max_abs_F_B"] - 1) < 1e-12
+
+
+def test_hot_start_l12_molecular_dynamics_diverges_as_recorded():
+    """Reading of the starting configuration: from the hot start one leapfrog
+    step of dt = 0.05 already multiplies H several hundred times (det M is
+    close to zero there), so the specified hot-start chain rejects every
+    trajectory.  The GPU's FP64 path reproduces the oracle record: H at the
+    start (S_F0 = R^dag R up to the solve, 1e-9), H after one step (1e-3: the
+    step amplifies the solves' round-off differences), and the blow-up after
+    two and three steps (within a factor of 2; the angles then move by
+    hundreds of radians, so only the divergence itself is reproducible)."""
+    rec = _hot_start_record()
+    wl = inputs.WORKLOADS["fp64_l12_hot"]
+    L, Nt = wl.L, wl.Nt
+    th = wl.initial_theta()
+    dt = wl.traj_len / wl.n_steps
+    with Q.Lattice(L, Nt, seed=wl.seed) as lat:
+        for fs in rec["first_steps"]:
+            k = fs["steps"]
+            thd = _dev(th)
+            print(f"hot start L={L}: trajectory 0 cut to {k} step(s)", flush=True)
+            res = lat.hmc_trajectory(thd, traj=0, n_steps=k, traj_len=dt * k, tol=wl.tol, prec="fp64")
+            print(f"  H0 {res['H0']:.9e} (oracle {fs['H_before']:.9e}), H1 {res['H1']:.6e} "
+                  f"(oracle {fs['H_after']:.6e}), accepted {res['accepted']}", flush=True)
+            assert res["status"] == 0
+            assert abs(res["H0"] / fs["H_before"] - 1) < 1e-9
+            assert res["accepted"] == 0 and np.array_equal(_host(thd), th)
+            if k == 1:
+                assert abs(res["H1"] / fs["H_after"] - 1) < 1e-3
+            else:
+                assert 0.5 < res["H1"] / fs["H_after"] < 2.0
+            assert res["H1"] > 100 * res["H0"]
