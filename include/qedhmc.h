@@ -49,6 +49,7 @@
 #ifndef QEDHMC_H
 #define QEDHMC_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -158,6 +159,25 @@ qedhmc_status qedhmc_apply_M(qedhmc_t h, const double *theta, const void *in,
 qedhmc_status qedhmc_apply_MdagM(qedhmc_t h, const double *theta,
                                  const void *in, void *out,
                                  qedhmc_precision prec);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * out = M^dag M in as qedhmc_apply_MdagM (same kernels, bitwise the same
+ * result), without a handle and without any allocation.  params as for
+ * qedhmc_init_lattice; theta, in and out device buffers as for
+ * qedhmc_apply_MdagM (caller-owned, not aliased); stream a hipStream_t (NULL:
+ * the null stream); the call only enqueues work on it.  The phase cache the
+ * kernels read (2 L^2 N_tau complex values of the working precision) lives in
+ * a static device array of QEDHMC_NOALLOC_SCRATCH_BYTES per GPU, held until
+ * the process ends; larger lattices return EINVAL before any device work.
+ * Every call on one GPU shares that array: calls that overlap on one GPU (on
+ * different streams, or from different threads) race and must be ordered by
+ * the caller. */
+#define QEDHMC_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+qedhmc_status qedhmc_apply_MdagM_noalloc(const qedhmc_params *params,
+                                         const double *theta, const void *in,
+                                         void *out, qedhmc_precision prec,
+                                         void *stream);
 
 /* Solve M^dag M x = rhs by conjugate gradient from x = 0 (Eq. pCG), stopping
  * when the true residual |rhs - M^dag M x| / |rhs| <= tol (recomputed in FP64

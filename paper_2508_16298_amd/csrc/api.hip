@@ -86,17 +86,12 @@ using namespace qh;
 
 static size_t nsites(const qedhmc_ctx* h) { return (size_t)h->lat.Nt * h->lat.Vs; }
 
-static qedhmc_status check_prec(qedhmc_precision p) {
+qedhmc_status qh::check_prec(qedhmc_precision p) {
     if (p != QEDHMC_FP64 && p != QEDHMC_FP32) return einval("bad precision");
     return QEDHMC_OK;
 }
 
-extern "C" {
-
-const char* qedhmc_last_error(void) { return g_err.c_str(); }
-
-qedhmc_status qedhmc_init_lattice(const qedhmc_params* params, void* stream, qedhmc_t* out) {
-    if (!params || !out) return einval("null argument");
+qedhmc_status qh::check_params(const qedhmc_params* params) {
     const qedhmc_params& p = *params;
     if (p.L < 2 || p.L % 2 != 0) return einval("L must be even and >= 2");
     if (p.L > 2048) return einval("L > 2048 is not supported");
@@ -106,9 +101,10 @@ qedhmc_status qedhmc_init_lattice(const qedhmc_params* params, void* stream, qed
     if ((size_t)p.L * p.L * p.Nt >= ((size_t)1 << 31)) return einval("lattice too large");
     if ((p.action != QEDHMC_COMPACT && p.action != QEDHMC_NONCOMPACT) || p.reserved != 0)
         return einval("bad gauge action (QEDHMC_COMPACT or QEDHMC_NONCOMPACT; reserved 0)");
-    *out = nullptr;
-    qedhmc_ctx* h = new (std::nothrow) qedhmc_ctx{};
-    if (!h) return QEDHMC_ENOMEM;
+    return QEDHMC_OK;
+}
+
+qedhmc_status qh::ctx_geometry(qedhmc_ctx* h, const qedhmc_params& p, void* stream) {
     h->p = p;
     h->lat.L = p.L;
     h->lat.Nt = p.Nt;
@@ -120,11 +116,28 @@ qedhmc_status qedhmc_init_lattice(const qedhmc_params* params, void* stream, qed
     int lds = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, h->device);
-    if (e != hipSuccess) {
-        delete h;
-        return hip_fail(e, "hipGetDevice / attribute");
-    }
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice / attribute");
     h->max_lds = (size_t)lds;
+    return QEDHMC_OK;
+}
+
+extern "C" {
+
+const char* qedhmc_last_error(void) { return g_err.c_str(); }
+
+qedhmc_status qedhmc_init_lattice(const qedhmc_params* params, void* stream, qedhmc_t* out) {
+    if (!params || !out) return einval("null argument");
+    QH_TRY(check_params(params));
+    const qedhmc_params& p = *params;
+    *out = nullptr;
+    qedhmc_ctx* h = new (std::nothrow) qedhmc_ctx{};
+    if (!h) return QEDHMC_ENOMEM;
+    const qedhmc_status gst = ctx_geometry(h, p, stream);
+    if (gst != QEDHMC_OK) {
+        delete h;
+        return gst;
+    }
+    hipError_t e = hipSuccess;
     const size_t N = nsites(h);
     const size_t vec = N * sizeof(cplx<double>);
     bool ok = true;

@@ -606,6 +606,11 @@ qedhmc_status prof_drain(qedhmc_ctx* h);
 
 // Launch helpers implemented in lattice.hip
 qedhmc_status ensure_gauge(qedhmc_ctx* h, const double* theta, qedhmc_precision prec);
+// argument checks shared by the handle and the allocation-free entry point
+qedhmc_status check_prec(qedhmc_precision p);
+qedhmc_status check_params(const qedhmc_params* params);
+// lattice geometry, stream and device limits of a context (allocates nothing)
+qedhmc_status ctx_geometry(qedhmc_ctx* h, const qedhmc_params& p, void* stream);
 qedhmc_status launch_apply_M(qedhmc_ctx* h, qedhmc_precision prec, const void* in, void* out, int dagger);
 qedhmc_status launch_apply_B(qedhmc_ctx* h, qedhmc_precision prec, int tau, const void* in, void* out);
 // out = M^dag M in; gate (nullable): a CG slot's stop flag, the launch runs

@@ -74,6 +74,7 @@ def load():
         "qedhmc_apply_B": [_P, _P, C.c_int32, _P, _P, C.c_int],
         "qedhmc_apply_M": [_P, _P, _P, _P, C.c_int32, C.c_int],
         "qedhmc_apply_MdagM": [_P, _P, _P, _P, C.c_int],
+        "qedhmc_apply_MdagM_noalloc": [C.POINTER(Params), _P, _P, _P, C.c_int, _P],
         "qedhmc_cg_solve": [_P, _P, _P, _P, C.c_double, C.c_int32, C.c_int, C.c_int,
                             C.POINTER(C.c_int32), C.POINTER(C.c_double)],
         "qedhmc_fermion_force": [_P, _P, _P, _P, C.c_int],
@@ -145,6 +146,24 @@ def checkpoint_info(path):
     nxt = C.c_uint64(0)
     _check(load().qedhmc_checkpoint_info(os.fsencode(path), C.byref(p), C.byref(nxt)))
     return {k: getattr(p, k) for k, _ in p._fields_}, nxt.value
+
+
+NOALLOC_SCRATCH_BYTES = 16 << 20
+
+
+def apply_MdagM_noalloc(theta, v, out, L, Nt, dtau=0.1, t=1.0, J=1.0, K=1.0, noncompact=False,
+                        prec="fp64"):
+    """qedhmc_apply_MdagM_noalloc on torch's current stream: out = M^dag M v with
+    no handle and no device allocation (caller-owned theta, v and out)."""
+    import torch
+    params = Params(int(L), int(Nt), dtau, t, J, K, 0, NONCOMPACT if noncompact else COMPACT, 0)
+    n = int(L) * int(L) * int(Nt)
+    dt = torch.complex128 if _PREC[prec] == FP64 else torch.complex64
+    for a, d, m in ((theta, torch.float64, 2 * n), (v, dt, n), (out, dt, n)):
+        assert a.is_cuda and a.dtype == d and a.is_contiguous() and a.numel() == m, (a.dtype, a.shape)
+    _check(load().qedhmc_apply_MdagM_noalloc(C.byref(params), _ptr(theta), _ptr(v), _ptr(out), _PREC[prec],
+                                             _stream_handle()))
+    return out
 
 
 class Lattice:
