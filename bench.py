@@ -290,6 +290,119 @@ def run_batched(a):
     print(json.dumps(out), flush=True)
 
 
+def run_se(a):
+    """--workload se_l24: one measurement of the stochastic estimation per
+    step (Methods, "Stochastic estimation of fermionic observables"): 40
+    Philox probes, the multi-RHS solve X_p = (M^dag M)^-1 M^dag xi_p (mixed
+    precision, true residual 1e-8, one gauge field for all 40 right-hand
+    sides) and the FFT-averaged spin correlator over the 780 probe pairs, at
+    L=24, Nt=240 on the angles of the trajectory workload.  value = seconds
+    per measurement.  The roofline block is the solve phase: 104 B per site
+    and right-hand side for every batched CG iteration (as k_cg_iter), over
+    the solve's measured time (reliable updates and launch gaps included:
+    a lower bound on the kernel's rate)."""
+    import numpy as np
+    import torch
+    from paper_2508_16298_amd import inputs
+    from paper_2508_16298_amd import qedhmc as Q
+
+    wl = inputs.WORKLOADS["se_l24"]
+    n_rv = inputs.SE_PROBES
+    prec = a.prec or wl.precision
+    L, Nt = wl.L, wl.Nt
+    N = L * L * Nt
+    theta = torch.from_numpy(wl.initial_theta()).cuda()
+    se = Q.Stochastic(L, Nt, n_rv, dtau=wl.dtau, t=wl.t, J=wl.J, K=wl.K, seed=wl.seed)
+    xi = se._set()
+    X = se._set()
+    C = torch.empty((Nt, L, L), dtype=torch.complex128, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+
+    def measure(m):
+        ev[0].record()
+        se.probes(m, out=xi)
+        _, st, it, rel = se.solve(theta, xi, tol=wl.tol, prec=prec, out=X)
+        ev[1].record()
+        se.spin_correlator(xi, X, out=C)
+        ev[2].record()
+        torch.cuda.synchronize()
+        return st, it, rel, ev[0].elapsed_time(ev[1]) * 1e-3, ev[1].elapsed_time(ev[2]) * 1e-3
+
+    for m in range(a.warmup):
+        measure(m)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rows = [measure(1000 + m) for m in range(a.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    s_per = elapsed / a.steps
+    t_solve = float(np.mean([r[3] for r in rows]))
+    t_corr = float(np.mean([r[4] for r in rows]))
+    iters = np.array([r[1] for r in rows])
+    # every launch of the batched iteration covers the right-hand sides still running
+    it_sum = float(iters.sum(axis=1).mean())
+    achieved = (104 if prec != "fp64" else 176) * N * it_sum / t_solve / 1e9
+    npairs = n_rv * (n_rv - 1) // 2
+    dft_flop = 8.0 * N * (2 * L + Nt)          # one 3-D DFT by direct sums along each axis
+    corr_tflops = (2 * npairs + 1) * dft_flop / t_corr / 1e12
+    Ch = C.cpu().numpy()
+    out = {
+        "metric": "s per stochastic-estimation measurement (40 probes, spin correlator) at L=24 Nt=240, "
+                  "CG resid 1e-8",
+        "value": s_per, "unit": "s/measurement", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": 1e3 * s_per, "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
+        "dtype": "c64+f64" if prec != "fp64" else "c128", "data": "synthetic",
+        "config": {"workload": (f"se_l24: L={L} Nt={Nt}, theta pi flux + N(0, 0.3^2) (seed 1013), {n_rv} "
+                                f"probes (seed {wl.seed}), multi-RHS CG true residual {wl.tol} {prec}, "
+                                f"spin correlator C_S(Delta) over {npairs} probe pairs"),
+                   "L": L, "Nt": Nt, "sites": N, "probes": n_rv, "precision": prec},
+        "solve_s": t_solve, "correlator_s": t_corr,
+        "cg_iters_per_probe": {"mean": float(iters.mean()), "max": int(iters.max())},
+        "max_true_resid": float(max(r[2].max() for r in rows)),
+        "status": [int(r[0]) for r in rows],
+        "C_S": {"Delta0": float(Ch[0, 0, 0].real), "Delta_x1": float(Ch[0, 0, 1].real),
+                "Delta_tau1": float(Ch[1, 0, 0].real)},
+        "correlator": {"kernels": "k_se_xy / k_se_t / k_se_accum (FP64 DFTs by direct sums)",
+                       "dft_count": 2 * npairs + 1, "tflops": corr_tflops, "peak_fp64_tflops": 78.6},
+        "roofline": {"bound": "hbm", "kernel": "k_b_cg_iter (multi-RHS CG iteration, 40 right-hand sides)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "alg_bytes_per_launch": (104 if prec != "fp64" else 176) * N * n_rv,
+                     "timing": "solve phase between events (includes updates and launch gaps)"},
+    }
+    se.close()
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_se(wl, theta.cpu().numpy(), n_rv, it_sum, a.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_se(wl, th, n_rv, it_sum, n_iter):
+    """Oracle (plain FP64, one thread) on a bounded sample of the measurement:
+    n_iter CG iterations of one probe and the FFT estimator (numpy) over 3
+    probes; scaled to the measurement's total CG iterations (all probes) and
+    780 probe pairs."""
+    import numpy as np
+    import oracle as O
+    from oracle import se as SE
+    p = O.lat(wl.L, wl.Nt, wl.dtau, wl.t, wl.J, wl.K)
+    xi = O.probes(p, wl.seed, 0, 3)
+    R = O.apply_M(p, th, xi[0], dagger=True)
+    t0 = time.perf_counter()
+    X, st, it, rel = O.cg_solve(p, th, R, tol=1e-30, maxit=n_iter)
+    t_cg = (time.perf_counter() - t0) / max(it, 1)
+    Xs = np.stack([X.reshape(wl.Nt, wl.L, wl.L)] * 3)
+    t0 = time.perf_counter()
+    SE.spin_correlator_se(p, xi, Xs)
+    t_pair = (time.perf_counter() - t0) / 3
+    npairs = n_rv * (n_rv - 1) // 2
+    hi = host_info()
+    return {"value": t_cg * it_sum + t_pair * npairs, "unit": "s/measurement", "cores": 1, "kind": "oracle",
+            "host": hi,
+            "sample": (f"oracle FP64 CG {it} iterations ({t_cg * it:.1f} s) on one probe and the numpy FFT "
+                       f"estimator over 3 probe pairs ({3 * t_pair:.1f} s) at L={wl.L} Nt={wl.Nt}; scaled to "
+                       f"{it_sum:.0f} CG iterations over all probes and {npairs} pairs (extrapolation, single "
+                       f"thread; host {hi['nproc']} cores, {hi['cpu_model']})")}
+
+
 def cpu_baseline_batched(wl, sizes, ths, per_chain_iters, n_iter):
     """Oracle (plain FP64 C, one thread) on a bounded sample: n_iter CG
     iterations and one fermion + gauge force on one chain of each lattice size
@@ -535,6 +648,8 @@ def main():
         return run_batched(a)
     if a.workload == "learned_l66":
         return run_learned(a)
+    if a.workload == "se_l24":
+        return run_se(a)
     if a.solve_only:
         return run_solve_only(a)
     if a.precond_only:
@@ -613,9 +728,11 @@ def main():
                 "time_ratio_vs_timed_path": t_path / t_here, "first": m}
 
     paths = {}
-    if not (prec == "fp64" and pc is None):
+    if m == 0:
+        pass
+    elif not (prec == "fp64" and pc is None):
         paths["fp64"] = side_by_side("plain FP64 GPU path (FP64 CG at the same tolerance)", "fp64", None)
-    if a.compare_learned and pc != "learned" and prec != "fp64":
+    if m > 0 and a.compare_learned and pc != "learned" and prec != "fp64":
         try:
             with Q.Net(lat) as cnet:
                 tr = train_learned(lat, cnet, th_start)
@@ -625,7 +742,7 @@ def main():
                 cnet.unbind()
         except Q.QedhmcError as e:
             paths["learned"] = {"error": str(e)}
-    if pc is not None and prec != "fp64":
+    if m > 0 and pc is not None and prec != "fp64":
         paths["mixed_plain"] = side_by_side("mixed precision, no preconditioner", prec, None)
 
     # standalone fused M^dag M on the same lattice (the metric's matvec)

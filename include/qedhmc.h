@@ -338,6 +338,124 @@ qedhmc_status qedhmc_batch_trajectory(qedhmc_batch_t b, double *theta_all,
                                       qedhmc_traj_result *out);
 
 /* ------------------------------------------------------------------------
+ * Production loop (Methods, "HQMC algorithm": N_leapfrog = 3 leapfrog steps
+ * per trajectory, the step size tuned to keep a moderate acceptance rate),
+ * the gauge observables it logs (Supplemental Material SV), the flux
+ * correlator (Results, Eq. (33)) and the autocorrelation of a logged series.
+ * ------------------------------------------------------------------------ */
+
+/* S_tau and S_plaq, the two terms of the handle's gauge action at theta:
+ * S_tau = 1/(J dtau) sum (theta_{tau+1} - theta_tau)^2 (non-compact; the
+ * compact action's 1 - cos of the difference), S_plaq = K dtau sum cos(curl
+ * theta) over the plaquettes.  Host outputs; synchronises. */
+qedhmc_status qedhmc_gauge_observables(qedhmc_t h, const double *theta,
+                                       double *S_tau, double *S_plaq);
+
+/* C_out[dtau] = 1/(L^2 Nt) sum_{tau, plaquettes} sin Phi(tau + dtau)
+ * sin Phi(tau), dtau = 0 .. Nt - 1, tau periodic (Eq. (33) averaged over the
+ * time origin); C_out: device double[Nt].  Enqueued, not synchronised. */
+qedhmc_status qedhmc_flux_correlator(qedhmc_t h, const double *theta,
+                                     double *C_out);
+
+typedef struct {
+    uint64_t first_traj;     /* trajectory index of the first trajectory     */
+    int32_t n_therm, n_meas; /* thermalisation (dt adapted), then measured   */
+    int32_t n_steps;         /* leapfrog steps per trajectory (3 in the paper) */
+    int32_t maxit;           /* CG iteration budget per solve                */
+    double dt0;              /* initial leapfrog step                        */
+    double target_accept;    /* in (0, 1): acceptance the step is tuned to   */
+    double gain;             /* >= 0: step-size adaptation gain              */
+    double tol;              /* CG true relative residual                    */
+    qedhmc_precision prec;
+    qedhmc_precond pc;
+} qedhmc_prod_params;
+
+typedef struct {
+    uint64_t traj;
+    double dt;               /* leapfrog step of this trajectory             */
+    double dH;
+    double S_tau, S_plaq;    /* of the chain's configuration after the
+                                Metropolis decision                          */
+    int32_t accepted, cg_iters, status, reserved;
+} qedhmc_prod_record;
+
+/* n_therm + n_meas chained trajectories from theta_inout (updated in place).
+ * Trajectory k has index first_traj + k and n_steps steps of dt.  During
+ * thermalisation, after each trajectory, dt <- dt exp(gain (min(1, e^{-dH})
+ * - target_accept)), the factor clipped to [1/2, 2]; dt is frozen for the
+ * measured trajectories.  records: host array of n_therm + n_meas.
+ * C_flux_mean (nullable): device double[Nt], the flux correlator averaged
+ * over the measured configurations.  dt_final (nullable, host): the frozen
+ * step.  Synchronises.  ENOCONV when some trajectory had an unconverged solve
+ * (that trajectory was rejected; the loop went on). */
+qedhmc_status qedhmc_production(qedhmc_t h, double *theta_inout,
+                                const qedhmc_prod_params *params,
+                                qedhmc_prod_record *records,
+                                double *C_flux_mean, double *dt_final);
+
+/* Host analysis of a series x[0..n): rho[k] = C(k)/C(0) for k = 0 .. kmax,
+ * C(k) = 1/(n-k) sum_t (x_t - mean)(x_{t+k} - mean); tau_int = 1/2 +
+ * sum_{k=1..W} rho[k] with the smallest window W >= 5 tau_int (Sokal);
+ * tau_exp from the least-squares fit of log rho[k] = -k/tau_exp over the
+ * k >= 1 before rho first drops below 0.1 (0 if none).  1 <= kmax < n.
+ * No device work. */
+qedhmc_status qedhmc_autocorrelation(const double *series, int32_t n,
+                                     int32_t kmax, double *rho,
+                                     double *tau_int, double *tau_exp);
+
+/* ------------------------------------------------------------------------
+ * Stochastic estimation of fermionic observables (Methods, "Stochastic
+ * estimation of fermionic observables", Eq. (Cij_est) and the FFT
+ * translational average after it; Supplemental Material SIV).
+ *
+ * G = M^{-1} is the Green's function of one gauge configuration.  With n_rv
+ * probes xi_p (E[xi^* xi^T] = 1) and X_p = G xi_p, computed as
+ * (M^dag M)^{-1} M^dag xi_p, the spin correlator of SIV,
+ *   C_S(i, j) = Gbar(i, j) G(i, j),  Gbar(i, j) = delta_ij - G(j, i),
+ * averaged over translations of the periodic space-time torus,
+ *   C_S(Delta) = (1/N) sum_i C_S(i, i + Delta),
+ * is estimated without bias as delta_{Delta,0} T1 - T2(Delta):
+ *   T1 = (1/(n_rv N)) sum_p sum_i X_p,i conj(xi_p,i),
+ *   T2 = average over ordered probe pairs p != q of (1/N) sum_i a_i b_{i+Delta},
+ *        a = X_p conj(xi_q), b = X_q conj(xi_p),
+ * each correlation evaluated by three-dimensional DFTs (N = L^2 Nt sites).
+ * ------------------------------------------------------------------------ */
+typedef struct qedhmc_se *qedhmc_se_t;
+
+/* A context for n_rv probes on one lattice: a multi-RHS CG (n_rv right-hand
+ * sides whose iterations share one gauge field) and the transform workspace.
+ * 2 <= n_rv, n_rv L^2 Nt < 2^32, L <= 44 (EUNSUPPORTED beyond).  The probes'
+ * Philox key is params->seed.  Work is enqueued on stream. */
+qedhmc_status qedhmc_se_create(const qedhmc_params *params, int32_t n_rv,
+                               void *stream, qedhmc_se_t *out);
+qedhmc_status qedhmc_se_destroy(qedhmc_se_t se);
+
+/* xi_all: device complex FP64 [n_rv][Nt][L][L], written with the probes of
+ * measurement meas_index: Re, Im ~ N(0, 1/2), Philox purpose 4, counter
+ * element p * N + n, index words meas_index. */
+qedhmc_status qedhmc_se_probes(qedhmc_se_t se, uint64_t meas_index,
+                               double *xi_all);
+
+/* X_p = (M^dag M)^{-1} M^dag xi_p for every probe, at relative true residual
+ * tol (FP64, or the mixed path with QEDHMC_FP32), at most maxit iterations
+ * each.  xi_all, X_all: device complex FP64 [n_rv][Nt][L][L], not aliased;
+ * theta as for qedhmc_apply_M.  iters, true_rel: host arrays of n_rv, written
+ * per probe.  Synchronises.  ENOCONV if any probe missed tol (all outputs
+ * still written). */
+qedhmc_status qedhmc_se_solve(qedhmc_se_t se, const double *theta,
+                              const double *xi_all, double *X_all, double tol,
+                              int32_t maxit, qedhmc_precision prec,
+                              int32_t *iters, double *true_rel);
+
+/* C_out = the estimate of C_S(Delta) from xi_all and X_all (as written by
+ * qedhmc_se_probes and qedhmc_se_solve, or any probes and X_p = G xi_p):
+ * device complex FP64 [Nt][L][L] indexed by Delta = (dtau, dy, dx), all
+ * arithmetic in FP64 in a fixed order.  Enqueued on the stream; does not
+ * synchronise. */
+qedhmc_status qedhmc_se_spin_correlator(qedhmc_se_t se, const double *xi_all,
+                                        const double *X_all, double *C_out);
+
+/* ------------------------------------------------------------------------
  * Learned preconditioner (not in the paper; its fixed preconditioner of
  * Methods, "CG method and preconditioner", is the fallback): a network
  * z = N(theta, r) of six 3x3x3 convolutions over the (tau, y, x) lattice,

@@ -186,6 +186,8 @@ qedhmc_status qedhmc_destroy(qedhmc_t h) {
     (void)hipFree(h->cg_arena);
     if (h->pc_dev64) (void)hipFree(h->pc_dev64);
     if (h->pc_dev32) (void)hipFree(h->pc_dev32);
+    if (h->pc_roll64) (void)hipFree(h->pc_roll64);
+    if (h->pc_roll32) (void)hipFree(h->pc_roll32);
     (void)hipFree(h->theta0);
     (void)hipFree(h->mom);
     (void)hipFree(h->force);

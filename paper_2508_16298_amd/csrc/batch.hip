@@ -255,6 +255,9 @@ struct qedhmc_batch {
     float tune_us[2][4] = {};       // per-iteration time of each candidate (0: not a candidate)
     hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [R is double][start parity]
     double graph_tol2[2][2] = {{-1, -1}, {-1, -1}};
+    // every chain reads chain 0's phase caches: one gauge field, many right-hand
+    // sides (the multi-RHS solve of the stochastic estimation)
+    bool shared = false;
 };
 
 namespace qh {
@@ -372,8 +375,9 @@ static void init_tab(qedhmc_batch* b) {
         d.B.p = base + 6 * N;
         d.B.Ox = reinterpret_cast<const cplx<double>*>(h->ws[3]);
         d.B.part = h->partial;
-        d.gauge = gauge_for<R>(h);
-        d.gauge64 = h->gauge64;
+        qedhmc_ctx* hg = b->shared ? b->ctx[0] : h;
+        d.gauge = gauge_for<R>(hg);
+        d.gauge64 = hg->gauge64;
         d.scal = b->d_scal + (size_t)c * 2 * S_NSLOT;
         d.co = coef_of<R>(h->p);
         d.co64 = coef_of<double>(h->p);
@@ -834,6 +838,70 @@ qedhmc_status qedhmc_batch_cg_solve(qedhmc_batch_t b, const double* theta_all, c
     if (st != QEDHMC_OK) set_error("batched CG: at least one chain did not converge");
     return st;
 }
+
+}  // extern "C"
+
+namespace qh {
+
+qedhmc_status batch_create_shared(const qedhmc_params& params, int n, void* stream, qedhmc_batch** out) {
+    *out = nullptr;
+    const std::vector<qedhmc_params> ps(n, params);
+    qedhmc_batch* b = nullptr;
+    QH_TRY(qedhmc_batch_create(ps.data(), n, stream, &b));
+    b->shared = true;
+    init_tab<float>(b);
+    init_tab<double>(b);
+    const std::vector<const double*> no_rhs(n, nullptr);
+    const std::vector<double*> no_x(n, nullptr);
+    qedhmc_status st = push_tab<float>(b, no_rhs, no_x, 0, false);
+    if (st == QEDHMC_OK) st = push_tab<double>(b, no_rhs, no_x, 0, false);
+    if (st == QEDHMC_OK && hipStreamSynchronize(b->stream) != hipSuccess)
+        st = hip_fail(hipGetLastError(), "shared batch create");
+    if (st != QEDHMC_OK) return batch_fail(b, st);
+    *out = b;
+    return QEDHMC_OK;
+}
+
+qedhmc_ctx* batch_ctx0(qedhmc_batch* b) { return b->ctx[0]; }
+
+qedhmc_status batch_enter(qedhmc_batch* b) { return enter(b); }
+
+qedhmc_status batch_solve_shared(qedhmc_batch* b, const double* theta, const double* rhs_all, double* x_all,
+                                 double tol, int maxit, qedhmc_precision prec, int32_t* iters, double* true_rel) {
+    if (!b->shared) {
+        set_error("batch_solve_shared needs a batch made by batch_create_shared");
+        return QEDHMC_EINVAL;
+    }
+    QH_TRY(batch_args(b, theta, rhs_all, tol, maxit, prec));
+    QH_TRY(enter(b));
+    qedhmc_ctx* h0 = b->ctx[0];
+    QH_TRY(ensure_gauge(h0, theta, QEDHMC_FP64));
+    if (prec != QEDHMC_FP64) QH_TRY(ensure_gauge(h0, theta, QEDHMC_FP32));
+    const int64_t N = b->voff[1];
+    std::vector<const double*> rhs(b->n);
+    std::vector<double*> x(b->n);
+    for (int c = 0; c < b->n; c++) {
+        rhs[c] = rhs_all + 2 * N * c;
+        x[c] = x_all + 2 * N * c;
+    }
+    SolveOut so;
+    if (prec == QEDHMC_FP64)
+        QH_TRY(batch_cg<double>(b, rhs, x, tol, maxit, false, so));
+    else
+        QH_TRY(batch_cg<float>(b, rhs, x, tol, maxit, true, so));
+    qedhmc_status st = QEDHMC_OK;
+    for (int c = 0; c < b->n; c++) {
+        iters[c] = so.iters[c];
+        true_rel[c] = so.rel[c];
+        if (so.status[c] != QEDHMC_OK) st = QEDHMC_ENOCONV;
+    }
+    if (st != QEDHMC_OK) set_error("multi-RHS CG: at least one right-hand side did not converge");
+    return st;
+}
+
+}  // namespace qh
+
+extern "C" {
 
 qedhmc_status qedhmc_batch_trajectory(qedhmc_batch_t b, double* theta_all, uint64_t traj, int32_t n_steps,
                                       double traj_len, double tol, int32_t maxit, qedhmc_precision prec,

@@ -200,4 +200,92 @@ qedhmc_status launch_restore(qedhmc_ctx* h, double* theta, const double* theta0,
     return QEDHMC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Gauge observables of the production loop (Supplemental Material SV; Results,
+// Eq. 33): the time-link and plaquette terms of the action separately, and
+// the flux correlator C(dtau) = 1/(V_s N_tau) sum_{tau,s} sin Phi(tau + dtau, s)
+// sin Phi(tau, s) with tau periodic.
+// ---------------------------------------------------------------------------
+__global__ void k_gauge_parts(Lat lt, double J, double K, double dtau, int noncompact, const double* __restrict__ th,
+                              double* __restrict__ part) {
+    __shared__ double red[16];
+    const double cj = 1.0 / (J * dtau), kd = K * dtau;
+    const size_t N = (size_t)lt.Nt * lt.Vs;
+    double st = 0.0, sp = 0.0;
+    for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N; n += (size_t)gridDim.x * blockDim.x) {
+        const int tau = (int)(n / lt.Vs), s = (int)(n - (size_t)tau * lt.Vs);
+        const int tp = tau + 1 == lt.Nt ? 0 : tau + 1;
+        sp += kd * cos(plaq(th, lt, tau, s % lt.L, s / lt.L));
+        for (int d = 0; d < 2; d++) {
+            const double u = th[(size_t)d * N + (size_t)tp * lt.Vs + s] - th[(size_t)d * N + (size_t)tau * lt.Vs + s];
+            st += cj * (noncompact ? u * u : 1.0 - cos(u));
+        }
+    }
+    st = block_sum(st, red);
+    __syncthreads();
+    sp = block_sum(sp, red);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = st;
+        part[gridDim.x + blockIdx.x] = sp;
+    }
+}
+
+qedhmc_status launch_gauge_parts(qedhmc_ctx* h, const double* theta, double* out_dev) {
+    double* part = (h->partial + 12 * (size_t)h->lat.Nt);  // 2 x kGridR of the 4096 spare doubles
+    hipLaunchKernelGGL(k_gauge_parts, dim3(kGridR), dim3(kBlockR), 0, h->stream, h->lat, h->p.J, h->p.K, h->p.dtau,
+                       h->p.action == QEDHMC_NONCOMPACT ? 1 : 0, theta, part);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, h->stream, (const double*)part, kGridR, out_dev);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, h->stream, (const double*)(part + kGridR), kGridR,
+                       out_dev + 1);
+    QH_HIP(hipGetLastError());
+    return QEDHMC_OK;
+}
+
+__global__ void k_sin_plaq(Lat lt, const double* __restrict__ th, double* __restrict__ sp) {
+    const size_t N = (size_t)lt.Nt * lt.Vs;
+    for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N; n += (size_t)gridDim.x * blockDim.x) {
+        const int tau = (int)(n / lt.Vs), s = (int)(n - (size_t)tau * lt.Vs);
+        sp[n] = sin(plaq(th, lt, tau, s % lt.L, s / lt.L));
+    }
+}
+
+// one workgroup per dtau; acc: C is added to out (accumulate = 1) or written
+__global__ void k_flux_corr(Lat lt, const double* __restrict__ sp, int accumulate, double* __restrict__ out) {
+    __shared__ double red[16];
+    const int dt = blockIdx.x;
+    const size_t N = (size_t)lt.Nt * lt.Vs;
+    double c = 0.0;
+    for (size_t n = threadIdx.x; n < N; n += blockDim.x) {
+        const int tau = (int)(n / lt.Vs), s = (int)(n - (size_t)tau * lt.Vs);
+        int t2 = tau + dt;
+        if (t2 >= lt.Nt) t2 -= lt.Nt;
+        c += sp[n] * sp[(size_t)t2 * lt.Vs + s];
+    }
+    c = block_sum(c, red);
+    if (threadIdx.x == 0) {
+        c /= (double)N;
+        out[dt] = accumulate ? out[dt] + c : c;
+    }
+}
+
+qedhmc_status launch_flux_corr(qedhmc_ctx* h, const double* theta, bool accumulate, double* out_dev) {
+    double* sp = static_cast<double*>(h->ws[10]);
+    hipLaunchKernelGGL(k_sin_plaq, dim3(kGridR), dim3(kBlockR), 0, h->stream, h->lat, theta, sp);
+    hipLaunchKernelGGL(k_flux_corr, dim3(h->lat.Nt), dim3(kBlockR), 0, h->stream, h->lat, (const double*)sp,
+                       accumulate ? 1 : 0, out_dev);
+    QH_HIP(hipGetLastError());
+    return QEDHMC_OK;
+}
+
+__global__ void k_scale(double* __restrict__ a, int n, double c) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] *= c;
+}
+
+qedhmc_status launch_scale(qedhmc_ctx* h, double* a, int n, double c) {
+    hipLaunchKernelGGL(k_scale, dim3((n + 255) / 256), dim3(256), 0, h->stream, a, n, c);
+    QH_HIP(hipGetLastError());
+    return QEDHMC_OK;
+}
+
 }  // namespace qh

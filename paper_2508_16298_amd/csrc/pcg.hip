@@ -29,6 +29,7 @@
 #include <vector>
 
 #include <cstdlib>
+#include <cstring>
 #include "cg_common.h"
 
 namespace qh {
@@ -222,6 +223,43 @@ static qedhmc_status build_paper_precond(qedhmc_ctx* h) {
             }
         }
     }
+    // the same passes grouped by spatial offset for the tau-rolling kernel
+    // (a pass reaching exactly kRollNS tau offsets; otherwise rcount stays 0)
+    std::vector<RTap<double>> r64;
+    std::vector<RTap<float>> r32;
+    for (int ps = 0; ps < 2; ps++) {
+        PcPass& g = h->pc_pass[ps];
+        const int half = (h->lat.L + g.cmax - g.cmin + 1) / 2;
+        for (int par = 0; par < 2; par++) {
+            g.rfirst[par] = (int)r64.size();
+            g.rcount[par] = 0;
+            if (g.amax - g.amin + 1 != kRollNS) continue;
+            std::vector<std::pair<int, int>> offs;  // (dy, dx) in first-seen order of the sorted list
+            for (const auto& t : pass[ps][par])
+                if (std::find(offs.begin(), offs.end(), std::make_pair(t.dy, t.dx)) == offs.end())
+                    offs.push_back({t.dy, t.dx});
+            std::sort(offs.begin(), offs.end());
+            for (const auto& od : offs) {
+                const int q = par + od.second - g.cmin;
+                RTap<double> a{od.first * half + (q >> 1), q & 1, 0, 0, {}};
+                for (int k = 0; k < kRollNS; k++) a.g[k] = mk<double>(0.0, 0.0);
+                for (const auto& t : pass[ps][par])
+                    if (t.dy == od.first && t.dx == od.second) a.g[t.dt - g.amin] = mk<double>(t.gre, t.gim);
+                RTap<float> b{a.off, a.plane, 0, 0, {}};
+                for (int k = 0; k < kRollNS; k++) b.g[k] = mk<float>((float)a.g[k].re, (float)a.g[k].im);
+                r64.push_back(a);
+                r32.push_back(b);
+            }
+            g.rcount[par] = (int)offs.size();
+        }
+    }
+    const size_t nr = r64.size();
+    QH_HIP(hipMalloc(&h->pc_roll64, std::max<size_t>(nr, 1) * sizeof(RTap<double>)));
+    QH_HIP(hipMalloc(&h->pc_roll32, std::max<size_t>(nr, 1) * sizeof(RTap<float>)));
+    if (nr) {
+        QH_HIP(hipMemcpyAsync(h->pc_roll64, r64.data(), nr * sizeof(RTap<double>), hipMemcpyHostToDevice, h->stream));
+        QH_HIP(hipMemcpyAsync(h->pc_roll32, r32.data(), nr * sizeof(RTap<float>), hipMemcpyHostToDevice, h->stream));
+    }
     const size_t nt = t64.size();
     QH_HIP(hipMalloc(&h->pc_dev64, std::max<size_t>(nt, 1) * sizeof(PTap<double>)));
     QH_HIP(hipMalloc(&h->pc_dev32, std::max<size_t>(nt, 1) * sizeof(PTap<float>)));
@@ -389,6 +427,220 @@ __global__ __launch_bounds__(1024, 2) void k_pc_stream(PcGeo g, const PTap<R>* _
     }
 }
 
+// ---------------------------------------------------------------------------
+// The same stencil pass rolled along tau.  The taps of a spatial offset
+// (b, c) at the kRollNS tau offsets a = amin .. amax act on one input value
+// in(s, y + b, x + c); a lane reads that value once per input slice s and
+// adds its kRollNS products into the running sums of the outputs s - a, held
+// in registers (output tau is complete once slice tau + amax has been read).
+// A workgroup owns one x parity of a band of TY rows and a run of Tc output
+// slices, reads Tc + kRollNS - 1 input slices one at a time into a double
+// buffer in LDS (window of the band plus the rows and columns the taps reach,
+// even and odd columns as two planes, sign-flipped where the slice index
+// leaves [0, Nt)), and gives each output site Q lanes in Q different
+// wavefronts, each taking every Q-th spatial offset: the offset index is
+// uniform across a wavefront, so the taps come through scalar loads.  The
+// Q partial sums of a completed output meet in LDS.  One barrier per slice.
+// ---------------------------------------------------------------------------
+struct PcRollGeo {
+    int L, Nt, Vs;
+    int TY, nband, Tc, nrun;
+    int rows, cols, half, bmin, cmin, amin;
+    int S, Q;  // lanes per copy of the band's sites (a multiple of 64) and copies
+    int first[2], count[2];
+};
+
+static constexpr int kRollElems = 4;  // window elements per thread at most
+
+template <typename R>
+__global__ __launch_bounds__(1024) void k_pc_roll(PcRollGeo g, const RTap<R>* __restrict__ taps,
+                                                  const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
+                                                  const double* __restrict__ stop) {
+    if (stop && *stop != 0.0) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int plane = g.rows * g.half, slice_elems = 2 * plane;
+    cplx<R>* win = reinterpret_cast<cplx<R>*>(smem);  // [2][slice_elems]
+    cplx<R>* red = win + 2 * slice_elems;             // [2][Q][S] partial sums of completed outputs
+    const int nwork = g.nband * g.nrun * 2;
+    const int per = (nwork + 7) >> 3;
+    const int w = (blockIdx.x & 7) * per + (blockIdx.x >> 3);  // runs of one XCD are contiguous
+    if (w >= nwork) return;
+    const int par = w & 1, band = (w >> 1) % g.nband, run = (w >> 1) / g.nband;
+    const int y0 = band * g.TY;
+    const int tau0 = run * g.Tc, tau1 = min(g.Nt, tau0 + g.Tc);
+    const int hx = g.L / 2;
+    const int o = (int)threadIdx.x % g.S;
+    const int q = __builtin_amdgcn_readfirstlane((int)threadIdx.x / g.S);
+    const int iy = o / hx, jx = o - iy * hx;
+    const bool act = iy < g.TY && y0 + iy < g.L;
+    const int base = act ? (iy - g.bmin) * g.half + jx : 0;  // idle lanes read a valid element
+    int soff[kRollElems], doff[kRollElems];
+    {
+        const int total = g.rows * g.cols;
+#pragma unroll
+        for (int k = 0; k < kRollElems; k++) {
+            const int e = (int)threadIdx.x + k * (int)blockDim.x;
+            doff[k] = -1;
+            soff[k] = 0;
+            if (e < total) {
+                const int r = e / g.cols, c = e - r * g.cols;
+                const int yy = (y0 + g.bmin + r + 8 * g.L) % g.L, xx = (g.cmin + c + 8 * g.L) % g.L;
+                soff[k] = yy * g.L + xx;
+                doff[k] = (c & 1) * plane + r * g.half + (c >> 1);
+            }
+        }
+    }
+    auto fetch = [&](int s, cplx<R> (&v)[kRollElems]) {
+        const cplx<R>* src = in + (size_t)(((s % g.Nt) + g.Nt) % g.Nt) * g.Vs;
+#pragma unroll
+        for (int k = 0; k < kRollElems; k++) v[k] = src[soff[k]];  // unused entries read site 0
+    };
+    auto store = [&](int buf, int s, const cplx<R> (&v)[kRollElems]) {
+        const R sg = (s < 0 || s >= g.Nt) ? R(-1) : R(1);
+        cplx<R>* dst = win + (size_t)buf * slice_elems;
+#pragma unroll
+        for (int k = 0; k < kRollElems; k++)
+            if (doff[k] >= 0) dst[doff[k]] = mk<R>(sg * v[k].re, sg * v[k].im);
+    };
+    const RTap<R>* tp = taps + g.first[par];
+    const int ntap = g.count[par];
+    const int nsteps = (tau1 - tau0) + kRollNS - 1;
+    const int s0 = tau0 + g.amin;
+    cplx<R> acc[kRollNS];
+#pragma unroll
+    for (int k = 0; k < kRollNS; k++) acc[k] = mk<R>(R(0), R(0));
+    cplx<R> nxt[kRollElems];
+    fetch(s0, nxt);
+    store(0, s0, nxt);
+    __syncthreads();
+    for (int j0 = 0; j0 < nsteps; j0 += kRollNS) {
+#pragma unroll
+        for (int u = 0; u < kRollNS; u++) {
+            const int j = j0 + u;
+            if (j >= nsteps) break;
+            if (j + 1 < nsteps) fetch(s0 + j + 1, nxt);  // in flight during the taps
+            const cplx<R>* ws = win + (size_t)(j & 1) * slice_elems + base;
+            // wavefronts past the Q copies only help load the window
+            for (int k = q; k < (q < g.Q ? ntap : 0); k += g.Q) {
+                const RTap<R> t = tp[k];
+                const cplx<R> v = ws[t.plane * plane + t.off];
+                // input slice s0 + j feeds output tau0 + j - kk through the tap of tau offset amin + kk
+#pragma unroll
+                for (int kk = 0; kk < kRollNS; kk++) {
+                    cplx<R>& A = acc[(u - kk + kRollNS) % kRollNS];
+                    A.re = fma(t.g[kk].re, v.re, A.re);
+                    A.re = fma(-t.g[kk].im, v.im, A.re);
+                    A.im = fma(t.g[kk].re, v.im, A.im);
+                    A.im = fma(t.g[kk].im, v.re, A.im);
+                }
+            }
+            // output tau0 + j - (kRollNS - 1) is complete in slot (u + 1) mod kRollNS
+            const int cs = (u + 1) % kRollNS;
+            cplx<R>* rb = red + (size_t)(j & 1) * g.Q * g.S;
+            if (g.Q > 1 && q < g.Q) rb[q * g.S + o] = acc[cs];
+            if (j + 1 < nsteps) store((j + 1) & 1, s0 + j + 1, nxt);
+            __syncthreads();
+            const int tau = tau0 + j - (kRollNS - 1);
+            if (q == 0 && act && tau >= tau0) {
+                cplx<R> sum = acc[cs];
+                if (g.Q > 1) {
+                    sum = rb[o];
+                    for (int k = 1; k < g.Q; k++) {
+                        sum.re += rb[k * g.S + o].re;
+                        sum.im += rb[k * g.S + o].im;
+                    }
+                }
+                out[(size_t)tau * g.Vs + (y0 + iy) * g.L + 2 * jx + par] = sum;
+            }
+            acc[cs] = mk<R>(R(0), R(0));
+        }
+    }
+}
+
+template <typename R>
+static const RTap<R>* rtaps_for(qedhmc_ctx* h) {
+    if constexpr (sizeof(R) == 8)
+        return (const RTap<double>*)h->pc_roll64;
+    else
+        return (const RTap<float>*)h->pc_roll32;
+}
+
+// Plan: a band of TY rows whose TY * L/2 output sites fill whole wavefronts
+// best (at most 256 lanes per copy), Q = 4 copies, and runs of Tc slices
+// aiming at about 2048 wavefronts per pass (at least 6 slices: each run
+// reads kRollNS - 1 slices more than it writes).  QEDHMC_PC_TY, QEDHMC_PC_TC
+// and QEDHMC_PC_Q (read per call) override the plan.
+template <typename R>
+static qedhmc_status launch_pc_roll(qedhmc_ctx* h, int ps, const cplx<R>* in, cplx<R>* out, const double* stop) {
+    const PcPass& pp = h->pc_pass[ps];
+    const Lat& lt = h->lat;
+    PcRollGeo g{};
+    g.L = lt.L;
+    g.Nt = lt.Nt;
+    g.Vs = lt.Vs;
+    g.bmin = pp.bmin;
+    g.cmin = pp.cmin;
+    g.amin = pp.amin;
+    g.cols = lt.L + pp.cmax - pp.cmin;
+    g.half = (g.cols + 1) / 2;
+    for (int par = 0; par < 2; par++) {
+        g.first[par] = pp.rfirst[par];
+        g.count[par] = pp.rcount[par];
+    }
+    const int hx = lt.L / 2;
+    auto pad64 = [](int n) { return ((n + 63) / 64) * 64; };
+    int TY = 1;
+    double best = -1.0;
+    for (int ty = 1; ty <= lt.L && pad64(ty * hx) <= 256; ty++) {
+        const double eff = (double)(ty * hx) / pad64(ty * hx);
+        if (eff >= best - 1e-9) {
+            best = eff;
+            TY = ty;
+        }
+    }
+    const char* ety = std::getenv("QEDHMC_PC_TY");
+    const char* etc = std::getenv("QEDHMC_PC_TC");
+    const char* eq = std::getenv("QEDHMC_PC_Q");
+    if (ety && std::atoi(ety) > 0) TY = std::min(lt.L, std::atoi(ety));
+    g.nband = (lt.L + TY - 1) / TY;
+    g.TY = (lt.L + g.nband - 1) / g.nband;
+    g.rows = g.TY + pp.bmax - pp.bmin;
+    g.S = pad64(g.TY * hx);
+    g.Q = 4;
+    if (eq && std::atoi(eq) > 0) g.Q = std::atoi(eq);
+    while (g.Q > 1 && g.Q * g.S > 1024) g.Q--;
+    if (g.S > 1024) {
+        set_error("paper preconditioner: a band row exceeds one workgroup at this L");
+        return QEDHMC_EUNSUPPORTED;
+    }
+    // every window element of a slice has a thread (kRollElems each at most):
+    // whole wavefronts past the Q copies only load
+    const int need = ((g.rows * g.cols + kRollElems - 1) / kRollElems + 63) / 64 * 64;
+    const int threads = std::max(g.Q * g.S, need);
+    if (threads > 1024) {
+        set_error("paper preconditioner: the stencil window exceeds the rolling kernel's workgroup");
+        return QEDHMC_EUNSUPPORTED;
+    }
+    const int waves_per_run = 2 * g.nband * g.Q * g.S / 64;
+    int nrun = std::max(1, (2048 + waves_per_run - 1) / waves_per_run);
+    g.Tc = std::max(6, (lt.Nt + nrun - 1) / nrun);
+    if (etc && std::atoi(etc) > 0) g.Tc = std::atoi(etc);
+    g.Tc = std::min(g.Tc, lt.Nt);
+    g.nrun = (lt.Nt + g.Tc - 1) / g.Tc;
+    const size_t lds = (size_t)2 * 2 * g.rows * g.half * sizeof(cplx<R>) +
+                       (g.Q > 1 ? (size_t)2 * g.Q * g.S * sizeof(cplx<R>) : 0);
+    if (lds > h->max_lds) {
+        set_error("paper preconditioner: the rolling kernel's window exceeds the LDS");
+        return QEDHMC_EUNSUPPORTED;
+    }
+    if (lds > 65536) QH_TRY(allow_lds((const void*)k_pc_roll<R>, h->max_lds));
+    const int nwork = g.nband * g.nrun * 2;
+    hipLaunchKernelGGL(k_pc_roll<R>, dim3(8 * ((nwork + 7) / 8)), dim3(threads), lds, h->stream, g, rtaps_for<R>(h),
+                       in, out, stop);
+    QH_HIP(hipGetLastError());
+    return QEDHMC_OK;
+}
+
 template <typename R>
 static const PTap<R>* taps_for(qedhmc_ctx* h) {
     if constexpr (sizeof(R) == 8)
@@ -406,6 +658,11 @@ static const PTap<R>* taps_for(qedhmc_ctx* h) {
 template <typename R>
 static qedhmc_status launch_pc(qedhmc_ctx* h, int ps, const cplx<R>* in, cplx<R>* out, const double* stop) {
     const PcPass& pp = h->pc_pass[ps];
+    // the tau-rolling kernel where the pass was grouped for it;
+    // QEDHMC_PC_KERNEL=stream (read per call) keeps the per-tap kernel
+    const char* ek = std::getenv("QEDHMC_PC_KERNEL");
+    if (pp.rcount[0] > 0 && pp.rcount[1] > 0 && !(ek && std::strcmp(ek, "stream") == 0))
+        return launch_pc_roll<R>(h, ps, in, out, stop);
     const Lat& lt = h->lat;
     PcGeo g{};
     g.L = lt.L;

@@ -502,7 +502,24 @@ struct PcPass {
     int amin, amax, bmin, bmax, cmin, cmax;
     int first[2], count[2];
     int gstart[2][9];  // per parity: start of the taps of tau offset amin + k, k = 0 .. 8
+    // the same taps grouped by spatial offset (the tau-rolling kernel): where
+    // each parity's offset list starts and its length (0: not built)
+    int rfirst[2], rcount[2];
 };
+
+namespace qh {
+// tau offsets of a pass the tau-rolling stencil kernel holds in registers
+constexpr int kRollNS = 7;
+// One spatial offset of a stencil pass with the taps of all its tau offsets:
+// off and plane locate the source relative to the output in the LDS window
+// (as for the per-tap lists), g[k] is the tap of tau offset amin + k (zero
+// when the stencil has none there).
+template <typename R>
+struct RTap {
+    int off, plane, pad0, pad1;
+    cplx<R> g[kRollNS];
+};
+}  // namespace qh
 
 struct qedhmc_net;
 
@@ -569,6 +586,8 @@ struct qedhmc_ctx {
     PcPass pc_pass[2];                // G and G^dag
     void* pc_dev64;                   // device taps, FP64 and FP32
     void* pc_dev32;
+    void* pc_roll64;                  // device taps grouped by spatial offset (RTap), FP64 and FP32
+    void* pc_roll32;
     // the learned preconditioner (QEDHMC_PC_LEARNED): a network bound to this
     // handle, its arithmetic and the fallback its residual judge hands over to
     qedhmc_net* pc_net;
@@ -653,6 +672,18 @@ qedhmc_status launch_apply_precond_fp32(qedhmc_ctx* h, const double* in, double*
 // Gauge-field and trajectory kernels (boson.hip)
 qedhmc_status launch_bosonic(qedhmc_ctx* h, const double* theta, double* F_B, double* S_dev);
 qedhmc_status launch_heatbath(qedhmc_ctx* h, uint64_t traj, double* mom, double* R);
+// production-loop observables: (S_tau, S_plaq) into out_dev[0..1]; C_flux(dtau)
+// into (or added to) out_dev[0..Nt); out_dev[0..n) *= c
+qedhmc_status launch_gauge_parts(qedhmc_ctx* h, const double* theta, double* out_dev);
+qedhmc_status launch_flux_corr(qedhmc_ctx* h, const double* theta, bool accumulate, double* out_dev);
+qedhmc_status launch_scale(qedhmc_ctx* h, double* a, int n, double c);
+// batches of right-hand sides on one lattice and one gauge field (every chain
+// reads chain 0's phase caches): the multi-RHS CG
+qedhmc_status batch_create_shared(const qedhmc_params& params, int n, void* stream, qedhmc_batch** out);
+qedhmc_ctx* batch_ctx0(qedhmc_batch* b);
+qedhmc_status batch_enter(qedhmc_batch* b);
+qedhmc_status batch_solve_shared(qedhmc_batch* b, const double* theta, const double* rhs_all, double* x_all,
+                                 double tol, int maxit, qedhmc_precision prec, int32_t* iters, double* true_rel);
 qedhmc_status launch_dot_re(qedhmc_ctx* h, const double* a, const double* b, size_t n, double* out_dev);
 qedhmc_status launch_sumsq(qedhmc_ctx* h, const double* a, size_t n, double* out_dev);
 qedhmc_status launch_kick(qedhmc_ctx* h, double* mom, const double* F, const double* Fb, double c, size_t n);

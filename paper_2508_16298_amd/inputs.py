@@ -74,7 +74,11 @@ WORKLOADS = {
                                tol=1e-8, precision="mixed"),
     "learned_l66": Workload("learned_l66", L=66, Nt=660, seed=1005, n_steps=20, tol=1e-8,
                             precision="mixed"),
+    # stochastic estimation: the angles of mixed_l24, 40 probes per measurement (seed 1006)
+    "se_l24": Workload("se_l24", L=24, Nt=240, seed=1006, n_steps=0, tol=1e-8, precision="mixed",
+                       theta="pi_noise", sigma=0.3, theta_seed=1013),
 }
+SE_PROBES = 40
 
 
 def hot_start_theta(L: int, Nt: int, seed: int) -> np.ndarray:

@@ -53,6 +53,22 @@ class TrajResult(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ProdParams(C.Structure):
+    _fields_ = [("first_traj", C.c_uint64), ("n_therm", C.c_int32), ("n_meas", C.c_int32),
+                ("n_steps", C.c_int32), ("maxit", C.c_int32), ("dt0", C.c_double),
+                ("target_accept", C.c_double), ("gain", C.c_double), ("tol", C.c_double),
+                ("prec", C.c_int), ("pc", C.c_int)]
+
+
+class ProdRecord(C.Structure):
+    _fields_ = [("traj", C.c_uint64), ("dt", C.c_double), ("dH", C.c_double), ("S_tau", C.c_double),
+                ("S_plaq", C.c_double), ("accepted", C.c_int32), ("cg_iters", C.c_int32),
+                ("status", C.c_int32), ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 _lib = None
 _P = C.c_void_p
 
@@ -100,6 +116,15 @@ def load():
         "qedhmc_checkpoint_load": [_P, C.c_char_p, _P, C.POINTER(C.c_uint64)],
         "qedhmc_fcg_solve": [_P, _P, _P, _P, C.c_double, C.c_int32, C.c_int, C.c_int, C.POINTER(C.c_int32),
                              C.POINTER(C.c_double), C.POINTER(C.c_int32)],
+        "qedhmc_gauge_observables": [_P, _P, C.POINTER(C.c_double), C.POINTER(C.c_double)],
+        "qedhmc_flux_correlator": [_P, _P, _P],
+        "qedhmc_production": [_P, _P, C.POINTER(ProdParams), _P, _P, C.POINTER(C.c_double)],
+        "qedhmc_autocorrelation": [_P, C.c_int32, C.c_int32, _P, C.POINTER(C.c_double), C.POINTER(C.c_double)],
+        "qedhmc_se_create": [C.POINTER(Params), C.c_int32, _P, C.POINTER(_P)],
+        "qedhmc_se_destroy": [_P],
+        "qedhmc_se_probes": [_P, C.c_uint64, _P],
+        "qedhmc_se_solve": [_P, _P, _P, _P, C.c_double, C.c_int32, C.c_int, _P, _P],
+        "qedhmc_se_spin_correlator": [_P, _P, _P, _P],
         "qedhmc_batch_create": [C.POINTER(Params), C.c_int32, _P, C.POINTER(_P)],
         "qedhmc_batch_destroy": [_P],
         "qedhmc_batch_layout": [_P, _P, _P],
@@ -146,6 +171,17 @@ def checkpoint_info(path):
     nxt = C.c_uint64(0)
     _check(load().qedhmc_checkpoint_info(os.fsencode(path), C.byref(p), C.byref(nxt)))
     return {k: getattr(p, k) for k, _ in p._fields_}, nxt.value
+
+
+def autocorrelation(series, kmax):
+    """qedhmc_autocorrelation: (rho[0..kmax], tau_int, tau_exp) of a host series."""
+    import numpy as np
+    x = np.ascontiguousarray(series, dtype=np.float64)
+    rho = np.zeros(int(kmax) + 1, dtype=np.float64)
+    ti, te = C.c_double(0.0), C.c_double(0.0)
+    _check(load().qedhmc_autocorrelation(x.ctypes.data_as(C.c_void_p), x.size, int(kmax),
+                                         rho.ctypes.data_as(C.c_void_p), C.byref(ti), C.byref(te)))
+    return rho, ti.value, te.value
 
 
 NOALLOC_SCRATCH_BYTES = 16 << 20
@@ -319,6 +355,37 @@ class Lattice:
                                             _PC[precond], C.byref(res)), allow=(OK, ENOCONV))
         return res.as_dict()
 
+    def gauge_observables(self, theta):
+        """(S_tau, S_plaq) at theta."""
+        self._check_theta(theta)
+        a, b = C.c_double(0.0), C.c_double(0.0)
+        self._sync_stream()
+        _check(load().qedhmc_gauge_observables(self.h, _ptr(theta), C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def flux_correlator(self, theta, out=None):
+        self._check_theta(theta)
+        out = self._torch.empty(self.Nt, dtype=self._torch.float64, device="cuda") if out is None else out
+        self._sync_stream()
+        _check(load().qedhmc_flux_correlator(self.h, _ptr(theta), _ptr(out)))
+        return out
+
+    def production(self, theta, first_traj, n_therm, n_meas, dt0, target_accept=0.7, gain=1.0, n_steps=3,
+                   tol=1e-10, maxit=1_000_000, prec="fp64", precond=None, flux=True):
+        """Chained trajectories with step-size adaptation during thermalisation
+        (theta updated in place); returns (status, records, C_flux mean or None, dt_final)."""
+        self._check_theta(theta)
+        n = int(n_therm) + int(n_meas)
+        pp = ProdParams(int(first_traj), int(n_therm), int(n_meas), int(n_steps), int(maxit), float(dt0),
+                        float(target_accept), float(gain), float(tol), _PREC[prec], _PC[precond])
+        recs = (ProdRecord * max(n, 1))()
+        Cf = self._torch.empty(self.Nt, dtype=self._torch.float64, device="cuda") if flux else None
+        dtf = C.c_double(0.0)
+        self._sync_stream()
+        st = _check(load().qedhmc_production(self.h, _ptr(theta), C.byref(pp), C.cast(recs, C.c_void_p),
+                                             _ptr(Cf) if flux else None, C.byref(dtf)), allow=(OK, ENOCONV))
+        return st, [recs[k].as_dict() for k in range(n)], Cf, dtf.value
+
 
     def checkpoint_save(self, theta, next_traj, path):
         """Write the chain state (parameters, theta, next trajectory index) to path."""
@@ -447,6 +514,75 @@ class Batch:
 
 NET_FP32, NET_BF16 = 0, 1
 _ARITH = {"fp32": NET_FP32, "bf16": NET_BF16, NET_FP32: NET_FP32, NET_BF16: NET_BF16}
+
+
+class Stochastic:
+    """Stochastic estimation of the spin correlator on one lattice with n_rv
+    probes (qedhmc_se_create); bound to torch's current stream at creation.
+    Probe sets and solutions are complex128 tensors (n_rv, Nt, L, L)."""
+
+    def __init__(self, L, Nt, n_rv, dtau=0.1, t=1.0, J=1.0, K=1.0, seed=0, noncompact=False):
+        import torch
+        self._torch = torch
+        self.L, self.Nt, self.n_rv = int(L), int(Nt), int(n_rv)
+        self.params = Params(self.L, self.Nt, dtau, t, J, K, seed, NONCOMPACT if noncompact else COMPACT, 0)
+        h = _P()
+        _check(load().qedhmc_se_create(C.byref(self.params), self.n_rv, _stream_handle(), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().qedhmc_se_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _set(self):
+        return self._torch.empty((self.n_rv, self.Nt, self.L, self.L), dtype=self._torch.complex128, device="cuda")
+
+    def _check_set(self, v):
+        assert v.is_cuda and v.dtype == self._torch.complex128 and v.is_contiguous()
+        assert tuple(v.shape) == (self.n_rv, self.Nt, self.L, self.L), v.shape
+
+    def probes(self, meas, out=None):
+        out = self._set() if out is None else out
+        self._check_set(out)
+        _check(load().qedhmc_se_probes(self.h, int(meas), _ptr(out)))
+        return out
+
+    def solve(self, theta, xi, tol=1e-10, maxit=1_000_000, prec="fp64", out=None):
+        """Returns (X, status, iters[n_rv], true_rel[n_rv]); status OK or ENOCONV."""
+        import numpy as np
+        assert theta.is_cuda and theta.dtype == self._torch.float64 and theta.is_contiguous()
+        assert theta.numel() == 2 * self.L * self.L * self.Nt
+        self._check_set(xi)
+        X = self._set() if out is None else out
+        self._check_set(X)
+        it = np.zeros(self.n_rv, dtype=np.int32)
+        rel = np.zeros(self.n_rv, dtype=np.float64)
+        st = _check(load().qedhmc_se_solve(self.h, _ptr(theta), _ptr(xi), _ptr(X), float(tol), int(maxit),
+                                           _PREC[prec], it.ctypes.data_as(C.c_void_p),
+                                           rel.ctypes.data_as(C.c_void_p)), allow=(OK, ENOCONV))
+        return X, st, it, rel
+
+    def spin_correlator(self, xi, X, out=None):
+        self._check_set(xi)
+        self._check_set(X)
+        out = (self._torch.empty((self.Nt, self.L, self.L), dtype=self._torch.complex128, device="cuda")
+               if out is None else out)
+        assert out.is_cuda and out.dtype == self._torch.complex128 and out.numel() == self.Nt * self.L * self.L
+        _check(load().qedhmc_se_spin_correlator(self.h, _ptr(xi), _ptr(X), _ptr(out)))
+        return out
 
 
 class Net:

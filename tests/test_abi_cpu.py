@@ -106,3 +106,22 @@ def test_checkpoint_info_reads_the_documented_format(tmp_path):
         Q.checkpoint_info(path)
     with pytest.raises(Q.QedhmcError):
         Q.checkpoint_info(str(tmp_path / "missing.ckpt"))
+
+
+def test_library_autocorrelation_matches_the_oracle():
+    """qedhmc_autocorrelation is host code of the library (no device): the
+    same rho(k), tau_int and tau_exp as the oracle's analysis of an AR(1)
+    series; a constant series is rejected."""
+    import numpy as np
+    from oracle import production as PR
+    rng = np.random.default_rng(3)
+    x = np.empty(5000)
+    x[0] = rng.standard_normal()
+    for t in range(1, x.size):
+        x[t] = 0.6 * x[t - 1] + rng.standard_normal()
+    rho, ti, te = Q.autocorrelation(x, 40)
+    rho_o, ti_o, te_o = PR.autocorrelation(x, 40)
+    assert np.abs(rho - rho_o).max() < 1e-12
+    assert abs(ti - ti_o) < 1e-12 * ti_o and abs(te - te_o) < 1e-12 * te_o
+    with pytest.raises(Q.QedhmcError):
+        Q.autocorrelation(np.ones(10), 3)

@@ -64,12 +64,16 @@ def test_apply_precond_matches_oracle(L, Nt, prec, tol):
 
 @pytest.mark.parametrize("L,Nt,ty,tc", [(24, 30, 5, 3), (12, 7, 1, 4), (16, 9, 3, 1), (6, 11, 2, 16), (66, 8, 0, 0)])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 5e-6)])
-def test_apply_precond_forced_plans(L, Nt, ty, tc, prec, tol, monkeypatch):
-    """The streamed stencil under plans forced through its tuning variables:
-    ragged last bands (24 = 5 + 5 + 5 + 5 + 4), one-row bands, one-slice
-    runs, runs longer than N_tau, and the default plan at L = 66."""
+@pytest.mark.parametrize("kernel,q", [("roll", 0), ("roll", 1), ("roll", 3), ("stream", 0)])
+def test_apply_precond_forced_plans(L, Nt, ty, tc, prec, tol, kernel, q, monkeypatch):
+    """Both stencil kernels (rolled along tau with 1, 3 or the default 4
+    lanes per site; streamed per tap) under plans forced through their tuning
+    variables: ragged last bands (24 = 5 + 5 + 5 + 5 + 4), one-row bands,
+    one-slice runs, runs longer than N_tau, and the default plan at L = 66."""
     monkeypatch.setenv("QEDHMC_PC_TY", str(ty))
     monkeypatch.setenv("QEDHMC_PC_TC", str(tc))
+    monkeypatch.setenv("QEDHMC_PC_KERNEL", kernel)
+    monkeypatch.setenv("QEDHMC_PC_Q", str(q))
     taps = _oracle_taps()
     v = inputs.gauss_cvec(L, Nt, 41 + L)
     cdt = torch.complex128 if prec == "fp64" else torch.complex64
