@@ -231,6 +231,76 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(NetGeo g, const float* __res
     if (bias) out[E + threadIdx.x] = accb;
 }
 
+// Weight gradient of a 32 -> 32 layer on the matrix cores: per tap k the
+// product dW_k = A_k^T G over the chunk's sites, A_k[n][c] = in[n + tap k][c]
+// and G[n][o] = gout[n][o], as v_mfma_f32_16x16x4f32 (FP32 operands, FP32
+// accumulation: the same arithmetic as the vector kernel, summed in another
+// order).  A wavefront holds 7 taps (k = wave + 4 j) as four 16 x 16 output
+// blocks each; the last wavefront's seventh slot is the bias gradient, the
+// same product with A = 1.  Per step of 4 sites a lane loads one G value per
+// output half (shared by its taps) and one input value per tap and input
+// half, and issues four MFMAs per tap.  Partials per chunk as the vector
+// kernel writes them.
+typedef float wg_f32x4 __attribute__((ext_vector_type(4)));
+static constexpr int kWgTaps = 7;
+
+__global__ __launch_bounds__(256) void k_wgrad_mfma(NetGeo g, const float* __restrict__ in,
+                                                    const float* __restrict__ gout, float* __restrict__ part) {
+    constexpr int EK = 32 * 32, E = 27 * EK;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int n0 = blockIdx.x * kWChunk, n1 = min(n0 + kWChunk, g.N);
+    const int c16 = lane & 15, kq = lane >> 4;
+    wg_f32x4 acc[kWgTaps][2][2];
+#pragma unroll
+    for (int j = 0; j < kWgTaps; j++)
+#pragma unroll
+        for (int cb = 0; cb < 2; cb++)
+#pragma unroll
+            for (int ob = 0; ob < 2; ob++) acc[j][cb][ob] = wg_f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 1
+    for (int n = n0; n < n1; n += 4) {
+        const int nn = n + kq;  // this lane's site of the 4-site step
+        const bool valid = nn < n1;
+        int tau, y, x;
+        site_of(g, valid ? nn : n0, tau, y, x);
+        const float b0 = valid ? gout[(size_t)nn * 32 + c16] : 0.0f;
+        const float b1 = valid ? gout[(size_t)nn * 32 + 16 + c16] : 0.0f;
+#pragma unroll
+        for (int j = 0; j < kWgTaps; j++) {
+            const int k = wave + 4 * j;
+            float a0 = 1.0f, a1 = 1.0f;  // k = 27: the bias slot
+            if (k < 27) {
+                const int dt = k / 9 - 1, dy = (k / 3) % 3 - 1, dx = k % 3 - 1;
+                const int m = wrap(tau + dt, g.Nt) * g.Vs + wrap(y + dy, g.L) * g.L + wrap(x + dx, g.L);
+                a0 = in[(size_t)m * 32 + c16];
+                a1 = in[(size_t)m * 32 + 16 + c16];
+            }
+            acc[j][0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[j][0][0], 0, 0, 0);
+            acc[j][0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[j][0][1], 0, 0, 0);
+            acc[j][1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[j][1][0], 0, 0, 0);
+            acc[j][1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[j][1][1], 0, 0, 0);
+        }
+    }
+    // D fragment: lane holds rows 4 (lane / 16) + r (input channels), column lane % 16 (output channel)
+    float* out = part + (size_t)blockIdx.x * (E + 32);
+#pragma unroll
+    for (int j = 0; j < kWgTaps; j++) {
+        const int k = wave + 4 * j;
+#pragma unroll
+        for (int cb = 0; cb < 2; cb++)
+#pragma unroll
+            for (int ob = 0; ob < 2; ob++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int c = 16 * cb + 4 * kq + r, o = 16 * ob + c16;
+                    if (k < 27)
+                        out[(size_t)k * EK + c * 32 + o] = acc[j][cb][ob][r];
+                    else if (k == 27 && c == 0)
+                        out[E + o] = acc[j][cb][ob][r];
+                }
+    }
+}
+
 // grad[e] = sum over chunks b (in order) of part[b][e]
 __global__ void k_wgrad_reduce(const float* __restrict__ part, int nchunk, int E, float* __restrict__ grad) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -499,6 +569,8 @@ static qedhmc_status fwd_layer_f32(qedhmc_net* n, int l, const void* r, bool r32
                            static_cast<const cplx<float>*>(r), rr, W, b, pre, act);
     else if (l == 0)
         hipLaunchKernelGGL((k_conv_fwd<6, 32, true, true, float, float>), grid, blk, 0, st, g, in, g32, rc, rr, W, b, pre, act);
+    else if (l < kNetLayers - 1 && !net_f32_on_vector_alus())
+        return launch_fwd_mfma32(n, l, in, pre, act);
     else if (l < kNetLayers - 1) {
         hipEvent_t e0, e1;
         if (prof_sample(n->h, QEDHMC_K_NET_FP32, e0, e1))
@@ -556,6 +628,13 @@ qedhmc_status net_infer(qedhmc_net* n, const void* r, bool r32, const double* rr
     return QEDHMC_OK;
 }
 
+// QEDHMC_NET_WGRAD=valu (read per call) keeps the hidden layers' weight
+// gradients on the vector ALUs (tests compare the two kernels)
+static bool wgrad_on_vector_alus() {
+    const char* e = std::getenv("QEDHMC_NET_WGRAD");
+    return e && std::strcmp(e, "valu") == 0;
+}
+
 static qedhmc_status launch_wgrad(qedhmc_net* n, int l, const double* r, const float* gout) {
     const NetGeo& g = n->g;
     const int nchunk = blocks_for(g.N, kWChunk);
@@ -568,9 +647,11 @@ static qedhmc_status launch_wgrad(qedhmc_net* n, int l, const double* r, const f
     if (l == 0)
         hipLaunchKernelGGL((k_conv_wgrad<6, 32, true>), grid, dim3(256), 0, st, g, (const float*)nullptr, g32, rc,
                            n->dscal, gout, n->wpart);
-    else if (l < kNetLayers - 1)
+    else if (l < kNetLayers - 1 && wgrad_on_vector_alus())
         hipLaunchKernelGGL((k_conv_wgrad<32, 32, false>), grid, dim3(256), 0, st, g, n->act[l], g32, rc, n->dscal,
                            gout, n->wpart);
+    else if (l < kNetLayers - 1)
+        hipLaunchKernelGGL(k_wgrad_mfma, dim3(nchunk), dim3(256), 0, st, g, (const float*)n->act[l], gout, n->wpart);
     else
         hipLaunchKernelGGL((k_conv_wgrad<32, 2, false>), grid, dim3(256), 0, st, g, n->act[l], g32, rc, n->dscal,
                            gout, n->wpart);
@@ -581,7 +662,14 @@ static qedhmc_status launch_wgrad(qedhmc_net* n, int l, const double* r, const f
     return QEDHMC_OK;
 }
 
+bool net_f32_on_vector_alus() {
+    const char* e = std::getenv("QEDHMC_NET_F32");
+    return e && std::strcmp(e, "valu") == 0;
+}
+
 static qedhmc_status launch_dgrad(qedhmc_net* n, int l, const float* gout, float* gin) {
+    if (l < kNetLayers - 1 && !net_f32_on_vector_alus())
+        return launch_dgrad_mfma32(n, l, gout, (const float*)n->pre[l - 1], gin);
     const NetGeo& g = n->g;
     hipStream_t st = n->h->stream;
     const float* W = n->params + n->woff[l];
@@ -627,6 +715,7 @@ qedhmc_status qedhmc_net_create(qedhmc_t h, qedhmc_net_t* out) {
     ok = ok && hipMalloc(&n->adam_m, total * sizeof(float)) == hipSuccess;
     ok = ok && hipMalloc(&n->adam_v, total * sizeof(float)) == hipSuccess;
     ok = ok && hipMalloc(&n->wbf, net_bf16_weight_elems() * sizeof(uint16_t)) == hipSuccess;
+    ok = ok && hipMalloc(&n->wf32, net_f32_weight_elems() * sizeof(float)) == hipSuccess;
     for (int k = 0; k < 2; k++) ok = ok && hipMalloc(&n->gbuf[k], N * 32 * sizeof(float)) == hipSuccess;
     ok = ok && hipMalloc(&n->act[kNetLayers], N * 2 * sizeof(float)) == hipSuccess;
     for (int k = 0; k < 2; k++) ok = ok && hipMalloc(&n->actb[k], N * 32 * sizeof(uint16_t)) == hipSuccess;
@@ -660,6 +749,7 @@ qedhmc_status qedhmc_net_destroy(qedhmc_net_t n) {
     (void)hipFree(n->adam_m);
     (void)hipFree(n->adam_v);
     (void)hipFree(n->wbf);
+    (void)hipFree(n->wf32);
     for (int l = 0; l <= kNetLayers; l++) (void)hipFree(n->act[l]);
     for (int l = 0; l < kNetLayers; l++) (void)hipFree(n->pre[l]);
     for (int k = 0; k < 2; k++) {
@@ -703,6 +793,7 @@ qedhmc_status qedhmc_net_set_params(qedhmc_net_t n, const float* host, int64_t c
     QH_HIP(hipMemcpyAsync(n->params, dev.data(), n->nparam * sizeof(float), hipMemcpyHostToDevice, n->h->stream));
     QH_HIP(hipStreamSynchronize(n->h->stream));
     n->wbf_ready = false;
+    n->wf32_ready = false;
     return QEDHMC_OK;
 }
 
@@ -860,6 +951,7 @@ qedhmc_status net_backward_adam(qedhmc_net* n, const double* r, double lr, float
                        (const float*)n->grads, n->adam_m, n->adam_v, (float)lr, (float)b1, (float)b2, 1e-8f, c1, c2);
     QH_HIP(hipGetLastError());
     n->wbf_ready = false;
+    n->wf32_ready = false;
     return QEDHMC_OK;
 }
 

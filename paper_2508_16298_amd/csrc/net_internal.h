@@ -81,6 +81,16 @@ qedhmc_status net_forward_bf16(qedhmc_net* n, const void* r, bool r32, const dou
 qedhmc_status net_infer(qedhmc_net* n, const void* r, bool r32, const double* rr, qedhmc_net_arith a);
 // number of BF16 weight elements the MFMA layers keep (fragment order)
 size_t net_bf16_weight_elems();
+// FP32 hidden layers of training on the matrix cores: the packed weights
+// (forward and transposed, fragment order), the forward with the
+// pre-activations and the data gradient of layer l (1 .. 4)
+size_t net_f32_weight_elems();
+qedhmc_status net_pack_f32(qedhmc_net* n);
+qedhmc_status launch_fwd_mfma32(qedhmc_net* n, int l, const float* in, float* pre, float* act);
+qedhmc_status launch_dgrad_mfma32(qedhmc_net* n, int l, const float* gout, const float* pre_prev, float* gin);
+// QEDHMC_NET_F32=valu (read per call) keeps the FP32 hidden layers on the
+// vector ALUs (tests compare both)
+bool net_f32_on_vector_alus();
 // mixed-precision flexible CG with the network as preconditioner (mfcg.hip):
 // FP32 residual, direction and matvec, FP64 solution, reductions and
 // reliable updates; the handle's FP64 and FP32 e^{i theta} caches built
@@ -102,6 +112,8 @@ struct qedhmc_net {
     int adam_t = 0;
     uint16_t* wbf = nullptr;   // BF16 weights of the hidden layers in MFMA fragment order
     bool wbf_ready = false;
+    float* wf32 = nullptr;     // FP32 weights of the hidden layers in MFMA fragment order (forward, transposed)
+    bool wf32_ready = false;
     // activations: act[l] = input of layer l (l >= 1), [N][32]; pre[l] pre-activation of layer l
     float* act[qh::kNetLayers + 1] = {};
     float* pre[qh::kNetLayers] = {};

@@ -138,4 +138,146 @@ qedhmc_status net_forward_bf16(qedhmc_net* n, const void* r, bool r32, const dou
                             n->params + n->boff[kNetLayers - 1], n->act[kNetLayers]);
 }
 
+// ---------------------------------------------------------------------------
+// FP32 32 -> 32 layers of training (forward with the pre-activations, and the
+// data gradient) on the matrix cores: v_mfma_f32_16x16x4f32 (FP32 operands
+// and accumulation, the same arithmetic as the vector kernels in another
+// summation order).  Per tap the product [16 sites x 32] x [32 x 32] is
+// 2 x 8 MFMAs: K = 32 channels in steps of 4, the lane of k-group q holding
+// channel 8 q + kk of step kk, so each lane loads 8 consecutive channels of
+// its site (two 16-byte loads) and the weights are packed in the matching
+// fragment order: frag[((k 2 + ob) 8 + kk) 64 + lane] = Wt_k[8 (lane / 16) +
+// kk][16 ob + lane % 16], Wt_k = W_k ([in][out], forward) or W_k^T (data
+// gradient, whose tap offsets are mirrored).  The layer's 108 KB of packed
+// weights are staged in LDS per workgroup of 16 wavefronts.
+// ---------------------------------------------------------------------------
+static constexpr int kF32Frag = 27 * 2 * 8 * 64;  // floats per layer
+static constexpr int kTiles32 = 2;
+static constexpr int kSitesPerBlock32 = (kBlock / 64) * 16 * kTiles32;
+
+size_t net_f32_weight_elems() { return (size_t)2 * kHidden * kF32Frag; }
+
+__global__ void k_pack_f32(const float* __restrict__ params, size_t w0, size_t stride_layer,
+                           float* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 2 * kHidden * kF32Frag) return;
+    const int lane = i & 63, f = (i >> 6) % (kF32Frag / 64), hl = ((i >> 6) / (kF32Frag / 64)) % kHidden;
+    const int transpose = (i >> 6) / (kF32Frag / 64) / kHidden;
+    const int kk = f % 8, ob = (f / 8) % 2, k = f / 16;
+    const int row = 8 * (lane >> 4) + kk, col = 16 * ob + (lane & 15);
+    const float* W = params + w0 + (size_t)hl * stride_layer;
+    out[i] = transpose ? W[((size_t)k * 32 + col) * 32 + row] : W[((size_t)k * 32 + row) * 32 + col];
+}
+
+// DGRAD = false: pre = conv(in) + b, out = SiLU(pre) (pre nullable);
+// DGRAD = true: out = conv^T(in = the output gradient) * SiLU'(pre_prev).
+template <bool DGRAD>
+__global__ __launch_bounds__(kBlock) void k_conv_mfma32(NetGeo g, const float* __restrict__ in,
+                                                     const float* __restrict__ wfrag,
+                                                     const float* __restrict__ bias,
+                                                     const float* __restrict__ pre_prev, float* __restrict__ pre,
+                                                     float* __restrict__ out) {
+    __shared__ float sW[kF32Frag];
+    for (int i = threadIdx.x; i < kF32Frag; i += blockDim.x) sW[i] = wfrag[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int site0 = blockIdx.x * kSitesPerBlock32 + wave * 16 * kTiles32;
+    if (site0 >= g.N) return;
+    const int row = lane & 15, kq = lane >> 4;
+    int st[kTiles32], sy[kTiles32], sx[kTiles32];
+#pragma unroll
+    for (int t = 0; t < kTiles32; t++) {
+        const int m = min(site0 + 16 * t + row, g.N - 1);
+        site_of(g, m, st[t], sy[t], sx[t]);
+    }
+    f32x4 acc[kTiles32][2];
+#pragma unroll
+    for (int t = 0; t < kTiles32; t++)
+#pragma unroll
+        for (int h = 0; h < 2; h++) acc[t][h] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int sgn = DGRAD ? -1 : 1;
+#pragma unroll 1
+    for (int k = 0; k < 27; k++) {
+        const int dt = sgn * (k / 9 - 1), dy = sgn * ((k / 3) % 3 - 1), dx = sgn * (k % 3 - 1);
+        f32x4 a[kTiles32][2];
+#pragma unroll
+        for (int t = 0; t < kTiles32; t++) {
+            const int m = wrap(st[t] + dt, g.Nt) * g.Vs + wrap(sy[t] + dy, g.L) * g.L + wrap(sx[t] + dx, g.L);
+            const f32x4* src = reinterpret_cast<const f32x4*>(in + (size_t)m * 32 + 8 * kq);
+            a[t][0] = src[0];
+            a[t][1] = src[1];
+        }
+#pragma unroll
+        for (int ob = 0; ob < 2; ob++)
+#pragma unroll
+            for (int kk = 0; kk < 8; kk++) {
+                const float b = sW[((k * 2 + ob) * 8 + kk) * 64 + lane];
+#pragma unroll
+                for (int t = 0; t < kTiles32; t++)
+                    acc[t][ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][kk >> 2][kk & 3], b, acc[t][ob], 0, 0, 0);
+            }
+    }
+    // D fragment: lane holds sites 4 (lane / 16) + i, channel 16 ob + lane % 16
+#pragma unroll
+    for (int t = 0; t < kTiles32; t++)
+#pragma unroll
+        for (int ob = 0; ob < 2; ob++) {
+            const int c = 16 * ob + row;
+            const float bc = DGRAD ? 0.0f : bias[c];
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int site = site0 + 16 * t + 4 * kq + i;
+                if (site >= g.N) continue;
+                const size_t e = (size_t)site * 32 + c;
+                if constexpr (DGRAD) {
+                    out[e] = acc[t][ob][i] * dsilu_f(pre_prev[e]);
+                } else {
+                    const float v = acc[t][ob][i] + bc;
+                    if (pre) pre[e] = v;
+                    out[e] = silu_f(v);
+                }
+            }
+        }
+}
+
+qedhmc_status net_pack_f32(qedhmc_net* n) {
+    if (n->wf32_ready) return QEDHMC_OK;
+    const size_t stride = n->woff[2] - n->woff[1];
+    const int total = 2 * kHidden * kF32Frag;
+    hipLaunchKernelGGL(k_pack_f32, dim3((total + 255) / 256), dim3(256), 0, n->h->stream, (const float*)n->params,
+                       n->woff[1], stride, n->wf32);
+    QH_HIP(hipGetLastError());
+    n->wf32_ready = true;
+    return QEDHMC_OK;
+}
+
+// hidden layer l (1 .. 4) forward in FP32 on the matrix cores
+qedhmc_status launch_fwd_mfma32(qedhmc_net* n, int l, const float* in, float* pre, float* act) {
+    QH_TRY(net_pack_f32(n));
+    const NetGeo& g = n->g;
+    const int blocks = (g.N + kSitesPerBlock32 - 1) / kSitesPerBlock32;
+    const float* wf = n->wf32 + (size_t)(l - 1) * kF32Frag;
+    hipEvent_t e0, e1;
+    if (prof_sample(n->h, QEDHMC_K_NET_FP32, e0, e1))
+        hipExtLaunchKernelGGL(k_conv_mfma32<false>, dim3(blocks), dim3(kBlock), 0, n->h->stream, e0, e1, 0, g, in, wf,
+                              (const float*)(n->params + n->boff[l]), (const float*)nullptr, pre, act);
+    else
+        hipLaunchKernelGGL(k_conv_mfma32<false>, dim3(blocks), dim3(kBlock), 0, n->h->stream, g, in, wf,
+                           (const float*)(n->params + n->boff[l]), (const float*)nullptr, pre, act);
+    QH_HIP(hipGetLastError());
+    return QEDHMC_OK;
+}
+
+// data gradient through hidden layer l (1 .. 4): gin = W_l^T * gout, times SiLU'(pre of layer l - 1)
+qedhmc_status launch_dgrad_mfma32(qedhmc_net* n, int l, const float* gout, const float* pre_prev, float* gin) {
+    QH_TRY(net_pack_f32(n));
+    const NetGeo& g = n->g;
+    const int blocks = (g.N + kSitesPerBlock32 - 1) / kSitesPerBlock32;
+    const float* wf = n->wf32 + (size_t)(kHidden + l - 1) * kF32Frag;
+    hipLaunchKernelGGL(k_conv_mfma32<true>, dim3(blocks), dim3(kBlock), 0, n->h->stream, g, gout, wf,
+                       (const float*)nullptr, pre_prev, (float*)nullptr, gin);
+    QH_HIP(hipGetLastError());
+    return QEDHMC_OK;
+}
+
 }  // namespace qh

@@ -76,7 +76,14 @@ def test_net_forward_zero_residual():
 
 
 @pytest.mark.parametrize("L,Nt", [(4, 6), (6, 10), (12, 40)])
-def test_net_train_step_gradients_and_adam(L, Nt):
+@pytest.mark.parametrize("kernels", ["mfma", "valu"])
+def test_net_train_step_gradients_and_adam(L, Nt, kernels, monkeypatch):
+    """Loss, every layer's gradient and Adam's first step against the oracle,
+    with the hidden layers' FP32 forward, data and weight gradients on the
+    matrix cores or, forced, on the vector ALUs; (12, 40) spans six
+    weight-gradient chunks (the last one ragged) and twelve MFMA workgroups."""
+    monkeypatch.setenv("QEDHMC_NET_WGRAD", kernels)
+    monkeypatch.setenv("QEDHMC_NET_F32", kernels)
     th, r = _case(L, Nt, 400 + L)
     e = inputs.gauss_cvec(L, Nt, 401 + L)
     params = _params(9)
@@ -99,7 +106,7 @@ def test_net_train_step_gradients_and_adam(L, Nt):
     assert _rel(newp, Q.Net.pack(ref)) <= 1e-6
 
 
-@pytest.mark.parametrize("L,Nt", [(4, 6), (6, 10), (12, 40)])
+@pytest.mark.parametrize("L,Nt", [(4, 6), (6, 10), (12, 40), (16, 24)])
 def test_net_train_step_residual_gradients_and_adam(L, Nt):
     """The residual-form step (two FP64 M^dag M inside) against the oracle's
     loss and gradients; Adam's first step from the GPU's gradient."""
