@@ -80,6 +80,8 @@ def parse():
                     help="only the standalone M^dag M at the large size with this L (for profiler runs)")
     ap.add_argument("--precond-only", type=int, default=0, metavar="L",
                     help="only the paper preconditioner z = G^dag G r at L, Nt = 10 L, FP32 (for profiler runs)")
+    ap.add_argument("--train-only", type=int, default=0, metavar="L",
+                    help="only 3 + 20 residual-form training steps of the network at L, Nt = 10 L (profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="counter calibration: 5 device copies of 256 MiB (torch copy kernel)")
     return ap.parse_args()
@@ -127,6 +129,30 @@ def matvec_large(n_calls=100, only_L=0):
         del theta
         torch.cuda.empty_cache()
     return rows
+
+
+def run_train_only(L, n_steps=20):
+    """Residual-form training steps of the learned preconditioner at L,
+    Nt = 10 L (pi flux + noise angles, a Gaussian residual, the initial
+    weights): 3 untimed, then n_steps timed between a host clock pair."""
+    import torch
+    from paper_2508_16298_amd import inputs
+    from paper_2508_16298_amd import qedhmc as Q
+    Nt = 10 * L
+    th = torch.from_numpy(inputs.noisy_pi_flux_theta(L, Nt, 0.3, 5000)).cuda()
+    r = torch.from_numpy(inputs.gauss_cvec(L, Nt, 5001)).cuda()
+    with Q.Lattice(L, Nt) as lat, Q.Net(lat) as net:
+        net.set_params(inputs.net_init_weights(3))
+        for _ in range(3):
+            net.train_step_residual(th, r, lr=1e-3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n_steps):
+            loss, _ = net.train_step_residual(th, r, lr=1e-3)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / n_steps * 1e3
+    print(json.dumps({"train_only": {"L": L, "Nt": Nt, "steps": n_steps, "ms_per_step": ms, "loss": loss}}),
+          flush=True)
 
 
 def run_precond_only(L, n_calls=6):
@@ -654,6 +680,8 @@ def main():
         return run_solve_only(a)
     if a.precond_only:
         return run_precond_only(a.precond_only)
+    if a.train_only:
+        return run_train_only(a.train_only)
     if a.matvec_only:
         print(json.dumps({"matvec_large": matvec_large(only_L=a.matvec_only)}), flush=True)
         return
