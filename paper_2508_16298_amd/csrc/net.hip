@@ -231,74 +231,116 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(NetGeo g, const float* __res
     if (bias) out[E + threadIdx.x] = accb;
 }
 
-// Weight gradient of a 32 -> 32 layer on the matrix cores: per tap k the
-// product dW_k = A_k^T G over the chunk's sites, A_k[n][c] = in[n + tap k][c]
-// and G[n][o] = gout[n][o], as v_mfma_f32_16x16x4f32 (FP32 operands, FP32
-// accumulation: the same arithmetic as the vector kernel, summed in another
-// order).  A wavefront holds 7 taps (k = wave + 4 j) as four 16 x 16 output
-// blocks each; the last wavefront's seventh slot is the bias gradient, the
-// same product with A = 1.  Per step of 4 sites a lane loads one G value per
-// output half (shared by its taps) and one input value per tap and input
-// half, and issues four MFMAs per tap.  Partials per chunk as the vector
-// kernel writes them.
+// Weight gradients on the matrix cores: per tap k the product dW_k = A_k^T G
+// over a chunk of sites, A_k[n][c] = in[n + tap k][c] and G[n][o] =
+// gout[n][o], as v_mfma_f32_16x16x4f32 (FP32 operands, FP32 accumulation:
+// the same arithmetic as the vector kernel, summed in another order), the
+// channels in blocks of 16 (zero-padded: the first layer's 6 inputs, the last
+// layer's 2 outputs).  A wavefront holds 7 taps (k = wave + 4 j) as
+// CINB x COUTB output blocks each; the last wavefront's seventh slot is the
+// bias gradient, the same product with A = 1.  Per step of 4 sites a lane
+// loads one G value per output block (shared by its taps) and one input value
+// per tap and input block.  The first layer reads the feature map from feat
+// ([N][8], the residual channels 4, 5 sign-flipped where the tap wraps in
+// tau).  Partials per chunk as the vector kernel writes them.
 typedef float wg_f32x4 __attribute__((ext_vector_type(4)));
 static constexpr int kWgTaps = 7;
 
-__global__ __launch_bounds__(256) void k_wgrad_mfma(NetGeo g, const float* __restrict__ in,
+template <int CIN, int COUT, bool FIRST>
+__global__ __launch_bounds__(256) void k_wgrad_mfma(NetGeo g, int chunk, const float* __restrict__ in,
                                                     const float* __restrict__ gout, float* __restrict__ part) {
-    constexpr int EK = 32 * 32, E = 27 * EK;
+    constexpr int CINB = (CIN + 15) / 16, COUTB = (COUT + 15) / 16;
+    constexpr int EK = CIN * COUT, E = 27 * EK;
+    constexpr int IS = FIRST ? 8 : CIN;  // row stride of the input
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int n0 = blockIdx.x * kWChunk, n1 = min(n0 + kWChunk, g.N);
+    const int n0 = blockIdx.x * chunk, n1 = min(n0 + chunk, g.N);
     const int c16 = lane & 15, kq = lane >> 4;
-    wg_f32x4 acc[kWgTaps][2][2];
+    wg_f32x4 acc[kWgTaps][CINB][COUTB];
 #pragma unroll
     for (int j = 0; j < kWgTaps; j++)
 #pragma unroll
-        for (int cb = 0; cb < 2; cb++)
+        for (int cb = 0; cb < CINB; cb++)
 #pragma unroll
-            for (int ob = 0; ob < 2; ob++) acc[j][cb][ob] = wg_f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            for (int ob = 0; ob < COUTB; ob++) acc[j][cb][ob] = wg_f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll 1
     for (int n = n0; n < n1; n += 4) {
         const int nn = n + kq;  // this lane's site of the 4-site step
         const bool valid = nn < n1;
         int tau, y, x;
         site_of(g, valid ? nn : n0, tau, y, x);
-        const float b0 = valid ? gout[(size_t)nn * 32 + c16] : 0.0f;
-        const float b1 = valid ? gout[(size_t)nn * 32 + 16 + c16] : 0.0f;
+        float b[COUTB];
+#pragma unroll
+        for (int ob = 0; ob < COUTB; ob++) {
+            const int o = 16 * ob + c16;
+            b[ob] = (valid && o < COUT) ? gout[(size_t)nn * COUT + o] : 0.0f;
+        }
 #pragma unroll
         for (int j = 0; j < kWgTaps; j++) {
             const int k = wave + 4 * j;
-            float a0 = 1.0f, a1 = 1.0f;  // k = 27: the bias slot
+            float a[CINB];
+#pragma unroll
+            for (int cb = 0; cb < CINB; cb++) a[cb] = 1.0f;  // k = 27: the bias slot
             if (k < 27) {
                 const int dt = k / 9 - 1, dy = (k / 3) % 3 - 1, dx = k % 3 - 1;
-                const int m = wrap(tau + dt, g.Nt) * g.Vs + wrap(y + dy, g.L) * g.L + wrap(x + dx, g.L);
-                a0 = in[(size_t)m * 32 + c16];
-                a1 = in[(size_t)m * 32 + 16 + c16];
+                float sg = 1.0f;
+                const int tt = wrap_tau(tau + dt, g.Nt, sg);
+                const int m = tt * g.Vs + wrap(y + dy, g.L) * g.L + wrap(x + dx, g.L);
+#pragma unroll
+                for (int cb = 0; cb < CINB; cb++) {
+                    const int c = 16 * cb + c16;
+                    float v = c < CIN ? in[(size_t)m * IS + c] : 0.0f;
+                    if (FIRST && c >= 4) v *= sg;
+                    a[cb] = v;
+                }
             }
-            acc[j][0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[j][0][0], 0, 0, 0);
-            acc[j][0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[j][0][1], 0, 0, 0);
-            acc[j][1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[j][1][0], 0, 0, 0);
-            acc[j][1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[j][1][1], 0, 0, 0);
+#pragma unroll
+            for (int cb = 0; cb < CINB; cb++)
+#pragma unroll
+                for (int ob = 0; ob < COUTB; ob++)
+                    acc[j][cb][ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[cb], b[ob], acc[j][cb][ob], 0, 0, 0);
         }
     }
     // D fragment: lane holds rows 4 (lane / 16) + r (input channels), column lane % 16 (output channel)
-    float* out = part + (size_t)blockIdx.x * (E + 32);
+    float* out = part + (size_t)blockIdx.x * (E + COUT);
 #pragma unroll
     for (int j = 0; j < kWgTaps; j++) {
         const int k = wave + 4 * j;
 #pragma unroll
-        for (int cb = 0; cb < 2; cb++)
+        for (int cb = 0; cb < CINB; cb++)
 #pragma unroll
-            for (int ob = 0; ob < 2; ob++)
+            for (int ob = 0; ob < COUTB; ob++)
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
                     const int c = 16 * cb + 4 * kq + r, o = 16 * ob + c16;
-                    if (k < 27)
-                        out[(size_t)k * EK + c * 32 + o] = acc[j][cb][ob][r];
+                    if (o >= COUT) continue;
+                    if (k < 27 && c < CIN)
+                        out[(size_t)k * EK + c * COUT + o] = acc[j][cb][ob][r];
                     else if (k == 27 && c == 0)
                         out[E + o] = acc[j][cb][ob][r];
                 }
     }
+}
+
+// the first layer's feature map [N][8] (channels 6, 7 zero), unsigned
+template <typename TR>
+__global__ void k_features(NetGeo g, const cplx<float>* __restrict__ g32, const cplx<TR>* __restrict__ r,
+                           const double* __restrict__ rr, float* __restrict__ feat) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= g.N) return;
+    float f[6];
+    features(g, g32, r, m, 1.0f, inv_scale(rr, g.N), f);
+#pragma unroll
+    for (int c = 0; c < 6; c++) feat[(size_t)m * 8 + c] = f[c];
+    feat[(size_t)m * 8 + 6] = 0.0f;
+    feat[(size_t)m * 8 + 7] = 0.0f;
+}
+
+// sites per weight-gradient chunk on the matrix cores: about 2048 chunks,
+// 256 .. 4096 sites each (a multiple of 4)
+int wgrad_mfma_chunk(int N) {
+    int c = (N + 2047) / 2048;
+    c = ((c + 255) / 256) * 256;
+    return c < 256 ? 256 : (c > 4096 ? 4096 : c);
 }
 
 // grad[e] = sum over chunks b (in order) of part[b][e]
@@ -539,8 +581,10 @@ qedhmc_status net_alloc_train(qedhmc_net* n) {
     ok = ok && hipMalloc(&n->pre[kNetLayers - 1], N * 2 * sizeof(float)) == hipSuccess;
     // act[kNetLayers] (the output channels) and gbuf exist from creation
     for (int l = 1; l < kNetLayers; l++) ok = ok && hipMalloc(&n->act[l], N * 32 * sizeof(float)) == hipSuccess;
-    const size_t nchunk = (N + kWChunk - 1) / kWChunk;
+    const size_t nchunk = std::max((N + kWChunk - 1) / kWChunk,
+                                   (N + wgrad_mfma_chunk((int)N) - 1) / (size_t)wgrad_mfma_chunk((int)N));
     ok = ok && hipMalloc(&n->wpart, nchunk * (27 * 32 * 32 + 32) * sizeof(float)) == hipSuccess;
+    ok = ok && hipMalloc(&n->feat, N * 8 * sizeof(float)) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         return net_fail(n, "net: training buffers: device allocation failed", QEDHMC_ENOMEM);
@@ -637,24 +681,39 @@ static bool wgrad_on_vector_alus() {
 
 static qedhmc_status launch_wgrad(qedhmc_net* n, int l, const double* r, const float* gout) {
     const NetGeo& g = n->g;
-    const int nchunk = blocks_for(g.N, kWChunk);
+    int nchunk = blocks_for(g.N, kWChunk);
     hipStream_t st = n->h->stream;
     const cplx<float>* g32 = n->h->gauge32;
     const cplx<double>* rc = reinterpret_cast<const cplx<double>*>(r);
     const int cin = kNetCh[l], cout = kNetCh[l + 1];
     const int E = 27 * cin * cout + cout;
     const dim3 grid(nchunk, 27);
-    if (l == 0)
-        hipLaunchKernelGGL((k_conv_wgrad<6, 32, true>), grid, dim3(256), 0, st, g, (const float*)nullptr, g32, rc,
-                           n->dscal, gout, n->wpart);
-    else if (l < kNetLayers - 1 && wgrad_on_vector_alus())
-        hipLaunchKernelGGL((k_conv_wgrad<32, 32, false>), grid, dim3(256), 0, st, g, n->act[l], g32, rc, n->dscal,
-                           gout, n->wpart);
-    else if (l < kNetLayers - 1)
-        hipLaunchKernelGGL(k_wgrad_mfma, dim3(nchunk), dim3(256), 0, st, g, (const float*)n->act[l], gout, n->wpart);
-    else
-        hipLaunchKernelGGL((k_conv_wgrad<32, 2, false>), grid, dim3(256), 0, st, g, n->act[l], g32, rc, n->dscal,
-                           gout, n->wpart);
+    if (wgrad_on_vector_alus()) {
+        if (l == 0)
+            hipLaunchKernelGGL((k_conv_wgrad<6, 32, true>), grid, dim3(256), 0, st, g, (const float*)nullptr, g32,
+                               rc, n->dscal, gout, n->wpart);
+        else if (l < kNetLayers - 1)
+            hipLaunchKernelGGL((k_conv_wgrad<32, 32, false>), grid, dim3(256), 0, st, g, n->act[l], g32, rc,
+                               n->dscal, gout, n->wpart);
+        else
+            hipLaunchKernelGGL((k_conv_wgrad<32, 2, false>), grid, dim3(256), 0, st, g, n->act[l], g32, rc,
+                               n->dscal, gout, n->wpart);
+    } else {
+        const int chunk = wgrad_mfma_chunk(g.N);
+        nchunk = blocks_for(g.N, chunk);
+        if (l == 0) {
+            hipLaunchKernelGGL(k_features<double>, dim3(blocks_for(g.N, 256)), dim3(256), 0, st, g, g32, rc,
+                               (const double*)n->dscal, n->feat);
+            hipLaunchKernelGGL((k_wgrad_mfma<6, 32, true>), dim3(nchunk), dim3(256), 0, st, g, chunk,
+                               (const float*)n->feat, gout, n->wpart);
+        } else if (l < kNetLayers - 1) {
+            hipLaunchKernelGGL((k_wgrad_mfma<32, 32, false>), dim3(nchunk), dim3(256), 0, st, g, chunk,
+                               (const float*)n->act[l], gout, n->wpart);
+        } else {
+            hipLaunchKernelGGL((k_wgrad_mfma<32, 2, false>), dim3(nchunk), dim3(256), 0, st, g, chunk,
+                               (const float*)n->act[l], gout, n->wpart);
+        }
+    }
     // W and b are contiguous in the parameter vector (b follows W)
     hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for(E, 256)), dim3(256), 0, st, (const float*)n->wpart, nchunk, E,
                        n->grads + n->woff[l]);
@@ -757,6 +816,7 @@ qedhmc_status qedhmc_net_destroy(qedhmc_net_t n) {
         (void)hipFree(n->actb[k]);
     }
     (void)hipFree(n->wpart);
+    (void)hipFree(n->feat);
     (void)hipFree(n->dscal);
     (void)hipFree(n->dpart);
     if (n->hpin) (void)hipHostFree(n->hpin);

@@ -451,6 +451,9 @@ struct PcRollGeo {
 };
 
 static constexpr int kRollElems = 4;  // window elements per thread at most
+// per application of G^dag G, FP32: L = 24 per-tap 53 us / rolled 63 us;
+// L = 48 242 / 200 us; L = 66 603 / 450 us
+static constexpr int kRollFromL = 40;
 
 template <typename R>
 __global__ __launch_bounds__(1024) void k_pc_roll(PcRollGeo g, const RTap<R>* __restrict__ taps,
@@ -524,7 +527,10 @@ __global__ __launch_bounds__(1024) void k_pc_roll(PcRollGeo g, const RTap<R>* __
             for (int k = q; k < (q < g.Q ? ntap : 0); k += g.Q) {
                 const RTap<R> t = tp[k];
                 const cplx<R> v = ws[t.plane * plane + t.off];
-                // input slice s0 + j feeds output tau0 + j - kk through the tap of tau offset amin + kk
+                // input slice s0 + j feeds output tau0 + j - kk through the
+                // tap of tau offset amin + kk (products for outputs outside
+                // the run land in slots that are cleared unwritten: skipping
+                // them measured slower)
 #pragma unroll
                 for (int kk = 0; kk < kRollNS; kk++) {
                     cplx<R>& A = acc[(u - kk + kRollNS) % kRollNS];
@@ -566,10 +572,10 @@ static const RTap<R>* rtaps_for(qedhmc_ctx* h) {
 }
 
 // Plan: a band of TY rows whose TY * L/2 output sites fill whole wavefronts
-// best (at most 256 lanes per copy), Q = 4 copies, and runs of Tc slices
-// aiming at about 2048 wavefronts per pass (at least 6 slices: each run
-// reads kRollNS - 1 slices more than it writes).  QEDHMC_PC_TY, QEDHMC_PC_TC
-// and QEDHMC_PC_Q (read per call) override the plan.
+// best (at most 256 lanes per copy), Q = 2 copies for 256-lane bands and 4
+// below, runs of 12 slices (each run reads kRollNS - 1 slices more than it
+// writes).  QEDHMC_PC_TY, QEDHMC_PC_TC and QEDHMC_PC_Q (read per call)
+// override the plan.
 template <typename R>
 static qedhmc_status launch_pc_roll(qedhmc_ctx* h, int ps, const cplx<R>* in, cplx<R>* out, const double* stop) {
     const PcPass& pp = h->pc_pass[ps];
@@ -606,7 +612,7 @@ static qedhmc_status launch_pc_roll(qedhmc_ctx* h, int ps, const cplx<R>* in, cp
     g.TY = (lt.L + g.nband - 1) / g.nband;
     g.rows = g.TY + pp.bmax - pp.bmin;
     g.S = pad64(g.TY * hx);
-    g.Q = 4;
+    g.Q = g.S >= 256 ? 2 : 4;  // measured best at L = 48 (4) and 66 (2)
     if (eq && std::atoi(eq) > 0) g.Q = std::atoi(eq);
     while (g.Q > 1 && g.Q * g.S > 1024) g.Q--;
     if (g.S > 1024) {
@@ -621,9 +627,7 @@ static qedhmc_status launch_pc_roll(qedhmc_ctx* h, int ps, const cplx<R>* in, cp
         set_error("paper preconditioner: the stencil window exceeds the rolling kernel's workgroup");
         return QEDHMC_EUNSUPPORTED;
     }
-    const int waves_per_run = 2 * g.nband * g.Q * g.S / 64;
-    int nrun = std::max(1, (2048 + waves_per_run - 1) / waves_per_run);
-    g.Tc = std::max(6, (lt.Nt + nrun - 1) / nrun);
+    g.Tc = 12;  // a sweep of 6, 12, 24 at L = 48 and 66 put 12 first or within 1 %
     if (etc && std::atoi(etc) > 0) g.Tc = std::atoi(etc);
     g.Tc = std::min(g.Tc, lt.Nt);
     g.nrun = (lt.Nt + g.Tc - 1) / g.Tc;
@@ -658,11 +662,12 @@ static const PTap<R>* taps_for(qedhmc_ctx* h) {
 template <typename R>
 static qedhmc_status launch_pc(qedhmc_ctx* h, int ps, const cplx<R>* in, cplx<R>* out, const double* stop) {
     const PcPass& pp = h->pc_pass[ps];
-    // the tau-rolling kernel where the pass was grouped for it;
-    // QEDHMC_PC_KERNEL=stream (read per call) keeps the per-tap kernel
+    // the tau-rolling kernel from L = kRollFromL on (below it the per-tap
+    // kernel measured as fast or faster: too few rolled work items to fill
+    // the device); QEDHMC_PC_KERNEL=roll|stream (read per call) forces one
     const char* ek = std::getenv("QEDHMC_PC_KERNEL");
-    if (pp.rcount[0] > 0 && pp.rcount[1] > 0 && !(ek && std::strcmp(ek, "stream") == 0))
-        return launch_pc_roll<R>(h, ps, in, out, stop);
+    const bool roll = ek ? std::strcmp(ek, "roll") == 0 : h->lat.L >= kRollFromL;
+    if (pp.rcount[0] > 0 && pp.rcount[1] > 0 && roll) return launch_pc_roll<R>(h, ps, in, out, stop);
     const Lat& lt = h->lat;
     PcGeo g{};
     g.L = lt.L;
