@@ -10,9 +10,11 @@
 //   z = N(r) (or the fallback);  beta = -<s, z> / <p, s>;  p = z + beta p,
 // with <a, b> = sum conj(a) b.  The residual judges the network: it keeps the
 // solve while |r| at least halves over every 10 iterations and its
-// directions descend (<p, O p> > 0); otherwise the solve restarts from the
-// current x and r with the fallback (the paper's preconditioner with FP32
-// stencil passes, or none).
+// directions descend (<p, O p> > 0); otherwise the fallback finishes the
+// solve from the current x: the residual system O d = eta - O x (residual in
+// FP64) goes to the library's device-driven mixed CG (with the paper's
+// preconditioner, or none) at the tolerance that makes x + d meet the
+// original one, and x += d.
 //
 // alpha and beta are formed on the device from the partial sums (one small
 // kernel each), so the host reads back only <p, O p> and |r|^2 once per
@@ -163,6 +165,26 @@ __global__ __launch_bounds__(kMfThreads) void k_mf_replace(int N, const cplx<dou
     part_out(acc, red, part, 0);
 }
 
+// r64 = eta - O x in FP64; partials of |r64|^2
+__global__ __launch_bounds__(kMfThreads) void k_mf_resid64(int N, const cplx<double>* __restrict__ eta,
+                                                           const cplx<double>* __restrict__ Ox,
+                                                           cplx<double>* __restrict__ r, double* __restrict__ part) {
+    __shared__ double red[16];
+    double acc = 0.0;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < N; n += gridDim.x * blockDim.x) {
+        const double re = eta[n].re - Ox[n].re, im = eta[n].im - Ox[n].im;
+        r[n] = mk<double>(re, im);
+        acc += re * re + im * im;
+    }
+    part_out(acc, red, part, 0);
+}
+
+// x += d
+__global__ void k_mf_add64(int N, cplx<double>* __restrict__ x, const cplx<double>* __restrict__ d) {
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < N; n += gridDim.x * blockDim.x)
+        x[n] = mk<double>(x[n].re + d[n].re, x[n].im + d[n].im);
+}
+
 // the network's output in FP32: z = s (o_0 + i o_1), s = |r| / sqrt(N)
 __global__ void k_net_out32(int N, const float* __restrict__ o, const double* __restrict__ rr,
                             cplx<float>* __restrict__ z) {
@@ -197,6 +219,7 @@ qedhmc_status mfcg_solve_impl(qedhmc_net* n, const double* rhs, double* x, doubl
     *true_rel = 0.0;
     *n_reliable = 0;
     *switched_at = -1;
+    double true_rr_out = 0.0;  // the fallback's finish: true |r|^2 of its result
     if (fallback == QEDHMC_PC_PAPER) QH_TRY(ensure_paper_precond(h));
 
     auto read = [&](int a, int b) -> qedhmc_status {  // host copies of sc[a], sc[b]
@@ -234,6 +257,47 @@ qedhmc_status mfcg_solve_impl(qedhmc_net* n, const double* rhs, double* x, doubl
         return QEDHMC_OK;
     };
 
+    // the fallback's finish: O d = eta - O x by the device-driven mixed (P)CG,
+    // x += d; true_rr from the FP64 residual of the sum
+    auto finish = [&](double nb2_, bool& conv) -> qedhmc_status {
+        cplx<double>* r64 = n->fp;  // FP64-sized buffers of the network's solver, free now
+        cplx<double>* d = n->fz;
+        auto resid = [&](double& rr) -> qedhmc_status {
+            QH_TRY(launch_mdagm(h, QEDHMC_FP64, x, h->ws[3], nullptr));
+            hipLaunchKernelGGL(k_mf_resid64, grid, blk, 0, st, N, eta, (const cplx<double>*)h->ws[3], r64, part);
+            hipLaunchKernelGGL(k_mf_coef, dim3(1), dim3(64), 0, st, (const double*)part, nb, 0, sc);
+            QH_HIP(hipGetLastError());
+            QH_TRY(read(M_RR, M_RR));
+            rr = n->hpin[0];
+            return QEDHMC_OK;
+        };
+        double rr = 0.0;
+        QH_TRY(resid(rr));
+        conv = rr <= tol * tol * nb2_;
+        if (conv || !std::isfinite(rr)) {
+            true_rr_out = rr;
+            return QEDHMC_OK;
+        }
+        const double tol_d = tol * std::sqrt(nb2_ / rr);
+        int it_d = 0, nrel_d = 0;
+        double rel_d = 0.0;
+        const int budget = std::max(1, maxit - *iters);
+        const qedhmc_status sd = fallback == QEDHMC_PC_PAPER
+                                     ? pcg_solve_impl(h, (const double*)r64, (double*)d, tol_d, budget, QEDHMC_FP32,
+                                                      &it_d, &rel_d, &nrel_d)
+                                     : cg_solve_impl(h, (const double*)r64, (double*)d, tol_d, budget, QEDHMC_FP32,
+                                                     &it_d, &rel_d, &nrel_d);
+        if (sd != QEDHMC_OK && sd != QEDHMC_ENOCONV) return sd;
+        *iters += it_d;
+        *n_reliable += nrel_d;
+        hipLaunchKernelGGL(k_mf_add64, grid, blk, 0, st, N, X, (const cplx<double>*)d);
+        QH_HIP(hipGetLastError());
+        QH_TRY(resid(rr));
+        true_rr_out = rr;
+        conv = rr <= tol * tol * nb2_;
+        return QEDHMC_OK;
+    };
+
     hipLaunchKernelGGL(k_mf_start, grid, blk, 0, st, N, eta, X, r, part);
     hipLaunchKernelGGL(k_mf_coef, dim3(1), dim3(64), 0, st, (const double*)part, nb, 0, sc);
     QH_HIP(hipGetLastError());
@@ -250,7 +314,7 @@ qedhmc_status mfcg_solve_impl(qedhmc_net* n, const double* rhs, double* x, doubl
     double rr_rel = nb2;      // |r|^2 at the last reliable update
     double best_true = nb2;   // smallest true |r|^2 so far
     double true_rr = nb2;
-    bool converged = false, broke = false;
+    bool converged = false, broke = false, handed_over = false;
     const char* why = "maximum iteration count reached";
     QH_TRY(restart());
     while (true) {
@@ -274,9 +338,8 @@ qedhmc_status mfcg_solve_impl(qedhmc_net* n, const double* rhs, double* x, doubl
             if (net_on) {
                 net_on = false;
                 *switched_at = it;
-                hist.clear();
-                QH_TRY(restart());
-                continue;
+                handed_over = true;
+                break;
             }
             // the fallback lost descent in FP32: restart from the FP64 residual
             double t2;
@@ -329,9 +392,8 @@ qedhmc_status mfcg_solve_impl(qedhmc_net* n, const double* rhs, double* x, doubl
         if (judge_out) {
             net_on = false;
             *switched_at = it;
-            hist.clear();
-            QH_TRY(restart());
-            continue;
+            handed_over = true;
+            break;
         }
         QH_TRY(precond());
         hipLaunchKernelGGL(k_mf_dot_sz, grid, blk, 0, st, N, (const cplx<float>*)s, (const cplx<float>*)z, part);
@@ -340,6 +402,12 @@ qedhmc_status mfcg_solve_impl(qedhmc_net* n, const double* rhs, double* x, doubl
         QH_HIP(hipGetLastError());
     }
     *iters = it;
+    if (handed_over) {
+        QH_TRY(finish(nb2, converged));
+        true_rr = true_rr_out;
+        broke = !converged;
+        why = "the fallback did not reach the tolerance";
+    }
     *true_rel = std::sqrt(true_rr / nb2);
     if (converged) return QEDHMC_OK;
     set_error(std::string("mixed flexible CG: ") + (broke ? why : "maximum iteration count reached") + " after " +

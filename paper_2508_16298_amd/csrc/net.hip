@@ -352,6 +352,21 @@ __global__ void k_wgrad_reduce(const float* __restrict__ part, int nchunk, int E
     grad[e] = s;
 }
 
+// The same sum in two passes for many chunks: group g of kWgGroups adds its
+// contiguous range of chunks in order, then the groups' sums are added in
+// order (a fixed order either way).
+static constexpr int kWgGroups = 16;
+
+__global__ void k_wgrad_reduce_groups(const float* __restrict__ part, int nchunk, int E, float* __restrict__ tmp) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x, gidx = blockIdx.y;
+    if (e >= E) return;
+    const int per = (nchunk + kWgGroups - 1) / kWgGroups;
+    const int b0 = gidx * per, b1 = min(nchunk, b0 + per);
+    float s = 0.0f;
+    for (int b = b0; b < b1; b++) s += part[(size_t)b * E + e];
+    tmp[(size_t)gidx * E + e] = s;
+}
+
 // ---------------------------------------------------------------------------
 // Output: z = s (o_0 + i o_1) in FP64
 // ---------------------------------------------------------------------------
@@ -585,6 +600,7 @@ qedhmc_status net_alloc_train(qedhmc_net* n) {
                                    (N + wgrad_mfma_chunk((int)N) - 1) / (size_t)wgrad_mfma_chunk((int)N));
     ok = ok && hipMalloc(&n->wpart, nchunk * (27 * 32 * 32 + 32) * sizeof(float)) == hipSuccess;
     ok = ok && hipMalloc(&n->feat, N * 8 * sizeof(float)) == hipSuccess;
+    ok = ok && hipMalloc(&n->wtmp, (size_t)kWgGroups * (27 * 32 * 32 + 32) * sizeof(float)) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         return net_fail(n, "net: training buffers: device allocation failed", QEDHMC_ENOMEM);
@@ -715,6 +731,14 @@ static qedhmc_status launch_wgrad(qedhmc_net* n, int l, const double* r, const f
         }
     }
     // W and b are contiguous in the parameter vector (b follows W)
+    if (nchunk > 4 * kWgGroups) {
+        hipLaunchKernelGGL(k_wgrad_reduce_groups, dim3(blocks_for(E, 256), kWgGroups), dim3(256), 0, st,
+                           (const float*)n->wpart, nchunk, E, n->wtmp);
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for(E, 256)), dim3(256), 0, st, (const float*)n->wtmp,
+                           kWgGroups, E, n->grads + n->woff[l]);
+        QH_HIP(hipGetLastError());
+        return QEDHMC_OK;
+    }
     hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for(E, 256)), dim3(256), 0, st, (const float*)n->wpart, nchunk, E,
                        n->grads + n->woff[l]);
     QH_HIP(hipGetLastError());
@@ -817,6 +841,7 @@ qedhmc_status qedhmc_net_destroy(qedhmc_net_t n) {
     }
     (void)hipFree(n->wpart);
     (void)hipFree(n->feat);
+    (void)hipFree(n->wtmp);
     (void)hipFree(n->dscal);
     (void)hipFree(n->dpart);
     if (n->hpin) (void)hipHostFree(n->hpin);

@@ -120,6 +120,7 @@ struct qedhmc_net {
     float* gbuf[2] = {nullptr, nullptr};
     float* wpart = nullptr;  // weight-gradient partials
     float* feat = nullptr;   // the first layer's feature map [N][8] (weight gradient on the matrix cores)
+    float* wtmp = nullptr;   // group sums of the weight-gradient partials
     uint16_t* actb[2] = {nullptr, nullptr};  // BF16 ping-pong activations (inference)
     double* dscal = nullptr;  // [0] |r|^2, [1] |e|^2, [8..12) reductions
     double* dpart = nullptr;  // reduction partials

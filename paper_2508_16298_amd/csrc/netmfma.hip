@@ -196,10 +196,9 @@ __global__ __launch_bounds__(kBlock) void k_conv_mfma32(NetGeo g, const float* _
 #pragma unroll
         for (int h = 0; h < 2; h++) acc[t][h] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     const int sgn = DGRAD ? -1 : 1;
-#pragma unroll 1
-    for (int k = 0; k < 27; k++) {
+    // A fragments of tap k (this lane's 8 channels of its tap-shifted site)
+    auto load_a = [&](int k, f32x4 (&a)[kTiles32][2]) {
         const int dt = sgn * (k / 9 - 1), dy = sgn * ((k / 3) % 3 - 1), dx = sgn * (k % 3 - 1);
-        f32x4 a[kTiles32][2];
 #pragma unroll
         for (int t = 0; t < kTiles32; t++) {
             const int m = wrap(st[t] + dt, g.Nt) * g.Vs + wrap(sy[t] + dy, g.L) * g.L + wrap(sx[t] + dx, g.L);
@@ -207,6 +206,18 @@ __global__ __launch_bounds__(kBlock) void k_conv_mfma32(NetGeo g, const float* _
             a[t][0] = src[0];
             a[t][1] = src[1];
         }
+    };
+    f32x4 an[kTiles32][2];
+    load_a(0, an);
+#pragma unroll 1
+    for (int k = 0; k < 27; k++) {
+        f32x4 a[kTiles32][2];
+#pragma unroll
+        for (int t = 0; t < kTiles32; t++) {
+            a[t][0] = an[t][0];
+            a[t][1] = an[t][1];
+        }
+        if (k + 1 < 27) load_a(k + 1, an);  // the next tap's rows in flight during this tap's MFMAs
 #pragma unroll
         for (int ob = 0; ob < 2; ob++)
 #pragma unroll
