@@ -199,10 +199,36 @@ __device__ __forceinline__ void tile_load(cplx<R> (&v)[4], const cplx<R>* __rest
     v[3] = slice[k.s0 + G.L + 1];
 }
 
+// A value from the cell one to the right (+x, lane + 1) or left (-x, lane - 1)
+// in a region whose rows are whole wavefronts and whole rings in x: the
+// wavefront rotations wave_rol:1 and wave_ror:1 (DPP controls 0x134 / 0x13C;
+// lane i receives lane i + 1, resp. i - 1, with 63 and 0 wrapping), per
+// 32-bit word.
+template <int CTRL>
+__device__ __forceinline__ float dpp_word(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_word(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int CTRL, typename R>
+__device__ __forceinline__ cplx<R> dpp_cplx(cplx<R> v) {
+    return mk<R>(dpp_word<CTRL>(v.re), dpp_word<CTRL>(v.im));
+}
+static constexpr int kDppFromRight = 0x134;  // wave_rol:1
+static constexpr int kDppFromLeft = 0x13C;   // wave_ror:1
+
 // One cross sweep (f1 if X, else f3) of the cell through exchange buffer b,
 // then the in-cell sweep IN (0: none, 1: f0, 2: f2).  The phases of both are
-// read first, so lazily fetched ones are in flight across the barrier.
-template <typename R, bool X, int IN, typename HS>
+// read first, so lazily fetched ones are in flight across the barrier.  DPPX
+// (x sweeps of a region whose rows are whole wavefronts and x rings): the x
+// neighbours' values come by wavefront rotation, with no buffer and no
+// barrier.
+template <typename R, bool X, int IN, bool DPPX, typename HS>
 __device__ __forceinline__ void tile_phase(cplx<R> (&v)[4], const HS& hs, cplx<R>* b, int nreg, const TCell& k) {
     // keep lazily fetched phases at their sweep (no hoisting of every fetch
     // of the slice to its start, which would undo the register saving)
@@ -218,6 +244,14 @@ __device__ __forceinline__ void tile_phase(cplx<R> (&v)[4], const HS& hs, cplx<R
         he = hs.template get<4>();
         hf = hs.template get<5>();
     }
+    if (X && DPPX) {
+        const cplx<R> R0 = dpp_cplx<kDppFromRight>(v[0]), R2 = dpp_cplx<kDppFromRight>(v[2]);
+        const cplx<R> L1 = dpp_cplx<kDppFromLeft>(v[1]), L3 = dpp_cplx<kDppFromLeft>(v[3]);
+        v[1] = pl_hw(v[1], ha, R0);
+        v[3] = pl_hw(v[3], hb, R2);
+        v[0] = pl_hcw(v[0], hc, L1);
+        v[2] = pl_hcw(v[2], hd, L3);
+    } else {
     if (k.act) {
         b[k.c] = v[0];
         b[nreg + k.c] = v[1];
@@ -238,6 +272,7 @@ __device__ __forceinline__ void tile_phase(cplx<R> (&v)[4], const HS& hs, cplx<R
         v[0] = pl_hcw(v[0], hc, D2);
         v[1] = pl_hcw(v[1], hd, D3);
     }
+    }
     const cplx<R> a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3];
     if constexpr (IN == 1) {  // f0: pairs (0, 1) and (2, 3)
         v[0] = pl_hw(a0, he, a1);
@@ -253,17 +288,19 @@ __device__ __forceinline__ void tile_phase(cplx<R> (&v)[4], const HS& hs, cplx<R
     }
 }
 
-// v <- B'_tau v (normalised factors, rightmost first: f3 f2 f1 f0 f1 f2 f3)
-template <typename R, typename HS>
+// v <- B'_tau v (normalised factors, rightmost first: f3 f2 f1 f0 f1 f2 f3).
+// The exchange buffers alternate over the sweeps that use them (with DPPX
+// only the y sweeps), so one barrier per such sweep suffices.
+template <typename R, bool DPPX, typename HS>
 __device__ __forceinline__ void tile_B(cplx<R> (&v)[4], const HS& hs, cplx<R>* xb, int nreg, const TCell& k,
                                        int& kb) {
-    tile_phase<R, false, 2>(v, hs, xb + (size_t)kb * 4 * nreg, nreg, k);
+    tile_phase<R, false, 2, DPPX>(v, hs, xb + (size_t)kb * 4 * nreg, nreg, k);
     kb ^= 1;
-    tile_phase<R, true, 1>(v, hs, xb + (size_t)kb * 4 * nreg, nreg, k);
-    kb ^= 1;
-    tile_phase<R, true, 2>(v, hs, xb + (size_t)kb * 4 * nreg, nreg, k);
-    kb ^= 1;
-    tile_phase<R, false, 0>(v, hs, xb + (size_t)kb * 4 * nreg, nreg, k);
+    tile_phase<R, true, 1, DPPX>(v, hs, xb + (size_t)kb * 4 * nreg, nreg, k);
+    if (!DPPX) kb ^= 1;
+    tile_phase<R, true, 2, DPPX>(v, hs, xb + (size_t)kb * 4 * nreg, nreg, k);
+    if (!DPPX) kb ^= 1;
+    tile_phase<R, false, 0, DPPX>(v, hs, xb + (size_t)kb * 4 * nreg, nreg, k);
     kb ^= 1;
 }
 
@@ -295,7 +332,7 @@ __device__ __forceinline__ double tdot(const cplx<R> (&a)[4], const cplx<R> (&b)
     return d;
 }
 
-template <typename R, bool FX, bool FY, bool PART>
+template <typename R, bool FX, bool FY, bool PART, bool DPPX = false>
 __global__ __launch_bounds__(kTileMaxThreads<R>) void k_mdagm_tiled(TiledGeo G, const cplx<R>* __restrict__ in,
                                                       cplx<R>* __restrict__ out, const cplx<R>* __restrict__ gauge,
                                                       TCoef<R> co, TPart<R> ops) {
@@ -322,7 +359,7 @@ __global__ __launch_bounds__(kTileMaxThreads<R>) void k_mdagm_tiled(TiledGeo G, 
         const int tm = tau0 == 0 ? Nt - 1 : tau0 - 1;
         hs.set(gauge, G, k, tm, co);
         tile_load<R>(u, in + (size_t)tm * Vs, G, k);
-        tile_B<R>(u, hs, xb, nreg, k, kb);
+        tile_B<R, DPPX>(u, hs, xb, nreg, k, kb);
         tile_load<R>(y, in + (size_t)tau0 * Vs, G, k);
         const R e = tm == Nt - 1 ? -co.C : co.C;
 #pragma unroll
@@ -340,7 +377,7 @@ __global__ __launch_bounds__(kTileMaxThreads<R>) void k_mdagm_tiled(TiledGeo G, 
         // FP64 after it, where its registers are free
         if constexpr (sizeof(R) == 4) tile_load<R>(vn, in + (size_t)tp * Vs, G, k);
         const R e = tau == Nt - 1 ? -co.C : co.C;
-        tile_B<R>(u, hs, xb, nreg, k, kb);  // B'_tau v_tau
+        tile_B<R, DPPX>(u, hs, xb, nreg, k, kb);  // B'_tau v_tau
         if constexpr (sizeof(R) == 8) tile_load<R>(vn, in + (size_t)tp * Vs, G, k);
         cplx<R> yn[4];
 #pragma unroll
@@ -348,7 +385,7 @@ __global__ __launch_bounds__(kTileMaxThreads<R>) void k_mdagm_tiled(TiledGeo G, 
             yn[q] = mk<R>(vn[q].re - e * u[q].re, vn[q].im - e * u[q].im);
             u[q] = yn[q];
         }
-        tile_B<R>(u, hs, xb, nreg, k, kb);  // B'_tau y_{tau+1}
+        tile_B<R, DPPX>(u, hs, xb, nreg, k, kb);  // B'_tau y_{tau+1}
         cplx<R> w[4];
 #pragma unroll
         for (int q = 0; q < 4; q++) w[q] = mk<R>(y[q].re - e * u[q].re, y[q].im - e * u[q].im);
@@ -540,7 +577,13 @@ static qedhmc_status mdagm_tiled_t(qedhmc_ctx* h, const void* in, void* out, con
         QH_HIP(hipGetLastError());
         return QEDHMC_OK;
     };
+    // x exchanges by wavefront rotation when every region row is one whole
+    // wavefront and a whole x ring; QEDHMC_TILE_DPP=0 (read per call) keeps
+    // them in LDS
+    const bool dppx = p.fx && !p.fy && p.g.RW == 64 && p.threads == p.g.RW * p.g.RH &&
+                      env_int("QEDHMC_TILE_DPP", 1) != 0;
     if (p.fx && p.fy) return go(k_mdagm_tiled<R, true, true, PART>);
+    if (dppx) return go(k_mdagm_tiled<R, true, false, PART, true>);
     if (p.fx) return go(k_mdagm_tiled<R, true, false, PART>);
     return go(k_mdagm_tiled<R, false, false, PART>);
 }

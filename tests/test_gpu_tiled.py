@@ -78,6 +78,27 @@ def test_tiled_mdagm_default_large_slices(L, Nt, prec):
     assert err < TOL[prec]
 
 
+@pytest.mark.parametrize("L,Nt,tc", [(128, 6, 0), (128, 5, 2)])
+def test_tiled_x_exchange_by_wavefront_rotation(L, Nt, tc, monkeypatch):
+    """At L = 128 every FP32 strip row is one wavefront and one x ring: the x
+    exchanges go by wavefront rotation instead of LDS.  Same arithmetic on the
+    same values: bitwise equal to the LDS exchange, and to the oracle to the
+    FP32 bar (default and forced ragged runs)."""
+    th = inputs.noisy_pi_flux_theta(L, Nt, 0.3, seed=950 + Nt)
+    v = _dev(inputs.gauss_cvec(L, Nt, seed=951 + Nt), CDT["fp32"])
+    monkeypatch.setenv("QEDHMC_TILE_TC", str(tc))
+    with Q.Lattice(L, Nt) as lat:
+        thd = _dev(th)
+        monkeypatch.setenv("QEDHMC_TILE_DPP", "0")
+        a = lat.apply_MdagM(thd, v, prec="fp32")
+        torch.cuda.synchronize()
+        monkeypatch.setenv("QEDHMC_TILE_DPP", "1")
+        b = lat.apply_MdagM(thd, v, prec="fp32")
+        torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert _rel(_host(b), O.apply_MdagM(O.lat(L, Nt), th, v.cpu().numpy().astype(np.complex128))) < TOL["fp32"]
+
+
 def test_tiled_matches_whole_slice_kernel(tiled_env):
     """Both forms run at L = 48: the same operator to rounding."""
     L, Nt = 48, 16
