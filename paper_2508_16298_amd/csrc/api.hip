@@ -17,7 +17,11 @@ qedhmc_status allow_lds(const void* k, size_t max_lds) {
     static std::unordered_set<const void*> done;
     std::lock_guard<std::mutex> g(m);
     if (done.count(k)) return QEDHMC_OK;
-    QH_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds));
+    // the dynamic room is what the kernel's static LDS leaves of the limit
+    hipFuncAttributes fa{};
+    QH_HIP(hipFuncGetAttributes(&fa, k));
+    const size_t room = max_lds > fa.sharedSizeBytes ? max_lds - fa.sharedSizeBytes : 0;
+    QH_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)room));
     done.insert(k);
     return QEDHMC_OK;
 }
@@ -188,6 +192,10 @@ qedhmc_status qedhmc_destroy(qedhmc_t h) {
     if (h->pc_dev32) (void)hipFree(h->pc_dev32);
     if (h->pc_roll64) (void)hipFree(h->pc_roll64);
     if (h->pc_roll32) (void)hipFree(h->pc_roll32);
+    if (h->pc_spec64) (void)hipFree(h->pc_spec64);
+    if (h->pc_spec32) (void)hipFree(h->pc_spec32);
+    if (h->pc_tw64) (void)hipFree(h->pc_tw64);
+    if (h->pc_tw32) (void)hipFree(h->pc_tw32);
     (void)hipFree(h->theta0);
     (void)hipFree(h->mom);
     (void)hipFree(h->force);
@@ -212,6 +220,9 @@ qedhmc_status qedhmc_destroy(qedhmc_t h) {
         for (auto& b : a)
             for (auto& g : b)
                 if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    for (auto& a : h->pcg_round)
+        for (auto& g : a)
+            if (g.exec) (void)hipGraphExecDestroy(g.exec);
     delete h;
     return QEDHMC_OK;
 }

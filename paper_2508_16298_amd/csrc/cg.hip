@@ -41,14 +41,6 @@ __global__ __launch_bounds__(BS) void k_cg_replace(Lat lt, CgBufs<R> B, const cp
     cg_replace_body<R, MC, NB>(lt, B, gauge, co, scal, kpar, tau, tl);
 }
 
-// Record of the solve kept on the device (pipelined driver): iterations,
-// |rhs|^2 and the latest |r|^2 estimate (the FP64 true residual after an
-// update, else the recursion's gamma) after every round; from the latest
-// decision the FP64 true |r|^2, the reliable updates so far, the state (0
-// resumed, 4 failed, 5 converged) and, for a failure, its cause.
-enum { CR_ITERS = 0, CR_TRUE = 1, CR_B2 = 2, CR_NREL = 3, CR_DONE = 4, CR_WHY = 5, CR_EST = 6, CR_N = 8 };
-enum { WHY_BREAKDOWN = 1, WHY_NONFINITE = 2, WHY_BUDGET = 3, WHY_STALL = 4 };
-
 // The reliable-update decision on the device, after the gated FP64 O x and
 // replacement: converged (5) when the FP64 true residual meets the target;
 // failed (4) on a non-finite residual, the iteration budget used or no
@@ -276,7 +268,7 @@ static qedhmc_status cg_pipelined(qedhmc_ctx* h, const CgBufs<R>& B, double* x, 
                                   int* iters, double* true_rel, int* n_reliable) {
     const int chunk = mixed ? kCap + 1 : 64;
     static_assert((kCap + 1) & 1, "mixed rounds alternate the launch parity");
-    double* rec = h->scal + 40;
+    double* rec = h->scal + kRecOff;
     for (auto& e : h->cg_ev)
         if (!e) QH_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     QH_TRY(launch_start<R>(h, B));

@@ -28,6 +28,17 @@ enum {
     S_NREL = 13,   // batched driver: updates so far
     S_NSLOT = 16,
 };
+// Record of a solve kept on the device (pipelined drivers of cg.hip and
+// pcg.hip): iterations, |rhs|^2 and the latest |r|^2 estimate (the FP64 true
+// residual after an update, else the recursion's gamma) after every round;
+// from the latest decision the FP64 true |r|^2, the reliable updates so far,
+// the state (0 resumed, 4 failed, 5 converged) and, for a failure, its cause.
+// Kept at scal + kRecOff, mirrored to pinned host memory at h_pinned + 32
+// (two records by round parity).
+enum { CR_ITERS = 0, CR_TRUE = 1, CR_B2 = 2, CR_NREL = 3, CR_DONE = 4, CR_WHY = 5, CR_EST = 6, CR_N = 8 };
+enum { WHY_BREAKDOWN = 1, WHY_NONFINITE = 2, WHY_BUDGET = 3, WHY_STALL = 4 };
+static constexpr int kRecOff = 40;
+
 // Per-slice partials of one parity: <r,r>, <w,r>, <r,s>, <p,w>, <p,s>, aux
 // (aux: |rhs|^2 from the start kernel, the FP64 true |r|^2 from a reliable update)
 static constexpr int kNP = 6;

@@ -62,6 +62,101 @@ __global__ void k_unit(cplx<double>* __restrict__ e, size_t n, size_t k) {
         e[i] = mk<double>(i == k ? 1.0 : 0.0, 0.0);
 }
 
+// ---------------------------------------------------------------------------
+// Spectral form of P.  Both passes are gathers whose taps depend only on the
+// output's x parity, with space periodic and one sign flip per wrap of tau
+// (the antiperiodic extension itself once N_tau exceeds a pass's tau reach).
+// So each pass commutes with translations by the two-site cell (2 in x, 1 in
+// y) and by one slice, and on the cell momenta kx = 2 pi nx / (L/2),
+// ky = 2 pi ny / L it acts on the pair (v_even, v_odd) of a slice as a 2x2
+// matrix S(k, a) per tau offset a:
+//   S[p][p'](k, a) = sum over the taps (a, b, c, g) of parity p with
+//                    (p + c) mod 2 = p' of g exp(i (kx (p + c - p') / 2 + ky b)).
+// P = S_1 S_0 has the blocks H(k, a) = sum_{a1 + a2 = a} S_1(k, a2) S_0(k, a1)
+// for a in [amin_0 + amin_1, amax_0 + amax_1], and one application is a 2D DFT
+// of every slice's two parity planes, the banded tau sum
+// z^(k, tau) = sum_a sign H(k, a) v^(k, tau + a) (sign -1 per wrap), and the
+// inverse DFT (its 1 / (L L/2) folded into H).  Same operator, far fewer
+// operations than the taps at the sizes the stencil is latency-bound at.
+// ---------------------------------------------------------------------------
+static constexpr int kSpecNA = 2 * kCapTau + 1;  // combined tau offsets at most
+static constexpr int kSpecE = 8;                // DFT outputs per thread at most (L * L/2 <= 8192)
+
+static qedhmc_status build_spectral(qedhmc_ctx* h, const std::vector<HostTap> (&pass)[2][2]) {
+    h->pc_spec_na = 0;
+    const int L = h->lat.L, Lh = L / 2, nk = L * Lh;
+    if (L % 2 || h->lat.Nt <= kCapTau || nk > kSpecE * 1024) return QEDHMC_OK;
+    const int a0 = h->pc_pass[0].amin + h->pc_pass[1].amin, a1 = h->pc_pass[0].amax + h->pc_pass[1].amax;
+    const int na = a1 - a0 + 1;
+    if (na > kSpecNA) return QEDHMC_OK;
+    // e^{+2 pi i j / n} by integer index, so every phase is one table entry
+    auto unit = [](int n) {
+        std::vector<cplx<double>> t(n);
+        for (int j = 0; j < n; j++) t[j] = mk<double>(std::cos(2 * M_PI * j / n), std::sin(2 * M_PI * j / n));
+        return t;
+    };
+    const std::vector<cplx<double>> ex = unit(Lh), ey = unit(L);
+    auto pmod = [](int v, int n) { return ((v % n) + n) % n; };
+    auto cmul = [](cplx<double> x, cplx<double> y) {
+        return mk<double>(x.re * y.re - x.im * y.im, x.re * y.im + x.im * y.re);
+    };
+    std::vector<cplx<double>> H((size_t)na * 4 * nk, mk<double>(0.0, 0.0));  // [a][entry pp'][k]
+    const int n0 = h->pc_pass[0].amax - h->pc_pass[0].amin + 1, n1 = h->pc_pass[1].amax - h->pc_pass[1].amin + 1;
+    std::vector<cplx<double>> S0((size_t)n0 * 4), S1((size_t)n1 * 4);
+    for (int ny = 0; ny < L; ny++)
+        for (int nx = 0; nx < Lh; nx++) {
+            const int k = ny * Lh + nx;
+            for (int ps = 0; ps < 2; ps++) {
+                std::vector<cplx<double>>& S = ps ? S1 : S0;
+                std::fill(S.begin(), S.end(), mk<double>(0.0, 0.0));
+                for (int p = 0; p < 2; p++)
+                    for (const auto& t : pass[ps][p]) {
+                        const int pp = pmod(p + t.dx, 2), m = (p + t.dx - pp) / 2;
+                        const cplx<double> ph = cmul(ex[pmod(m * nx, Lh)], ey[pmod(t.dy * ny, L)]);
+                        cplx<double>& e = S[(size_t)(t.dt - h->pc_pass[ps].amin) * 4 + 2 * p + pp];
+                        const cplx<double> c = cmul(mk<double>(t.gre, t.gim), ph);
+                        e.re += c.re;
+                        e.im += c.im;
+                    }
+            }
+            for (int i0 = 0; i0 < n0; i0++)
+                for (int i1 = 0; i1 < n1; i1++) {
+                    const int ia = h->pc_pass[0].amin + i0 + h->pc_pass[1].amin + i1 - a0;
+                    for (int p = 0; p < 2; p++)
+                        for (int pp = 0; pp < 2; pp++) {
+                            cplx<double>& e = H[((size_t)ia * 4 + 2 * p + pp) * nk + k];
+                            for (int q = 0; q < 2; q++) {
+                                const cplx<double> c = cmul(S1[(size_t)i1 * 4 + 2 * p + q], S0[(size_t)i0 * 4 + 2 * q + pp]);
+                                e.re += c.re;
+                                e.im += c.im;
+                            }
+                        }
+                }
+        }
+    const double norm = 1.0 / nk;
+    for (auto& e : H) e = mk<double>(e.re * norm, e.im * norm);
+    // forward twiddles e^{-2 pi i j / n}: L/2 for x, then L for y
+    std::vector<cplx<double>> tw(Lh + L);
+    for (int j = 0; j < Lh; j++) tw[j] = mk<double>(ex[j].re, -ex[j].im);
+    for (int j = 0; j < L; j++) tw[Lh + j] = mk<double>(ey[j].re, -ey[j].im);
+    std::vector<cplx<float>> H32(H.size()), tw32(tw.size());
+    for (size_t i = 0; i < H.size(); i++) H32[i] = mk<float>((float)H[i].re, (float)H[i].im);
+    for (size_t i = 0; i < tw.size(); i++) tw32[i] = mk<float>((float)tw[i].re, (float)tw[i].im);
+    QH_HIP(hipMalloc(&h->pc_spec64, H.size() * sizeof(cplx<double>)));
+    QH_HIP(hipMalloc(&h->pc_spec32, H.size() * sizeof(cplx<float>)));
+    QH_HIP(hipMalloc(&h->pc_tw64, tw.size() * sizeof(cplx<double>)));
+    QH_HIP(hipMalloc(&h->pc_tw32, tw.size() * sizeof(cplx<float>)));
+    QH_HIP(hipMemcpyAsync(h->pc_spec64, H.data(), H.size() * sizeof(cplx<double>), hipMemcpyHostToDevice, h->stream));
+    QH_HIP(hipMemcpyAsync(h->pc_spec32, H32.data(), H32.size() * sizeof(cplx<float>), hipMemcpyHostToDevice, h->stream));
+    QH_HIP(hipMemcpyAsync(h->pc_tw64, tw.data(), tw.size() * sizeof(cplx<double>), hipMemcpyHostToDevice, h->stream));
+    QH_HIP(hipMemcpyAsync(h->pc_tw32, tw32.data(), tw32.size() * sizeof(cplx<float>), hipMemcpyHostToDevice, h->stream));
+    // the host vectors die at return: wait for the copies
+    QH_HIP(hipStreamSynchronize(h->stream));
+    h->pc_spec_a0 = a0;
+    h->pc_spec_na = na;
+    return QEDHMC_OK;
+}
+
 static qedhmc_status build_paper_precond(qedhmc_ctx* h) {
     qedhmc_params bp = h->p;
     bp.L = kBuildL;
@@ -267,6 +362,7 @@ static qedhmc_status build_paper_precond(qedhmc_ctx* h) {
         QH_HIP(hipMemcpyAsync(h->pc_dev64, t64.data(), nt * sizeof(PTap<double>), hipMemcpyHostToDevice, h->stream));
         QH_HIP(hipMemcpyAsync(h->pc_dev32, t32.data(), nt * sizeof(PTap<float>), hipMemcpyHostToDevice, h->stream));
     }
+    QH_TRY(build_spectral(h, pass));
     QH_HIP(hipStreamSynchronize(h->stream));
     h->pc_ready = true;
     return QEDHMC_OK;
@@ -653,9 +749,6 @@ static const PTap<R>* taps_for(qedhmc_ctx* h) {
         return (const PTap<float>*)h->pc_dev32;
 }
 
-// Band height TY: at most 512 output sites of one parity per step and an LDS
-// window within 64 KB (FP32) or 128 KB (FP64); runs of 2 .. 16 slices aiming
-// at about 512 workgroups.
 // Band height TY: four lanes per output site, about 448 lanes, and an LDS
 // window within 64 KB (FP32) or 128 KB (FP64); runs of 2 .. 16 slices aiming
 // at about 4096 workgroups.
@@ -666,7 +759,8 @@ static qedhmc_status launch_pc(qedhmc_ctx* h, int ps, const cplx<R>* in, cplx<R>
     // kernel measured as fast or faster: too few rolled work items to fill
     // the device); QEDHMC_PC_KERNEL=roll|stream (read per call) forces one
     const char* ek = std::getenv("QEDHMC_PC_KERNEL");
-    const bool roll = ek ? std::strcmp(ek, "roll") == 0 : h->lat.L >= kRollFromL;
+    const bool forced = ek && (std::strcmp(ek, "roll") == 0 || std::strcmp(ek, "stream") == 0);
+    const bool roll = forced ? std::strcmp(ek, "roll") == 0 : h->lat.L >= kRollFromL;
     if (pp.rcount[0] > 0 && pp.rcount[1] > 0 && roll) return launch_pc_roll<R>(h, ps, in, out, stop);
     const Lat& lt = h->lat;
     PcGeo g{};
@@ -733,9 +827,402 @@ static qedhmc_status launch_pc(qedhmc_ctx* h, int ps, const cplx<R>* in, cplx<R>
     return QEDHMC_OK;
 }
 
-// z = G^dag (G r); tmp: scratch vector of the same precision
+// ---------------------------------------------------------------------------
+// Spectral application (the tables of build_spectral).  Momentum-space
+// vectors use the memory of a site vector: slice tau holds the even plane
+// [ny][nx] and then the odd one.
+// ---------------------------------------------------------------------------
+// acc += m v (complex), four FMAs
+template <typename R>
+__device__ __forceinline__ void v_cmac(cplx<R>& acc, cplx<R> m, cplx<R> v) {
+    acc.re = fma(m.re, v.re, acc.re);
+    acc.re = fma(-m.im, v.im, acc.re);
+    acc.im = fma(m.re, v.im, acc.im);
+    acc.im = fma(m.im, v.re, acc.im);
+}
+
+struct PcSpecGeo {
+    int L, Lh, Nt, Vs, nk, a0, na;
+};
+
+// (slice, parity) of a workgroup of the per-plane spectral kernels: both
+// planes of a slice on the XCD that slice_of_block gives the slice (so
+// momentum planes written and read by consecutive launches stay in that
+// XCD's L2); spec_grid(Nt) workgroups, the surplus ones get -1
+__host__ __device__ __forceinline__ int spec_grid(int Nt) { return 16 * ((Nt + 7) / 8); }
+__device__ __forceinline__ int spec_slice_of_block(int b, int Nt, int& p) {
+    const int per = (Nt + 7) >> 3, j = b >> 3;
+    const int tau = (b & 7) * per + (j >> 1);
+    p = j & 1;
+    return tau < Nt ? tau : -1;
+}
+
+// 2D DFT of nplanes parity planes held in LDS (buf[plane][row][column],
+// Lh columns), by the whole workgroup: a direct DFT over the column index
+// (L/2 points) for every row, written back to buf, then one over the row
+// index (L points) for every column, whose results go to
+// emit(plane, kr * Lh + col, value).  Twiddles twx[Lh], twy[L] hold
+// e^{-2 pi i j / n} (forward) or their conjugates (inverse).  Outputs per
+// thread: at most kSpecE (nplanes * L * L/2 <= kSpecE * blockDim.x).
+template <typename R, typename Emit>
+__device__ __forceinline__ void dft_planes(cplx<R>* buf, const cplx<R>* twx, const cplx<R>* twy, int L, int Lh,
+                                           int nplanes, Emit emit) {
+    const int n = L * Lh, tot = nplanes * n;
+    cplx<R> acc[kSpecE];
+#pragma unroll
+    for (int j = 0; j < kSpecE; j++) {
+        const int ea = (int)threadIdx.x + j * (int)blockDim.x;
+        if (ea < tot) {
+            const int pl = ea / n, e = ea - pl * n;
+            const int row = e / Lh, kc = e - row * Lh;
+            const cplx<R>* src = buf + pl * n + row * Lh;
+            R ar = 0, ai = 0;
+            int idx = 0;
+            for (int m = 0; m < Lh; m++) {
+                const cplx<R> v = src[m], t = twx[idx];
+                ar = fma(v.re, t.re, ar);
+                ar = fma(-v.im, t.im, ar);
+                ai = fma(v.re, t.im, ai);
+                ai = fma(v.im, t.re, ai);
+                idx += kc;
+                idx = idx >= Lh ? idx - Lh : idx;
+            }
+            acc[j] = mk<R>(ar, ai);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kSpecE; j++) {
+        const int ea = (int)threadIdx.x + j * (int)blockDim.x;
+        if (ea < tot) buf[ea] = acc[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kSpecE; j++) {
+        const int ea = (int)threadIdx.x + j * (int)blockDim.x;
+        if (ea < tot) {
+            const int pl = ea / n, e = ea - pl * n;
+            const int kr = e / Lh, col = e - kr * Lh;
+            const cplx<R>* src = buf + pl * n + col;
+            R ar = 0, ai = 0;
+            int idx = 0;
+            for (int r = 0; r < L; r++) {
+                const cplx<R> v = src[r * Lh], t = twy[idx];
+                ar = fma(v.re, t.re, ar);
+                ar = fma(-v.im, t.im, ar);
+                ai = fma(v.re, t.im, ai);
+                ai = fma(v.im, t.re, ai);
+                idx += kr;
+                idx = idx >= L ? idx - L : idx;
+            }
+            emit(pl, e, mk<R>(ar, ai));
+        }
+    }
+}
+
+// twiddles of both axes into LDS (twx then twy, contiguous), conjugated for
+// the inverse
+template <typename R, bool INV>
+__device__ __forceinline__ void load_twiddles(const cplx<R>* __restrict__ tw, cplx<R>* twx, int n) {
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const cplx<R> t = tw[j];
+        twx[j] = INV ? mk<R>(t.re, -t.im) : t;
+    }
+}
+
+// Site vector <-> momentum planes, a workgroup per (slice, parity).
+// Forward: in a site vector, out momentum planes (e^{-i k.r}); INV: the
+// reverse with e^{+i k.r} (the normalisation sits in H).
+template <typename R, bool INV>
+__global__ __launch_bounds__(1024) void k_pcs_dft(PcSpecGeo g, const cplx<R>* __restrict__ tw,
+                                                  const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
+                                                  const double* __restrict__ stop) {
+    if (stop && *stop != 0.0) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int L = g.L, Lh = g.Lh, n = g.nk;
+    cplx<R>* buf = reinterpret_cast<cplx<R>*>(smem);  // [row][column]
+    cplx<R>* twx = buf + n;                           // [Lh], then twy [L]
+    int p;
+    const int tau = spec_slice_of_block(blockIdx.x, g.Nt, p);
+    if (tau < 0) return;
+    const size_t sbase = (size_t)tau * g.Vs;
+    load_twiddles<R, INV>(tw, twx, Lh + L);
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int row = e / Lh, col = e - row * Lh;
+        buf[e] = INV ? in[sbase + (size_t)p * n + e] : in[sbase + (size_t)row * L + 2 * col + p];
+    }
+    __syncthreads();
+    dft_planes<R>(buf, twx, twx + Lh, L, Lh, 1, [&](int, int e, cplx<R> v) {
+        if (INV) {
+            const int y = e / Lh, m = e - y * Lh;
+            out[sbase + (size_t)y * L + 2 * m + p] = v;
+        } else {
+            out[sbase + (size_t)p * n + e] = v;
+        }
+    });
+}
+
+// input slice s of the banded tau sum: its index in [0, N_tau) and the sign
+// (-1 per wrap of the antiperiodic direction)
+__device__ __forceinline__ int wrap_slice(int s, int Nt, int& flip) {
+    const int q = s >= 0 ? s / Nt : -((-s + Nt - 1) / Nt);  // floor(s / Nt)
+    flip = q & 1;
+    return s - q * Nt;
+}
+
+// z^(k, tau) = sum_a sign H(k, a) v^(k, tau + a) on momentum planes: a thread
+// per (momentum, run of TC slices) holds the TC + na - 1 input slices it
+// needs in registers.  H is [a][entry][k] (coalesced across k).
+template <typename R, int TC>
+__global__ __launch_bounds__(256) void k_pcs_tconv(PcSpecGeo g, const cplx<R>* __restrict__ H,
+                                                   const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
+                                                   const double* __restrict__ stop) {
+    if (stop && *stop != 0.0) return;
+    const int nk = g.nk;
+    const int nrun = (g.Nt + TC - 1) / TC;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= nk * nrun) return;
+    const int k = gid % nk, tau0 = (gid / nk) * TC;
+    constexpr int NW = TC + kSpecNA - 1;
+    // window slices past the last one needed read slice 0 with sign 0: no
+    // branches, every load in flight together
+    cplx<R> v0[NW], v1[NW];
+    R sgw[NW];
+#pragma unroll
+    for (int j = 0; j < NW; j++) {
+        int flip = 0;
+        const bool on = j < TC + g.na - 1;
+        const int sr = on ? wrap_slice(tau0 + g.a0 + j, g.Nt, flip) : 0;
+        sgw[j] = on ? (flip ? R(-1) : R(1)) : R(0);
+        const cplx<R>* src = in + (size_t)sr * g.Vs + k;
+        v0[j] = src[0];
+        v1[j] = src[nk];
+    }
+#pragma unroll
+    for (int j = 0; j < NW; j++) {
+        v0[j] = mk<R>(sgw[j] * v0[j].re, sgw[j] * v0[j].im);
+        v1[j] = mk<R>(sgw[j] * v1[j].re, sgw[j] * v1[j].im);
+    }
+    cplx<R> z0[TC], z1[TC];
+#pragma unroll
+    for (int t = 0; t < TC; t++) z0[t] = z1[t] = mk<R>(R(0), R(0));
+    // (guards rather than an early exit keep every window index a constant,
+    // so the window stays in registers)
+#pragma unroll
+    for (int ia = 0; ia < kSpecNA; ia++) {
+        if (ia < g.na) {
+            const cplx<R>* hp = H + (size_t)ia * 4 * nk + k;
+            const cplx<R> h00 = hp[0], h01 = hp[nk], h10 = hp[2 * nk], h11 = hp[3 * nk];
+#pragma unroll
+            for (int t = 0; t < TC; t++) {
+                v_cmac(z0[t], h00, v0[t + ia]);
+                v_cmac(z0[t], h01, v1[t + ia]);
+                v_cmac(z1[t], h10, v0[t + ia]);
+                v_cmac(z1[t], h11, v1[t + ia]);
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < TC; t++)
+        if (tau0 + t < g.Nt) {
+            cplx<R>* dst = out + (size_t)(tau0 + t) * g.Vs + k;
+            dst[0] = z0[t];
+            dst[nk] = z1[t];
+        }
+}
+
+// The tau sum and the inverse DFT in one launch, a workgroup per (slice,
+// parity): the plane z^_p(tau) is formed in LDS from the na input slices
+// (read through the L2; used where a slice is small), then transformed back.
+template <typename R>
+__global__ __launch_bounds__(1024) void k_pcs_tconv_idft(PcSpecGeo g, const cplx<R>* __restrict__ H,
+                                                         const cplx<R>* __restrict__ tw,
+                                                         const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
+                                                         const double* __restrict__ stop) {
+    const double stopv = stop ? *stop : 0.0;  // tested once the data below is in flight
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int L = g.L, Lh = g.Lh, n = g.nk;
+    cplx<R>* buf = reinterpret_cast<cplx<R>*>(smem);
+    cplx<R>* twx = buf + n;
+    int p;
+    const int tau = spec_slice_of_block(blockIdx.x, g.Nt, p);
+    if (tau < 0) return;
+    const int ntw = Lh + L;  // <= blockDim.x (spec_fits)
+    const cplx<R> twv = (int)threadIdx.x < ntw ? tw[threadIdx.x] : mk<R>(R(0), R(0));
+    // slice offset, H offset and sign of every tau offset, once per
+    // workgroup; offsets past na read valid entries with sign 0, so every
+    // load below is unconditional and all of them are in flight together
+    size_t soff[kSpecNA], hoff[kSpecNA];
+    R sgn[kSpecNA];
+#pragma unroll
+    for (int ia = 0; ia < kSpecNA; ia++) {
+        int flip = 0;
+        const bool on = ia < g.na;
+        soff[ia] = on ? (size_t)wrap_slice(tau + g.a0 + ia, g.Nt, flip) * g.Vs : 0;
+        hoff[ia] = ((size_t)(on ? ia : 0) * 4 + 2 * p) * n;
+        sgn[ia] = on ? (flip ? R(-1) : R(1)) : R(0);
+    }
+    cplx<R> h0[kSpecNA], h1[kSpecNA], v0[kSpecNA], v1[kSpecNA];
+    auto fetch = [&](int e) {
+#pragma unroll
+        for (int ia = 0; ia < kSpecNA; ia++) {
+            h0[ia] = H[hoff[ia] + e];
+            h1[ia] = H[hoff[ia] + n + e];
+            v0[ia] = in[soff[ia] + e];
+            v1[ia] = in[soff[ia] + n + e];
+        }
+    };
+    auto form = [&](int e) {
+        cplx<R> z = mk<R>(R(0), R(0));
+#pragma unroll
+        for (int ia = 0; ia < kSpecNA; ia++) {
+            cplx<R> t = mk<R>(R(0), R(0));
+            v_cmac(t, h0[ia], v0[ia]);
+            v_cmac(t, h1[ia], v1[ia]);
+            z.re = fma(sgn[ia], t.re, z.re);
+            z.im = fma(sgn[ia], t.im, z.im);
+        }
+        buf[e] = z;
+    };
+    const int e0 = threadIdx.x;
+    fetch(e0 < n ? e0 : 0);
+    if (stopv != 0.0) return;
+    if (e0 < ntw) {
+        twx[e0] = mk<R>(twv.re, -twv.im);  // inverse twiddles
+    }
+    if (e0 < n) form(e0);
+    for (int e = e0 + blockDim.x; e < n; e += blockDim.x) {
+        fetch(e);
+        form(e);
+    }
+    __syncthreads();
+    const size_t sbase = (size_t)tau * g.Vs;
+    dft_planes<R>(buf, twx, twx + Lh, L, Lh, 1, [&](int, int e, cplx<R> v) {
+        const int y = e / Lh, m = e - y * Lh;
+        out[sbase + (size_t)y * L + 2 * m + p] = v;
+    });
+}
+
+// whether apply_P_t takes the spectral form: built (L even, N_tau above the
+// tau reach of a pass, L * L/2 <= 8192) and not overridden by
+// QEDHMC_PC_KERNEL=roll|stream (read per call)
+static bool use_spectral(const qedhmc_ctx* h) {
+    if (h->pc_spec_na <= 0) return false;
+    const char* ek = std::getenv("QEDHMC_PC_KERNEL");
+    return !ek || !*ek || std::strcmp(ek, "spectral") == 0;
+}
+
+// the tau sum fused into the inverse DFT up to this many momenta per plane
+// (each workgroup then reads na input planes of both parities through the
+// L2); QEDHMC_PC_FUSE=0|1 (read per call) forces either form
+static constexpr int kSpecFuseNK = 1152;  // L = 48
+
+static bool spec_fused(const qedhmc_ctx* h) {
+    const char* ef = std::getenv("QEDHMC_PC_FUSE");
+    if (ef && *ef) return std::atoi(ef) != 0;
+    return h->lat.L * (h->lat.L / 2) <= kSpecFuseNK;
+}
+
+template <typename R>
+static PcSpecGeo spec_geo(const qedhmc_ctx* h) {
+    const Lat& lt = h->lat;
+    return PcSpecGeo{lt.L, lt.L / 2, lt.Nt, lt.Vs, lt.L * (lt.L / 2), h->pc_spec_a0, h->pc_spec_na};
+}
+
+template <typename R>
+static const cplx<R>* spec_tw(const qedhmc_ctx* h) {
+    return (const cplx<R>*)(sizeof(R) == 8 ? h->pc_tw64 : h->pc_tw32);
+}
+
+template <typename R>
+static const cplx<R>* spec_H(const qedhmc_ctx* h) {
+    return (const cplx<R>*)(sizeof(R) == 8 ? h->pc_spec64 : h->pc_spec32);
+}
+
+// threads of a workgroup transforming nplanes planes (kSpecE outputs each at
+// most) and its dynamic LDS; EUNSUPPORTED if the plan does not fit
+template <typename R>
+static bool spec_fits(const qedhmc_ctx* h, int nplanes, int& threads, size_t& lds) {
+    const int L = h->lat.L, tot = nplanes * L * (L / 2);
+    threads = std::min(1024, (tot + 63) / 64 * 64);
+    lds = (size_t)(tot + L / 2 + L) * sizeof(cplx<R>);
+    // (room for the update kernel's static reduction scratch; one thread per
+    // twiddle)
+    return (tot + threads - 1) / threads <= kSpecE && lds + 2048 <= h->max_lds && L / 2 + L <= threads;
+}
+
+template <typename R>
+static qedhmc_status spec_plan(qedhmc_ctx* h, int nplanes, int& threads, size_t& lds) {
+    if (!spec_fits<R>(h, nplanes, threads, lds)) {
+        set_error("paper preconditioner: the spectral plan does not fit one workgroup");
+        return QEDHMC_EUNSUPPORTED;
+    }
+    return QEDHMC_OK;
+}
+
+// where the forward transform of r should land for launch_pcs_rest(z, tmp):
+// tmp when the rest is fused (it reads neighbouring slices and writes z),
+// z otherwise
+template <typename R>
+static cplx<R>* spec_vhat(const qedhmc_ctx* h, cplx<R>* z, cplx<R>* tmp) {
+    return spec_fused(h) ? tmp : z;
+}
+
+template <typename R>
+static qedhmc_status launch_pcs_fwd(qedhmc_ctx* h, const cplx<R>* r, cplx<R>* vhat, const double* stop) {
+    int threads;
+    size_t lds;
+    QH_TRY(spec_plan<R>(h, 1, threads, lds));
+    if (lds > 65536) QH_TRY(allow_lds((const void*)k_pcs_dft<R, false>, h->max_lds));
+    hipLaunchKernelGGL((k_pcs_dft<R, false>), dim3(spec_grid(h->lat.Nt)), dim3(threads), lds, h->stream,
+                       spec_geo<R>(h), spec_tw<R>(h), r, vhat, stop);
+    QH_HIP(hipGetLastError());
+    return QEDHMC_OK;
+}
+
+// z = P r from vhat = the forward transform of r (at spec_vhat(z, tmp))
+template <typename R>
+static qedhmc_status launch_pcs_rest(qedhmc_ctx* h, const cplx<R>* vhat, cplx<R>* z, cplx<R>* tmp,
+                                     const double* stop) {
+    const PcSpecGeo g = spec_geo<R>(h);
+    int threads;
+    size_t lds;
+    QH_TRY(spec_plan<R>(h, 1, threads, lds));
+    const dim3 dgrid(spec_grid(g.Nt));
+    if (spec_fused(h)) {
+        if (lds > 65536) QH_TRY(allow_lds((const void*)k_pcs_tconv_idft<R>, h->max_lds));
+        hipLaunchKernelGGL(k_pcs_tconv_idft<R>, dgrid, dim3(threads), lds, h->stream, g, spec_H<R>(h), spec_tw<R>(h),
+                           vhat, z, stop);
+        QH_HIP(hipGetLastError());
+        return QEDHMC_OK;
+    }
+    // longer runs once there are enough threads without them
+    if ((size_t)g.nk * g.Nt >= ((size_t)1 << 20)) {
+        const int nth = g.nk * ((g.Nt + 7) / 8);
+        hipLaunchKernelGGL((k_pcs_tconv<R, 8>), dim3((nth + 255) / 256), dim3(256), 0, h->stream, g, spec_H<R>(h),
+                           vhat, tmp, stop);
+    } else {
+        const int nth = g.nk * ((g.Nt + 3) / 4);
+        hipLaunchKernelGGL((k_pcs_tconv<R, 4>), dim3((nth + 255) / 256), dim3(256), 0, h->stream, g, spec_H<R>(h),
+                           vhat, tmp, stop);
+    }
+    QH_HIP(hipGetLastError());
+    if (lds > 65536) QH_TRY(allow_lds((const void*)k_pcs_dft<R, true>, h->max_lds));
+    hipLaunchKernelGGL((k_pcs_dft<R, true>), dgrid, dim3(threads), lds, h->stream, g, spec_tw<R>(h),
+                       (const cplx<R>*)tmp, z, stop);
+    QH_HIP(hipGetLastError());
+    return QEDHMC_OK;
+}
+
+// z = G^dag (G r); tmp: scratch vector of the same precision (r, z and tmp
+// distinct)
 template <typename R>
 static qedhmc_status apply_P_t(qedhmc_ctx* h, const cplx<R>* r, cplx<R>* z, cplx<R>* tmp, const double* stop) {
+    if (use_spectral(h)) {
+        cplx<R>* vhat = spec_vhat<R>(h, z, tmp);
+        QH_TRY(launch_pcs_fwd<R>(h, r, vhat, stop));
+        return launch_pcs_rest<R>(h, vhat, z, tmp, stop);
+    }
     QH_TRY(launch_pc<R>(h, 0, r, tmp, stop));
     return launch_pc<R>(h, 1, tmp, z, stop);
 }
@@ -848,32 +1335,81 @@ __device__ __forceinline__ void reduce_k(const double* __restrict__ part, int Nt
     for (int k = 0; k < K; k++) out[k] = bc[k];
 }
 
-// One slice per block: scalars from the partials, then the elementwise update.
-template <typename R>
-__global__ __launch_bounds__(256) void k_pcg_upd(Lat lt, PcgBufs<R> B, double* __restrict__ scal, int kpar,
-                                                 int mixed) {
+// One slice per block (dealt to the XCDs as slice_of_block deals them):
+// scalars from the partials, then the elementwise update.
+// DFT: the block then also transforms the new r of its slice (both parity
+// planes, through LDS) into vhat, the first step of the spectral P r; vhat
+// may be u itself, whose slice only this block reads.
+// Latency: the slot, this block's share of the partials and the vectors of
+// the thread's first kUpdPre sites are all requested before any of them is
+// waited for (one round trip to memory instead of three in a row).
+static constexpr int kUpdPre = 4;
+
+template <typename R, bool DFT>
+__global__ __launch_bounds__(1024) void k_pcg_upd(Lat lt, PcgBufs<R> B, double* __restrict__ scal, int kpar,
+                                                  int mixed, int maxit, PcSpecGeo sg, const cplx<R>* __restrict__ tw,
+                                                  cplx<R>* __restrict__ vhat) {
     __shared__ double red[kNP7 * 16 + 16];
+    extern __shared__ __align__(16) unsigned char smem[];
+    cplx<R>* buf = reinterpret_cast<cplx<R>*>(smem);  // [plane][row][column]: the new r by x parity
+    cplx<R>* twx = buf + (DFT ? 2 * sg.nk : 0);
     const double* sin_ = scal + S_NSLOT * kpar;
     double* sout = scal + S_NSLOT * (kpar ^ 1);
-    if (sin_[S_DONE] != 0.0) {
+    const int tau = slice_of_block(blockIdx.x, lt.Nt);
+    const size_t base = (size_t)(tau < 0 ? 0 : tau) * lt.Vs;
+    // requests, all in flight together: the vectors first (the partials'
+    // loop waits inside)
+    cplx<R> p0[kUpdPre], u0[kUpdPre], s0[kUpdPre], w0[kUpdPre], r0[kUpdPre];
+    cplx<double> x0[kUpdPre];
+#pragma unroll
+    for (int j = 0; j < kUpdPre; j++) {
+        const int k = (int)threadIdx.x + j * (int)blockDim.x;
+        const size_t i = base + (k < lt.Vs ? k : 0);
+        p0[j] = B.p[i];
+        u0[j] = B.u[i];
+        s0[j] = B.s[i];
+        w0[j] = B.w[i];
+        r0[j] = B.r[i];
+        x0[j] = B.x[i];
+    }
+    const int ntw = DFT ? sg.Lh + sg.L : 0;  // <= blockDim.x (spec_fits)
+    const cplx<R> twv = (int)threadIdx.x < ntw ? tw[threadIdx.x] : mk<R>(R(0), R(0));
+    double sl[S_NSLOT];
+#pragma unroll
+    for (int k = 0; k < S_NSLOT; k++) sl[k] = sin_[k];
+    double pv[kNP7];
+#pragma unroll
+    for (int k = 0; k < kNP7; k++) pv[k] = 0.0;
+    for (int t = threadIdx.x; t < B.nparts; t += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < kNP7; k++) pv[k] += B.part[kNP7 * t + k];
+    if (sl[S_DONE] != 0.0) {
         if (blockIdx.x == 0 && threadIdx.x < S_NSLOT) sout[threadIdx.x] = sin_[threadIdx.x];
         return;
     }
     double pr[kNP7];
-    reduce_k<kNP7>(B.part, B.nparts, red, red + kNP7 * 16, pr);
+    block_sumk<kNP7>(pv, red);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < kNP7; k++) red[kNP7 * 16 + k] = pv[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kNP7; k++) pr[k] = red[kNP7 * 16 + k];
     const double rr = pr[0], gam = pr[1], del = pr[2];
-    const int it = (int)sin_[S_ITERS];
+    const int it = (int)sl[S_ITERS];
     int stop = 0;
     double alpha = 0.0, beta = 0.0;
-    const bool first = sin_[S_FIRST] != 0.0;
+    const bool first = sl[S_FIRST] != 0.0;
     if (!isfinite(rr) || !isfinite(gam) || !isfinite(del))
         stop = 4;
-    else if (rr <= sin_[S_TARGET])
+    else if (rr <= sl[S_TARGET])
         stop = 1;
-    else if (mixed && (rr <= kDecade2 * sin_[S_RRUPD] || it - (int)sin_[S_ITUPD] >= kCap))
+    else if (it >= maxit)
+        stop = 2;  // the budget is used: the update decides
+    else if (mixed && (rr <= kDecade2 * sl[S_RRUPD] || it - (int)sl[S_ITUPD] >= kCap))
         stop = 2;
     else {
-        beta = first ? 0.0 : gam / sin_[S_GPREV];
+        beta = first ? 0.0 : gam / sl[S_GPREV];
         const double den = first ? del : del + beta * (pr[3] + pr[4]) + beta * beta * pr[5];
         if (!(den > 0.0))
             stop = 3;
@@ -894,20 +1430,38 @@ __global__ __launch_bounds__(256) void k_pcg_upd(Lat lt, PcgBufs<R> B, double* _
         }
         sout[threadIdx.x] = v;
     }
-    if (stop) return;
+    if (stop || tau < 0) return;
+    if (DFT && (int)threadIdx.x < ntw) twx[threadIdx.x] = twv;
     const R a = (R)alpha, b = (R)beta;
-    const size_t base = (size_t)blockIdx.x * lt.Vs;
-    for (int k = threadIdx.x; k < lt.Vs; k += blockDim.x) {
+    auto update = [&](int k, cplx<R> pk, cplx<R> uk, cplx<R> sk, cplx<R> wk, cplx<R> rk, cplx<double> xv) {
         const size_t i = base + k;
-        const cplx<R> pn = cfma(b, B.p[i], B.u[i]);
-        const cplx<R> sn = cfma(b, B.s[i], B.w[i]);
+        const cplx<R> pn = cfma(b, pk, uk);
+        const cplx<R> sn = cfma(b, sk, wk);
         B.p[i] = pn;
         B.s[i] = sn;
-        cplx<double> xv = B.x[i];
         xv.re += alpha * (double)pn.re;
         xv.im += alpha * (double)pn.im;
         B.x[i] = xv;
-        B.r[i] = cfma(-a, sn, B.r[i]);
+        const cplx<R> rn = cfma(-a, sn, rk);
+        B.r[i] = rn;
+        if (DFT) {
+            const int y = k / sg.L, x = k - y * sg.L;
+            buf[(x & 1) * sg.nk + y * sg.Lh + (x >> 1)] = rn;
+        }
+    };
+#pragma unroll
+    for (int j = 0; j < kUpdPre; j++) {
+        const int k = (int)threadIdx.x + j * (int)blockDim.x;
+        if (k < lt.Vs) update(k, p0[j], u0[j], s0[j], w0[j], r0[j], x0[j]);
+    }
+    for (int k = (int)threadIdx.x + kUpdPre * (int)blockDim.x; k < lt.Vs; k += blockDim.x) {
+        const size_t i = base + k;
+        update(k, B.p[i], B.u[i], B.s[i], B.w[i], B.r[i], B.x[i]);
+    }
+    if (DFT) {
+        __syncthreads();
+        dft_planes<R>(buf, twx, twx + sg.Lh, sg.L, sg.Lh, 2,
+                      [&](int pl, int e, cplx<R> v) { vhat[base + (size_t)pl * sg.nk + e] = v; });
     }
 }
 
@@ -915,7 +1469,9 @@ __global__ __launch_bounds__(256) void k_pcg_upd(Lat lt, PcgBufs<R> B, double* _
 template <typename R, int MC, int NB, int BS>
 __global__ __launch_bounds__(BS) void k_pcg_mv(Lat lt, PcgBufs<R> B, const cplx<R>* __restrict__ gauge, Coef<R> co,
                                                const double* __restrict__ stop) {
-    if (stop && *stop != 0.0) return;
+    // the flag is requested with the slice's data and tested once both are
+    // in flight (a no-op launch costs one round trip, a live one no extra)
+    const double stopv = stop ? *stop : 0.0;
     extern __shared__ __align__(16) unsigned char smem[];
     cplx<R>* buf2 = reinterpret_cast<cplx<R>*>(smem);
     double* red = reinterpret_cast<double*>(smem + (size_t)NB * 2 * lt.Vs * sizeof(cplx<R>));
@@ -931,6 +1487,7 @@ __global__ __launch_bounds__(BS) void k_pcg_mv(Lat lt, PcgBufs<R> B, const cplx<
     load_cells<R, MC>(um, B.u + c.tm * Vs, c.g, c.own);
     load_cells<R, MC>(ut, B.u + c.tau * Vs, c.g, c.own);
     load_cells<R, MC>(un, B.u + c.tp * Vs, c.g, c.own);
+    if (stopv != 0.0) return;
     mdagm_cells<R, MC, NB>(um, ut, un, hm, ht, c.g, c.own, co, c.tau == 0 ? R(-1) : R(1),
                            c.tau == lt.Nt - 1 ? R(-1) : R(1), buf2, lt.Vs, w);
     store_cells<R, MC>(w, B.w + c.tau * Vs, c.g, c.own);
@@ -950,9 +1507,12 @@ __global__ __launch_bounds__(BS) void k_pcg_mv(Lat lt, PcgBufs<R> B, const cplx<
         for (int k = 0; k < kNP7; k++) B.part[kNP7 * (size_t)c.tau + k] = v[k];
 }
 
-// r = rhs - O x from the FP64 O x; partb = FP64 |rhs - O x|^2 per slice
+// r = rhs - O x from the FP64 O x; partb = FP64 |rhs - O x|^2 per slice.
+// gate (nullable): a slot's stop flag; the launch is a no-op unless it asks
+// for a reliable update.
 template <typename R>
-__global__ __launch_bounds__(256) void k_pcg_rep(Lat lt, PcgBufs<R> B) {
+__global__ __launch_bounds__(256) void k_pcg_rep(Lat lt, PcgBufs<R> B, const double* __restrict__ gate) {
+    if (gate && !gate_open(*gate)) return;
     __shared__ double red[64];
     const size_t base = (size_t)blockIdx.x * lt.Vs;
     double t2 = 0.0;
@@ -987,6 +1547,78 @@ __global__ void k_pcg_check(double* __restrict__ scal, int kpar, const double* _
             sl[S_ITUPD] = sl[S_ITERS];
             sl[S_RRUPD] = v[1];
         }
+    }
+}
+
+// skip = 0 when the slot's flag asks for a reliable update, else 1: the stop
+// flag of the gated preconditioner and matvec of the update
+__global__ void k_pcg_gate(const double* __restrict__ flag, double* __restrict__ skip) {
+    if (threadIdx.x == 0) *skip = gate_open(*flag) ? 0.0 : 1.0;
+}
+
+// The reliable-update decision on the device (pipelined driver), after the
+// gated replacement: converged (5) when the FP64 true residual meets the
+// target; failed (4) on a non-finite residual, the iteration budget used or
+// no progress across three updates, or a breakdown flagged by the recursion;
+// otherwise resume (0; restart with beta = 0 after a non-positive
+// denominator, and after every update with restart_all).  A solve already
+// final is left as it is.  The record is mirrored to out (pinned host
+// memory).
+__global__ void k_pcg_check_dev(double* __restrict__ scal, int kpar, const double* __restrict__ part, int nparts,
+                                const double* __restrict__ partb, int Nt, int maxit, int restart_all,
+                                double* __restrict__ rec, double* __restrict__ out) {
+    __shared__ double red[64];
+    double* sl = scal + S_NSLOT * kpar;
+    const double done = sl[S_DONE];
+    const int it = (int)sl[S_ITERS];
+    int nd = -1, why = 0;
+    double est = sl[S_GCUR];
+    if (done == 4.0 && rec[CR_DONE] != 4.0) {
+        nd = 4;
+        why = WHY_BREAKDOWN;
+    }
+    if (gate_open(done)) {
+        double v[2] = {0.0, 0.0};
+        for (int t = threadIdx.x; t < Nt; t += blockDim.x) v[0] += partb[t];
+        for (int t = threadIdx.x; t < nparts; t += blockDim.x) v[1] += part[kNP7 * t];
+        block_sumk<2>(v, red);
+        if (threadIdx.x == 0) {
+            const double tr = v[0];
+            const int stall = (it + 1 == (int)sl[S_LASTUP]) ? (int)sl[S_STALL] + 1 : 0;
+            sl[S_STALL] = stall;
+            sl[S_LASTUP] = it + 1;
+            sl[S_NREL] += 1.0;
+            sl[S_TRUE] = tr;
+            est = tr;
+            if (!isfinite(tr)) {
+                nd = 4;
+                why = WHY_NONFINITE;
+            } else if (tr <= sl[S_TARGET]) {
+                nd = 5;
+            } else if (it >= maxit || stall >= 3) {
+                nd = 4;
+                why = it >= maxit ? WHY_BUDGET : WHY_STALL;
+            } else {
+                nd = 0;
+                if (restart_all || done == 3.0) sl[S_FIRST] = 1.0;
+                sl[S_ITUPD] = it;
+                sl[S_RRUPD] = v[1];
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
+        rec[CR_ITERS] = it;
+        rec[CR_B2] = sl[S_B2];
+        rec[CR_EST] = est;
+        if (nd >= 0) {
+            sl[S_DONE] = nd;
+            rec[CR_TRUE] = sl[S_TRUE];
+            rec[CR_NREL] = sl[S_NREL];
+            rec[CR_DONE] = nd;
+            rec[CR_WHY] = why;
+        }
+#pragma unroll
+        for (int k = 0; k < CR_N; k++) out[k] = rec[k];
     }
 }
 
@@ -1048,13 +1680,37 @@ static qedhmc_status pcg_tail(qedhmc_ctx* h, const PcgBufs<R>& B, const double* 
 
 // n iterations from launch parity kpar: update, then preconditioner and
 // matvec, each gated on the slot's stop flag
+// Spectral P with the update kernel doing its first step: the plan's
+// threads and LDS for both planes of a slice, or false where it does not fit
 template <typename R>
-static qedhmc_status pcg_chunk(qedhmc_ctx* h, const PcgBufs<R>& B, int kpar, int n, bool mixed, bool identity) {
+static bool upd_dft_plan(qedhmc_ctx* h, int& threads, size_t& lds) {
+    return use_spectral(h) && spec_fits<R>(h, 2, threads, lds);
+}
+
+template <typename R>
+static qedhmc_status pcg_chunk(qedhmc_ctx* h, const PcgBufs<R>& B, int kpar, int n, bool mixed, bool identity,
+                               int maxit) {
+    int threads = 256;
+    size_t lds = 0;
+    const bool fdft = !identity && upd_dft_plan<R>(h, threads, lds);
+    if (fdft && lds > 65536) QH_TRY(allow_lds((const void*)k_pcg_upd<R, true>, h->max_lds));
+    const PcSpecGeo sg = fdft ? spec_geo<R>(h) : PcSpecGeo{};
+    cplx<R>* vhat = fdft ? spec_vhat<R>(h, B.u, B.t) : nullptr;
     for (int k = 0; k < n; k++) {
-        hipLaunchKernelGGL(k_pcg_upd<R>, dim3(h->lat.Nt), dim3(256), 0, h->stream, h->lat, B, h->scal, kpar,
-                           mixed ? 1 : 0);
+        if (fdft)
+            hipLaunchKernelGGL((k_pcg_upd<R, true>), dim3(slice_grid(h->lat.Nt)), dim3(threads), lds, h->stream, h->lat, B, h->scal,
+                               kpar, mixed ? 1 : 0, maxit, sg, spec_tw<R>(h), vhat);
+        else
+            hipLaunchKernelGGL((k_pcg_upd<R, false>), dim3(slice_grid(h->lat.Nt)), dim3(256), 0, h->stream, h->lat, B, h->scal,
+                               kpar, mixed ? 1 : 0, maxit, sg, (const cplx<R>*)nullptr, (cplx<R>*)nullptr);
         kpar ^= 1;
-        QH_TRY(pcg_tail<R>(h, B, h->scal + S_NSLOT * kpar + S_DONE, identity));
+        const double* stop = h->scal + S_NSLOT * kpar + S_DONE;
+        if (fdft) {
+            QH_TRY(launch_pcs_rest<R>(h, vhat, B.u, B.t, stop));
+            QH_TRY(launch_mv<R>(h, B, stop, true));
+        } else {
+            QH_TRY(pcg_tail<R>(h, B, stop, identity));
+        }
     }
     QH_HIP(hipGetLastError());
     return QEDHMC_OK;
@@ -1065,9 +1721,12 @@ static qedhmc_status pcg_chunk(qedhmc_ctx* h, const PcgBufs<R>& B, int kpar, int
 // shapes (and kernel attributes) are those of the solve's first matvec,
 // made before any capture.
 template <typename R>
-static qedhmc_status pcg_chunk_graph(qedhmc_ctx* h, const PcgBufs<R>& B, int kpar, int n, bool mixed, bool identity) {
+static qedhmc_status pcg_chunk_graph(qedhmc_ctx* h, const PcgBufs<R>& B, int kpar, int n, bool mixed, bool identity,
+                                     int maxit) {
     qedhmc_ctx::PcgGraph& gr = h->pcg_graph[sizeof(R) == 8 ? 1 : 0][identity ? 1 : 0][kpar];
-    if (gr.exec && (gr.x != B.x || gr.rhs != B.rhs || gr.mixed != (int)mixed || gr.count != n)) {
+    const int plan = identity ? 0 : (use_spectral(h) ? 1 : 0) | (spec_fused(h) ? 2 : 0);
+    if (gr.exec && (gr.x != B.x || gr.rhs != B.rhs || gr.mixed != (int)mixed || gr.count != n || gr.plan != plan ||
+                    gr.maxit != maxit)) {
         QH_HIP(hipGraphExecDestroy(gr.exec));
         gr.exec = nullptr;
     }
@@ -1081,7 +1740,7 @@ static qedhmc_status pcg_chunk_graph(qedhmc_ctx* h, const PcgBufs<R>& B, int kpa
         qedhmc_status st = QEDHMC_OK;
         hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            st = pcg_chunk<R>(h, B, kpar, n, mixed, identity);
+            st = pcg_chunk<R>(h, B, kpar, n, mixed, identity, maxit);
             e = hipStreamEndCapture(h->cap_stream, &g);
         }
         h->stream = user;
@@ -1098,9 +1757,172 @@ static qedhmc_status pcg_chunk_graph(qedhmc_ctx* h, const PcgBufs<R>& B, int kpa
         gr.rhs = B.rhs;
         gr.mixed = mixed ? 1 : 0;
         gr.count = n;
+        gr.plan = plan;
+        gr.maxit = maxit;
     }
     QH_HIP(hipGraphLaunch(gr.exec, h->stream));
     return QEDHMC_OK;
+}
+
+// One round of the pipelined PCG from launch parity kp: the chunk of n
+// iterations (the mixed recursion pauses itself for a reliable update at a
+// decade or after kCap iterations; FP64 pauses only to stop or restart, or
+// at the budget), then the replacement gated on a pause in slot ke (FP64
+// O x, r = rhs - O x, s = O p, u = P r, w = O u and the partials) and the
+// decision, which mirrors the solve's record to out (pinned host memory).
+template <typename R>
+static qedhmc_status pcg_round(qedhmc_ctx* h, const PcgBufs<R>& B, double* x, int kp, int n, bool mixed, int maxit,
+                               double* out) {
+    const int ke = kp ^ (n & 1);
+    double* skip = h->scal + kRecOff - 4;  // between the two slots and the record
+    QH_TRY(pcg_chunk<R>(h, B, kp, n, mixed, false, maxit));
+    const double* gate = h->scal + S_NSLOT * ke + S_DONE;
+    QH_TRY(launch_mdagm(h, QEDHMC_FP64, x, h->ws[3], gate));
+    hipLaunchKernelGGL(k_pcg_rep<R>, dim3(h->lat.Nt), dim3(256), 0, h->stream, h->lat, B, gate);
+    QH_HIP(hipGetLastError());
+    QH_TRY(launch_mdagm(h, mixed ? QEDHMC_FP32 : QEDHMC_FP64, B.p, B.s, gate));
+    hipLaunchKernelGGL(k_pcg_gate, dim3(1), dim3(64), 0, h->stream, gate, skip);
+    QH_HIP(hipGetLastError());
+    QH_TRY(pcg_tail<R>(h, B, skip, false));
+    hipLaunchKernelGGL(k_pcg_check_dev, dim3(1), dim3(256), 0, h->stream, h->scal, ke, (const double*)B.part,
+                       B.nparts, (const double*)B.partb, h->lat.Nt, maxit, mixed ? 0 : 1, h->scal + kRecOff, out);
+    QH_HIP(hipGetLastError());
+    return QEDHMC_OK;
+}
+
+// The same round replayed from a graph captured the first time this
+// (buffers, mode, round parity) combination is seen on the handle (every
+// kernel attribute was set by an eager round before).
+template <typename R>
+static qedhmc_status pcg_round_graph(qedhmc_ctx* h, const PcgBufs<R>& B, double* x, int kp, int n, bool mixed,
+                                     int maxit, int par, double* out) {
+    qedhmc_ctx::PcgGraph& gr = h->pcg_round[sizeof(R) == 8 ? 1 : 0][par];
+    const int plan = (use_spectral(h) ? 1 : 0) | (spec_fused(h) ? 2 : 0);
+    if (gr.exec && (gr.x != x || gr.rhs != B.rhs || gr.mixed != (int)mixed || gr.count != n || gr.plan != plan ||
+                    gr.maxit != maxit || gr.kp != kp)) {
+        QH_HIP(hipGraphExecDestroy(gr.exec));
+        gr.exec = nullptr;
+    }
+    if (!gr.exec) {
+        if (!h->cap_stream) QH_HIP(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+        hipStream_t user = h->stream;
+        const int prof = h->prof_every;
+        h->stream = h->cap_stream;
+        h->prof_every = 0;  // no event launches inside a graph
+        hipGraph_t g = nullptr;
+        qedhmc_status st = QEDHMC_OK;
+        hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            st = pcg_round<R>(h, B, x, kp, n, mixed, maxit, out);
+            e = hipStreamEndCapture(h->cap_stream, &g);
+        }
+        h->stream = user;
+        h->prof_every = prof;
+        if (st != QEDHMC_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        QH_HIP(e);
+        e = hipGraphInstantiate(&gr.exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        QH_HIP(e);
+        gr.x = x;
+        gr.rhs = B.rhs;
+        gr.mixed = mixed ? 1 : 0;
+        gr.count = n;
+        gr.plan = plan;
+        gr.maxit = maxit;
+        gr.kp = kp;
+    }
+    QH_HIP(hipGraphLaunch(gr.exec, h->stream));
+    return QEDHMC_OK;
+}
+
+// iterations per round of the mixed pipelined PCG: odd (so the launch parity
+// alternates with the round parity) and shorter than the kCap + 1 of the
+// unpreconditioned solver, since the paper's preconditioner reaches a decade,
+// and with it a pause, within about 30 iterations (the launches of a round
+// past its pause are no-ops).  QEDHMC_PCG_CHUNK (read per solve, made odd)
+// overrides.
+static constexpr int kPcgChunk = 17;
+
+// Rounds queued on the device as in the pipelined CG: the host keeps the
+// next round queued behind the running one and reads each round's record
+// through an event; the round after the last is skipped when the residual
+// estimates of the last two rounds, extrapolated geometrically, say the
+// running round converges.  Rounds after the first replay a captured graph.
+// Whole-slice lattices (the gated M^dag M has no tiled form).
+template <typename R>
+static qedhmc_status pcg_pipelined(qedhmc_ctx* h, const PcgBufs<R>& B, double* x, double tol, int maxit,
+                                   qedhmc_precision prec, int* iters, double* true_rel, int* n_reliable) {
+    const bool mixed = prec != QEDHMC_FP64;
+    int chunk = mixed ? kPcgChunk : 64;
+    if (const char* ec = std::getenv("QEDHMC_PCG_CHUNK"); ec && mixed && std::atoi(ec) > 0)
+        chunk = std::atoi(ec) | 1;
+    const int Nt = h->lat.Nt;
+    for (auto& e : h->cg_ev)
+        if (!e) QH_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    hipLaunchKernelGGL(k_pcg_start<R>, dim3(Nt), dim3(256), 0, h->stream, h->lat, B);
+    hipLaunchKernelGGL(k_pcg_init_slot, dim3(1), dim3(256), 0, h->stream, h->scal, (const double*)B.partb, Nt,
+                       tol * tol);
+    QH_HIP(hipGetLastError());
+    QH_TRY(pcg_tail<R>(h, B, nullptr, false));
+    QH_HIP(hipMemsetAsync(h->scal + kRecOff, 0, CR_N * sizeof(double), h->stream));
+    auto round = [&](long n) -> qedhmc_status {
+        const int kp = (chunk & 1) ? (int)(n & 1) : 0, par = (int)(n & 1);
+        double* out = h->h_pinned + 32 + 16 * par;
+        if (n == 0)
+            QH_TRY(pcg_round<R>(h, B, x, kp, chunk, mixed, maxit, out));
+        else
+            QH_TRY(pcg_round_graph<R>(h, B, x, kp, chunk, mixed, maxit, par, out));
+        QH_HIP(hipEventRecord(h->cg_ev[par], h->stream));
+        return QEDHMC_OK;
+    };
+    // every round that does not end the solve advances the iteration count
+    // or the count of updates without progress, which ends it at 3
+    const long max_rounds = 4L * maxit + 16;
+    long queued = 0;
+    double prev = -1.0;
+    const double* r = nullptr;
+    QH_TRY(round(queued++));
+    QH_TRY(round(queued++));
+    for (long n = 0;; n++) {
+        // queued: round n, and rounds n + 1 and n + 2 unless held back
+        QH_HIP(hipEventSynchronize(h->cg_ev[n & 1]));
+        r = h->h_pinned + 32 + 16 * (n & 1);
+        if (r[CR_DONE] == 4.0 || r[CR_DONE] == 5.0) break;
+        if (n + 2 >= max_rounds) {
+            QH_HIP(hipStreamSynchronize(h->stream));
+            set_error("PCG did not end within " + std::to_string(max_rounds) + " rounds");
+            return QEDHMC_ENOCONV;
+        }
+        if (queued < n + 2) QH_TRY(round(queued++));  // round n + 1 was held back wrongly
+        const double tr = r[CR_EST], target = tol * tol * r[CR_B2];
+        const bool last = prev > 0.0 && tr > 0.0 && tr * (tr / prev) <= target;
+        prev = tr;
+        if (!last && queued < n + 3) QH_TRY(round(queued++));
+    }
+    QH_HIP(hipStreamSynchronize(h->stream));  // a round queued past the end runs as no-ops
+    const int it = (int)r[CR_ITERS];
+    const double b2 = r[CR_B2], rel = b2 > 0.0 ? std::sqrt(r[CR_TRUE] / b2) : 0.0;
+    if (iters) *iters = it;
+    if (true_rel) *true_rel = rel;
+    if (n_reliable) *n_reliable = (int)r[CR_NREL];
+    if (r[CR_DONE] == 5.0) return QEDHMC_OK;
+    switch ((int)r[CR_WHY]) {
+        case WHY_BREAKDOWN:
+            set_error("PCG breakdown: non-finite inner products after " + std::to_string(it) + " iterations");
+            break;
+        case WHY_NONFINITE:
+            set_error("PCG breakdown: non-finite true residual after " + std::to_string(it) + " iterations");
+            break;
+        case WHY_STALL:
+            set_error("PCG made no progress across reliable updates at iteration " + std::to_string(it));
+            break;
+        default:
+            break;
+    }
+    return QEDHMC_ENOCONV;
 }
 
 // identity = true: plain CG in the same two-launch form (update, then
@@ -1116,8 +1938,11 @@ static qedhmc_status pcg_t(qedhmc_ctx* h, const double* rhs, double* x, double t
     if (identity) B.u = B.r;
     const int Nt = h->lat.Nt;
     const int chunk = mixed ? kCap + 1 : 64;
-    // QEDHMC_NO_GRAPH (read per solve) launches every chunk directly
+    // QEDHMC_NO_GRAPH (read per solve) launches every chunk directly from the
+    // host-driven loop below
     const bool no_graph = std::getenv("QEDHMC_NO_GRAPH") != nullptr;
+    if (!identity && !no_graph && h->lat.ncell <= 1024)
+        return pcg_pipelined<R>(h, B, x, tol, maxit, prec, iters, true_rel, n_reliable);
     int kpar = 0, nrel = 0, it = 0, stalled = 0, last_it = -1;
     double rel = 1.0;
     bool converged = false, broken = false;
@@ -1130,9 +1955,9 @@ static qedhmc_status pcg_t(qedhmc_ctx* h, const double* rhs, double* x, double t
         const int left = maxit - it;
         const int n = left < chunk ? left : chunk;
         if (n == chunk && !no_graph)
-            QH_TRY(pcg_chunk_graph<R>(h, B, kpar, n, mixed, identity));
+            QH_TRY(pcg_chunk_graph<R>(h, B, kpar, n, mixed, identity, maxit));
         else
-            QH_TRY(pcg_chunk<R>(h, B, kpar, n, mixed, identity));
+            QH_TRY(pcg_chunk<R>(h, B, kpar, n, mixed, identity, maxit));
         if (n & 1) kpar ^= 1;
         QH_TRY(read_slot(h, kpar));
         it = (int)h->h_pinned[S_ITERS];
@@ -1151,7 +1976,7 @@ static qedhmc_status pcg_t(qedhmc_ctx* h, const double* rhs, double* x, double t
         }
         // FP64 true residual; r replaced, s = O p refreshed, u, w and partials recomputed
         QH_TRY(launch_mdagm(h, QEDHMC_FP64, x, h->ws[3], nullptr));
-        hipLaunchKernelGGL(k_pcg_rep<R>, dim3(Nt), dim3(256), 0, h->stream, h->lat, B);
+        hipLaunchKernelGGL(k_pcg_rep<R>, dim3(Nt), dim3(256), 0, h->stream, h->lat, B, (const double*)nullptr);
         QH_HIP(hipGetLastError());
         QH_TRY(launch_mdagm(h, prec == QEDHMC_FP64 ? QEDHMC_FP64 : QEDHMC_FP32, B.p, B.s, nullptr));
         QH_TRY(pcg_tail<R>(h, B, nullptr, identity));

@@ -578,7 +578,13 @@ struct qedhmc_ctx {
         const void* x;
         const void* rhs;
         int mixed, count;
+        int plan;  // the preconditioner's launch plan the graph holds
+        int maxit;
+        int kp;    // launch parity at the start (whole rounds)
     } pcg_graph[2][2][2];
+    // whole pipelined PCG rounds (chunk, gated update, decision) by
+    // precision and round parity
+    PcgGraph pcg_round[2][2];
     // the paper's preconditioner (built on first use)
     bool pc_ready;
     double pc_shift;
@@ -588,6 +594,14 @@ struct qedhmc_ctx {
     void* pc_dev32;
     void* pc_roll64;                  // device taps grouped by spatial offset (RTap), FP64 and FP32
     void* pc_roll32;
+    // the same P as 2x2 blocks per spatial momentum of the two-site cell
+    // (spectral application): H[a][entry][k] and the DFT twiddles, FP64 and
+    // FP32; pc_spec_na = 0 when not built
+    void* pc_spec64;
+    void* pc_spec32;
+    void* pc_tw64;
+    void* pc_tw32;
+    int pc_spec_a0, pc_spec_na;
     // the learned preconditioner (QEDHMC_PC_LEARNED): a network bound to this
     // handle, its arithmetic and the fallback its residual judge hands over to
     qedhmc_net* pc_net;
@@ -638,8 +652,8 @@ qedhmc_status launch_mdagm(qedhmc_ctx* h, qedhmc_precision prec, const void* in,
                            const double* gate = nullptr);
 qedhmc_status launch_force(qedhmc_ctx* h, qedhmc_precision prec, const double* X, double* F);
 // Per-launch host work done once per kernel (api.hip): allow_lds lets kernel
-// k take up to max_lds bytes of dynamic LDS (every caller sets the same
-// value); blocks_per_cu returns the workgroups of `threads` threads and
+// k take up to max_lds bytes of LDS, its static LDS included (every caller
+// sets the same value); blocks_per_cu returns the workgroups of `threads` threads and
 // `lds` bytes one compute unit holds, cached per (kernel, shape).
 qedhmc_status allow_lds(const void* k, size_t max_lds);
 qedhmc_status blocks_per_cu(const void* k, int threads, size_t lds, int* out);

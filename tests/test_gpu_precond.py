@@ -62,18 +62,29 @@ def test_apply_precond_matches_oracle(L, Nt, prec, tol):
     assert _rel(out, PC.apply_P(taps, v)) < tol
 
 
-@pytest.mark.parametrize("L,Nt,ty,tc", [(24, 30, 5, 3), (12, 7, 1, 4), (16, 9, 3, 1), (6, 11, 2, 16), (66, 8, 0, 0)])
+@pytest.mark.parametrize("L,Nt,ty,tc", [(24, 30, 5, 3), (12, 7, 1, 4), (16, 9, 3, 1), (6, 11, 2, 16), (66, 8, 0, 0),
+                                         (8, 5, 0, 0)])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 5e-6)])
-@pytest.mark.parametrize("kernel,q", [("roll", 0), ("roll", 1), ("roll", 3), ("stream", 0)])
+@pytest.mark.parametrize("kernel,q", [("roll", 0), ("roll", 1), ("roll", 3), ("stream", 0), ("spectral", 0),
+                                      ("spectral", 1), ("spectral", 2)])
 def test_apply_precond_forced_plans(L, Nt, ty, tc, prec, tol, kernel, q, monkeypatch):
     """Both stencil kernels (rolled along tau with 1, 3 or the default 4
     lanes per site; streamed per tap) under plans forced through their tuning
     variables: ragged last bands (24 = 5 + 5 + 5 + 5 + 4), one-row bands,
-    one-slice runs, runs longer than N_tau, and the default plan at L = 66."""
+    one-slice runs, runs longer than N_tau, and the default plan at L = 66;
+    and the spectral form (per-momentum 2x2 blocks, banded in tau) at the same
+    shapes: L/2 = 3 cells, N_tau = 7 (the combined tau offsets wrap twice),
+    L = 66, with the tau sum fused into the inverse DFT as planned (q = 0),
+    forced fused (1) or forced separate (2).  At N_tau = 5 a pass's tau reach
+    exceeds N_tau, the spectral form is not built and the stencil takes the
+    call."""
     monkeypatch.setenv("QEDHMC_PC_TY", str(ty))
     monkeypatch.setenv("QEDHMC_PC_TC", str(tc))
     monkeypatch.setenv("QEDHMC_PC_KERNEL", kernel)
-    monkeypatch.setenv("QEDHMC_PC_Q", str(q))
+    if kernel == "spectral":
+        monkeypatch.setenv("QEDHMC_PC_FUSE", {0: "", 1: "1", 2: "0"}[q])
+    else:
+        monkeypatch.setenv("QEDHMC_PC_Q", str(q))
     taps = _oracle_taps()
     v = inputs.gauss_cvec(L, Nt, 41 + L)
     cdt = torch.complex128 if prec == "fp64" else torch.complex64
@@ -82,9 +93,18 @@ def test_apply_precond_forced_plans(L, Nt, ty, tc, prec, tol, kernel, q, monkeyp
     assert _rel(out, PC.apply_P(taps, v)) < tol
 
 
+_PLANS = {"spectral": {}, "spectral_separate": {"QEDHMC_PC_FUSE": "0"}, "stencil": {"QEDHMC_PC_KERNEL": "stream"}}
+
+
 @pytest.mark.parametrize("which", ["pi", "noisy", "hot"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_pcg_small_vs_oracle(which, prec):
+@pytest.mark.parametrize("plan", list(_PLANS))
+def test_pcg_small_vs_oracle(which, prec, plan, monkeypatch):
+    """PCG with P applied in spectral form (the update kernel transforming r,
+    then the tau sum fused into the inverse DFT, or separate, in which case
+    the transform lands in u itself) and as the per-tap stencil."""
+    for k, v in _PLANS[plan].items():
+        monkeypatch.setenv(k, v)
     L, Nt = 8, 40
     p = O.lat(L, Nt)
     th = {"pi": inputs.pi_flux_theta(L, Nt), "noisy": inputs.noisy_pi_flux_theta(L, Nt, 0.3, 5),
