@@ -46,6 +46,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# vector ALU peaks of the MI355X (256 CUs x 2.4 GHz): FP32 with packed
+# instructions 157.3 TFLOP/s (the library builds without them, so half of it
+# is the reachable rate), FP64 78.6 TFLOP/s
+VALU_PEAK_FP32_TFLOPS = 157.3
+VALU_PEAK_FP64_TFLOPS = 78.6
 
 # HBM bytes per launch of the fused CG iteration from rocprofv3 counters
 # (profiles/k_cg_iter_mixed_l24_hbm_counters.md): FETCH_SIZE and WRITE_SIZE in
@@ -61,8 +66,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="mixed_l24")
     ap.add_argument("--prec", default=None, help="override: fp64 or mixed")
-    ap.add_argument("--precond", default="none", choices=["none", "paper", "learned"],
-                    help="preconditioner of the timed path: none, the paper's G^dag G stencil, or the "
+    ap.add_argument("--precond", default="paper", choices=["none", "paper", "learned"],
+                    help="preconditioner of the timed path: the paper's G^dag G (default), none, or the "
                          "learned network (trained at setup on the method's own residuals)")
     ap.add_argument("--equilibrate", type=int, default=10,
                     help="chained trajectories from the workload's angles before the timed set (untimed)")
@@ -219,20 +224,28 @@ def run_solve_only(a):
                                      "matvec_launches": 200}}), flush=True)
 
 
-def cpu_baseline(wl, th, total_cg_iters, n_solves, n_iter):
+def cpu_baseline(wl, th, total_cg_iters, n_solves, n_iter, pc=None):
     """Oracle (plain FP64 C, single thread) on a bounded sample of the same
-    workload: n_iter CG iterations and one fermion force at the same lattice
-    and angles (the timed trajectories' start), scaled to the trajectory's
-    CG iteration and solve counts.  The oracle is single-threaded: a
-    trajectory is a sequence of dependent solves and the oracle's CG runs on
-    one core."""
+    workload: n_iter CG iterations (PCG with the oracle's own G^dag G when
+    the timed path uses the paper's preconditioner, whose stencil build is
+    not counted) and one fermion force at the same lattice and angles (the
+    timed trajectories' start), scaled to the trajectory's CG iteration and
+    solve counts.  The oracle is single-threaded: a trajectory is a sequence
+    of dependent solves and the oracle's CG runs on one core."""
     import oracle as O
     from paper_2508_16298_amd import inputs
     p = O.lat(wl.L, wl.Nt, wl.dtau, wl.t, wl.J, wl.K)
     R = inputs.gauss_cvec(wl.L, wl.Nt, wl.seed + 1)
     eta = O.apply_M(p, th, R, dagger=True)
+    precond, kind = None, "CG"
+    if pc == "paper":
+        from oracle import precond as PC
+        taps = PC.build_stencil(8, 24)[0]
+        shape = (wl.Nt, wl.L, wl.L)
+        precond, kind = (lambda r: PC.apply_P(taps, r.reshape(shape)).reshape(-1)), "PCG (G^dag G)"
+        n_iter = max(4, n_iter // 40)
     t0 = time.perf_counter()
-    X, st, it, rel = O.cg_solve(p, th, eta, tol=1e-30, maxit=n_iter)
+    X, st, it, rel = O.cg_solve(p, th, eta, tol=1e-30, maxit=n_iter, precond=precond)
     t_cg = time.perf_counter() - t0
     t0 = time.perf_counter()
     O.fermion_force(p, th, X)
@@ -244,7 +257,7 @@ def cpu_baseline(wl, th, total_cg_iters, n_solves, n_iter):
     return {
         "value": est, "unit": "s/trajectory", "cores": 1, "kind": "oracle", "host": hi,
         "s_per_cg_iter": per_iter,
-        "sample": (f"oracle FP64 CG, {it} iterations ({t_cg:.1f} s) + one fermion and gauge force "
+        "sample": (f"oracle FP64 {kind}, {it} iterations ({t_cg:.1f} s) + one fermion and gauge force "
                    f"({t_force:.2f} s) at L={wl.L} Nt={wl.Nt}, the timed trajectories' start angles; scaled to "
                    f"the GPU trajectory's {total_cg_iters:.0f} CG iterations and {n_solves} forces "
                    f"(extrapolation, single thread; host {hi['nproc']} cores, {hi['cpu_model']})"),
@@ -786,7 +799,8 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = {c: lat.profile_read(c) for c in (Q.K_CG_FP32, Q.K_CG_FP64, Q.K_NET_MFMA, Q.K_MDAGM_FP32,
-                                             Q.K_MDAGM_FP64, Q.K_PCG_MV_FP32, Q.K_PCG_MV_FP64)}
+                                             Q.K_MDAGM_FP64, Q.K_PCG_MV_FP32, Q.K_PCG_MV_FP64,
+                                             Q.K_PC_SPEC_FP32, Q.K_PC_SPEC_FP64)}
     lat.profile(0)
 
     # (4) the same trajectories (same start, same indices) on the other
@@ -860,9 +874,16 @@ def main():
         kcls, work, unit, bound, peak, kname = (Q.K_NET_MFMA, 2.0 * 27 * 32 * 32 * N, "TFLOP/s", "mfma", 2500.0,
                                                 "k_conv_mfma<true> (one 32->32 3x3x3 layer, BF16 MFMA)")
     elif pc == "paper":
-        kcls = Q.K_PCG_MV_FP32 if prec != "fp64" else Q.K_PCG_MV_FP64
-        work, unit, bound, peak = (24 if prec != "fp64" else 48) * N, "GB/s", "hbm", HBM_PEAK_GBS
-        kname = "k_mdagm (M^dag M of the preconditioned CG, 24 / 48 B per site counted)"
+        # the largest of the PCG iteration's three kernels: the tau sum over
+        # 13 offsets (2 x 2 blocks: 26 complex FMAs per site) and the inverse
+        # DFT (L/2 + L complex FMAs per site), 8 flops per complex FMA;
+        # 31 flops per algorithmic HBM byte (16 B per site), so vector-ALU
+        # bound by the roofline
+        kcls = Q.K_PC_SPEC_FP32 if prec != "fp64" else Q.K_PC_SPEC_FP64
+        work = 8.0 * (2 * 13 + wl.L // 2 + wl.L) * N
+        unit, bound, peak = "TFLOP/s", "alu", (VALU_PEAK_FP32_TFLOPS if prec != "fp64" else VALU_PEAK_FP64_TFLOPS)
+        kname = (f"k_pcs_tconv_idft<{'float' if prec != 'fp64' else 'double'}> (spectral paper preconditioner: "
+                 f"tau sum + inverse 2D DFT)")
     else:
         kcls = Q.K_CG_FP32 if prec != "fp64" else Q.K_CG_FP64
         work, unit, bound, peak = (104 if prec != "fp64" else 176) * N, "GB/s", "hbm", HBM_PEAK_GBS
@@ -937,7 +958,7 @@ def main():
     lat.close()
     out["matvec_large"] = matvec_large()
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, th_start.cpu().numpy(), cg_all / a.steps, n_solves, a.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(wl, th_start.cpu().numpy(), cg_all / a.steps, n_solves, a.cpu_iters, pc)
     print(json.dumps(out), flush=True)
 
 

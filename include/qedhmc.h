@@ -569,7 +569,9 @@ typedef enum {
     QEDHMC_K_PCG_MV_FP64 = 6,  /* the same, FP64 */
     QEDHMC_K_NET_MFMA = 7,     /* one 32 -> 32 network layer, BF16 MFMA */
     QEDHMC_K_NET_FP32 = 8,     /* one 32 -> 32 network layer, FP32 */
-    QEDHMC_K_COUNT = 9
+    QEDHMC_K_PC_SPEC_FP32 = 9, /* tau sum + inverse DFT of the spectral paper preconditioner, FP32 */
+    QEDHMC_K_PC_SPEC_FP64 = 10,/* the same, FP64 */
+    QEDHMC_K_COUNT = 11
 } qedhmc_kernel_class;
 
 qedhmc_status qedhmc_profile(qedhmc_t h, int32_t every);

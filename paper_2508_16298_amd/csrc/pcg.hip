@@ -1039,7 +1039,7 @@ __global__ __launch_bounds__(1024) void k_pcs_tconv_idft(PcSpecGeo g, const cplx
                                                          const cplx<R>* __restrict__ tw,
                                                          const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
                                                          const double* __restrict__ stop) {
-    const double stopv = stop ? *stop : 0.0;  // tested once the data below is in flight
+    if (stop && *stop != 0.0) return;
     extern __shared__ __align__(16) unsigned char smem[];
     const int L = g.L, Lh = g.Lh, n = g.nk;
     cplx<R>* buf = reinterpret_cast<cplx<R>*>(smem);
@@ -1086,7 +1086,6 @@ __global__ __launch_bounds__(1024) void k_pcs_tconv_idft(PcSpecGeo g, const cplx
     };
     const int e0 = threadIdx.x;
     fetch(e0 < n ? e0 : 0);
-    if (stopv != 0.0) return;
     if (e0 < ntw) {
         twx[e0] = mk<R>(twv.re, -twv.im);  // inverse twiddles
     }
@@ -1191,8 +1190,13 @@ static qedhmc_status launch_pcs_rest(qedhmc_ctx* h, const cplx<R>* vhat, cplx<R>
     const dim3 dgrid(spec_grid(g.Nt));
     if (spec_fused(h)) {
         if (lds > 65536) QH_TRY(allow_lds((const void*)k_pcs_tconv_idft<R>, h->max_lds));
-        hipLaunchKernelGGL(k_pcs_tconv_idft<R>, dgrid, dim3(threads), lds, h->stream, g, spec_H<R>(h), spec_tw<R>(h),
-                           vhat, z, stop);
+        hipEvent_t e0, e1;
+        if (prof_sample(h, sizeof(R) == 4 ? QEDHMC_K_PC_SPEC_FP32 : QEDHMC_K_PC_SPEC_FP64, e0, e1))
+            hipExtLaunchKernelGGL(k_pcs_tconv_idft<R>, dgrid, dim3(threads), lds, h->stream, e0, e1, 0, g,
+                                  spec_H<R>(h), spec_tw<R>(h), vhat, z, stop);
+        else
+            hipLaunchKernelGGL(k_pcs_tconv_idft<R>, dgrid, dim3(threads), lds, h->stream, g, spec_H<R>(h),
+                               spec_tw<R>(h), vhat, z, stop);
         QH_HIP(hipGetLastError());
         return QEDHMC_OK;
     }
@@ -1340,9 +1344,9 @@ __device__ __forceinline__ void reduce_k(const double* __restrict__ part, int Nt
 // DFT: the block then also transforms the new r of its slice (both parity
 // planes, through LDS) into vhat, the first step of the spectral P r; vhat
 // may be u itself, whose slice only this block reads.
-// Latency: the slot, this block's share of the partials and the vectors of
-// the thread's first kUpdPre sites are all requested before any of them is
-// waited for (one round trip to memory instead of three in a row).
+// Latency: once the slot says the solve runs, this block's share of the
+// partials and the vectors of the thread's first kUpdPre sites are requested
+// together (one round trip to memory instead of two in a row).
 static constexpr int kUpdPre = 4;
 
 template <typename R, bool DFT>
@@ -1357,6 +1361,10 @@ __global__ __launch_bounds__(1024) void k_pcg_upd(Lat lt, PcgBufs<R> B, double* 
     double* sout = scal + S_NSLOT * (kpar ^ 1);
     const int tau = slice_of_block(blockIdx.x, lt.Nt);
     const size_t base = (size_t)(tau < 0 ? 0 : tau) * lt.Vs;
+    if (sin_[S_DONE] != 0.0) {
+        if (blockIdx.x == 0 && threadIdx.x < S_NSLOT) sout[threadIdx.x] = sin_[threadIdx.x];
+        return;
+    }
     // requests, all in flight together: the vectors first (the partials'
     // loop waits inside)
     cplx<R> p0[kUpdPre], u0[kUpdPre], s0[kUpdPre], w0[kUpdPre], r0[kUpdPre];
@@ -1383,10 +1391,6 @@ __global__ __launch_bounds__(1024) void k_pcg_upd(Lat lt, PcgBufs<R> B, double* 
     for (int t = threadIdx.x; t < B.nparts; t += blockDim.x)
 #pragma unroll
         for (int k = 0; k < kNP7; k++) pv[k] += B.part[kNP7 * t + k];
-    if (sl[S_DONE] != 0.0) {
-        if (blockIdx.x == 0 && threadIdx.x < S_NSLOT) sout[threadIdx.x] = sin_[threadIdx.x];
-        return;
-    }
     double pr[kNP7];
     block_sumk<kNP7>(pv, red);
     if (threadIdx.x == 0)
@@ -1469,9 +1473,9 @@ __global__ __launch_bounds__(1024) void k_pcg_upd(Lat lt, PcgBufs<R> B, double* 
 template <typename R, int MC, int NB, int BS>
 __global__ __launch_bounds__(BS) void k_pcg_mv(Lat lt, PcgBufs<R> B, const cplx<R>* __restrict__ gauge, Coef<R> co,
                                                const double* __restrict__ stop) {
-    // the flag is requested with the slice's data and tested once both are
-    // in flight (a no-op launch costs one round trip, a live one no extra)
-    const double stopv = stop ? *stop : 0.0;
+    // (testing the flag only once the slice's data is in flight measured
+    // slower: the launches after a pause then load everything too)
+    if (stop && *stop != 0.0) return;
     extern __shared__ __align__(16) unsigned char smem[];
     cplx<R>* buf2 = reinterpret_cast<cplx<R>*>(smem);
     double* red = reinterpret_cast<double*>(smem + (size_t)NB * 2 * lt.Vs * sizeof(cplx<R>));
@@ -1487,7 +1491,6 @@ __global__ __launch_bounds__(BS) void k_pcg_mv(Lat lt, PcgBufs<R> B, const cplx<
     load_cells<R, MC>(um, B.u + c.tm * Vs, c.g, c.own);
     load_cells<R, MC>(ut, B.u + c.tau * Vs, c.g, c.own);
     load_cells<R, MC>(un, B.u + c.tp * Vs, c.g, c.own);
-    if (stopv != 0.0) return;
     mdagm_cells<R, MC, NB>(um, ut, un, hm, ht, c.g, c.own, co, c.tau == 0 ? R(-1) : R(1),
                            c.tau == lt.Nt - 1 ? R(-1) : R(1), buf2, lt.Vs, w);
     store_cells<R, MC>(w, B.w + c.tau * Vs, c.g, c.own);

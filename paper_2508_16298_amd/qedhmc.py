@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libqedhmc.so")
 
 OK, EINVAL, ENOCONV, EHIP, ENOMEM, EUNSUPPORTED = range(6)
 (K_MDAGM_FP32, K_MDAGM_FP64, K_FORCE, K_CG_FP32, K_CG_FP64, K_PCG_MV_FP32, K_PCG_MV_FP64, K_NET_MFMA,
- K_NET_FP32) = range(9)
+ K_NET_FP32, K_PC_SPEC_FP32, K_PC_SPEC_FP64) = range(11)
 FP64, FP32 = 0, 1
 COMPACT, NONCOMPACT = 0, 1
 PC_NONE, PC_PAPER, PC_LEARNED = 0, 1, 2
