@@ -57,6 +57,10 @@ VALU_PEAK_FP64_TFLOPS = 78.6
 # KiB, scaled by the copy-kernel calibration (x2.0 and x1.0).  Valid for the
 # kernel as measured there; set to None whenever k_cg_iter changes.
 CG_ITER_COUNTER_BYTES = {"fp32": (4652.0 * 2.0 + 6491.4 * 1.0) * 1024, "fp64": None}
+# the same for the spectral preconditioner's tau-sum + inverse-DFT kernel at
+# L=24, Nt=240 (profiles/k_pcs_tconv_idft_mixed_l24.md): 1423.0 KiB fetched,
+# 1080.0 KiB written per live launch, x2.0 and x1.0
+PC_SPEC_COUNTER_BYTES = {"fp32": (1423.0 * 2.0 + 1080.0 * 1.0) * 1024, "fp64": None}
 
 
 def parse():
@@ -202,8 +206,9 @@ def run_copy_calibration():
 
 def run_solve_only(a):
     """One mixed-precision solve of a fixed iteration count on the workload
-    (k_cg_iter in the trajectory's launch shape) and 200 standalone M^dag M
-    launches; prints the iteration count."""
+    (with --precond: PCG with the paper's preconditioner, or plain CG, whose
+    iteration is k_cg_iter in the trajectory's launch shape) and 200
+    standalone M^dag M launches; prints the iteration count."""
     import torch
     from paper_2508_16298_amd import inputs
     from paper_2508_16298_amd import qedhmc as Q
@@ -213,14 +218,15 @@ def run_solve_only(a):
     with Q.Lattice(wl.L, wl.Nt, dtau=wl.dtau, t=wl.t, J=wl.J, K=wl.K, seed=wl.seed) as lat:
         _, R = lat.heatbath(0)
         eta = lat.apply_M(theta, R, dagger=True)
-        x, st, it, rel = lat.cg_solve(theta, eta, tol=1e-30, maxit=a.solve_only, prec=prec)
+        pc = "paper" if a.precond == "paper" else None
+        x, st, it, rel = lat.cg_solve(theta, eta, tol=1e-30, maxit=a.solve_only, prec=prec, precond=pc)
         cdt = torch.complex64 if prec != "fp64" else torch.complex128
         vin = torch.from_numpy(inputs.gauss_cvec(wl.L, wl.Nt, 99)).to(cdt).cuda()
         vout = torch.empty_like(vin)
         for _ in range(200):
             lat.apply_MdagM(theta, vin, prec="fp32" if prec != "fp64" else "fp64", out=vout)
         torch.cuda.synchronize()
-    print(json.dumps({"solve_only": {"workload": wl.name, "iterations": it, "true_rel": rel,
+    print(json.dumps({"solve_only": {"workload": wl.name, "precond": a.precond, "iterations": it, "true_rel": rel,
                                      "matvec_launches": 200}}), flush=True)
 
 
@@ -865,6 +871,21 @@ def main():
     torch.cuda.synchronize()
     b2b_us = 1e3 * ev0.elapsed_time(ev1) / 200
 
+    # the paper preconditioner z = P r, 200 back-to-back applications on the
+    # same lattice in the trajectory's launch shape, every launch of its
+    # tau-sum + inverse-DFT kernel timed by its own dispatch events (the
+    # trajectory's PCG replays captured graphs, which carry no events)
+    pc_block = None
+    if pc == "paper":
+        zin = torch.from_numpy(inputs.gauss_cvec(wl.L, wl.Nt, 98)).to(cdt).cuda()
+        zout = torch.empty_like(zin)
+        lat.apply_precond(zin, prec=mv_prec, out=zout)
+        lat.profile(1)
+        for _ in range(200):
+            lat.apply_precond(zin, prec=mv_prec, out=zout)
+        pc_block = lat.profile_read(Q.K_PC_SPEC_FP32 if prec != "fp64" else Q.K_PC_SPEC_FP64)
+        lat.profile(0)
+
     N = wl.L * wl.L * wl.Nt
     mv_bytes = (24 if prec != "fp64" else 48) * N
     mv_us = 1e3 * ms_mv / max(n_mv, 1)
@@ -883,19 +904,20 @@ def main():
         work = 8.0 * (2 * 13 + wl.L // 2 + wl.L) * N
         unit, bound, peak = "TFLOP/s", "alu", (VALU_PEAK_FP32_TFLOPS if prec != "fp64" else VALU_PEAK_FP64_TFLOPS)
         kname = (f"k_pcs_tconv_idft<{'float' if prec != 'fp64' else 'double'}> (spectral paper preconditioner: "
-                 f"tau sum + inverse 2D DFT)")
+                 f"tau sum + inverse 2D DFT; 200 applications of P back to back)")
     else:
         kcls = Q.K_CG_FP32 if prec != "fp64" else Q.K_CG_FP64
         work, unit, bound, peak = (104 if prec != "fp64" else 176) * N, "GB/s", "hbm", HBM_PEAK_GBS
         kname = f"k_cg_iter<{'float' if prec != 'fp64' else 'double'}> (one fused CG iteration)"
-    n_k, ms_k = prof[kcls]
+    n_k, ms_k = pc_block if pc == "paper" else prof[kcls]
     avg_ms = ms_k / max(n_k, 1)
     scale = 1e12 if unit == "TFLOP/s" else 1e9
     achieved = work / (avg_ms * 1e-3) / scale if n_k else None
     s_per_traj = elapsed / a.steps
     cg_all = sum(r["cg_iters_total"] for r in results)
     n_solves = results[-1]["n_solves"]
-    traffic = CG_ITER_COUNTER_BYTES["fp32" if prec != "fp64" else "fp64"] if pc is None else None
+    traffic = {None: CG_ITER_COUNTER_BYTES, "paper": PC_SPEC_COUNTER_BYTES}.get(pc, {}).get(
+        "fp32" if prec != "fp64" else "fp64")
 
     out = {
         "metric": "s per HMC trajectory + M†M matvec HBM GB/s at L=24 Nτ=240, CG resid 1e-8",

@@ -1491,16 +1491,24 @@ __global__ __launch_bounds__(BS) void k_pcg_mv(Lat lt, PcgBufs<R> B, const cplx<
     load_cells<R, MC>(um, B.u + c.tm * Vs, c.g, c.own);
     load_cells<R, MC>(ut, B.u + c.tau * Vs, c.g, c.own);
     load_cells<R, MC>(un, B.u + c.tp * Vs, c.g, c.own);
+    // the own-slice vectors of the inner products: with one cell a thread
+    // requested with u (one round trip less); with two, after the matvec so
+    // they are not live across it (fewer registers)
+    Cells<R, MC> rt, pt, st;
+    if constexpr (MC == 1) {
+        load_cells<R, MC>(rt, B.r + c.tau * Vs, c.g, c.own);
+        load_cells<R, MC>(pt, B.p + c.tau * Vs, c.g, c.own);
+        load_cells<R, MC>(st, B.s + c.tau * Vs, c.g, c.own);
+    }
     mdagm_cells<R, MC, NB>(um, ut, un, hm, ht, c.g, c.own, co, c.tau == 0 ? R(-1) : R(1),
                            c.tau == lt.Nt - 1 ? R(-1) : R(1), buf2, lt.Vs, w);
     store_cells<R, MC>(w, B.w + c.tau * Vs, c.g, c.own);
-    // the own-slice vectors of the inner products, read after the matvec so
-    // they are not live across it (fewer registers with two cells a thread)
-    Cells<R, MC> u0, rt, pt, st;
-    load_cells<R, MC>(u0, B.u + c.tau * Vs, c.g, c.own);
-    load_cells<R, MC>(rt, B.r + c.tau * Vs, c.g, c.own);
-    load_cells<R, MC>(pt, B.p + c.tau * Vs, c.g, c.own);
-    load_cells<R, MC>(st, B.s + c.tau * Vs, c.g, c.own);
+    if constexpr (MC != 1) {
+        load_cells<R, MC>(rt, B.r + c.tau * Vs, c.g, c.own);
+        load_cells<R, MC>(pt, B.p + c.tau * Vs, c.g, c.own);
+        load_cells<R, MC>(st, B.s + c.tau * Vs, c.g, c.own);
+    }
+    const Cells<R, MC>& u0 = ut;  // the matvec reads its own slice without changing it
     double v[kNP7] = {dot_cells<R, MC>(rt, rt, c.own), dot_cells<R, MC>(rt, u0, c.own),
                       dot_cells<R, MC>(w, u0, c.own),  dot_cells<R, MC>(u0, st, c.own),
                       dot_cells<R, MC>(pt, w, c.own),  dot_cells<R, MC>(pt, st, c.own), 0.0};
@@ -1847,7 +1855,7 @@ static qedhmc_status pcg_round_graph(qedhmc_ctx* h, const PcgBufs<R>& B, double*
 // and with it a pause, within about 30 iterations (the launches of a round
 // past its pause are no-ops).  QEDHMC_PCG_CHUNK (read per solve, made odd)
 // overrides.
-static constexpr int kPcgChunk = 17;
+static constexpr int kPcgChunk = 9;
 
 // Rounds queued on the device as in the pipelined CG: the host keeps the
 // next round queued behind the running one and reads each round's record
@@ -1871,10 +1879,13 @@ static qedhmc_status pcg_pipelined(qedhmc_ctx* h, const PcgBufs<R>& B, double* x
     QH_HIP(hipGetLastError());
     QH_TRY(pcg_tail<R>(h, B, nullptr, false));
     QH_HIP(hipMemsetAsync(h->scal + kRecOff, 0, CR_N * sizeof(double), h->stream));
+    // the first round of a handle's first pipelined solve runs eagerly: it
+    // sets every kernel attribute before any capture
+    const bool eager0 = !h->pcg_round[sizeof(R) == 8 ? 1 : 0][0].exec;
     auto round = [&](long n) -> qedhmc_status {
         const int kp = (chunk & 1) ? (int)(n & 1) : 0, par = (int)(n & 1);
         double* out = h->h_pinned + 32 + 16 * par;
-        if (n == 0)
+        if (n == 0 && eager0)
             QH_TRY(pcg_round<R>(h, B, x, kp, chunk, mixed, maxit, out));
         else
             QH_TRY(pcg_round_graph<R>(h, B, x, kp, chunk, mixed, maxit, par, out));
