@@ -422,7 +422,8 @@ def run_se(a):
 
 def run_production(a):
     """--workload production_l24: the production loop at L=24, Nt=240 (mixed
-    precision, CG residual 1e-8): --equilibrate thermalisation trajectories
+    precision, CG residual 1e-8, the paper's preconditioner unless --precond
+    none): --equilibrate thermalisation trajectories
     with step-size adaptation (3 leapfrog steps each, target acceptance 0.7,
     gain 0.5, from dt = 0.1), then --steps measured trajectories at the frozen step with
     S_tau, S_plaq and the flux correlator logged; value = seconds per measured
@@ -435,15 +436,17 @@ def run_production(a):
 
     wl = inputs.WORKLOADS["mixed_l24"]
     prec = a.prec or wl.precision
+    pc = "paper" if a.precond == "paper" else None
     theta = torch.from_numpy(wl.initial_theta()).cuda()
     with Q.Lattice(wl.L, wl.Nt, dtau=wl.dtau, t=wl.t, J=wl.J, K=wl.K, seed=wl.seed) as lat:
         t0 = time.perf_counter()
         st, rec_t, _, dt = lat.production(theta, 0, a.equilibrate, 0, 0.1, 0.7, 0.5, 3, tol=wl.tol, prec=prec,
-                                          flux=False)
+                                          precond=pc, flux=False)
         t_therm = time.perf_counter() - t0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st2, rec, Cf, _ = lat.production(theta, 10_000, 0, a.steps, dt, 0.7, 0.0, 3, tol=wl.tol, prec=prec)
+        st2, rec, Cf, _ = lat.production(theta, 10_000, 0, a.steps, dt, 0.7, 0.0, 3, tol=wl.tol, prec=prec,
+                                         precond=pc)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         Cf = Cf.cpu().numpy()
@@ -460,7 +463,8 @@ def run_production(a):
         "dtype": "c64+f64" if prec != "fp64" else "c128", "data": "synthetic",
         "config": {"workload": (f"production_l24: L={wl.L} Nt={wl.Nt}, theta pi flux + N(0, 0.3^2), "
                                 f"{a.equilibrate} thermalisation trajectories adapting dt from 0.1 to target "
-                                f"acceptance 0.7, then {a.steps} at dt frozen, 3 leapfrog steps, {prec}")},
+                                f"acceptance 0.7, then {a.steps} at dt frozen, 3 leapfrog steps, {prec}, "
+                                f"preconditioner {pc or 'none'}")},
         "status": [int(st), int(st2)],
         "dt_final": dt, "thermalisation_s": t_therm,
         "dt_history": [r["dt"] for r in rec_t],
