@@ -246,7 +246,8 @@ def cpu_baseline(wl, th, total_cg_iters, n_solves, n_iter, pc=None):
     precond, kind = None, "CG"
     if pc == "paper":
         from oracle import precond as PC
-        taps = PC.build_stencil(8, 24)[0]
+        from paper_2508_16298_amd import qedhmc as Q
+        taps = PC.build_stencil(8, 24, cap=Q.PC_TAU_REACH)[0]
         shape = (wl.Nt, wl.L, wl.L)
         precond, kind = (lambda r: PC.apply_P(taps, r.reshape(shape)).reshape(-1)), "PCG (G^dag G)"
         n_iter = max(4, n_iter // 40)
@@ -661,7 +662,7 @@ def cpu_baseline_learned(iters, switched, flat_params, L, Nt):
     t1 = time.perf_counter()
     O.apply_MdagM(p, th, r)
     t2 = time.perf_counter()
-    taps, _ = PC.build_stencil()
+    taps, _ = PC.build_stencil(cap=Q.PC_TAU_REACH)
     t3 = time.perf_counter()
     PC.apply_P(taps, r)
     t4 = time.perf_counter()

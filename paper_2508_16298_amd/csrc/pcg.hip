@@ -11,7 +11,9 @@
 //      diagonal shift if a pivot is not positive;
 //   3. the rows of G = L^{-1} at an interior site of a bulk slice, one per x
 //      parity (the pi-flux unit cell), by one triangular solve each;
-//   4. taps (dtau, dx, dy, g) with 0 <= dtau <= kCapTau and |g| >= kThresh.
+//   4. taps (dtau, dx, dy, g) with 0 <= dtau <= kCapTau and |g| >= kThresh
+//      (the paper's matrix shows a band of 6 in tau; the reach here was
+//      chosen by time to solution).
 // Application: G[(tau,s),(tau-dtau, s+ds)] = g_{x(s) mod 2}(dtau, ds), with
 // -1 when tau-dtau wraps (antiperiodic), and P = G^dag G as two stencil
 // passes.  P is Hermitian positive definite whenever G is non-singular.
@@ -36,11 +38,12 @@ namespace qh {
 
 static constexpr int kBuildL = 8;
 static constexpr int kBuildNt = 24;
-static constexpr int kCapTau = 6;
+static constexpr int kCapTau = QEDHMC_PC_TAU_REACH;  // tau reach of G (QEDHMC_PC_CAP overrides, up to kCapMax)
+static constexpr int kCapMax = 12;
 static constexpr double kThresh = 1e-3;
 static constexpr int kNP7 = 7;  // PCG partials: <r,r>, <r,u>, <w,u>, <u,s>, <p,w>, <p,s>, unused
 
-static constexpr int kPcSlots = 8;  // tau offsets per stencil pass at most (0 <= dt <= 6, plus one)
+static constexpr int kPcSlots = 16;  // tau offsets per stencil pass at most (0 <= dt <= kCapMax, plus spare)
 
 // One stencil tap of a parity's list, q = parity + c - cmin: aidx = a - amin
 // (its slice in the window ring), off = b * half + (q >> 1) and plane = q & 1
@@ -79,13 +82,14 @@ __global__ void k_unit(cplx<double>* __restrict__ e, size_t n, size_t k) {
 // inverse DFT (its 1 / (L L/2) folded into H).  Same operator, far fewer
 // operations than the taps at the sizes the stencil is latency-bound at.
 // ---------------------------------------------------------------------------
-static constexpr int kSpecNA = 2 * kCapTau + 1;  // combined tau offsets at most
+static constexpr int kSpecNA = 2 * kCapMax + 1;  // combined tau offsets at most
 static constexpr int kSpecE = 8;                // DFT outputs per thread at most (L * L/2 <= 8192)
+static constexpr int kSpecChunk = 13;           // tau offsets per load batch of the fused tau sum
 
 static qedhmc_status build_spectral(qedhmc_ctx* h, const std::vector<HostTap> (&pass)[2][2]) {
     h->pc_spec_na = 0;
     const int L = h->lat.L, Lh = L / 2, nk = L * Lh;
-    if (L % 2 || h->lat.Nt <= kCapTau || nk > kSpecE * 1024) return QEDHMC_OK;
+    if (L % 2 || h->lat.Nt <= h->pc_cap || nk > kSpecE * 1024) return QEDHMC_OK;
     const int a0 = h->pc_pass[0].amin + h->pc_pass[1].amin, a1 = h->pc_pass[0].amax + h->pc_pass[1].amax;
     const int na = a1 - a0 + 1;
     if (na > kSpecNA) return QEDHMC_OK;
@@ -235,6 +239,14 @@ static qedhmc_status build_paper_precond(qedhmc_ctx* h) {
             return QEDHMC_EUNSUPPORTED;
         }
     }
+    // truncation of the taps: kThresh, or QEDHMC_PC_THRESH; tau reach:
+    // kCapTau, or QEDHMC_PC_CAP (1 .. kCapMax) (both read when the
+    // preconditioner is built; tuning knobs)
+    double thresh = kThresh;
+    if (const char* et = std::getenv("QEDHMC_PC_THRESH"); et && *et) thresh = std::atof(et);
+    h->pc_cap = kCapTau;
+    if (const char* ec = std::getenv("QEDHMC_PC_CAP"); ec && std::atoi(ec) > 0)
+        h->pc_cap = std::min(kCapMax, std::atoi(ec));
     // rows of G = L^{-1}: x^T L = e_n0^T  <=>  L^T x = e_n0 (back substitution)
     const int tau0 = kBuildNt / 2 + 4, y0 = L0 / 2;
     for (int par = 0; par < 2; par++) {
@@ -254,10 +266,10 @@ static qedhmc_status build_paper_precond(qedhmc_ctx* h) {
         taps.clear();
         for (int m = 0; m <= n0; m++) {
             const double mag = std::hypot(xr[m].re, xr[m].im);
-            if (!(mag >= kThresh)) continue;
+            if (!(mag >= thresh)) continue;
             const int tm = m / Vs, sm = m % Vs;
             const int dt = tau0 - tm;
-            if (dt < 0 || dt > kCapTau) continue;
+            if (dt < 0 || dt > h->pc_cap) continue;
             const int dx = ((sm % L0 - x0 + L0 / 2) % L0 + L0) % L0 - L0 / 2;
             const int dy = ((sm / L0 - y0 + L0 / 2) % L0 + L0) % L0 - L0 / 2;
             taps.push_back({dt, dx, dy, xr[m].re, xr[m].im});
@@ -857,6 +869,13 @@ __device__ __forceinline__ int spec_slice_of_block(int b, int Nt, int& p) {
     return tau < Nt ? tau : -1;
 }
 
+// Workgroup size cap of the spectral kernels: FP64 takes at most 512
+// threads (at 1024 its registers spill)
+template <typename R>
+constexpr int spec_max_threads() {
+    return sizeof(R) == 8 ? 512 : 1024;
+}
+
 // 2D DFT of nplanes parity planes held in LDS (buf[plane][row][column],
 // Lh columns), by the whole workgroup: a direct DFT over the column index
 // (L/2 points) for every row, written back to buf, then one over the row
@@ -934,7 +953,7 @@ __device__ __forceinline__ void load_twiddles(const cplx<R>* __restrict__ tw, cp
 // Forward: in a site vector, out momentum planes (e^{-i k.r}); INV: the
 // reverse with e^{+i k.r} (the normalisation sits in H).
 template <typename R, bool INV>
-__global__ __launch_bounds__(1024) void k_pcs_dft(PcSpecGeo g, const cplx<R>* __restrict__ tw,
+__global__ __launch_bounds__(spec_max_threads<R>()) void k_pcs_dft(PcSpecGeo g, const cplx<R>* __restrict__ tw,
                                                   const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
                                                   const double* __restrict__ stop) {
     if (stop && *stop != 0.0) return;
@@ -1035,7 +1054,7 @@ __global__ __launch_bounds__(256) void k_pcs_tconv(PcSpecGeo g, const cplx<R>* _
 // parity): the plane z^_p(tau) is formed in LDS from the na input slices
 // (read through the L2; used where a slice is small), then transformed back.
 template <typename R>
-__global__ __launch_bounds__(1024) void k_pcs_tconv_idft(PcSpecGeo g, const cplx<R>* __restrict__ H,
+__global__ __launch_bounds__(spec_max_threads<R>()) void k_pcs_tconv_idft(PcSpecGeo g, const cplx<R>* __restrict__ H,
                                                          const cplx<R>* __restrict__ tw,
                                                          const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
                                                          const double* __restrict__ stop) {
@@ -1049,50 +1068,43 @@ __global__ __launch_bounds__(1024) void k_pcs_tconv_idft(PcSpecGeo g, const cplx
     if (tau < 0) return;
     const int ntw = Lh + L;  // <= blockDim.x (spec_fits)
     const cplx<R> twv = (int)threadIdx.x < ntw ? tw[threadIdx.x] : mk<R>(R(0), R(0));
-    // slice offset, H offset and sign of every tau offset, once per
-    // workgroup; offsets past na read valid entries with sign 0, so every
-    // load below is unconditional and all of them are in flight together
-    size_t soff[kSpecNA], hoff[kSpecNA];
-    R sgn[kSpecNA];
-#pragma unroll
-    for (int ia = 0; ia < kSpecNA; ia++) {
-        int flip = 0;
-        const bool on = ia < g.na;
-        soff[ia] = on ? (size_t)wrap_slice(tau + g.a0 + ia, g.Nt, flip) * g.Vs : 0;
-        hoff[ia] = ((size_t)(on ? ia : 0) * 4 + 2 * p) * n;
-        sgn[ia] = on ? (flip ? R(-1) : R(1)) : R(0);
-    }
-    cplx<R> h0[kSpecNA], h1[kSpecNA], v0[kSpecNA], v1[kSpecNA];
-    auto fetch = [&](int e) {
-#pragma unroll
-        for (int ia = 0; ia < kSpecNA; ia++) {
-            h0[ia] = H[hoff[ia] + e];
-            h1[ia] = H[hoff[ia] + n + e];
-            v0[ia] = in[soff[ia] + e];
-            v1[ia] = in[soff[ia] + n + e];
-        }
-    };
-    auto form = [&](int e) {
-        cplx<R> z = mk<R>(R(0), R(0));
-#pragma unroll
-        for (int ia = 0; ia < kSpecNA; ia++) {
-            cplx<R> t = mk<R>(R(0), R(0));
-            v_cmac(t, h0[ia], v0[ia]);
-            v_cmac(t, h1[ia], v1[ia]);
-            z.re = fma(sgn[ia], t.re, z.re);
-            z.im = fma(sgn[ia], t.im, z.im);
-        }
-        buf[e] = z;
-    };
+    // the tau offsets in chunks of kSpecChunk: per chunk, the slice offset,
+    // H offset and sign of every offset (offsets past na read valid entries
+    // with sign 0, so every load is unconditional and a chunk's loads are in
+    // flight together)
+    constexpr int CH = kSpecChunk;
     const int e0 = threadIdx.x;
-    fetch(e0 < n ? e0 : 0);
     if (e0 < ntw) {
         twx[e0] = mk<R>(twv.re, -twv.im);  // inverse twiddles
     }
-    if (e0 < n) form(e0);
-    for (int e = e0 + blockDim.x; e < n; e += blockDim.x) {
-        fetch(e);
-        form(e);
+    for (int e = e0; e < n; e += blockDim.x) {
+        cplx<R> z = mk<R>(R(0), R(0));
+        for (int c0 = 0; c0 < g.na; c0 += CH) {
+            cplx<R> h0[CH], h1[CH], v0[CH], v1[CH];
+            R sgn[CH];
+#pragma unroll
+            for (int i = 0; i < CH; i++) {
+                const int ia = c0 + i;
+                int flip = 0;
+                const bool on = ia < g.na;
+                const size_t so = on ? (size_t)wrap_slice(tau + g.a0 + ia, g.Nt, flip) * g.Vs : 0;
+                const size_t ho = ((size_t)(on ? ia : 0) * 4 + 2 * p) * n;
+                sgn[i] = on ? (flip ? R(-1) : R(1)) : R(0);
+                h0[i] = H[ho + e];
+                h1[i] = H[ho + n + e];
+                v0[i] = in[so + e];
+                v1[i] = in[so + n + e];
+            }
+#pragma unroll
+            for (int i = 0; i < CH; i++) {
+                cplx<R> t = mk<R>(R(0), R(0));
+                v_cmac(t, h0[i], v0[i]);
+                v_cmac(t, h1[i], v1[i]);
+                z.re = fma(sgn[i], t.re, z.re);
+                z.im = fma(sgn[i], t.im, z.im);
+            }
+        }
+        buf[e] = z;
     }
     __syncthreads();
     const size_t sbase = (size_t)tau * g.Vs;
@@ -1103,10 +1115,18 @@ __global__ __launch_bounds__(1024) void k_pcs_tconv_idft(PcSpecGeo g, const cplx
 }
 
 // whether apply_P_t takes the spectral form: built (L even, N_tau above the
-// tau reach of a pass, L * L/2 <= 8192) and not overridden by
-// QEDHMC_PC_KERNEL=roll|stream (read per call)
+// tau reach of a pass, L * L/2 <= 8192), a plane fits one workgroup of the
+// precision, and not overridden by QEDHMC_PC_KERNEL=roll|stream (read per
+// call)
+template <typename R>
+static bool spec_fits(const qedhmc_ctx* h, int nplanes, int& threads, size_t& lds);
+
+template <typename R>
 static bool use_spectral(const qedhmc_ctx* h) {
     if (h->pc_spec_na <= 0) return false;
+    int threads;
+    size_t lds;
+    if (!spec_fits<R>(h, 1, threads, lds)) return false;
     const char* ek = std::getenv("QEDHMC_PC_KERNEL");
     return !ek || !*ek || std::strcmp(ek, "spectral") == 0;
 }
@@ -1143,7 +1163,7 @@ static const cplx<R>* spec_H(const qedhmc_ctx* h) {
 template <typename R>
 static bool spec_fits(const qedhmc_ctx* h, int nplanes, int& threads, size_t& lds) {
     const int L = h->lat.L, tot = nplanes * L * (L / 2);
-    threads = std::min(1024, (tot + 63) / 64 * 64);
+    threads = std::min(spec_max_threads<R>(), (tot + 63) / 64 * 64);
     lds = (size_t)(tot + L / 2 + L) * sizeof(cplx<R>);
     // (room for the update kernel's static reduction scratch; one thread per
     // twiddle)
@@ -1201,7 +1221,7 @@ static qedhmc_status launch_pcs_rest(qedhmc_ctx* h, const cplx<R>* vhat, cplx<R>
         return QEDHMC_OK;
     }
     // longer runs once there are enough threads without them
-    if ((size_t)g.nk * g.Nt >= ((size_t)1 << 20)) {
+    if (sizeof(R) == 4 && (size_t)g.nk * g.Nt >= ((size_t)1 << 20)) {
         const int nth = g.nk * ((g.Nt + 7) / 8);
         hipLaunchKernelGGL((k_pcs_tconv<R, 8>), dim3((nth + 255) / 256), dim3(256), 0, h->stream, g, spec_H<R>(h),
                            vhat, tmp, stop);
@@ -1222,7 +1242,7 @@ static qedhmc_status launch_pcs_rest(qedhmc_ctx* h, const cplx<R>* vhat, cplx<R>
 // distinct)
 template <typename R>
 static qedhmc_status apply_P_t(qedhmc_ctx* h, const cplx<R>* r, cplx<R>* z, cplx<R>* tmp, const double* stop) {
-    if (use_spectral(h)) {
+    if (use_spectral<R>(h)) {
         cplx<R>* vhat = spec_vhat<R>(h, z, tmp);
         QH_TRY(launch_pcs_fwd<R>(h, r, vhat, stop));
         return launch_pcs_rest<R>(h, vhat, z, tmp, stop);
@@ -1350,7 +1370,7 @@ __device__ __forceinline__ void reduce_k(const double* __restrict__ part, int Nt
 static constexpr int kUpdPre = 4;
 
 template <typename R, bool DFT>
-__global__ __launch_bounds__(1024) void k_pcg_upd(Lat lt, PcgBufs<R> B, double* __restrict__ scal, int kpar,
+__global__ __launch_bounds__(spec_max_threads<R>()) void k_pcg_upd(Lat lt, PcgBufs<R> B, double* __restrict__ scal, int kpar,
                                                   int mixed, int maxit, PcSpecGeo sg, const cplx<R>* __restrict__ tw,
                                                   cplx<R>* __restrict__ vhat) {
     __shared__ double red[kNP7 * 16 + 16];
@@ -1492,10 +1512,12 @@ __global__ __launch_bounds__(BS) void k_pcg_mv(Lat lt, PcgBufs<R> B, const cplx<
     load_cells<R, MC>(ut, B.u + c.tau * Vs, c.g, c.own);
     load_cells<R, MC>(un, B.u + c.tp * Vs, c.g, c.own);
     // the own-slice vectors of the inner products: with one cell a thread
-    // requested with u (one round trip less); with two, after the matvec so
-    // they are not live across it (fewer registers)
+    // and at most 512 threads requested with u (one round trip less);
+    // otherwise after the matvec so they are not live across it (fewer
+    // registers)
     Cells<R, MC> rt, pt, st;
-    if constexpr (MC == 1) {
+    constexpr bool early = MC == 1 && BS <= 512;  // 1024-thread workgroups would spill
+    if constexpr (early) {
         load_cells<R, MC>(rt, B.r + c.tau * Vs, c.g, c.own);
         load_cells<R, MC>(pt, B.p + c.tau * Vs, c.g, c.own);
         load_cells<R, MC>(st, B.s + c.tau * Vs, c.g, c.own);
@@ -1503,7 +1525,7 @@ __global__ __launch_bounds__(BS) void k_pcg_mv(Lat lt, PcgBufs<R> B, const cplx<
     mdagm_cells<R, MC, NB>(um, ut, un, hm, ht, c.g, c.own, co, c.tau == 0 ? R(-1) : R(1),
                            c.tau == lt.Nt - 1 ? R(-1) : R(1), buf2, lt.Vs, w);
     store_cells<R, MC>(w, B.w + c.tau * Vs, c.g, c.own);
-    if constexpr (MC != 1) {
+    if constexpr (!early) {
         load_cells<R, MC>(rt, B.r + c.tau * Vs, c.g, c.own);
         load_cells<R, MC>(pt, B.p + c.tau * Vs, c.g, c.own);
         load_cells<R, MC>(st, B.s + c.tau * Vs, c.g, c.own);
@@ -1695,7 +1717,7 @@ static qedhmc_status pcg_tail(qedhmc_ctx* h, const PcgBufs<R>& B, const double* 
 // threads and LDS for both planes of a slice, or false where it does not fit
 template <typename R>
 static bool upd_dft_plan(qedhmc_ctx* h, int& threads, size_t& lds) {
-    return use_spectral(h) && spec_fits<R>(h, 2, threads, lds);
+    return use_spectral<R>(h) && spec_fits<R>(h, 2, threads, lds);
 }
 
 template <typename R>
@@ -1735,7 +1757,7 @@ template <typename R>
 static qedhmc_status pcg_chunk_graph(qedhmc_ctx* h, const PcgBufs<R>& B, int kpar, int n, bool mixed, bool identity,
                                      int maxit) {
     qedhmc_ctx::PcgGraph& gr = h->pcg_graph[sizeof(R) == 8 ? 1 : 0][identity ? 1 : 0][kpar];
-    const int plan = identity ? 0 : (use_spectral(h) ? 1 : 0) | (spec_fused(h) ? 2 : 0);
+    const int plan = identity ? 0 : (use_spectral<R>(h) ? 1 : 0) | (spec_fused(h) ? 2 : 0);
     if (gr.exec && (gr.x != B.x || gr.rhs != B.rhs || gr.mixed != (int)mixed || gr.count != n || gr.plan != plan ||
                     gr.maxit != maxit)) {
         QH_HIP(hipGraphExecDestroy(gr.exec));
@@ -1808,7 +1830,7 @@ template <typename R>
 static qedhmc_status pcg_round_graph(qedhmc_ctx* h, const PcgBufs<R>& B, double* x, int kp, int n, bool mixed,
                                      int maxit, int par, double* out) {
     qedhmc_ctx::PcgGraph& gr = h->pcg_round[sizeof(R) == 8 ? 1 : 0][par];
-    const int plan = (use_spectral(h) ? 1 : 0) | (spec_fused(h) ? 2 : 0);
+    const int plan = (use_spectral<R>(h) ? 1 : 0) | (spec_fused(h) ? 2 : 0);
     if (gr.exec && (gr.x != x || gr.rhs != B.rhs || gr.mixed != (int)mixed || gr.count != n || gr.plan != plan ||
                     gr.maxit != maxit || gr.kp != kp)) {
         QH_HIP(hipGraphExecDestroy(gr.exec));

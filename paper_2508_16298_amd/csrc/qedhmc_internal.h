@@ -501,7 +501,7 @@ struct HostTap {
 struct PcPass {
     int amin, amax, bmin, bmax, cmin, cmax;
     int first[2], count[2];
-    int gstart[2][9];  // per parity: start of the taps of tau offset amin + k, k = 0 .. 8
+    int gstart[2][17];  // per parity: start of the taps of tau offset amin + k, k = 0 .. 16
     // the same taps grouped by spatial offset (the tau-rolling kernel): where
     // each parity's offset list starts and its length (0: not built)
     int rfirst[2], rcount[2];
@@ -588,6 +588,7 @@ struct qedhmc_ctx {
     // the paper's preconditioner (built on first use)
     bool pc_ready;
     double pc_shift;
+    int pc_cap;  // tau reach of G's taps
     std::vector<HostTap> pc_taps[2];  // per x parity
     PcPass pc_pass[2];                // G and G^dag
     void* pc_dev64;                   // device taps, FP64 and FP32

@@ -185,6 +185,7 @@ def autocorrelation(series, kmax):
 
 
 NOALLOC_SCRATCH_BYTES = 16 << 20
+PC_TAU_REACH = 12  # QEDHMC_PC_TAU_REACH: tau reach of the paper's preconditioner G as built
 
 
 def apply_MdagM_noalloc(theta, v, out, L, Nt, dtau=0.1, t=1.0, J=1.0, K=1.0, noncompact=False,

@@ -125,3 +125,11 @@ def test_library_autocorrelation_matches_the_oracle():
     assert abs(ti - ti_o) < 1e-12 * ti_o and abs(te - te_o) < 1e-12 * te_o
     with pytest.raises(Q.QedhmcError):
         Q.autocorrelation(np.ones(10), 3)
+
+
+def test_pc_tau_reach_matches_header():
+    """The binding's PC_TAU_REACH (the oracle's cap in the GPU parity tests)
+    is the library's QEDHMC_PC_TAU_REACH."""
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "qedhmc.h")).read()
+    m = re.search(r"#define QEDHMC_PC_TAU_REACH (\d+)", hdr)
+    assert m and int(m.group(1)) == Q.PC_TAU_REACH

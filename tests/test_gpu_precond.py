@@ -36,7 +36,7 @@ def _rel(a, b):
 
 @functools.lru_cache(maxsize=1)
 def _oracle_taps():
-    return PC.build_stencil(8, 24)[0]
+    return PC.build_stencil(8, 24, cap=Q.PC_TAU_REACH)[0]
 
 
 def test_stencil_matches_oracle_twin():
