@@ -58,9 +58,9 @@ VALU_PEAK_FP64_TFLOPS = 78.6
 # kernel as measured there; set to None whenever k_cg_iter changes.
 CG_ITER_COUNTER_BYTES = {"fp32": (4652.0 * 2.0 + 6491.4 * 1.0) * 1024, "fp64": None}
 # the same for the spectral preconditioner's tau-sum + inverse-DFT kernel at
-# L=24, Nt=240 (profiles/k_pcs_tconv_idft_mixed_l24.md): 1423.0 KiB fetched,
-# 1080.0 KiB written per live launch, x2.0 and x1.0
-PC_SPEC_COUNTER_BYTES = {"fp32": (1423.0 * 2.0 + 1080.0 * 1.0) * 1024, "fp64": None}
+# L=24, Nt=240 with a tau reach of 12 (profiles/k_pcs_tconv_idft_mixed_l24.md):
+# 2009.0 KiB fetched, 1080.0 KiB written per live launch, x2.0 and x1.0
+PC_SPEC_COUNTER_BYTES = {"fp32": (2009.0 * 2.0 + 1080.0 * 1.0) * 1024, "fp64": None}
 
 
 def parse():
@@ -901,12 +901,12 @@ def main():
                                                 "k_conv_mfma<true> (one 32->32 3x3x3 layer, BF16 MFMA)")
     elif pc == "paper":
         # the largest of the PCG iteration's three kernels: the tau sum over
-        # 13 offsets (2 x 2 blocks: 26 complex FMAs per site) and the inverse
-        # DFT (L/2 + L complex FMAs per site), 8 flops per complex FMA;
-        # 31 flops per algorithmic HBM byte (16 B per site), so vector-ALU
-        # bound by the roofline
+        # 2R + 1 offsets (2 x 2 blocks: 2(2R + 1) complex FMAs per site) and
+        # the inverse DFT (L/2 + L complex FMAs per site), 8 flops per complex
+        # FMA; 43 flops per algorithmic HBM byte (16 B per site) at R = 12,
+        # so vector-ALU bound by the roofline
         kcls = Q.K_PC_SPEC_FP32 if prec != "fp64" else Q.K_PC_SPEC_FP64
-        work = 8.0 * (2 * 13 + wl.L // 2 + wl.L) * N
+        work = 8.0 * (2 * (2 * Q.PC_TAU_REACH + 1) + wl.L // 2 + wl.L) * N
         unit, bound, peak = "TFLOP/s", "alu", (VALU_PEAK_FP32_TFLOPS if prec != "fp64" else VALU_PEAK_FP64_TFLOPS)
         kname = (f"k_pcs_tconv_idft<{'float' if prec != 'fp64' else 'double'}> (spectral paper preconditioner: "
                  f"tau sum + inverse 2D DFT; 200 applications of P back to back)")
