@@ -50,6 +50,7 @@ struct TiledGeo {
     int ntx, nty;    // tiles per direction
     int Tc, nchunk;  // slices per run, runs
     int nwork;       // ntx * nty * nchunk
+    int skip;        // wavefronts of halo rows skip the sweeps whose results are unused
 };
 
 template <typename R>
@@ -227,9 +228,12 @@ static constexpr int kDppFromLeft = 0x13C;   // wave_ror:1
 // read first, so lazily fetched ones are in flight across the barrier.  DPPX
 // (x sweeps of a region whose rows are whole wavefronts and x rings): the x
 // neighbours' values come by wavefront rotation, with no buffer and no
-// barrier.
+// barrier.  upd (uniform over the wavefront) false: the cell's result of
+// this sweep is never used, so only its share of the exchange is done.
 template <typename R, bool X, int IN, bool DPPX, typename HS>
-__device__ __forceinline__ void tile_phase(cplx<R> (&v)[4], const HS& hs, cplx<R>* b, int nreg, const TCell& k) {
+__device__ __forceinline__ void tile_phase(cplx<R> (&v)[4], const HS& hs, cplx<R>* b, int nreg, const TCell& k,
+                                           bool upd = true) {
+    if (X && DPPX && !upd) return;
     // keep lazily fetched phases at their sweep (no hoisting of every fetch
     // of the slice to its start, which would undo the register saving)
     if constexpr (HS::lazy) asm volatile("" ::: "memory");
@@ -259,6 +263,7 @@ __device__ __forceinline__ void tile_phase(cplx<R> (&v)[4], const HS& hs, cplx<R
         b[3 * nreg + k.c] = v[3];
     }
     __syncthreads();
+    if (!upd) return;
     if (X) {
         const cplx<R> R0 = b[k.xp], R2 = b[2 * nreg + k.xp], L1 = b[nreg + k.xm], L3 = b[3 * nreg + k.xm];
         v[1] = pl_hw(v[1], ha, R0);
@@ -290,17 +295,23 @@ __device__ __forceinline__ void tile_phase(cplx<R> (&v)[4], const HS& hs, cplx<R
 
 // v <- B'_tau v (normalised factors, rightmost first: f3 f2 f1 f0 f1 f2 f3).
 // The exchange buffers alternate over the sweeps that use them (with DPPX
-// only the y sweeps), so one barrier per such sweep suffices.
+// only the y sweeps), so one barrier per such sweep suffices.  Where the
+// result is needed only on region rows lo .. hi, the last y sweep updates
+// rows lo .. hi and the sweeps before it rows lo - 1 .. hi + 1 (the last one
+// reads them); the first y sweep reads rows lo - 2 .. hi + 2, which must hold
+// valid input.  A wavefront (region rows r0 .. r1, uniform) skips a sweep
+// when none of its rows is updated in it.
 template <typename R, bool DPPX, typename HS>
 __device__ __forceinline__ void tile_B(cplx<R> (&v)[4], const HS& hs, cplx<R>* xb, int nreg, const TCell& k,
-                                       int& kb) {
-    tile_phase<R, false, 2, DPPX>(v, hs, xb + (size_t)kb * 4 * nreg, nreg, k);
+                                       int& kb, int r0 = 0, int r1 = 0, int lo = -(1 << 20), int hi = 1 << 20) {
+    const bool u3 = r1 >= lo - 1 && r0 <= hi + 1, u4 = r1 >= lo && r0 <= hi;
+    tile_phase<R, false, 2, DPPX>(v, hs, xb + (size_t)kb * 4 * nreg, nreg, k, u3);
     kb ^= 1;
-    tile_phase<R, true, 1, DPPX>(v, hs, xb + (size_t)kb * 4 * nreg, nreg, k);
+    tile_phase<R, true, 1, DPPX>(v, hs, xb + (size_t)kb * 4 * nreg, nreg, k, u3);
     if (!DPPX) kb ^= 1;
-    tile_phase<R, true, 2, DPPX>(v, hs, xb + (size_t)kb * 4 * nreg, nreg, k);
+    tile_phase<R, true, 2, DPPX>(v, hs, xb + (size_t)kb * 4 * nreg, nreg, k, u3);
     if (!DPPX) kb ^= 1;
-    tile_phase<R, false, 0, DPPX>(v, hs, xb + (size_t)kb * 4 * nreg, nreg, k);
+    tile_phase<R, false, 0, DPPX>(v, hs, xb + (size_t)kb * 4 * nreg, nreg, k, u4);
     kb ^= 1;
 }
 
@@ -354,12 +365,32 @@ __global__ __launch_bounds__(kTileMaxThreads<R>) void k_mdagm_tiled(TiledGeo G, 
     int kb = 0;
     HopSet<R, sizeof(R) == 8> hs;
     cplx<R> y[4], u[4];
+    // Rows whose results are used (regions with a y halo of hy rows each
+    // side): B_tau v_tau feeds y_{tau+1}, which the second application reads
+    // two rows past the tile, so the first is needed on the tile and two rows
+    // either side; the second, and the one forming y_{tau0} (used only in
+    // out_{tau0}), on the tile.  r0 .. r1: the region rows of this wavefront
+    // (inactive threads take the last row).
+    int r0 = 0, r1 = 0, lo1 = -(1 << 20), hi1 = 1 << 20, lo2 = -(1 << 20), hi2 = 1 << 20;
+    if (!FY && G.skip) {
+        const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+        if constexpr (DPPX) {  // a wavefront per row
+            r0 = r1 = wv;
+        } else {
+            r0 = min(G.RH - 1, 64 * wv / G.RW);
+            r1 = min(G.RH - 1, (64 * wv + 63) / G.RW);
+        }
+        lo1 = G.hy - 2;
+        hi1 = G.hy + G.TY + 1;
+        lo2 = G.hy;
+        hi2 = G.hy + G.TY - 1;
+    }
     // y_{tau0} = v_{tau0} - e_{tau0-1} B_{tau0-1} v_{tau0-1}
     {
         const int tm = tau0 == 0 ? Nt - 1 : tau0 - 1;
         hs.set(gauge, G, k, tm, co);
         tile_load<R>(u, in + (size_t)tm * Vs, G, k);
-        tile_B<R, DPPX>(u, hs, xb, nreg, k, kb);
+        tile_B<R, DPPX>(u, hs, xb, nreg, k, kb, r0, r1, lo2, hi2);
         tile_load<R>(y, in + (size_t)tau0 * Vs, G, k);
         const R e = tm == Nt - 1 ? -co.C : co.C;
 #pragma unroll
@@ -377,7 +408,7 @@ __global__ __launch_bounds__(kTileMaxThreads<R>) void k_mdagm_tiled(TiledGeo G, 
         // FP64 after it, where its registers are free
         if constexpr (sizeof(R) == 4) tile_load<R>(vn, in + (size_t)tp * Vs, G, k);
         const R e = tau == Nt - 1 ? -co.C : co.C;
-        tile_B<R, DPPX>(u, hs, xb, nreg, k, kb);  // B'_tau v_tau
+        tile_B<R, DPPX>(u, hs, xb, nreg, k, kb, r0, r1, lo1, hi1);  // B'_tau v_tau
         if constexpr (sizeof(R) == 8) tile_load<R>(vn, in + (size_t)tp * Vs, G, k);
         cplx<R> yn[4];
 #pragma unroll
@@ -385,7 +416,7 @@ __global__ __launch_bounds__(kTileMaxThreads<R>) void k_mdagm_tiled(TiledGeo G, 
             yn[q] = mk<R>(vn[q].re - e * u[q].re, vn[q].im - e * u[q].im);
             u[q] = yn[q];
         }
-        tile_B<R, DPPX>(u, hs, xb, nreg, k, kb);  // B'_tau y_{tau+1}
+        tile_B<R, DPPX>(u, hs, xb, nreg, k, kb, r0, r1, lo2, hi2);  // B'_tau y_{tau+1}
         cplx<R> w[4];
 #pragma unroll
         for (int q = 0; q < 4; q++) w[q] = mk<R>(y[q].re - e * u[q].re, y[q].im - e * u[q].im);
@@ -582,6 +613,8 @@ static qedhmc_status mdagm_tiled_t(qedhmc_ctx* h, const void* in, void* out, con
     // them in LDS
     const bool dppx = p.fx && !p.fy && p.g.RW == 64 && p.threads == p.g.RW * p.g.RH &&
                       env_int("QEDHMC_TILE_DPP", 1) != 0;
+    // QEDHMC_TILE_SKIP=0 (read per call) keeps every halo row's sweeps
+    p.g.skip = env_int("QEDHMC_TILE_SKIP", 1) != 0;
     if (p.fx && p.fy) return go(k_mdagm_tiled<R, true, true, PART>);
     if (dppx) return go(k_mdagm_tiled<R, true, false, PART, true>);
     if (p.fx) return go(k_mdagm_tiled<R, true, false, PART>);

@@ -81,9 +81,11 @@ def test_tiled_mdagm_default_large_slices(L, Nt, prec):
 @pytest.mark.parametrize("L,Nt,tc", [(128, 6, 0), (128, 5, 2)])
 def test_tiled_x_exchange_by_wavefront_rotation(L, Nt, tc, monkeypatch):
     """At L = 128 every FP32 strip row is one wavefront and one x ring: the x
-    exchanges go by wavefront rotation instead of LDS.  Same arithmetic on the
-    same values: bitwise equal to the LDS exchange, and to the oracle to the
-    FP32 bar (default and forced ragged runs)."""
+    exchanges go by wavefront rotation instead of LDS, and the halo rows skip
+    the sweeps whose results are never used.  Same arithmetic on the same
+    values for every stored site: bitwise equal to the LDS exchange, with and
+    without the skipping, and to the oracle to the FP32 bar (default and
+    forced ragged runs)."""
     th = inputs.noisy_pi_flux_theta(L, Nt, 0.3, seed=950 + Nt)
     v = _dev(inputs.gauss_cvec(L, Nt, seed=951 + Nt), CDT["fp32"])
     monkeypatch.setenv("QEDHMC_TILE_TC", str(tc))
@@ -93,10 +95,38 @@ def test_tiled_x_exchange_by_wavefront_rotation(L, Nt, tc, monkeypatch):
         a = lat.apply_MdagM(thd, v, prec="fp32")
         torch.cuda.synchronize()
         monkeypatch.setenv("QEDHMC_TILE_DPP", "1")
+        monkeypatch.setenv("QEDHMC_TILE_SKIP", "0")
+        c = lat.apply_MdagM(thd, v, prec="fp32")
+        torch.cuda.synchronize()
+        monkeypatch.setenv("QEDHMC_TILE_SKIP", "1")
         b = lat.apply_MdagM(thd, v, prec="fp32")
         torch.cuda.synchronize()
-    assert torch.equal(a, b)
+    assert torch.equal(a, c) and torch.equal(a, b)
     assert _rel(_host(b), O.apply_MdagM(O.lat(L, Nt), th, v.cpu().numpy().astype(np.complex128))) < TOL["fp32"]
+
+
+@pytest.mark.parametrize("L,Nt,tc,cap", [(66, 6, 0, 1024), (172, 3, 2, 1024), (40, 5, 2, 100), (32, 6, 4, 224)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tiled_halo_rows_skip_unused_sweeps(L, Nt, tc, cap, prec, tiled_env, monkeypatch):
+    """Wavefronts whose region rows are all outside the rows a B application
+    is needed on skip its sweeps (strips at L = 66 and 32, squares at 172 and
+    40): every stored site is bitwise what the kernel gives when every row
+    computes every sweep, and within the bar of the oracle."""
+    tiled_env("tiled", tc, cap)
+    th = inputs.noisy_pi_flux_theta(L, Nt, 0.3, seed=980 + L)
+    v = inputs.gauss_cvec(L, Nt, seed=981 + L)
+    with Q.Lattice(L, Nt) as lat:
+        thd, vd = _dev(th), _dev(v, CDT[prec])
+        monkeypatch.setenv("QEDHMC_TILE_SKIP", "0")
+        a = lat.apply_MdagM(thd, vd, prec=prec)
+        torch.cuda.synchronize()
+        monkeypatch.setenv("QEDHMC_TILE_SKIP", "1")
+        b = lat.apply_MdagM(thd, vd, prec=prec)
+        torch.cuda.synchronize()
+    err = _rel(_host(b), O.apply_MdagM(O.lat(L, Nt), th, v))
+    print(f"L={L} Nt={Nt} {prec}: bitwise {torch.equal(a, b)}, oracle {err:.2e}", flush=True)
+    assert torch.equal(a, b)
+    assert err < TOL[prec]
 
 
 def test_tiled_matches_whole_slice_kernel(tiled_env):
