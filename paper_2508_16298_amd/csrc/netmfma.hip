@@ -12,7 +12,10 @@
 // 16-site tiles (the fastest of the tilings timed at L=66),
 // and reads the A fragments straight from the channels-last activations
 // (one 16-byte load per lane: 8 channels of one site).  Neighbour reuse
-// across taps is left to L1/L2.
+// across taps is left to L1/L2.  Each lane wraps its site's three
+// coordinates once (three offsets per direction); a tap's site is then one
+// three-way sum, and the taps are unrolled so the loads of later taps can be
+// issued ahead of the products of earlier ones.
 #include "net_internal.h"
 
 namespace qh {
@@ -58,28 +61,38 @@ __global__ __launch_bounds__(kBlock) void k_conv_mfma(NetGeo g, const uint16_t* 
     if (site0 >= g.N) return;
     const int row = lane & 15, kq = lane >> 4;
     // this lane's A rows: site site0 + 16 t + row (clamped into range; the
-    // stores below skip the clamped ones)
-    int st[kTiles], sy[kTiles], sx[kTiles];
+    // stores below skip the clamped ones), as the wrapped slice, row and
+    // column offsets of its three neighbours per direction (d = 0, 1, 2 for
+    // -1, 0, +1)
+    int ot[kTiles][3], oy[kTiles][3], ox[kTiles][3];
 #pragma unroll
     for (int t = 0; t < kTiles; t++) {
         const int m = min(site0 + 16 * t + row, g.N - 1);
-        site_of(g, m, st[t], sy[t], sx[t]);
+        int st, sy, sx;
+        site_of(g, m, st, sy, sx);
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            ot[t][d] = wrap(st + d - 1, g.Nt) * g.Vs;
+            oy[t][d] = wrap(sy + d - 1, g.L) * g.L;
+            ox[t][d] = wrap(sx + d - 1, g.L);
+        }
     }
+    const uint16_t* inq = in + 8 * kq;
     f32x4 acc[kTiles][2];
 #pragma unroll
     for (int t = 0; t < kTiles; t++)
 #pragma unroll
         for (int h = 0; h < 2; h++) acc[t][h] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll 1
+#pragma unroll
     for (int k = 0; k < 27; k++) {
-        const int dt = k / 9 - 1, dy = (k / 3) % 3 - 1, dx = k % 3 - 1;
+        const int dt = k / 9, dy = (k / 3) % 3, dx = k % 3;
         const bf16x8 b0 = sW[(2 * k) * 64 + lane];
         const bf16x8 b1 = sW[(2 * k + 1) * 64 + lane];
         bf16x8 a[kTiles];
 #pragma unroll
         for (int t = 0; t < kTiles; t++) {
-            const int m = wrap(st[t] + dt, g.Nt) * g.Vs + wrap(sy[t] + dy, g.L) * g.L + wrap(sx[t] + dx, g.L);
-            a[t] = *reinterpret_cast<const bf16x8*>(in + (size_t)m * 32 + 8 * kq);
+            const unsigned m = (unsigned)(ot[t][dt] + oy[t][dy] + ox[t][dx]);
+            a[t] = *reinterpret_cast<const bf16x8*>(inq + (size_t)m * 32);
         }
 #pragma unroll
         for (int t = 0; t < kTiles; t++) {
