@@ -155,7 +155,9 @@ qedhmc_status qedhmc_apply_M(qedhmc_t h, const double *theta, const void *in,
  * spatial tiles streamed along tau (two B_tau applications per slice); the
  * environment variables QEDHMC_MDAGM=slice|tiled, QEDHMC_TILE_TC and
  * QEDHMC_TILE_THREADS, read on every call, override that choice and the
- * tile plan (tuning and tests). */
+ * tile plan, and QEDHMC_TILE_DPP=0 / QEDHMC_TILE_SKIP=0 keep the x exchanges
+ * in LDS / every halo row's sweeps (tuning and tests; the result is bitwise
+ * the same). */
 qedhmc_status qedhmc_apply_MdagM(qedhmc_t h, const double *theta,
                                  const void *in, void *out,
                                  qedhmc_precision prec);
