@@ -249,9 +249,12 @@ qedhmc_status qedhmc_heatbath(qedhmc_t h, uint64_t traj_index, double *mom,
                               double *R);
 
 /* One HQMC trajectory: heat bath, eta = M^dag R, n_steps leapfrog steps of
- * length traj_len / n_steps with a fresh solve (from x = 0) at every theta,
- * Metropolis with u from Philox.  theta_inout: device double[2][Nt][L][L],
- * overwritten by the proposal on acceptance, unchanged on rejection. */
+ * length traj_len / n_steps with a solve at every theta (the first from
+ * x = 0, each later one started from the previous solution: it solves for the
+ * correction to the same absolute target tol |eta|; QEDHMC_WARM_START=0,
+ * read per call, starts every solve from x = 0), Metropolis with u from
+ * Philox.  theta_inout: device double[2][Nt][L][L], overwritten by the
+ * proposal on acceptance, unchanged on rejection. */
 qedhmc_status qedhmc_hmc_trajectory(qedhmc_t h, double *theta_inout,
                                     uint64_t traj_index, int32_t n_steps,
                                     double traj_len, double tol, int32_t maxit,

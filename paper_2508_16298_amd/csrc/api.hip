@@ -443,11 +443,49 @@ qedhmc_status qedhmc_hmc_trajectory(qedhmc_t h, double* theta, uint64_t traj, in
     double* X = (double*)h->ws[6];
     int it_total = 0, it_max = 0, nrel_total = 0, worst = 0;
     double max_rel = 0.0;
-    auto solve = [&](const double* th) -> qedhmc_status {
+    // The solves after the first share eta and see theta moved by one drift:
+    // each starts from the previous X (QEDHMC_WARM_START=0, read per
+    // trajectory, starts every solve from zero).  It solves O e = eta - O X
+    // for the correction from zero, to the tolerance that keeps the same
+    // target |eta - O (X + e)| <= tol |eta|, and adds e to X; solves that
+    // reach the tolerance give the same X to that tolerance, and every solver
+    // (CG, PCG, flexible CG) runs unchanged.
+    const char* ews = std::getenv("QEDHMC_WARM_START");
+    const bool warm_ok = !(ews && *ews && std::atoi(ews) == 0);
+    double* bres = (double*)h->ws[0];  // eta - O X
+    double* corr = (double*)h->ws[1];  // e
+    auto solve = [&](const double* th, bool warm) -> qedhmc_status {
         int32_t it = 0;
         double rel = 0.0;
         int nr = 0, sw = -1;
-        const qedhmc_status st = solve_at(h, th, eta, X, tol, maxit, prec, pc, &it, &rel, &nr, &sw);
+        qedhmc_status st = QEDHMC_OK;
+        if (!(warm && warm_ok)) {
+            st = solve_at(h, th, eta, X, tol, maxit, prec, pc, &it, &rel, &nr, &sw);
+        } else {
+            QH_TRY(ensure_gauge(h, th, QEDHMC_FP64));
+            QH_TRY(launch_mdagm(h, QEDHMC_FP64, X, bres, nullptr));
+            QH_TRY(launch_lincomb(h, bres, 1.0, eta, -1.0, bres, 2 * N));
+            QH_TRY(launch_sumsq(h, eta, 2 * N, h->scal + 80));
+            QH_TRY(launch_sumsq(h, bres, 2 * N, h->scal + 81));
+            QH_HIP(hipMemcpyAsync(h->h_pinned, h->scal + 80, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+            QH_HIP(hipStreamSynchronize(h->stream));
+            const double nb = std::sqrt(h->h_pinned[0]), nr0 = std::sqrt(h->h_pinned[1]);
+            if (!std::isfinite(nr0)) {
+                // as a solve that missed its tolerance: the proposal is rejected
+                worst = 2;
+                max_rel = HUGE_VAL;
+                return QEDHMC_OK;
+            }
+            if (nr0 > tol * nb) {
+                double relc = 0.0;
+                st = solve_at(h, th, bres, corr, tol * nb / nr0, maxit, prec, pc, &it, &relc, &nr, &sw);
+                if (st != QEDHMC_OK && st != QEDHMC_ENOCONV) return st;
+                QH_TRY(launch_lincomb(h, X, 1.0, X, 1.0, corr, 2 * N));
+                rel = relc * nr0 / nb;
+            } else {
+                rel = nb > 0.0 ? nr0 / nb : 0.0;
+            }
+        }
         if (st != QEDHMC_OK && st != QEDHMC_ENOCONV) return st;
         if (st == QEDHMC_ENOCONV) worst = 2;
         if (sw >= 0) out->pc_fallbacks++;
@@ -465,7 +503,7 @@ qedhmc_status qedhmc_hmc_trajectory(qedhmc_t h, double* theta, uint64_t traj, in
     QH_TRY(ensure_gauge(h, theta, QEDHMC_FP64));
     QH_TRY(launch_apply_M(h, QEDHMC_FP64, R, eta, 1));
     // H at the start
-    QH_TRY(solve(theta));
+    QH_TRY(solve(theta, false));
     QH_TRY(launch_dot_re(h, eta, X, 2 * N, sc + 2));
     QH_TRY(launch_sumsq(h, h->mom, nb, sc + 1));
     QH_TRY(launch_bosonic(h, theta, h->force_b, sc + 0));
@@ -475,7 +513,7 @@ qedhmc_status qedhmc_hmc_trajectory(qedhmc_t h, double* theta, uint64_t traj, in
     for (int n = 0; n < n_steps; n++) {
         QH_TRY(launch_kick(h, h->mom, h->force, h->force_b, 0.5 * dt, nb));
         QH_TRY(launch_drift(h, theta, h->mom, 2.0 * dt, nb));
-        QH_TRY(solve(theta));
+        QH_TRY(solve(theta, true));
         QH_TRY(ensure_gauge(h, theta, prec));
         QH_TRY(launch_force(h, prec, X, h->force));
         QH_TRY(launch_bosonic(h, theta, h->force_b, sc + 3));

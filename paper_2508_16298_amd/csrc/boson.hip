@@ -160,6 +160,19 @@ qedhmc_status launch_drift(qedhmc_ctx* h, double* theta, const double* mom, doub
     return QEDHMC_OK;
 }
 
+// out = a x + b y (n doubles; out may be x or y)
+__global__ void k_lincomb(double* out, double a, const double* x, double b, const double* y, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = a * x[i] + b * y[i];
+}
+
+qedhmc_status launch_lincomb(qedhmc_ctx* h, double* out, double a, const double* x, double b, const double* y,
+                             size_t n) {
+    hipLaunchKernelGGL(k_lincomb, dim3(kGridR), dim3(kBlockR), 0, h->stream, out, a, x, b, y, n);
+    QH_HIP(hipGetLastError());
+    return QEDHMC_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Metropolis (step iii): scalar slots sc[0..5] = SB0, K0, SF0, SB1, K1, SF1;
 // writes sc[6] = dH, sc[7] = u, sc[8] = accepted (1/0).

@@ -546,7 +546,8 @@ struct qedhmc_ctx {
     double* partial;            // per-block partial sums: [2][Nt][6] for CG, then 4096 more
     double* tpart;              // slices of more than 1024 cells: CG partials per (slice, tile), then Nt more
     int tpart_tiles;            // tiles per slice the buffer holds
-    double* scal;               // device scalars: [0,32) CG slots, [64,80) trajectory, [100] action
+    double* scal;               // device scalars: [0,32) CG slots, [64,80) trajectory, [80,82) warm-start
+                                // norms, [100] action
     double* h_pinned;           // pinned host mirror of a few scalars
     // sampled kernel timing (qedhmc_profile)
     int prof_every;
@@ -703,6 +704,8 @@ qedhmc_status launch_dot_re(qedhmc_ctx* h, const double* a, const double* b, siz
 qedhmc_status launch_sumsq(qedhmc_ctx* h, const double* a, size_t n, double* out_dev);
 qedhmc_status launch_kick(qedhmc_ctx* h, double* mom, const double* F, const double* Fb, double c, size_t n);
 qedhmc_status launch_drift(qedhmc_ctx* h, double* theta, const double* mom, double c, size_t n);
+qedhmc_status launch_lincomb(qedhmc_ctx* h, double* out, double a, const double* x, double b, const double* y,
+                             size_t n);
 // Metropolis test of the trajectory (dH, u, decision into scal_dev[6..8]);
 // reject = true refuses the proposal whatever dH is (an unconverged solve)
 qedhmc_status launch_metropolis(qedhmc_ctx* h, uint64_t traj, bool reject, double* scal_dev);

@@ -336,6 +336,42 @@ def test_trajectory_mixed_matches_fp64_at_workload_size():
     assert _rel(F32, F64) < 1e-6
 
 
+@pytest.mark.parametrize("prec,tol,precond", [("fp64", 1e-10, None), ("fp32", 1e-8, "paper")])
+def test_trajectory_warm_started_solves_match_cold(prec, tol, precond, monkeypatch):
+    """The solves after a trajectory's first start from the previous solution
+    (a correction solved to the same absolute target); starting every solve
+    from zero instead (QEDHMC_WARM_START=0) gives the same trajectory to the
+    solver tolerance: H0 to rounding, dH within 1e-6 |H0|, the same decision
+    where |dH + ln u| exceeds that gap, every solve at the tolerance, and no
+    more iterations warm than cold.  Both against the oracle's dH of the same
+    trajectory (tests/golden/fp64_l12_trajectories.json, trajectory 0)."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "fp64_l12_trajectories.json")))
+    ro = gold["trajectories"][0]
+    wl = inputs.WORKLOADS["fp64_l12"]
+    th0 = wl.initial_theta()
+    out = {}
+    with Q.Lattice(wl.L, wl.Nt, seed=wl.seed) as lat:
+        for w in ("0", "1"):
+            monkeypatch.setenv("QEDHMC_WARM_START", w)
+            thd = _dev(th0)
+            out[w] = lat.hmc_trajectory(thd, traj=0, n_steps=wl.n_steps, traj_len=wl.traj_len, tol=tol, prec=prec,
+                                        precond=precond)
+    a, b = out["0"], out["1"]
+    gap = 1e-6 * abs(a["H0"])
+    print(f"{prec} {precond}: dH cold {a['dH']:.6f} warm {b['dH']:.6f} oracle {ro['dH']:.6f}; iterations cold "
+          f"{a['cg_iters_total']} warm {b['cg_iters_total']}", flush=True)
+    assert a["status"] == 0 and b["status"] == 0
+    assert a["max_true_resid"] <= tol and b["max_true_resid"] <= tol
+    assert a["n_solves"] == b["n_solves"] == wl.n_steps + 1
+    assert abs(a["H0"] - b["H0"]) <= 1e-9 * abs(a["H0"])
+    assert abs(a["dH"] - b["dH"]) <= gap and abs(b["dH"] - ro["dH"]) <= gap
+    if abs(a["dH"] + np.log(a["u"])) > gap:
+        assert a["accepted"] == b["accepted"]
+    assert b["cg_iters_total"] <= a["cg_iters_total"]
+
+
 def test_fp64_chain_matches_oracle_golden():
     """The FP64 workload at L=12, Nt=120: 20 chained trajectories (20 leapfrog
     steps, CG 1e-10) from pi flux + N(0, 0.3^2), RNG seed 1002, against the
